@@ -1,0 +1,412 @@
+"""FP64 reference implementation of the per-beam LiDAR return (TEST INFRASTRUCTURE ONLY).
+
+This is the oracle: plain, slow, double-precision code that states what the
+simulation computes, step by step in the order of the paper (Jansen, Huebel,
+Steckel, "Physical LiDAR Simulation in Real-Time Engine", arXiv:2208.10295).
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+it.  It shares no code with the GPU library and imports nothing from it; the
+two meet only in the seeded inputs of ``lidar_inputs``.
+
+Steps (paper section in brackets):
+
+1. Beam pattern [II-A, eq.3 and the text after it]: azimuth theta_i spans
+   FOV_h in equal steps, elevations phi_j come from the sensor's table.  The
+   beam direction in the sensor frame is
+   s = (cos phi cos theta, cos phi sin theta, sin phi); this is the direction
+   whose pinhole projection gives eq.3 (tan theta horizontally,
+   sin phi / (cos phi cos theta) vertically).  World ray: o = p, d = R s.
+2. Depth [II-A]: the range of the first surface along the beam.  Computed as
+   the first ray/triangle intersection (``first_hit.c``).
+3. Labels [II-B]: the instance label of the object that owns the hit surface.
+4. Material model [II-C, eq.4]: R_lambda(theta) = R_lambda(0) cos(theta), with
+   cos(theta) from the dot product of the surface normal and the beam, and
+   R_lambda(0) the material's spectral reflectance at the sensor wavelength.
+   Generalised to cos^k with a per-material exponent k (k = 1 is eq.4).
+5. Range noise [II-A, last paragraph]: Gaussian noise with a per-material
+   scale sigma is added to the depth.  The Gaussian comes from a counter-based
+   generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the
+   seed, counter (beam, scan, instance, 0), then Box-Muller.
+6. Capability model [II-D, eq.5]: R_L(d) = R_L,max / d_max * d; the point is
+   kept iff R_L(d) <= R_lambda, with d including the noise, and anything beyond
+   d_max is dropped.
+7. Output [Fig.1 caption]: a point cloud with depth, intensity and instance
+   label per point.
+
+Readings of points where the paper is silent or garbled are listed with the
+functions that depend on them.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfirst_hit.so")
+_lib = None
+
+MISS_LABEL = 0xFFFFFFFF
+MISS_TRI = 0xFFFFFFFF
+# |z| of a Box-Muller normal from 32-bit uniforms is at most sqrt(-2 ln 2^-32) = 6.66043...
+BOX_MULLER_BOUND = 6.6605
+TIE_MARGIN_M = 1e-6          # second-hit margin below which a ray is ambiguous
+EDGE_ABS_M = 1e-6            # edge-graze margin: EDGE_ABS_M + EDGE_REL * t
+EDGE_REL = 1e-6
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.oracle_first_hit.argtypes = [ctypes.c_int64, P, P, ctypes.c_int64, P, P,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, P, P, P, P, P]
+        lib.oracle_first_hit.restype = ctypes.c_int
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+# ----------------------------------------------------------------------------
+# step 1: beam pattern [II-A]
+# ----------------------------------------------------------------------------
+def beam_angles(sensor):
+    """(theta [n_az], phi [n_ch]) in radians.
+
+    theta_i = az0 + i * FOV_h / N_az (FOV_h usually 0..360 deg, Section II-A);
+    phi_j = the data-sheet elevation of channel j.  Reading: azimuth 0 is the
+    sensor x axis and grows counter-clockwise (right-handed, z up).
+    """
+    i = np.arange(sensor.n_az, dtype=np.float64)
+    theta = np.deg2rad(sensor.az0_deg + i * (sensor.fov_h_deg / sensor.n_az))
+    phi = np.deg2rad(np.asarray(sensor.elev_deg, dtype=np.float64))
+    return theta, phi
+
+
+def beam_directions(sensor) -> np.ndarray:
+    """Unit beam directions in the sensor frame, [n_ch, n_az, 3], beam b = j * n_az + i."""
+    theta, phi = beam_angles(sensor)
+    cp, sp = np.cos(phi)[:, None], np.sin(phi)[:, None]
+    ct, st = np.cos(theta)[None, :], np.sin(theta)[None, :]
+    return np.stack([cp * ct, cp * st, np.broadcast_to(sp, (len(phi), len(theta)))], axis=-1)
+
+
+def pixel_of_beam(theta, phi, width, fov_c):
+    """Eq.1-3: pixel of beam (theta, phi) in a square pinhole camera of width W.
+
+    f = W / (2 tan(FOV_c / 2)), c_u = c_v = W / 2 (eq.2).  The printed eq.3 for
+    n_y is garbled ("(sin phi - f_y)" and "c_y"); it is read as the pinhole
+    projection n_y = -f sin(phi) / (cos(phi) cos(theta)) + c_v.
+    """
+    f = width / (2.0 * math.tan(fov_c / 2.0))
+    c = width / 2.0
+    nx = math.sin(theta) * f / math.cos(theta) + c
+    ny = -f * math.sin(phi) / (math.cos(phi) * math.cos(theta)) + c
+    return nx, ny
+
+
+def rotation_from_quat(q) -> np.ndarray:
+    """Rotation matrix of the unit quaternion (w, x, y, z), FP64 (q normalised first)."""
+    w, x, y, z = np.asarray(q, dtype=np.float64) / np.linalg.norm(np.asarray(q, dtype=np.float64))
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def so3_exp(w) -> np.ndarray:
+    """Rodrigues' formula: rotation by angle |w| about w / |w|."""
+    w = np.asarray(w, dtype=np.float64)
+    th = np.linalg.norm(w)
+    K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    if th < 1e-12:
+        return np.eye(3) + K + 0.5 * K @ K
+    return np.eye(3) + math.sin(th) / th * K + (1 - math.cos(th)) / th ** 2 * K @ K
+
+
+def so3_left_jacobian(w) -> np.ndarray:
+    """J_l(w) with Exp(w + e) = Exp(J_l(w) e) Exp(w) to first order in e."""
+    w = np.asarray(w, dtype=np.float64)
+    th = np.linalg.norm(w)
+    K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    if th < 1e-8:
+        return np.eye(3) + 0.5 * K + K @ K / 6.0
+    return np.eye(3) + (1 - math.cos(th)) / th ** 2 * K + (th - math.sin(th)) / th ** 3 * K @ K
+
+
+# ----------------------------------------------------------------------------
+# step 2: first hit (delegated to first_hit.c)
+# ----------------------------------------------------------------------------
+def first_hit(scene, orig, dirs, t_min, t_max):
+    """Brute-force FP64 first hit of rays (orig[n,3], dirs[n,3]) against every triangle.
+
+    Returns dict of arrays: tri (int64, -1 = none), t, t_second, edge_in, near_t.
+    """
+    lib = _load()
+    orig = np.ascontiguousarray(np.broadcast_to(orig, dirs.shape), dtype=np.float64)
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+    n = dirs.shape[0]
+    vtx = np.ascontiguousarray(scene.vertices, dtype=np.float32)
+    idx = np.ascontiguousarray(scene.indices, dtype=np.uint32)
+    out = dict(tri=np.empty(n, np.int64), t=np.empty(n), t_second=np.empty(n),
+               edge_in=np.empty(n), near_t=np.empty(n))
+    rc = lib.oracle_first_hit(n, orig.ctypes.data, dirs.ctypes.data, idx.shape[0], vtx.ctypes.data,
+                              idx.ctypes.data, float(t_min), float(t_max), EDGE_ABS_M, EDGE_REL,
+                              out["tri"].ctypes.data, out["t"].ctypes.data, out["t_second"].ctypes.data,
+                              out["edge_in"].ctypes.data, out["near_t"].ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_first_hit allocation failed")
+    return out
+
+
+def face_normals(scene, tri) -> np.ndarray:
+    """Geometric unit normal normalize((v1 - v0) x (v2 - v0)) of triangles `tri`, FP64."""
+    v = scene.vertices.astype(np.float64)[scene.indices[tri].astype(np.int64)]
+    n = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    return n / np.linalg.norm(n, axis=1, keepdims=True)
+
+
+# ----------------------------------------------------------------------------
+# step 4: spectral reflectance at the sensor wavelength [II-C]
+# ----------------------------------------------------------------------------
+def reflectance_at_wavelength(spectra, wavelength_nm, lambda0_nm=400.0, dlambda_nm=10.0):
+    """R_lambda(0 deg) per material at the sensor wavelength.
+
+    Reading: linear interpolation between the 10-nm bins, clamped to the first
+    and last bin outside the table (returns (R0[nmat], clamped_flag)).
+    """
+    T = np.asarray(spectra, dtype=np.float64)
+    nb = T.shape[1]
+    q = (float(wavelength_nm) - lambda0_nm) / dlambda_nm
+    if q <= 0.0:
+        return T[:, 0].copy(), q < 0.0
+    if q >= nb - 1:
+        return T[:, nb - 1].copy(), q > nb - 1
+    i = int(math.floor(q))
+    f = q - i
+    return (1.0 - f) * T[:, i] + f * T[:, i + 1], False
+
+
+# ----------------------------------------------------------------------------
+# step 5: counter-based Gaussian noise [II-A]
+# ----------------------------------------------------------------------------
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(counter, key):
+    """Philox4x32 with 10 rounds (Salmon et al., SC'11).
+
+    counter: uint32 [n, 4]; key: (k0, k1).  Each round multiplies words 0 and 2
+    by the two Philox multipliers, and the new block is
+    (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0));
+    the key is advanced by the Weyl constants between rounds.
+    """
+    c = np.asarray(counter, dtype=np.uint64).reshape(-1, 4)
+    m32 = np.uint64(0xFFFFFFFF)
+    c0, c1, c2, c3 = (c[:, i].copy() for i in range(4))
+    k0 = np.uint64(int(key[0]) & 0xFFFFFFFF)
+    k1 = np.uint64(int(key[1]) & 0xFFFFFFFF)
+    for r in range(10):
+        if r:
+            k0 = np.uint64((int(k0) + PHILOX_W0) & 0xFFFFFFFF)
+            k1 = np.uint64((int(k1) + PHILOX_W1) & 0xFFFFFFFF)
+        p0 = np.uint64(PHILOX_M0) * c0
+        p1 = np.uint64(PHILOX_M1) * c2
+        c0, c1, c2, c3 = ((p1 >> np.uint64(32)) ^ c1 ^ k0, p1 & m32,
+                          (p0 >> np.uint64(32)) ^ c3 ^ k1, p0 & m32)
+    return np.stack([c0, c1, c2, c3], axis=1).astype(np.uint32)
+
+
+def box_muller(xa, xb):
+    """Standard normal from two 32-bit words: u1 = (xa + 1) 2^-32 in (0, 1], u2 = xb 2^-32,
+    z = sqrt(-2 ln u1) cos(2 pi u2).  |z| <= sqrt(64 ln 2) ~ 6.6604."""
+    u1 = (np.asarray(xa, dtype=np.float64) + 1.0) * 2.0 ** -32
+    u2 = np.asarray(xb, dtype=np.float64) * 2.0 ** -32
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+def beam_normals(seed: int, scan: int, inst: int, beams):
+    """(z_range, z_intensity) for beams, from Philox counter (beam, scan, inst, 0), key = seed."""
+    beams = np.asarray(beams, dtype=np.uint64)
+    ctr = np.zeros((len(beams), 4), dtype=np.uint64)
+    ctr[:, 0] = beams
+    ctr[:, 1] = scan
+    ctr[:, 2] = inst
+    x = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    return box_muller(x[:, 0], x[:, 1]), box_muller(x[:, 2], x[:, 3])
+
+
+# ----------------------------------------------------------------------------
+# the whole path for one scan
+# ----------------------------------------------------------------------------
+def trace_limit(scene, sensor) -> float:
+    """Largest first-hit distance that can still be detected: d_max plus the
+    largest possible noise excursion (Box-Muller is bounded)."""
+    if not sensor.noise_on:
+        return float(sensor.d_max)
+    return float(sensor.d_max) + BOX_MULLER_BOUND * float(np.max(scene.sigma_range))
+
+
+def simulate(scene, sensor, pose, seed: int = 0, scan: int = 0, inst: int = 0, beams=None,
+             rho=None, angle_exp=None, R=None, p=None):
+    """Oracle for one scan.  Returns a dict of per-beam FP64/int arrays.
+
+    beams: optional subset of beam indices (b = j * n_az + i); default all.
+    rho: optional per-material R_lambda(0) used directly instead of the spectral
+    table; angle_exp: optional per-material exponent k; R, p: optional rotation
+    matrix / origin (FP64) overriding the pose.
+    """
+    with np.errstate(invalid="ignore", over="ignore"):
+        return _simulate(scene, sensor, pose, seed, scan, inst, beams, rho, angle_exp, R, p)
+
+
+def _simulate(scene, sensor, pose, seed, scan, inst, beams, rho, angle_exp, R, p):
+    n_all = sensor.n_beams
+    beams = np.arange(n_all, dtype=np.int64) if beams is None else np.asarray(beams, dtype=np.int64)
+    s_all = beam_directions(sensor).reshape(-1, 3)
+    s = s_all[beams]
+    Rm = rotation_from_quat(pose.q) if R is None else np.asarray(R, dtype=np.float64)
+    o = np.asarray(pose.p, dtype=np.float64) if p is None else np.asarray(p, dtype=np.float64)
+    d = s @ Rm.T
+
+    # step 2: first hit within the traceable range (traced a little beyond it
+    # so that hits straddling the limit are seen and can be flagged)
+    t_lim = trace_limit(scene, sensor)
+    fh = first_hit(scene, o, d, sensor.t_min, t_lim * (1 + 1e-5) + 1e-3)
+    tri = fh["tri"]
+    t1 = fh["t"]
+    hit = (tri >= 0) & (t1 <= t_lim)
+    safe = np.where(hit, tri, 0)
+
+    # step 3 + 4: attributes of the hit triangle, return model
+    n = face_normals(scene, safe)
+    c = np.einsum("ij,ij->i", n, d)
+    cos_t = np.abs(c)
+    m = scene.material[safe].astype(np.int64)
+    if rho is None:
+        r0_tab, clamped = reflectance_at_wavelength(scene.spectra, sensor.wavelength_nm)
+    else:
+        r0_tab, clamped = np.asarray(rho, dtype=np.float64), False
+    kexp = np.asarray(scene.angle_exp if angle_exp is None else angle_exp, dtype=np.float64)
+    k_b = kexp[m]
+    r_lambda = r0_tab[m] * np.where(k_b == 1.0, cos_t, cos_t ** k_b)
+
+    # step 5: noise
+    z_d, z_i = beam_normals(seed, scan, inst, beams)
+    sig = scene.sigma_range.astype(np.float64)[m] if sensor.noise_on else np.zeros(len(beams))
+    sig_i = float(sensor.sigma_intensity) if sensor.noise_on else 0.0
+    d_n = t1 + sig * z_d
+
+    # step 6: capability model
+    r_l = (sensor.r_l_max / sensor.d_max) * d_n
+    det = hit & (d_n > sensor.t_min) & (d_n <= sensor.d_max) & (r_l <= r_lambda)
+    inten = np.maximum(0.0, r_lambda + sig_i * z_i)
+
+    # step 7: outputs (misses and drops: valid 0, label all-ones, zeros elsewhere)
+    out = dict(
+        beams=beams,
+        valid=det.astype(np.uint8),
+        x=np.where(det, d_n * s[:, 0], 0.0),
+        y=np.where(det, d_n * s[:, 1], 0.0),
+        z=np.where(det, d_n * s[:, 2], 0.0),
+        intensity=np.where(det, inten, 0.0),
+        range=np.where(det, d_n, 0.0),
+        label=np.where(det, scene.label[safe].astype(np.int64), MISS_LABEL).astype(np.uint32),
+        tri=np.where(hit, tri, MISS_TRI).astype(np.uint32),
+        t_hit=np.where(hit, t1, 0.0),
+        material=np.where(hit, m, 0xFFFF).astype(np.uint16),
+        normal=np.where(hit[:, None], n, 0.0),
+        cos_theta=np.where(hit, cos_t, 0.0),
+        r_lambda=np.where(hit, r_lambda, 0.0),
+        hit=hit, wavelength_clamped=clamped, dir_world=d, dir_sensor=s,
+    )
+    # rays on which a 32-bit implementation may legitimately differ
+    has = tri >= 0
+    eps_e = EDGE_ABS_M + EDGE_REL * np.where(has, t1, 0.0)
+    out["amb_tie"] = has & (fh["t_second"] - t1 < TIE_MARGIN_M)
+    out["amb_edge"] = has & (fh["edge_in"] < eps_e)
+    out["amb_near"] = np.where(has, fh["near_t"] <= t1 + TIE_MARGIN_M, np.isfinite(fh["near_t"]))
+    out["amb_limit"] = has & (np.abs(t1 - t_lim) <= 1e-6 * (1.0 + t_lim))
+    out["ambiguous"] = out["amb_tie"] | out["amb_edge"] | out["amb_near"] | out["amb_limit"]
+    out["grazing"] = hit & (cos_t < 0.01)
+    out["marginal"] = hit & ((np.abs(r_lambda - r_l) <= 1e-5 * r_lambda)
+                             | (np.abs(d_n - sensor.d_max) <= 1e-5 * sensor.d_max)
+                             | (np.abs(d_n - sensor.t_min) <= 1e-5))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# adjoint: gradients of an intensity/depth loss with the hit triangles fixed
+# ----------------------------------------------------------------------------
+def _fixed_triangle_forward(scene, s, tri, R, p, rho, kexp):
+    """Noise-free I and t for beams whose hit triangle is held fixed.
+
+    c = n . d with d = R s; t = n . (v0 - p) / c (ray/plane distance of the
+    fixed triangle); I = rho_m |c|^k_m (eq.4 with the cos^k reading).
+    """
+    v = scene.vertices.astype(np.float64)[scene.indices[tri].astype(np.int64)]
+    n = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    d = s @ R.T
+    c = np.einsum("ij,ij->i", n, d)
+    t = np.einsum("ij,ij->i", n, v[:, 0] - p) / c
+    m = scene.material[tri].astype(np.int64)
+    I = rho[m] * np.abs(c) ** kexp[m]
+    return I, t, n, d, c, m
+
+
+def calib_loss(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0):
+    """L = mean((I - I*)^2) + lam_d * mean((t - t*)^2) over the given beams.
+
+    Pose: p = p_ref + dp, R = Exp(dw) R_ref.  FP64.
+    """
+    s = beam_directions(sensor).reshape(-1, 3)[np.asarray(beams)]
+    R = so3_exp(dw) @ rotation_from_quat(pose_ref.q)
+    p = np.asarray(pose_ref.p, dtype=np.float64) + np.asarray(dp, dtype=np.float64)
+    I, t, *_ = _fixed_triangle_forward(scene, s, np.asarray(tri), R, p,
+                                       np.asarray(rho, np.float64), np.asarray(kexp, np.float64))
+    N = len(beams)
+    return float(np.sum((I - I_tgt) ** 2) / N + lam_d * np.sum((t - t_tgt) ** 2) / N)
+
+
+def calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0):
+    """Analytic gradient of ``calib_loss``: returns (d_rho[nmat], d_k[nmat], d_pose6[6]).
+
+    With g_I = dL/dI and g_t = dL/dt per beam:
+      dL/drho_m = sum g_I |c|^k;  dL/dk_m = sum g_I rho |c|^k ln|c|;
+      dL/dp = sum -g_t n / c;
+      dL/d(left rotation perturbation) = sum gamma (d x n),
+        gamma = g_I rho k |c|^(k-1) sgn(c) - g_t t / c,
+      mapped to dw through the left Jacobian of Exp at dw.
+    """
+    rho = np.asarray(rho, np.float64)
+    kexp = np.asarray(kexp, np.float64)
+    s = beam_directions(sensor).reshape(-1, 3)[np.asarray(beams)]
+    R = so3_exp(dw) @ rotation_from_quat(pose_ref.q)
+    p = np.asarray(pose_ref.p, dtype=np.float64) + np.asarray(dp, dtype=np.float64)
+    I, t, n, d, c, m = _fixed_triangle_forward(scene, s, np.asarray(tri), R, p, rho, kexp)
+    N = len(beams)
+    gI = 2.0 * (I - I_tgt) / N
+    gt = 2.0 * lam_d * (t - t_tgt) / N
+    ac = np.abs(c)
+    k_b = kexp[m]
+    nmat = len(rho)
+    d_rho = np.bincount(m, weights=gI * ac ** k_b, minlength=nmat)
+    d_k = np.bincount(m, weights=gI * rho[m] * ac ** k_b * np.log(ac), minlength=nmat)
+    d_p = np.sum((-gt / c)[:, None] * n, axis=0)
+    gamma = gI * rho[m] * k_b * ac ** (k_b - 1.0) * np.sign(c) - gt * t / c
+    d_left = np.sum(gamma[:, None] * np.cross(d, n), axis=0)
+    d_w = so3_left_jacobian(dw).T @ d_left
+    return d_rho, d_k, np.concatenate([d_p, d_w])
