@@ -1,0 +1,354 @@
+/*
+ * lidar.h -- C ABI of the MI355X (gfx950) LiDAR simulation library.
+ *
+ * The library simulates a spinning multi-channel LiDAR in a triangle-mesh
+ * scene, after Jansen, Huebel and Steckel, "Physical LiDAR Simulation in
+ * Real-Time Engine" (arXiv:2208.10295).  For every beam it finds the first
+ * surface along the beam (the paper's depth, Section II-A), the instance label
+ * of that surface (Section II-B), the incidence angle from the surface normal
+ * and the material's spectral reflectance at the sensor wavelength (Section
+ * II-C, eq.4), adds Gaussian range noise (Section II-A) and applies the
+ * linear reflectance-limit capability model with its maximum-range cutoff
+ * (Section II-D, eq.5).  The result is a labelled point cloud (Fig.1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: 0 = success, < 0 = error (nothing was enqueued), > 0 = warning
+ *   (the call succeeded; see each call).  No C++ exception crosses the ABI.
+ *   lidar_last_error() returns a message for the last failing call.
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Device work is enqueued on it and the call returns without
+ *   waiting, unless the call says it synchronises.
+ * - Memory: every output and every buffer named "device" is caller-owned
+ *   device memory on the context's device (the Python binding uses PyTorch
+ *   tensors).  The library allocates small context-owned device tables at
+ *   set-up (lidar_sensor_set, lidar_materials_set, lidar_batch_create) and
+ *   never allocates in lidar_simulate, lidar_simulate_batch or
+ *   lidar_backward.
+ * - Frames: right-handed, z up.  Azimuth 0 is the sensor's +x axis and grows
+ *   counter-clockwise towards +y; elevation is positive upwards.  The beam of
+ *   channel j and azimuth step i has sensor-frame direction
+ *   s = (cos phi_j cos theta_i, cos phi_j sin theta_i, sin phi_j), the
+ *   direction whose pinhole projection is eq.3 of the paper.
+ * - Beam order: outputs of one scan are dense arrays in [n_ch][n_az] order,
+ *   beam b = j * n_az + i.
+ * - Threading: one context per host thread; contexts are independent.
+ */
+#ifndef LIDAR_H
+#define LIDAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lidar_status;
+
+#define LIDAR_OK                        0
+#define LIDAR_ERR_INVALID_ARG          -1  /* null/misaligned pointer, bad size, NaN, non-unit quaternion */
+#define LIDAR_ERR_NOT_READY            -2  /* no scene, sensor or materials set yet */
+#define LIDAR_ERR_WORKSPACE_TOO_SMALL  -3  /* caller buffer smaller than the queried size */
+#define LIDAR_ERR_HIP                  -4  /* a HIP runtime call failed (message has the HIP error) */
+#define LIDAR_ERR_UNSUPPORTED_DEVICE   -5  /* device is not gfx950 */
+#define LIDAR_ERR_STACK_OVERFLOW       -6  /* BVH deeper than the traversal stack; or a kernel overflowed it */
+#define LIDAR_ERR_NO_FORWARD_STATE     -7  /* backward called without the forward's saved triangle ids */
+#define LIDAR_ERR_OUT_OF_MEMORY        -8  /* a set-up allocation failed */
+#define LIDAR_WARN_WAVELENGTH_CLAMPED   1  /* wavelength outside the spectral table: end bin used */
+
+/* Miss / drop encodings in the outputs. */
+#define LIDAR_NO_LABEL     0xFFFFFFFFu
+#define LIDAR_NO_TRIANGLE  0xFFFFFFFFu
+#define LIDAR_NO_MATERIAL  0xFFFFu
+
+typedef struct lidar_ctx lidar_ctx;
+typedef struct lidar_batch lidar_batch;
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Creates a context on HIP device `hip_device`.  Fails with
+ * LIDAR_ERR_UNSUPPORTED_DEVICE unless the device is gfx950. */
+lidar_status lidar_create(int hip_device, lidar_ctx **out);
+
+/* Frees the context and its context-owned device tables (synchronises the
+ * device first).  Caller-owned buffers are untouched.  NULL is accepted. */
+lidar_status lidar_destroy(lidar_ctx *ctx);
+
+/* Message describing the last error on `ctx` (or of the last failing
+ * lidar_create when ctx is NULL).  Owned by the library; valid until the next
+ * call on the same context. */
+const char *lidar_last_error(const lidar_ctx *ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Scene: triangle soup, per-triangle material and instance label, BVH       */
+/* ------------------------------------------------------------------------ */
+
+#define LIDAR_SCENE_DEVICE_PTRS 1u   /* the four arrays below are device pointers */
+
+typedef struct {
+    uint64_t n_vertices;
+    uint64_t n_triangles;      /* >= 1 and < 2^28 */
+    const float *vertices;     /* [n_vertices][3] world coordinates, metres */
+    const uint32_t *indices;   /* [n_triangles][3] vertex indices (< n_vertices) */
+    const uint16_t *material;  /* [n_triangles] material id (< nmat of lidar_materials_set) */
+    const uint32_t *label;     /* [n_triangles] instance label (the paper's per-object
+                                  ground-truth id, Section II-B) */
+    uint32_t leaf_width;       /* max triangles per BVH leaf, 1..8 (0 = 4) */
+    uint32_t flags;            /* LIDAR_SCENE_DEVICE_PTRS or 0 (host pointers) */
+} lidar_scene_desc;
+
+/* Sizes of the two caller-owned device buffers that lidar_scene_load needs:
+ * `persistent` holds the BVH and triangle records and must stay allocated
+ * while the scene is used; `scratch` is only used during the load and may be
+ * freed when it returns.  Both must be 256-byte aligned. */
+lidar_status lidar_scene_bytes(const lidar_scene_desc *desc, uint64_t *persistent_bytes,
+                               uint64_t *scratch_bytes);
+
+/* Builds the BVH on the GPU (Morton codes, radix sort, binary radix tree,
+ * bounding-box refit, collapse to a 4-wide BVH with leaves of at most
+ * leaf_width triangles) into `persistent`, replacing any previous scene.
+ * Validates every triangle index on the device.  Synchronises `stream` (it
+ * reads back the tree size and depth).  Errors: INVALID_ARG (bad sizes,
+ * index out of range), WORKSPACE_TOO_SMALL, STACK_OVERFLOW (tree deeper than
+ * the traversal stack supports), HIP. */
+lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc,
+                              void *persistent, uint64_t persistent_bytes,
+                              void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Materials (Section II-C)                                                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t nmat;             /* 1..65535 */
+    uint32_t nbins;            /* spectral bins per material (61 for 400..1000 nm) */
+    float lambda0_nm;          /* wavelength of bin 0 */
+    float dlambda_nm;          /* bin spacing (> 0) */
+    const float *spectra;      /* host [nmat][nbins] reflectance at normal incidence, fraction */
+    const float *sigma_range;  /* host [nmat] Gaussian range-noise sigma, metres (>= 0) */
+    const float *angle_exp;    /* host [nmat] exponent k of cos^k (NULL = all 1, eq.4) */
+} lidar_material_desc;
+
+/* Copies the material tables into context-owned device memory (allocates;
+ * synchronous).  R_lambda(0) at a sensor wavelength is interpolated linearly
+ * between bins on the GPU, clamped at the table ends. */
+lidar_status lidar_materials_set(lidar_ctx *ctx, const lidar_material_desc *desc);
+
+/* ------------------------------------------------------------------------ */
+/* Sensor and pose (Sections II-A, II-C, II-D)                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t n_ch;             /* channels (1..4096) */
+    const double *elev_deg;    /* host [n_ch] channel elevations phi_j, degrees (data sheet) */
+    uint32_t n_az;             /* azimuth steps (1..2^20) */
+    double az0_deg;            /* theta_0 */
+    double fov_h_deg;          /* horizontal FOV; theta_i = theta_0 + i * fov_h / n_az */
+    float wavelength_nm;       /* sensor wavelength lambda */
+    float d_max;               /* maximum range d_max, metres (> 0) */
+    float r_l_max;             /* reflectance needed at d_max, fraction (eq.5) */
+    float t_min;               /* minimum range, metres (>= 0) */
+    float sigma_intensity;     /* additive intensity noise sigma (0 = none) */
+    uint32_t noise_on;         /* 0: no range or intensity noise */
+} lidar_sensor_desc;
+
+/* Sets the sensor used by lidar_simulate.  Computes the FP64 direction
+ * tables on the device (context-owned; synchronous).  Returns
+ * LIDAR_WARN_WAVELENGTH_CLAMPED if the wavelength lies outside the material
+ * table (materials must be set first for this check; otherwise it is made at
+ * simulate time). */
+lidar_status lidar_sensor_set(lidar_ctx *ctx, const lidar_sensor_desc *desc);
+
+/* Sets the sensor pose used by lidar_simulate: origin p (world, metres) and
+ * orientation quaternion q = (w, x, y, z), which must have unit norm to 1e-4
+ * (it is renormalised).  World beam direction d = R(q) s. */
+lidar_status lidar_pose_set(lidar_ctx *ctx, const float p[3], const float q_wxyz[4]);
+
+/* ------------------------------------------------------------------------ */
+/* Simulation                                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Per-beam outputs; every pointer is caller-owned device memory with one
+ * element per beam (normal: 3 planes of n elements), or NULL to skip.
+ * Detected points: xyz = d * s (sensor frame), intensity, label, valid = 1,
+ * range = d (with noise).  Misses and dropped points: valid = 0,
+ * label = LIDAR_NO_LABEL, zeros elsewhere.  The diagnostic outputs (tri,
+ * t_hit, material, normal, r_lambda) describe the first hit within the
+ * traceable range whether or not it is detected: tri = original triangle
+ * index (LIDAR_NO_TRIANGLE if none), t_hit = noise-free distance,
+ * material (LIDAR_NO_MATERIAL if none), unit geometric normal
+ * normalize((v1 - v0) x (v2 - v0)), r_lambda = noise-free reflectance R_lambda
+ * (eq.4, cos^k); zeros when there is no hit. */
+typedef struct {
+    float *x, *y, *z;
+    float *intensity;
+    uint32_t *label;
+    uint8_t *valid;
+    float *range;
+    uint32_t *tri;
+    float *t_hit;
+    uint16_t *material;
+    float *normal;             /* [3][n]: nx plane, ny plane, nz plane */
+    float *r_lambda;
+} lidar_outputs;
+
+/* Optional parameter overrides for lidar_simulate_ex and lidar_backward; all
+ * are caller-owned device pointers, NULL = not overridden. */
+typedef struct {
+    const float *rho;          /* [nmat] R_lambda(0) per material, used instead of the spectral table */
+    const float *angle_exp;    /* [nmat] exponent k per material (cos^k) */
+    const float *pose_delta;   /* [6] (dp, dw): p = p0 + dp, R = Exp(dw) R(q0) */
+} lidar_params;
+
+/* One scan of the current sensor at the current pose.  Gaussian noise comes
+ * from Philox4x32-10 (Salmon et al., SC'11) with key (seed low word, seed
+ * high word) and counter (beam, scan, 0, 0), through Box-Muller
+ * (z_range from words 0-1, z_intensity from words 2-3).  Asynchronous. */
+lidar_status lidar_simulate(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
+                            const lidar_outputs *out, void *stream);
+
+/* lidar_simulate with parameter overrides (`params` may be NULL). */
+lidar_status lidar_simulate_ex(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
+                               const lidar_params *params, const lidar_outputs *out,
+                               void *stream);
+
+/* Reference path: the same scan with every beam tested against every
+ * triangle (no BVH).  Outputs are bit-identical to lidar_simulate.  For
+ * tests; O(beams x triangles). */
+lidar_status lidar_simulate_bruteforce(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
+                                       const lidar_outputs *out, void *stream);
+
+/* Wavefront ray tile: each 64-lane wavefront traces tile_az consecutive
+ * azimuth steps of 64 / tile_az consecutive channels (tile_az a power of two
+ * in 1..64; default 8).  Only affects speed, never results.  A batch keeps
+ * the tile shape that was current when it was created. */
+lidar_status lidar_set_tile_shape(lidar_ctx *ctx, uint32_t tile_az);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: many sensors / poses in one persistent launch               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    lidar_sensor_desc sensor;  /* per-instance sensor (own tables, wavelength, range) */
+    float p[3];                /* pose origin */
+    float q_wxyz[4];           /* pose orientation (unit) */
+    uint64_t seed;             /* Philox key */
+    uint32_t scan;             /* Philox counter word 1 */
+} lidar_instance;
+
+/* Uploads n_inst instance descriptors and their direction tables
+ * (allocates; synchronous).  Instance k's beams are written at output
+ * offset out_offset[k] = sum of n_ch * n_az of instances before k, in the
+ * same [n_ch][n_az] order as a single scan; its Philox counter is
+ * (beam, scan, k, 0).  `packet_rays` (multiple of 64, 0 = tuned/default)
+ * is the number of rays a wavefront claims per queue pop.  Returns
+ * LIDAR_WARN_WAVELENGTH_CLAMPED if any instance clamps. */
+lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint32_t n_inst,
+                                uint32_t packet_rays, lidar_batch **out);
+
+/* Total rays of a batch (sum of n_ch * n_az). */
+lidar_status lidar_batch_rays(const lidar_batch *batch, uint64_t *n_rays);
+
+/* Runs every instance of the batch in one persistent kernel: wavefronts pop
+ * ray packets from a device queue until it is empty.  The queue reset and
+ * the kernel are captured once into a hipGraph per (stream-independent)
+ * output binding and replayed on `stream`.  Outputs as in lidar_simulate,
+ * indexed by out_offset[k] + beam.  Results are bit-identical to
+ * lidar_simulate_batch_sequential, and instance k equals a plain scan of the
+ * same sensor and pose whose Philox counter word 2 is k.  Asynchronous. */
+lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *batch, const lidar_outputs *out,
+                                  void *stream);
+
+/* The same instances as n_inst separate plain launches on `stream`
+ * (baseline for the batched form). */
+lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *batch,
+                                             const lidar_outputs *out, void *stream);
+
+lidar_status lidar_batch_destroy(lidar_batch *batch);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuner                                                                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const uint32_t *packet_rays;   /* host [n_packet] candidates (multiples of 64) */
+    uint32_t n_packet;
+    const uint32_t *leaf_widths;   /* host [n_leaf] candidates (1..8) */
+    uint32_t n_leaf;
+    uint32_t reps;                 /* timed repetitions per candidate (median) */
+} lidar_tune_desc;
+
+typedef struct {
+    uint32_t best_packet_rays;
+    uint32_t best_leaf_width;
+    float best_ms;
+    float ms[64];                  /* [n_leaf][n_packet] medians, row-major (<= 64 entries) */
+} lidar_tune_result;
+
+/* Times lidar_simulate_batch for every (leaf width, packet size) candidate on
+ * the batch, rebuilding the BVH per leaf width from `scene` into the given
+ * buffers, then leaves the scene built with the best leaf width and the batch
+ * set to the best packet size.  Synchronous. */
+lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *persistent,
+                        uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes,
+                        lidar_batch *batch, const lidar_outputs *out, const lidar_tune_desc *desc,
+                        lidar_tune_result *result, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint (eq.4 intensity and range with the hit triangle held fixed)       */
+/* ------------------------------------------------------------------------ */
+
+/* Gradients of a scalar loss L with respect to the per-material reflectance
+ * rho (R_lambda(0)), the per-material exponent k (I = rho |n.d|^k) and the
+ * pose delta (dp, dw) of lidar_params, given dL/dI and dL/drange per beam of
+ * the current sensor.  The forward state is the per-beam original triangle
+ * id from the forward call (outputs.tri) and the per-beam valid mask;
+ * beams with valid == 0 or tri == LIDAR_NO_TRIANGLE contribute nothing.  With
+ * the triangle fixed, range t = n.(v0 - p) / (n.d).  Per-block partial sums
+ * are reduced in a fixed order (deterministic); results are FP32 written to
+ * d_rho[nmat], d_k[nmat], d_pose6[6] (device).  `params` must be the same as
+ * in the forward call (without rho, R_lambda(0) is the spectral table at the
+ * sensor wavelength).  Materials are limited to nmat <= 256.  Asynchronous.
+ * Errors: NO_FORWARD_STATE if tri is NULL. */
+lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
+                            const uint8_t *valid, const float *dL_dI, const float *dL_drange,
+                            float *d_rho, float *d_k, float *d_pose6, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Introspection                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t n_triangles;
+    uint64_t n_nodes;              /* 4-wide BVH nodes */
+    uint64_t n_leaves;
+    uint32_t depth;                /* levels of the 4-wide BVH */
+    uint32_t leaf_width;
+    uint32_t stack_entries;        /* traversal stack per ray */
+    uint32_t root;                 /* root child reference */
+    uint64_t node_bytes;           /* bytes of nodes in use */
+    uint64_t tri_bytes;            /* bytes of triangle records */
+    float build_ms;                /* last lidar_scene_load, GPU time */
+    float box_pad;                 /* conservative bounding-box padding, metres */
+} lidar_stats;
+
+lidar_status lidar_get_stats(lidar_ctx *ctx, lidar_stats *out);
+
+/* Synchronises `stream` and reads the device error word written by kernels
+ * (e.g. traversal stack overflow).  Returns LIDAR_ERR_STACK_OVERFLOW if a
+ * kernel flagged it since the last check (and clears it). */
+lidar_status lidar_sync_check(lidar_ctx *ctx, void *stream);
+
+/* Copies the BVH and triangle records to host memory for inspection:
+ * nodes (n_nodes * 128 bytes) and triangle records (n_triangles * 48 bytes).
+ * Synchronous.  For tests. */
+lidar_status lidar_debug_copy_bvh(lidar_ctx *ctx, void *host_nodes, uint64_t node_bytes,
+                                  void *host_tris, uint64_t tri_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIDAR_H */

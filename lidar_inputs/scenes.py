@@ -86,6 +86,13 @@ class Sensor:
     sigma_intensity: float = 0.0  # additive intensity noise sigma
     noise_on: bool = True
 
+    def __post_init__(self):
+        # the library's sensor descriptor carries these as float32; keep the
+        # values exactly representable so both consumers see the same numbers
+        for k in ("wavelength_nm", "d_max", "r_l_max", "t_min", "sigma_intensity"):
+            setattr(self, k, float(np.float32(getattr(self, k))))
+        self.elev_deg = np.asarray(self.elev_deg, dtype=np.float64)
+
     @property
     def n_ch(self) -> int:
         return int(len(self.elev_deg))

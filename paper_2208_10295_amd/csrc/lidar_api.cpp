@@ -1,0 +1,791 @@
+// lidar_api.cpp -- the C ABI (include/lidar.h): argument checks on the host,
+// context state, and stream-ordered launches of the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lidar.h"
+#include "lidar_kernels.hpp"
+
+using namespace lidar;
+
+namespace {
+
+constexpr int kMaxStack = 96;
+constexpr uint32_t kMaxAdjMaterials = 256;
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n) return hipSuccess;
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) n = bytes;
+        return e;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct SensorHost {
+    lidar_sensor_desc d;
+    std::vector<double> elev;
+};
+
+}  // namespace
+
+struct lidar_ctx {
+    int device = 0;
+    int n_cu = 256;
+    std::string err;
+    // scene
+    bool has_scene = false;
+    SceneDev S{};
+    const uint32_t *slot_of = nullptr;
+    BuildResult br{};
+    int stack = 32;
+    uint32_t leaf_width = 4;
+    float build_ms = 0.f;
+    // materials
+    bool has_mat = false;
+    DevBuf mat_buf;
+    MaterialsDev M{};
+    std::vector<float> sigma_h;
+    // sensor
+    bool has_sensor = false;
+    SensorHost sensor;
+    DevBuf sensor_tables;   // elev_cs then az_cs
+    DevBuf adj_partials;
+    // pose
+    float p[3] = {0, 0, 0};
+    float q[4] = {1, 0, 0, 0};
+    // device words: [0] error flags, [1] queue counter
+    DevBuf words;
+    int tile_az_log2 = 3;
+
+    lidar_status fail(lidar_status st, const std::string &msg) {
+        err = msg;
+        return st;
+    }
+    lidar_status hip_fail(hipError_t e, const char *what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LIDAR_ERR_HIP;
+    }
+};
+
+struct lidar_batch {
+    lidar_ctx *ctx = nullptr;
+    uint32_t n_inst = 0;
+    std::vector<InstanceDev> h_insts;   // pointers into `tables`
+    DevBuf d_insts;
+    DevBuf tables;
+    uint64_t n_rays = 0, n_padded = 0;
+    uint32_t packet = 256;
+    int tile_az_log2 = 3;      // tile shape fixed at creation (padded ray layout depends on it)
+    int graph_stack = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Outputs bound{};
+    bool has_graph = false;
+    hipStream_t cap_stream = nullptr;
+    void drop_graph() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        has_graph = false;
+    }
+};
+
+namespace {
+
+bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+lidar_status check_sensor(lidar_ctx *ctx, const lidar_sensor_desc *d) {
+    if (!d) return ctx->fail(LIDAR_ERR_INVALID_ARG, "sensor descriptor is null");
+    if (d->n_ch < 1 || d->n_ch > 4096) return ctx->fail(LIDAR_ERR_INVALID_ARG, "n_ch must be in 1..4096");
+    if (d->n_az < 1 || d->n_az > (1u << 20)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "n_az must be in 1..2^20");
+    if ((uint64_t)d->n_ch * d->n_az >= (1ull << 31)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "too many beams");
+    if (!d->elev_deg) return ctx->fail(LIDAR_ERR_INVALID_ARG, "elev_deg is null");
+    for (uint32_t j = 0; j < d->n_ch; ++j)
+        if (!std::isfinite(d->elev_deg[j]) || std::fabs(d->elev_deg[j]) > 90.0)
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "elevations must be finite and within [-90, 90] deg");
+    if (!std::isfinite(d->az0_deg) || !std::isfinite(d->fov_h_deg) || d->fov_h_deg <= 0.0 || d->fov_h_deg > 360.0)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "fov_h_deg must be in (0, 360]");
+    if (!(d->d_max > 0.f) || !std::isfinite(d->d_max)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "d_max must be > 0");
+    if (!(d->t_min >= 0.f) || !(d->t_min < d->d_max)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "need 0 <= t_min < d_max");
+    if (!(d->r_l_max >= 0.f) || !std::isfinite(d->r_l_max)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "r_l_max must be >= 0");
+    if (!(d->sigma_intensity >= 0.f) || !std::isfinite(d->sigma_intensity))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "sigma_intensity must be >= 0");
+    if (!std::isfinite(d->wavelength_nm)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "wavelength must be finite");
+    return LIDAR_OK;
+}
+
+bool wavelength_clamped(const lidar_ctx *ctx, float lam) {
+    if (!ctx->has_mat) return false;
+    float q = (lam - ctx->M.lambda0) / ctx->M.dlambda;
+    return q < 0.0f || q > (float)(ctx->M.nbins - 1);
+}
+
+lidar_status check_quat(lidar_ctx *ctx, const float *p, const float *q) {
+    if (!p || !q) return ctx->fail(LIDAR_ERR_INVALID_ARG, "pose pointer is null");
+    if (!finite3(p) || !std::isfinite(q[0]) || !finite3(q + 1))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "pose has NaN/inf");
+    double n = std::sqrt((double)q[0] * q[0] + (double)q[1] * q[1] + (double)q[2] * q[2] + (double)q[3] * q[3]);
+    if (std::fabs(n - 1.0) > 1e-4) return ctx->fail(LIDAR_ERR_INVALID_ARG, "quaternion is not unit (|q| - 1 > 1e-4)");
+    return LIDAR_OK;
+}
+
+float trace_limit(const lidar_ctx *ctx, const lidar_sensor_desc &d) {
+    if (!d.noise_on) return d.d_max;
+    float smax = 0.f;
+    for (float s : ctx->sigma_h) smax = std::max(smax, s);
+    return d.d_max + kBoxMullerBound * smax;
+}
+
+uint32_t tiles_az(int tile_az_log2, uint32_t n_az) {
+    uint32_t ta = 1u << tile_az_log2;
+    return (n_az + ta - 1) / ta;
+}
+
+uint64_t padded_rays(int tile_az_log2, uint32_t n_ch, uint32_t n_az) {
+    uint32_t tc = 64u >> tile_az_log2;
+    uint64_t rows = (n_ch + tc - 1) / tc;
+    return rows * tiles_az(tile_az_log2, n_az) * 64ull;
+}
+
+InstanceDev make_instance(const lidar_ctx *ctx, int tile_az_log2, const lidar_sensor_desc &d, const double *elev_cs,
+                          const double *az_cs, const float *p, const float *q, uint64_t seed, uint32_t scan,
+                          uint32_t inst_id, uint64_t ray_base, uint64_t out_base) {
+    InstanceDev in{};
+    in.elev_cs = elev_cs;
+    in.az_cs = az_cs;
+    in.n_ch = d.n_ch;
+    in.n_az = d.n_az;
+    in.tiles_az = tiles_az(tile_az_log2, d.n_az);
+    in.ray_base = ray_base;
+    in.out_base = out_base;
+    for (int k = 0; k < 4; ++k) in.q[k] = q[k];
+    for (int k = 0; k < 3; ++k) in.p[k] = p[k];
+    in.wavelength_nm = d.wavelength_nm;
+    in.d_max = d.d_max;
+    in.r_l_max = d.r_l_max;
+    in.t_min = d.t_min;
+    in.sigma_i = d.sigma_intensity;
+    in.t_trace = trace_limit(ctx, d);
+    in.noise_on = d.noise_on ? 1u : 0u;
+    in.seed_lo = (uint32_t)(seed & 0xFFFFFFFFu);
+    in.seed_hi = (uint32_t)(seed >> 32);
+    in.scan = scan;
+    in.inst_id = inst_id;
+    return in;
+}
+
+Outputs to_outputs(const lidar_outputs *o, uint64_t plane) {
+    Outputs r{};
+    r.x = o->x; r.y = o->y; r.z = o->z; r.intensity = o->intensity; r.label = o->label; r.valid = o->valid;
+    r.range = o->range; r.tri = o->tri; r.t_hit = o->t_hit; r.material = o->material; r.normal = o->normal;
+    r.r_lambda = o->r_lambda; r.plane = plane;
+    return r;
+}
+
+bool same_outputs(const Outputs &a, const Outputs &b) { return std::memcmp(&a, &b, sizeof(Outputs)) == 0; }
+
+lidar_status ready(lidar_ctx *ctx, bool need_sensor) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!ctx->has_scene) return ctx->fail(LIDAR_ERR_NOT_READY, "no scene loaded");
+    if (!ctx->has_mat) return ctx->fail(LIDAR_ERR_NOT_READY, "no materials set");
+    if (need_sensor && !ctx->has_sensor) return ctx->fail(LIDAR_ERR_NOT_READY, "no sensor set");
+    if (ctx->br.max_material >= ctx->M.nmat)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "scene uses a material id >= nmat");
+    return LIDAR_OK;
+}
+
+int stack_for_depth(uint32_t depth) {
+    int need = 3 * (int)(depth > 0 ? depth - 1 : 0) + 1;
+    if (need <= 32) return 32;
+    if (need <= 64) return 64;
+    if (need <= 96) return 96;
+    return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+lidar_status lidar_create(int hip_device, lidar_ctx **out) {
+    if (!out) return LIDAR_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+        g_create_error = "no HIP device available";
+        return LIDAR_ERR_HIP;
+    }
+    if (hip_device < 0 || hip_device >= n) {
+        g_create_error = "device index out of range";
+        return LIDAR_ERR_INVALID_ARG;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, hip_device);
+    if (e != hipSuccess) {
+        g_create_error = hipGetErrorString(e);
+        return LIDAR_ERR_HIP;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        g_create_error = std::string("unsupported device ") + prop.gcnArchName + " (gfx950 required)";
+        return LIDAR_ERR_UNSUPPORTED_DEVICE;
+    }
+    lidar_ctx *ctx = new (std::nothrow) lidar_ctx();
+    if (!ctx) return LIDAR_ERR_OUT_OF_MEMORY;
+    ctx->device = hip_device;
+    ctx->n_cu = prop.multiProcessorCount;
+    hipSetDevice(hip_device);
+    if (ctx->words.ensure(256) != hipSuccess || hipMemset(ctx->words.p, 0, 256) != hipSuccess) {
+        delete ctx;
+        g_create_error = "device allocation failed";
+        return LIDAR_ERR_OUT_OF_MEMORY;
+    }
+    *out = ctx;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_destroy(lidar_ctx *ctx) {
+    if (!ctx) return LIDAR_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    ctx->mat_buf.release();
+    ctx->sensor_tables.release();
+    ctx->adj_partials.release();
+    ctx->words.release();
+    delete ctx;
+    return LIDAR_OK;
+}
+
+const char *lidar_last_error(const lidar_ctx *ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+lidar_status lidar_scene_bytes(const lidar_scene_desc *desc, uint64_t *persistent_bytes, uint64_t *scratch_bytes) {
+    if (!desc || !persistent_bytes || !scratch_bytes) return LIDAR_ERR_INVALID_ARG;
+    if (desc->n_triangles < 1 || desc->n_triangles >= (1ull << 28) || desc->n_vertices < 1 ||
+        desc->n_vertices >= (1ull << 32))
+        return LIDAR_ERR_INVALID_ARG;
+    uint32_t nt = (uint32_t)desc->n_triangles;
+    *persistent_bytes = build_persistent_bytes(nt);
+    uint64_t sc = build_scratch_bytes(nt);
+    if (!(desc->flags & LIDAR_SCENE_DEVICE_PTRS)) {
+        auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+        sc += al(12 * desc->n_vertices) + al(12 * (uint64_t)nt) + al(2 * (uint64_t)nt) + al(4 * (uint64_t)nt);
+    }
+    *scratch_bytes = sc;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void *persistent,
+                              uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!desc) return ctx->fail(LIDAR_ERR_INVALID_ARG, "scene descriptor is null");
+    if (!desc->vertices || !desc->indices || !desc->material || !desc->label)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "scene array pointer is null");
+    uint32_t W = desc->leaf_width ? desc->leaf_width : 4u;
+    if (W < 1 || W > 8) return ctx->fail(LIDAR_ERR_INVALID_ARG, "leaf_width must be in 1..8");
+    uint64_t need_p = 0, need_s = 0;
+    if (lidar_scene_bytes(desc, &need_p, &need_s) != LIDAR_OK)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "triangle/vertex count out of range");
+    if (!persistent || !scratch) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace pointer is null");
+    if (((uintptr_t)persistent & 255) || ((uintptr_t)scratch & 255))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspaces must be 256-byte aligned");
+    if (persistent_bytes < need_p || scratch_bytes < need_s)
+        return ctx->fail(LIDAR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than lidar_scene_bytes()");
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t nt = (uint32_t)desc->n_triangles;
+    BuildInputs in{};
+    in.nv = desc->n_vertices;
+    in.nt = nt;
+    in.leaf_width = W;
+    if (desc->flags & LIDAR_SCENE_DEVICE_PTRS) {
+        in.vtx = desc->vertices;
+        in.idx = desc->indices;
+        in.mat = desc->material;
+        in.label = desc->label;
+    } else {
+        auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+        char *base = (char *)scratch + build_scratch_bytes(nt);
+        float *v = (float *)base;
+        uint32_t *ix = (uint32_t *)(base + al(12 * in.nv));
+        uint16_t *m = (uint16_t *)((char *)ix + al(12 * (uint64_t)nt));
+        uint32_t *lb = (uint32_t *)((char *)m + al(2 * (uint64_t)nt));
+        hipError_t e;
+        if ((e = hipMemcpyAsync(v, desc->vertices, 12 * in.nv, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ix, desc->indices, 12 * (uint64_t)nt, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(m, desc->material, 2 * (uint64_t)nt, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(lb, desc->label, 4 * (uint64_t)nt, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return ctx->hip_fail(e, "scene upload");
+        in.vtx = v;
+        in.idx = ix;
+        in.mat = m;
+        in.label = lb;
+    }
+    ctx->has_scene = false;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventRecord(e0, s);
+    BuildResult br{};
+    hipError_t e = build_bvh(in, persistent, scratch, br, s);
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return ctx->hip_fail(e, "BVH build");
+    if (br.bad_index) return ctx->fail(LIDAR_ERR_INVALID_ARG, "a triangle index is >= n_vertices");
+    int stack = stack_for_depth(br.depth);
+    if (stack < 0) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "BVH depth %u needs more than %d stack entries", br.depth, kMaxStack);
+        return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, buf);
+    }
+    ctx->br = br;
+    ctx->stack = stack;
+    ctx->leaf_width = W;
+    ctx->build_ms = ms;
+    ctx->S.nodes = (const Node4 *)persistent;
+    ctx->S.tris = (const TriRec *)((const char *)persistent + persistent_nodes_bytes(nt));
+    ctx->slot_of = (const uint32_t *)((const char *)ctx->S.tris + persistent_recs_bytes(nt));
+    ctx->S.root = br.root;
+    ctx->S.n_tri = nt;
+    ctx->has_scene = true;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_materials_set(lidar_ctx *ctx, const lidar_material_desc *d) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!d || !d->spectra || !d->sigma_range) return ctx->fail(LIDAR_ERR_INVALID_ARG, "material arrays are null");
+    if (d->nmat < 1 || d->nmat > 65535 || d->nbins < 1 || d->nbins > 4096)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "nmat must be in 1..65535 and nbins in 1..4096");
+    if (!(d->dlambda_nm > 0.f) || !std::isfinite(d->lambda0_nm))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "dlambda_nm must be > 0");
+    size_t ns = (size_t)d->nmat * d->nbins;
+    for (size_t k = 0; k < ns; ++k)
+        if (!std::isfinite(d->spectra[k])) return ctx->fail(LIDAR_ERR_INVALID_ARG, "spectra contain NaN/inf");
+    for (uint32_t k = 0; k < d->nmat; ++k) {
+        if (!(d->sigma_range[k] >= 0.f) || !std::isfinite(d->sigma_range[k]))
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "sigma_range must be finite and >= 0");
+        if (d->angle_exp && (!std::isfinite(d->angle_exp[k]) || d->angle_exp[k] < 0.f))
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "angle_exp must be finite and >= 0");
+    }
+    hipSetDevice(ctx->device);
+    size_t bytes = ns * 4 + 2 * (size_t)d->nmat * 4;
+    hipError_t e = ctx->mat_buf.ensure(bytes);
+    if (e != hipSuccess) return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "material table allocation failed");
+    float *base = (float *)ctx->mat_buf.p;
+    std::vector<float> host(bytes / 4);
+    std::memcpy(host.data(), d->spectra, ns * 4);
+    std::memcpy(host.data() + ns, d->sigma_range, (size_t)d->nmat * 4);
+    for (uint32_t k = 0; k < d->nmat; ++k) host[ns + d->nmat + k] = d->angle_exp ? d->angle_exp[k] : 1.0f;
+    if ((e = hipMemcpy(base, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
+        return ctx->hip_fail(e, "material upload");
+    ctx->M.spectra = base;
+    ctx->M.sigma = base + ns;
+    ctx->M.angle_exp = base + ns + d->nmat;
+    ctx->M.nmat = d->nmat;
+    ctx->M.nbins = d->nbins;
+    ctx->M.lambda0 = d->lambda0_nm;
+    ctx->M.dlambda = d->dlambda_nm;
+    ctx->sigma_h.assign(d->sigma_range, d->sigma_range + d->nmat);
+    ctx->has_mat = true;
+    if (ctx->has_sensor && d->nmat <= kMaxAdjMaterials) {
+        size_t pb = adjoint_partial_bytes(ctx->sensor.d.n_ch * ctx->sensor.d.n_az, d->nmat);
+        if (ctx->adj_partials.ensure(pb) != hipSuccess)
+            return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "adjoint buffer allocation failed");
+    }
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sensor_set(lidar_ctx *ctx, const lidar_sensor_desc *d) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    lidar_status st = check_sensor(ctx, d);
+    if (st != LIDAR_OK) return st;
+    hipSetDevice(ctx->device);
+    size_t bytes = 16 * ((size_t)d->n_ch + d->n_az) + 8 * (size_t)d->n_ch;
+    hipError_t e = ctx->sensor_tables.ensure(bytes);
+    if (e != hipSuccess) return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "sensor table allocation failed");
+    double *elev_cs = (double *)ctx->sensor_tables.p;
+    double *az_cs = elev_cs + 2 * (size_t)d->n_ch;
+    double *elev_deg = az_cs + 2 * (size_t)d->n_az;
+    if ((e = hipMemcpy(elev_deg, d->elev_deg, 8 * (size_t)d->n_ch, hipMemcpyHostToDevice)) != hipSuccess)
+        return ctx->hip_fail(e, "sensor upload");
+    launch_dir_tables(elev_deg, d->n_ch, d->az0_deg, d->fov_h_deg, d->n_az, elev_cs, az_cs, 0);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return ctx->hip_fail(e, "direction tables");
+    ctx->sensor.d = *d;
+    ctx->sensor.elev.assign(d->elev_deg, d->elev_deg + d->n_ch);
+    ctx->sensor.d.elev_deg = ctx->sensor.elev.data();
+    ctx->has_sensor = true;
+    if (ctx->has_mat && ctx->M.nmat <= kMaxAdjMaterials) {
+        size_t pb = adjoint_partial_bytes(d->n_ch * d->n_az, ctx->M.nmat);
+        if (ctx->adj_partials.ensure(pb) != hipSuccess)
+            return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "adjoint buffer allocation failed");
+    }
+    return wavelength_clamped(ctx, d->wavelength_nm) ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK;
+}
+
+lidar_status lidar_pose_set(lidar_ctx *ctx, const float p[3], const float q[4]) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    lidar_status st = check_quat(ctx, p, q);
+    if (st != LIDAR_OK) return st;
+    std::memcpy(ctx->p, p, 12);
+    std::memcpy(ctx->q, q, 16);
+    return LIDAR_OK;
+}
+
+static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_params *params,
+                                    const lidar_outputs *out, void *stream, bool brute) {
+    lidar_status st = ready(ctx, true);
+    if (st != LIDAR_OK) return st;
+    if (!out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "outputs struct is null");
+    const lidar_sensor_desc &d = ctx->sensor.d;
+    const double *elev_cs = (const double *)ctx->sensor_tables.p;
+    const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
+    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, ctx->p, ctx->q, seed, scan, 0, 0, 0);
+    Overrides ov{};
+    if (params) {
+        ov.rho = params->rho;
+        ov.angle_exp = params->angle_exp;
+        ov.pose_delta = params->pose_delta;
+    }
+    uint64_t nb = (uint64_t)d.n_ch * d.n_az;
+    Outputs o = to_outputs(out, nb);
+    uint64_t np = padded_rays(ctx->tile_az_log2, d.n_ch, d.n_az);
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (brute) launch_bruteforce(ctx->S, in, ctx->M, ov, o, ctx->tile_az_log2, np, s);
+    else launch_trace_scan(ctx->stack, ctx->S, in, ctx->M, ov, o, ctx->tile_az_log2, np, (uint32_t *)ctx->words.p, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "trace launch");
+    return wavelength_clamped(ctx, d.wavelength_nm) && !(params && params->rho) ? LIDAR_WARN_WAVELENGTH_CLAMPED
+                                                                                : LIDAR_OK;
+}
+
+lidar_status lidar_simulate(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_outputs *out, void *stream) {
+    return simulate_common(ctx, seed, scan, nullptr, out, stream, false);
+}
+
+lidar_status lidar_simulate_ex(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_params *params,
+                               const lidar_outputs *out, void *stream) {
+    return simulate_common(ctx, seed, scan, params, out, stream, false);
+}
+
+lidar_status lidar_simulate_bruteforce(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_outputs *out,
+                                       void *stream) {
+    return simulate_common(ctx, seed, scan, nullptr, out, stream, true);
+}
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint32_t n_inst, uint32_t packet_rays,
+                                lidar_batch **out) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!inst || n_inst == 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "no instances");
+    if (packet_rays % 64 != 0 || packet_rays > 65536)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "packet_rays must be a multiple of 64 (<= 65536)");
+    if (!ctx->has_mat) return ctx->fail(LIDAR_ERR_NOT_READY, "materials must be set before a batch");
+    bool clamped = false;
+    size_t table_doubles = 0;
+    for (uint32_t k = 0; k < n_inst; ++k) {
+        lidar_status st = check_sensor(ctx, &inst[k].sensor);
+        if (st != LIDAR_OK) return st;
+        st = check_quat(ctx, inst[k].p, inst[k].q_wxyz);
+        if (st != LIDAR_OK) return st;
+        table_doubles += 2 * ((size_t)inst[k].sensor.n_ch + inst[k].sensor.n_az) + inst[k].sensor.n_ch;
+        clamped |= wavelength_clamped(ctx, inst[k].sensor.wavelength_nm);
+    }
+    lidar_batch *b = new (std::nothrow) lidar_batch();
+    if (!b) return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "batch allocation failed");
+    b->ctx = ctx;
+    b->n_inst = n_inst;
+    b->packet = packet_rays ? packet_rays : 256;
+    b->tile_az_log2 = ctx->tile_az_log2;
+    hipSetDevice(ctx->device);
+    if (b->tables.ensure(table_doubles * 8) != hipSuccess || b->d_insts.ensure(sizeof(InstanceDev) * n_inst) != hipSuccess) {
+        delete b;
+        return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "batch table allocation failed");
+    }
+    double *t = (double *)b->tables.p;
+    uint64_t ray_base = 0, out_base = 0;
+    for (uint32_t k = 0; k < n_inst; ++k) {
+        const lidar_sensor_desc &d = inst[k].sensor;
+        double *elev_cs = t;
+        double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
+        double *elev_deg = az_cs + 2 * (size_t)d.n_az;
+        t = elev_deg + d.n_ch;
+        hipMemcpy(elev_deg, d.elev_deg, 8 * (size_t)d.n_ch, hipMemcpyHostToDevice);
+        launch_dir_tables(elev_deg, d.n_ch, d.az0_deg, d.fov_h_deg, d.n_az, elev_cs, az_cs, 0);
+        b->h_insts.push_back(make_instance(ctx, b->tile_az_log2, d, elev_cs, az_cs, inst[k].p, inst[k].q_wxyz,
+                                           inst[k].seed, inst[k].scan, k, ray_base, out_base));
+        ray_base += padded_rays(b->tile_az_log2, d.n_ch, d.n_az);
+        out_base += (uint64_t)d.n_ch * d.n_az;
+    }
+    b->n_padded = ray_base;
+    b->n_rays = out_base;
+    hipError_t e = hipMemcpy(b->d_insts.p, b->h_insts.data(), sizeof(InstanceDev) * n_inst, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        b->tables.release();
+        b->d_insts.release();
+        delete b;
+        return ctx->hip_fail(e, "batch upload");
+    }
+    *out = b;
+    return clamped ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK;
+}
+
+lidar_status lidar_batch_rays(const lidar_batch *b, uint64_t *n) {
+    if (!b || !n) return LIDAR_ERR_INVALID_ARG;
+    *n = b->n_rays;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_outputs *out, void *stream) {
+    lidar_status st = ready(ctx, false);
+    if (st != LIDAR_OK) return st;
+    if (!b || b->ctx != ctx || !out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "bad batch or outputs");
+    hipSetDevice(ctx->device);
+    Outputs o = to_outputs(out, b->n_rays);
+    if (!b->has_graph || !same_outputs(o, b->bound) || b->graph_stack != ctx->stack) {
+        b->drop_graph();
+        uint32_t grid = (uint32_t)(ctx->n_cu * batch_blocks_per_cu(ctx->stack));
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return ctx->hip_fail(e, "graph capture begin");
+        uint32_t *words = (uint32_t *)ctx->words.p;
+        launch_trace_batch(ctx->stack, ctx->S, (const InstanceDev *)b->d_insts.p, b->n_inst, ctx->M, o,
+                           b->tile_az_log2, b->n_padded, b->packet, words + 1, words, grid, b->cap_stream);
+        e = hipStreamEndCapture(b->cap_stream, &b->graph);
+        if (e != hipSuccess) return ctx->hip_fail(e, "graph capture end");
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            b->drop_graph();
+            return ctx->hip_fail(e, "graph instantiate");
+        }
+        b->bound = o;
+        b->graph_stack = ctx->stack;
+        b->has_graph = true;
+    }
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return ctx->hip_fail(e, "graph launch");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *b, const lidar_outputs *out,
+                                             void *stream) {
+    lidar_status st = ready(ctx, false);
+    if (st != LIDAR_OK) return st;
+    if (!b || b->ctx != ctx || !out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "bad batch or outputs");
+    hipSetDevice(ctx->device);
+    Outputs o = to_outputs(out, b->n_rays);
+    Overrides ov{};
+    for (uint32_t k = 0; k < b->n_inst; ++k) {
+        const InstanceDev &in = b->h_insts[k];
+        uint64_t np = padded_rays(b->tile_az_log2, in.n_ch, in.n_az);
+        launch_trace_scan(ctx->stack, ctx->S, in, ctx->M, ov, o, b->tile_az_log2, np, (uint32_t *)ctx->words.p,
+                          (hipStream_t)stream);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "sequential launches");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_batch_destroy(lidar_batch *b) {
+    if (!b) return LIDAR_OK;
+    hipSetDevice(b->ctx->device);
+    hipDeviceSynchronize();
+    b->drop_graph();
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    b->tables.release();
+    b->d_insts.release();
+    delete b;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *persistent, uint64_t persistent_bytes,
+                        void *scratch, uint64_t scratch_bytes, lidar_batch *b, const lidar_outputs *out,
+                        const lidar_tune_desc *desc, lidar_tune_result *res, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!scene || !b || !out || !desc || !res) return ctx->fail(LIDAR_ERR_INVALID_ARG, "null argument");
+    if (!desc->packet_rays || !desc->leaf_widths || desc->n_packet == 0 || desc->n_leaf == 0 ||
+        desc->n_packet * desc->n_leaf > 64)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "need 1..64 candidate pairs");
+    for (uint32_t i = 0; i < desc->n_packet; ++i)
+        if (desc->packet_rays[i] == 0 || desc->packet_rays[i] % 64 != 0 || desc->packet_rays[i] > 65536)
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "packet sizes must be multiples of 64");
+    for (uint32_t i = 0; i < desc->n_leaf; ++i)
+        if (desc->leaf_widths[i] < 1 || desc->leaf_widths[i] > 8)
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "leaf widths must be in 1..8");
+    uint32_t reps = desc->reps ? desc->reps : 5;
+    hipStream_t s = (hipStream_t)stream;
+    std::memset(res, 0, sizeof *res);
+    res->best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    lidar_scene_desc sd = *scene;
+    for (uint32_t li = 0; li < desc->n_leaf; ++li) {
+        sd.leaf_width = desc->leaf_widths[li];
+        lidar_status st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
+        if (st != LIDAR_OK) {
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            return st;
+        }
+        for (uint32_t pi = 0; pi < desc->n_packet; ++pi) {
+            b->packet = desc->packet_rays[pi];
+            b->drop_graph();
+            std::vector<float> t;
+            for (uint32_t r = 0; r < reps + 1; ++r) {
+                hipEventRecord(e0, s);
+                st = lidar_simulate_batch(ctx, b, out, stream);
+                hipEventRecord(e1, s);
+                hipEventSynchronize(e1);
+                if (st != LIDAR_OK) {
+                    hipEventDestroy(e0);
+                    hipEventDestroy(e1);
+                    return st;
+                }
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (r > 0) t.push_back(ms);   // first run includes graph capture
+            }
+            std::sort(t.begin(), t.end());
+            float med = t[t.size() / 2];
+            res->ms[li * desc->n_packet + pi] = med;
+            if (med < res->best_ms) {
+                res->best_ms = med;
+                res->best_packet_rays = desc->packet_rays[pi];
+                res->best_leaf_width = desc->leaf_widths[li];
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    sd.leaf_width = res->best_leaf_width;
+    lidar_status st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
+    if (st != LIDAR_OK) return st;
+    b->packet = res->best_packet_rays;
+    b->drop_graph();
+    return LIDAR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri, const uint8_t *valid,
+                            const float *dL_dI, const float *dL_drange, float *d_rho, float *d_k, float *d_pose6,
+                            void *stream) {
+    lidar_status st = ready(ctx, true);
+    if (st != LIDAR_OK) return st;
+    if (!tri) return ctx->fail(LIDAR_ERR_NO_FORWARD_STATE, "backward needs the forward's triangle ids (tri)");
+    if (!valid) return ctx->fail(LIDAR_ERR_NO_FORWARD_STATE, "backward needs the forward's valid mask");
+    if (ctx->M.nmat > kMaxAdjMaterials) return ctx->fail(LIDAR_ERR_INVALID_ARG, "backward supports nmat <= 256");
+    const lidar_sensor_desc &d = ctx->sensor.d;
+    size_t pb = adjoint_partial_bytes(d.n_ch * d.n_az, ctx->M.nmat);
+    if (ctx->adj_partials.n < pb) return ctx->fail(LIDAR_ERR_NOT_READY, "adjoint buffer not allocated");
+    const double *elev_cs = (const double *)ctx->sensor_tables.p;
+    const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
+    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, ctx->p, ctx->q, 0, 0, 0, 0, 0);
+    Overrides ov{};
+    if (params) {
+        ov.rho = params->rho;
+        ov.angle_exp = params->angle_exp;
+        ov.pose_delta = params->pose_delta;
+    }
+    hipSetDevice(ctx->device);
+    launch_adjoint(ctx->S, ctx->slot_of, in, ctx->M, ov, tri, valid, dL_dI, dL_drange, (double *)ctx->adj_partials.p,
+                   d_rho, d_k, d_pose6, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "adjoint launch");
+    return LIDAR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// introspection
+// ---------------------------------------------------------------------------
+lidar_status lidar_get_stats(lidar_ctx *ctx, lidar_stats *o) {
+    if (!ctx || !o) return LIDAR_ERR_INVALID_ARG;
+    if (!ctx->has_scene) return ctx->fail(LIDAR_ERR_NOT_READY, "no scene loaded");
+    std::memset(o, 0, sizeof *o);
+    o->n_triangles = ctx->S.n_tri;
+    o->n_nodes = ctx->br.n_nodes;
+    o->n_leaves = ctx->br.n_leaves;
+    o->depth = ctx->br.depth;
+    o->leaf_width = ctx->leaf_width;
+    o->stack_entries = (uint32_t)ctx->stack;
+    o->root = ctx->S.root;
+    o->node_bytes = (uint64_t)ctx->br.n_nodes * sizeof(Node4);
+    o->tri_bytes = (uint64_t)ctx->S.n_tri * sizeof(TriRec);
+    o->build_ms = ctx->build_ms;
+    o->box_pad = ctx->br.box_pad;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_sync_check(lidar_ctx *ctx, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    hipSetDevice(ctx->device);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return ctx->hip_fail(e, "stream synchronize");
+    uint32_t w = 0;
+    e = hipMemcpy(&w, ctx->words.p, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ctx->hip_fail(e, "error word read");
+    if (w) {
+        hipMemset(ctx->words.p, 0, 4);
+        return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "a traversal overflowed its stack");
+    }
+    return LIDAR_OK;
+}
+
+lidar_status lidar_debug_copy_bvh(lidar_ctx *ctx, void *host_nodes, uint64_t node_bytes, void *host_tris,
+                                  uint64_t tri_bytes) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!ctx->has_scene) return ctx->fail(LIDAR_ERR_NOT_READY, "no scene loaded");
+    uint64_t nb = (uint64_t)ctx->br.n_nodes * sizeof(Node4), tb = (uint64_t)ctx->S.n_tri * sizeof(TriRec);
+    if (!host_nodes || !host_tris || node_bytes < nb || tri_bytes < tb)
+        return ctx->fail(LIDAR_ERR_WORKSPACE_TOO_SMALL, "host buffers too small");
+    hipSetDevice(ctx->device);
+    hipError_t e = hipMemcpy(host_nodes, ctx->S.nodes, nb, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(host_tris, ctx->S.tris, tb, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ctx->hip_fail(e, "BVH copy");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_set_tile_shape(lidar_ctx *ctx, uint32_t tile_az) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    int lg = -1;
+    for (int k = 0; k <= 6; ++k)
+        if ((1u << k) == tile_az) lg = k;
+    if (lg < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "tile_az must be a power of two in 1..64");
+    ctx->tile_az_log2 = lg;
+    return LIDAR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+// lidar_device.hpp -- device-side building blocks of the LiDAR simulation path
+// (gfx950, wave64).  Shared by the trace, batch and adjoint kernels.
+//
+// Data layouts in device memory
+// -----------------------------
+// BVH node (128 B, one per 4-wide node), structure-of-arrays inside the node so
+// that one lane reads it with 7 dwordx4 loads:
+//   float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];  uint32 child[4]; uint32 pad[4]
+// child reference: bit 31 clear -> index of a 4-wide node;
+//                  bit 31 set   -> leaf: first triangle record = (ref >> 3) & 0x0FFFFFFF,
+//                                  count = (ref & 7) + 1;
+//                  0xFFFFFFFF   -> empty slot (its box is inverted, never hit).
+// Triangle record (48 B, leaf order = Morton order):
+//   float4 a = (v0.xyz, original index bits), float4 b = (v1.xyz, label bits),
+//   float4 c = (v2.xyz, material bits).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lidar {
+
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kEmptyRef = 0xFFFFFFFFu;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr float kBoxMullerBound = 6.6605f;   // |z| <= sqrt(64 ln 2) = 6.66043..
+
+struct __align__(16) Node4 {
+    float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+    uint32_t child[4];
+    uint32_t pad[4];
+};
+static_assert(sizeof(Node4) == 128, "node must be 128 bytes");
+
+struct __align__(16) TriRec {
+    float4 a, b, c;
+};
+static_assert(sizeof(TriRec) == 48, "triangle record must be 48 bytes");
+
+__host__ __device__ inline uint32_t leaf_ref(uint32_t first, uint32_t count) {
+    return kLeafBit | (first << 3) | (count - 1u);
+}
+__device__ inline uint32_t leaf_first(uint32_t ref) { return (ref >> 3) & 0x0FFFFFFFu; }
+__device__ inline uint32_t leaf_count(uint32_t ref) { return (ref & 7u) + 1u; }
+
+// ---------------------------------------------------------------------------
+// Per-sensor parameters as seen by a kernel (one scan or one batch instance).
+// Direction tables are FP64: cos/sin of the channel elevations and of the
+// azimuth steps, computed on the device from the data-sheet angles.
+// ---------------------------------------------------------------------------
+struct InstanceDev {
+    const double *elev_cs;     // [2*n_ch]: cos phi_j, sin phi_j interleaved
+    const double *az_cs;       // [2*n_az]: cos theta_i, sin theta_i interleaved
+    uint32_t n_ch, n_az;
+    uint32_t tiles_az;         // ceil(n_az / tile_az)
+    uint32_t pad0;
+    uint64_t ray_base;         // first padded ray index of this instance (batch)
+    uint64_t out_base;         // output offset of beam 0
+    float q[4];                // pose quaternion (w, x, y, z), unit
+    float p[3];                // pose origin
+    float wavelength_nm, d_max, r_l_max, t_min, sigma_i, t_trace;
+    uint32_t noise_on;
+    uint32_t seed_lo, seed_hi, scan, inst_id;
+};
+
+struct MaterialsDev {
+    const float *spectra;      // [nmat][nbins]
+    const float *sigma;        // [nmat]
+    const float *angle_exp;    // [nmat]
+    uint32_t nmat, nbins;
+    float lambda0, dlambda;
+};
+
+struct Overrides {
+    const float *rho;          // [nmat] or null
+    const float *angle_exp;    // [nmat] or null
+    const float *pose_delta;   // [6] or null
+};
+
+struct Outputs {
+    float *x, *y, *z, *intensity;
+    uint32_t *label;
+    uint8_t *valid;
+    float *range;
+    uint32_t *tri;
+    float *t_hit;
+    uint16_t *material;
+    float *normal;
+    float *r_lambda;
+    uint64_t plane;            // element stride between the normal's planes
+};
+
+// ---------------------------------------------------------------------------
+// Pose: rotation matrix in FP64 from the unit quaternion, optionally
+// left-multiplied by Exp(dw) (Rodrigues), origin p + dp.
+// ---------------------------------------------------------------------------
+struct Pose64 {
+    double R[9];
+    double p[3];
+};
+
+__device__ inline void quat_to_rot(const float q[4], double R[9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    double n = sqrt(w * w + x * x + y * y + z * z);
+    w /= n; x /= n; y /= n; z /= n;
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__device__ inline void so3_exp(const double w[3], double E[9]) {
+    double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    double th = sqrt(th2);
+    double a, b;  // E = I + a K + b K^2
+    if (th < 1e-12) { a = 1.0; b = 0.5; }
+    else { a = sin(th) / th; b = (1.0 - cos(th)) / th2; }
+    double K[9] = {0.0, -w[2], w[1], w[2], 0.0, -w[0], -w[1], w[0], 0.0};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double k2 = K[r * 3 + 0] * K[0 * 3 + c] + K[r * 3 + 1] * K[1 * 3 + c] + K[r * 3 + 2] * K[2 * 3 + c];
+            E[r * 3 + c] = (r == c ? 1.0 : 0.0) + a * K[r * 3 + c] + b * k2;
+        }
+}
+
+__device__ inline Pose64 make_pose(const InstanceDev &in, const float *pose_delta) {
+    Pose64 P;
+    quat_to_rot(in.q, P.R);
+    P.p[0] = in.p[0]; P.p[1] = in.p[1]; P.p[2] = in.p[2];
+    if (pose_delta) {
+        double w[3] = {pose_delta[3], pose_delta[4], pose_delta[5]};
+        double E[9], R0[9];
+        so3_exp(w, E);
+        for (int i = 0; i < 9; ++i) R0[i] = P.R[i];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                P.R[r * 3 + c] = E[r * 3 + 0] * R0[0 * 3 + c] + E[r * 3 + 1] * R0[1 * 3 + c] + E[r * 3 + 2] * R0[2 * 3 + c];
+        P.p[0] += pose_delta[0]; P.p[1] += pose_delta[1]; P.p[2] += pose_delta[2];
+    }
+    return P;
+}
+
+// Beam (j, i) -> sensor-frame direction s (FP64 then rounded once) and world
+// ray (origin rounded once, direction R s rounded once).
+struct Ray {
+    float ox, oy, oz;
+    float dx, dy, dz;
+    float sx, sy, sz;          // sensor-frame unit direction (for the output point)
+};
+
+__device__ inline Ray make_ray(const InstanceDev &in, const Pose64 &P, uint32_t j, uint32_t i) {
+    double cp = in.elev_cs[2 * j], sp = in.elev_cs[2 * j + 1];
+    double ct = in.az_cs[2 * i], st = in.az_cs[2 * i + 1];
+    double s0 = cp * ct, s1 = cp * st, s2 = sp;
+    Ray r;
+    r.sx = (float)s0; r.sy = (float)s1; r.sz = (float)s2;
+    r.dx = (float)(P.R[0] * s0 + P.R[1] * s1 + P.R[2] * s2);
+    r.dy = (float)(P.R[3] * s0 + P.R[4] * s1 + P.R[5] * s2);
+    r.dz = (float)(P.R[6] * s0 + P.R[7] * s1 + P.R[8] * s2);
+    r.ox = (float)P.p[0]; r.oy = (float)P.p[1]; r.oz = (float)P.p[2];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013), two-sided.
+// The ray is sheared so that it becomes the +z axis; the three 2-D edge
+// functions decide the hit, with an FP64 re-evaluation when one is exactly 0.
+// ---------------------------------------------------------------------------
+struct RayTri {
+    float ox, oy, oz;
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+};
+
+__device__ inline float pick(float x, float y, float z, int k) {
+    return k == 0 ? x : (k == 1 ? y : z);
+}
+
+__device__ inline RayTri prep_tri_test(const Ray &r) {
+    RayTri R;
+    R.ox = r.ox; R.oy = r.oy; R.oz = r.oz;
+    float ax = fabsf(r.dx), ay = fabsf(r.dy), az = fabsf(r.dz);
+    int kz = (ax > ay) ? ((ax > az) ? 0 : 2) : ((ay > az) ? 1 : 2);
+    int kx = kz + 1; if (kx == 3) kx = 0;
+    int ky = kx + 1; if (ky == 3) ky = 0;
+    float dkz = pick(r.dx, r.dy, r.dz, kz);
+    if (dkz < 0.0f) { int t = kx; kx = ky; ky = t; }
+    R.kx = kx; R.ky = ky; R.kz = kz;
+    R.Sx = pick(r.dx, r.dy, r.dz, kx) / dkz;
+    R.Sy = pick(r.dx, r.dy, r.dz, ky) / dkz;
+    R.Sz = 1.0f / dkz;
+    return R;
+}
+
+// Returns true and the distance t if the ray hits the triangle with
+// t_lo < t; the caller compares t with its current best.
+__device__ inline bool tri_hit(const RayTri &R, float4 a, float4 b, float4 c, float t_lo, float &t_out) {
+    float Ax0 = a.x - R.ox, Ay0 = a.y - R.oy, Az0 = a.z - R.oz;
+    float Bx0 = b.x - R.ox, By0 = b.y - R.oy, Bz0 = b.z - R.oz;
+    float Cx0 = c.x - R.ox, Cy0 = c.y - R.oy, Cz0 = c.z - R.oz;
+    float Akx = pick(Ax0, Ay0, Az0, R.kx), Aky = pick(Ax0, Ay0, Az0, R.ky), Akz = pick(Ax0, Ay0, Az0, R.kz);
+    float Bkx = pick(Bx0, By0, Bz0, R.kx), Bky = pick(Bx0, By0, Bz0, R.ky), Bkz = pick(Bx0, By0, Bz0, R.kz);
+    float Ckx = pick(Cx0, Cy0, Cz0, R.kx), Cky = pick(Cx0, Cy0, Cz0, R.ky), Ckz = pick(Cx0, Cy0, Cz0, R.kz);
+    float Ax = fmaf(-R.Sx, Akz, Akx), Ay = fmaf(-R.Sy, Akz, Aky);
+    float Bx = fmaf(-R.Sx, Bkz, Bkx), By = fmaf(-R.Sy, Bkz, Bky);
+    float Cx = fmaf(-R.Sx, Ckz, Ckx), Cy = fmaf(-R.Sy, Ckz, Cky);
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = U + V + W;
+    if (det == 0.0f) return false;
+    float Az = R.Sz * Akz, Bz = R.Sz * Bkz, Cz = R.Sz * Ckz;
+    float T = U * Az + V * Bz + W * Cz;
+    float t = __fdiv_rn(T, det);
+    if (!(t > t_lo)) return false;
+    t_out = t;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Ray / 4 boxes slab test.  Boxes are padded outward at build time by more
+// than the triangle test's rounding error, so a triangle the test above
+// accepts at t is never culled by a box whose computed entry exceeds t.
+// ---------------------------------------------------------------------------
+struct RayBox {
+    float ix, iy, iz;          // 1/d (zero components replaced by +-1e-20)
+    float nox, noy, noz;       // -o/d
+};
+
+__device__ inline RayBox prep_box_test(const Ray &r) {
+    RayBox B;
+    float dx = fabsf(r.dx) < 1e-20f ? copysignf(1e-20f, r.dx) : r.dx;
+    float dy = fabsf(r.dy) < 1e-20f ? copysignf(1e-20f, r.dy) : r.dy;
+    float dz = fabsf(r.dz) < 1e-20f ? copysignf(1e-20f, r.dz) : r.dz;
+    B.ix = 1.0f / dx; B.iy = 1.0f / dy; B.iz = 1.0f / dz;
+    B.nox = -r.ox * B.ix; B.noy = -r.oy * B.iy; B.noz = -r.oz * B.iz;
+    return B;
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and Box-Muller.
+// ---------------------------------------------------------------------------
+__device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+        uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += W0;
+        k1 += W1;
+    }
+    return c;
+}
+
+// Standard normal from two words: u1 = (xa + 1) 2^-32, u2 = xb 2^-32,
+// z = sqrt(-2 ln u1) cos(2 pi u2).  ln u1 is taken as log1p(-(1 - u1)) when
+// u1 > 1/2 so that it keeps its relative accuracy near u1 = 1.
+__device__ inline float box_muller(uint32_t xa, uint32_t xb) {
+    float lnu;
+    if (xa < 0x80000000u) {
+        lnu = logf((float)(xa + 1u) * 2.3283064365386963e-10f);
+    } else {
+        lnu = log1pf(-(float)(~xa) * 2.3283064365386963e-10f);
+    }
+    float u2 = (float)xb * 2.3283064365386963e-10f;
+    return sqrtf(-2.0f * lnu) * cospif(2.0f * u2);
+}
+
+}  // namespace lidar

@@ -1,0 +1,75 @@
+// lidar_kernels.hpp -- host-visible launchers of the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lidar_device.hpp"
+
+namespace lidar {
+
+struct SceneDev {
+    const Node4 *nodes;
+    const TriRec *tris;
+    uint32_t root;
+    uint32_t n_tri;
+};
+
+// --- scan / sort utilities (bvh_build.hip) ---
+size_t scan_tmp_bytes(uint32_t n);
+void scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *tmp, hipStream_t s);
+size_t radix_sort_tmp_bytes(uint32_t n);
+// Stable LSD sort of (key, value) pairs on bits [0, key_bits); result in keys/vals.
+void radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint32_t n,
+                    int key_bits, void *tmp, hipStream_t s);
+
+// --- BVH build ---
+struct BuildInputs {
+    const float *vtx;          // device [nv][3]
+    const uint32_t *idx;       // device [nt][3]
+    const uint16_t *mat;       // device [nt]
+    const uint32_t *label;     // device [nt]
+    uint64_t nv;
+    uint32_t nt;
+    uint32_t leaf_width;
+};
+
+// Persistent layout: [nodes: Node4 x max(nt,1)] [records: TriRec x nt] [slot_of: u32 x nt]
+size_t persistent_nodes_bytes(uint32_t nt);
+size_t persistent_recs_bytes(uint32_t nt);
+
+struct BuildResult {
+    uint32_t root;
+    uint32_t n_nodes;
+    uint32_t n_leaves;
+    uint32_t depth;
+    uint32_t max_material;
+    uint32_t bad_index;
+    float box_pad;
+};
+
+size_t build_scratch_bytes(uint32_t nt);
+size_t build_persistent_bytes(uint32_t nt);
+// Runs the whole build on `s`; synchronises the stream (reads back sizes).
+hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, BuildResult &res, hipStream_t s);
+
+// --- trace (trace.hip) ---
+void launch_dir_tables(const double *elev_deg, uint32_t n_ch, double az0_deg, double fov_h_deg,
+                       uint32_t n_az, double *elev_cs, double *az_cs, hipStream_t s);
+void launch_trace_scan(int stack, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                       const Overrides &ov, const Outputs &out, int tile_az_log2, uint64_t n_padded,
+                       uint32_t *err, hipStream_t s);
+void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
+                       const Outputs &out, int tile_az_log2, uint64_t n_padded, hipStream_t s);
+void launch_trace_batch(int stack, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
+                        const MaterialsDev &M, const Outputs &out, int tile_az_log2, uint64_t n_padded,
+                        uint32_t packet, uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s);
+int batch_blocks_per_cu(int stack);
+
+// --- adjoint (adjoint.hip) ---
+constexpr int kAdjBlock = 256;
+size_t adjoint_partial_bytes(uint32_t n_beams, uint32_t nmat);
+void launch_adjoint(const SceneDev &S, const uint32_t *slot_of, const InstanceDev &in, const MaterialsDev &M,
+                    const Overrides &ov,
+                    const uint32_t *tri, const uint8_t *valid, const float *gI, const float *gd, double *partials, float *d_rho, float *d_k, float *d_pose6, hipStream_t s);
+
+}  // namespace lidar

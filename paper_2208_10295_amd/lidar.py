@@ -1,0 +1,319 @@
+"""Python binding of the gfx950 LiDAR library: argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels behind ``liblidar.so``;
+this module converts arrays to the C structs of ``include/lidar.h``,
+allocates outputs as PyTorch tensors (PyTorch supplies device memory and the
+current stream) and raises ``LidarError`` on error statuses.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import warnings
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from ._abi import lib, check
+
+POINT_OUTPUTS = ("x", "y", "z", "intensity", "label", "valid", "range")
+DEBUG_OUTPUTS = ("tri", "t_hit", "material", "normal", "r_lambda")
+_DTYPES = {"x": torch.float32, "y": torch.float32, "z": torch.float32, "intensity": torch.float32,
+           "label": torch.int32, "valid": torch.uint8, "range": torch.float32, "tri": torch.int32,
+           "t_hit": torch.float32, "material": torch.int16, "normal": torch.float32, "r_lambda": torch.float32}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _warn(status, what):
+    if status == A.WARN_WAVELENGTH_CLAMPED:
+        warnings.warn(f"{what}: sensor wavelength outside the spectral table; end bin used", RuntimeWarning)
+    return status
+
+
+def as_u32(t: torch.Tensor) -> torch.Tensor:
+    """View an int32 tensor holding u32 values as int64 with the unsigned values."""
+    return t.to(torch.int64) & 0xFFFFFFFF
+
+
+def alloc_outputs(n: int, names, device) -> dict:
+    out = {}
+    for k in names:
+        shape = (3, n) if k == "normal" else (n,)
+        out[k] = torch.empty(shape, dtype=_DTYPES[k], device=device)
+    return out
+
+
+def outputs_struct(out: dict) -> A.Outputs:
+    s = A.Outputs()
+    for k in ("x", "y", "z", "intensity", "label", "valid", "range", "tri", "t_hit", "material", "normal",
+              "r_lambda"):
+        t = out.get(k)
+        if t is not None:
+            assert t.is_cuda and t.is_contiguous()
+            setattr(s, k, t.data_ptr())
+    return s
+
+
+def sensor_struct(sensor):
+    """lidar_sensor_desc from an object with the sensor attributes (keeps the elevation array alive)."""
+    elev = np.ascontiguousarray(np.asarray(sensor.elev_deg, dtype=np.float64))
+    d = A.SensorDesc()
+    d.n_ch = len(elev)
+    d.elev_deg = elev.ctypes.data
+    d.n_az = int(sensor.n_az)
+    d.az0_deg = float(getattr(sensor, "az0_deg", 0.0))
+    d.fov_h_deg = float(getattr(sensor, "fov_h_deg", 360.0))
+    d.wavelength_nm = float(sensor.wavelength_nm)
+    d.d_max = float(sensor.d_max)
+    d.r_l_max = float(getattr(sensor, "r_l_max", 0.8))
+    d.t_min = float(getattr(sensor, "t_min", 0.01))
+    d.sigma_intensity = float(getattr(sensor, "sigma_intensity", 0.0))
+    d.noise_on = 1 if getattr(sensor, "noise_on", True) else 0
+    return d, elev
+
+
+class Context:
+    """A library context on one HIP device (owns the scene workspace tensors)."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        check(lib.lidar_create(device, C.byref(h)), None)
+        self.h = h
+        self.persistent = None
+        self.n_beams = 0
+        self.scene_desc = None
+        self._scene_keep = None
+        self.nmat = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.lidar_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- scene --------------------------------------------------------------
+    def _scene_desc(self, vertices, indices, material, label, leaf_width):
+        dev = self.device
+        v = torch.as_tensor(np.ascontiguousarray(vertices, np.float32)).to(dev) if not torch.is_tensor(vertices) else vertices.to(dev, torch.float32).contiguous()
+        i = torch.as_tensor(np.ascontiguousarray(indices, np.uint32).view(np.int32)).to(dev) if not torch.is_tensor(indices) else indices.to(dev, torch.int32).contiguous()
+        m = torch.as_tensor(np.ascontiguousarray(material, np.uint16).view(np.int16)).to(dev) if not torch.is_tensor(material) else material.to(dev, torch.int16).contiguous()
+        lab = torch.as_tensor(np.ascontiguousarray(label, np.uint32).view(np.int32)).to(dev) if not torch.is_tensor(label) else label.to(dev, torch.int32).contiguous()
+        d = A.SceneDesc()
+        d.n_vertices = v.shape[0]
+        d.n_triangles = i.shape[0]
+        d.vertices, d.indices, d.material, d.label = (t.data_ptr() for t in (v, i, m, lab))
+        d.leaf_width = int(leaf_width)
+        d.flags = A.SCENE_DEVICE_PTRS
+        return d, (v, i, m, lab)
+
+    def load_scene(self, vertices, indices, material, label, leaf_width: int = 4, stream=None):
+        d, keep = self._scene_desc(vertices, indices, material, label, leaf_width)
+        pb, sb = C.c_uint64(), C.c_uint64()
+        check(lib.lidar_scene_bytes(C.byref(d), C.byref(pb), C.byref(sb)), self.h)
+        persistent = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        check(lib.lidar_scene_load(self.h, C.byref(d), _ptr(persistent), pb.value, _ptr(scratch), sb.value,
+                                   _stream(stream)), self.h)
+        del scratch
+        self.persistent = persistent
+        self.scene_desc = d
+        self._scene_keep = keep
+        return self.stats()
+
+    def load(self, scene, leaf_width: int = 4):
+        """Scene + materials from an object with vertices/indices/material/label/spectra/sigma_range/angle_exp."""
+        st = self.load_scene(scene.vertices, scene.indices, scene.material, scene.label, leaf_width)
+        self.set_materials(scene.spectra, scene.sigma_range, scene.angle_exp)
+        return st
+
+    def stats(self) -> dict:
+        s = A.Stats()
+        check(lib.lidar_get_stats(self.h, C.byref(s)), self.h)
+        return {k: getattr(s, k) for k, _ in A.Stats._fields_}
+
+    # -- materials / sensor / pose -----------------------------------------
+    def set_materials(self, spectra, sigma_range, angle_exp=None, lambda0_nm: float = 400.0,
+                      dlambda_nm: float = 10.0):
+        sp = np.ascontiguousarray(spectra, np.float32)
+        sg = np.ascontiguousarray(sigma_range, np.float32)
+        ke = None if angle_exp is None else np.ascontiguousarray(angle_exp, np.float32)
+        d = A.MaterialDesc()
+        d.nmat, d.nbins = sp.shape
+        d.lambda0_nm, d.dlambda_nm = lambda0_nm, dlambda_nm
+        d.spectra = sp.ctypes.data
+        d.sigma_range = sg.ctypes.data
+        d.angle_exp = None if ke is None else ke.ctypes.data
+        check(lib.lidar_materials_set(self.h, C.byref(d)), self.h)
+        self.nmat = int(d.nmat)
+
+    def set_sensor(self, sensor) -> int:
+        d, keep = sensor_struct(sensor)
+        st = check(lib.lidar_sensor_set(self.h, C.byref(d)), self.h)
+        self.n_beams = int(d.n_ch) * int(d.n_az)
+        return _warn(st, "set_sensor")
+
+    def set_pose(self, p, q):
+        pa = (C.c_float * 3)(*[float(x) for x in p])
+        qa = (C.c_float * 4)(*[float(x) for x in q])
+        check(lib.lidar_pose_set(self.h, pa, qa), self.h)
+
+    def set_tile_shape(self, tile_az: int):
+        check(lib.lidar_set_tile_shape(self.h, int(tile_az)), self.h)
+
+    # -- simulation ---------------------------------------------------------
+    def simulate(self, seed: int = 0, scan: int = 0, debug: bool = False, out: dict | None = None,
+                 params: dict | None = None, stream=None, bruteforce: bool = False) -> dict:
+        if out is None:
+            out = alloc_outputs(self.n_beams, POINT_OUTPUTS + (DEBUG_OUTPUTS if debug else ()), self.device)
+        o = outputs_struct(out)
+        if bruteforce:
+            st = lib.lidar_simulate_bruteforce(self.h, seed, scan, C.byref(o), _stream(stream))
+        elif params:
+            p = A.Params()
+            for k in ("rho", "angle_exp", "pose_delta"):
+                t = params.get(k)
+                if t is not None:
+                    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                    setattr(p, k, t.data_ptr())
+            st = lib.lidar_simulate_ex(self.h, seed, scan, C.byref(p), C.byref(o), _stream(stream))
+        else:
+            st = lib.lidar_simulate(self.h, seed, scan, C.byref(o), _stream(stream))
+        check(st, self.h)
+        return out
+
+    def sync_check(self, stream=None):
+        check(lib.lidar_sync_check(self.h, _stream(stream)), self.h)
+
+    def backward(self, tri, valid, dL_dI=None, dL_drange=None, params: dict | None = None, stream=None):
+        nmat = self.nmat
+        d_rho = torch.empty(nmat, dtype=torch.float32, device=self.device)
+        d_k = torch.empty(nmat, dtype=torch.float32, device=self.device)
+        d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
+        p = A.Params()
+        for k in ("rho", "angle_exp", "pose_delta"):
+            t = (params or {}).get(k)
+            if t is not None:
+                setattr(p, k, t.data_ptr())
+        check(lib.lidar_backward(self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(dL_dI), _ptr(dL_drange),
+                                 _ptr(d_rho), _ptr(d_k), _ptr(d_pose), _stream(stream)), self.h)
+        return d_rho, d_k, d_pose
+
+    def batch(self, instances, packet_rays: int = 0) -> "Batch":
+        return Batch(self, instances, packet_rays)
+
+    def debug_bvh(self):
+        s = self.stats()
+        nodes = np.empty(s["n_nodes"] * 128, np.uint8)
+        tris = np.empty(s["n_triangles"] * 48, np.uint8)
+        check(lib.lidar_debug_copy_bvh(self.h, nodes.ctypes.data, nodes.nbytes, tris.ctypes.data, tris.nbytes),
+              self.h)
+        return nodes, tris
+
+
+class Batch:
+    """Many sensor instances simulated by one persistent, graph-captured launch."""
+
+    def __init__(self, ctx: Context, instances, packet_rays: int = 0):
+        self.ctx = ctx
+        arr = (A.Instance * len(instances))()
+        keep = []
+        for k, inst in enumerate(instances):
+            d, elev = sensor_struct(inst.sensor)
+            keep.append(elev)
+            arr[k].sensor = d
+            arr[k].p[:] = [float(x) for x in inst.pose.p]
+            arr[k].q_wxyz[:] = [float(x) for x in inst.pose.q]
+            arr[k].seed = int(inst.seed)
+            arr[k].scan = int(inst.scan)
+        h = C.c_void_p()
+        st = check(lib.lidar_batch_create(ctx.h, arr, len(instances), int(packet_rays), C.byref(h)), ctx.h)
+        self.clamped = st == A.WARN_WAVELENGTH_CLAMPED
+        self.h = h
+        n = C.c_uint64()
+        check(lib.lidar_batch_rays(h, C.byref(n)), ctx.h)
+        self.n_rays = int(n.value)
+        offs = np.zeros(len(instances) + 1, np.int64)
+        offs[1:] = np.cumsum([len(i.sensor.elev_deg) * int(i.sensor.n_az) for i in instances])
+        self.offsets = offs
+
+    def simulate(self, out: dict | None = None, debug: bool = False, stream=None, sequential: bool = False):
+        if out is None:
+            out = alloc_outputs(self.n_rays, POINT_OUTPUTS + (DEBUG_OUTPUTS if debug else ()), self.ctx.device)
+        o = outputs_struct(out)
+        fn = lib.lidar_simulate_batch_sequential if sequential else lib.lidar_simulate_batch
+        check(fn(self.ctx.h, self.h, C.byref(o), _stream(stream)), self.ctx.h)
+        return out
+
+    def tune(self, packet_rays=(64, 128, 256, 512), leaf_widths=(2, 4, 8), reps=5, out=None, stream=None):
+        ctx = self.ctx
+        if out is None:
+            out = alloc_outputs(self.n_rays, POINT_OUTPUTS, ctx.device)
+        o = outputs_struct(out)
+        pk = np.ascontiguousarray(packet_rays, np.uint32)
+        lw = np.ascontiguousarray(leaf_widths, np.uint32)
+        d = A.TuneDesc(pk.ctypes.data, len(pk), lw.ctypes.data, len(lw), int(reps))
+        r = A.TuneResult()
+        sd = ctx.scene_desc
+        pb, sb = C.c_uint64(), C.c_uint64()
+        check(lib.lidar_scene_bytes(C.byref(sd), C.byref(pb), C.byref(sb)), ctx.h)
+        scratch = torch.empty(sb.value, dtype=torch.uint8, device=ctx.device)
+        check(lib.lidar_tune(ctx.h, C.byref(sd), _ptr(ctx.persistent), ctx.persistent.numel(), _ptr(scratch),
+                             sb.value, self.h, C.byref(o), C.byref(d), C.byref(r), _stream(stream)), ctx.h)
+        grid = np.array(r.ms[:len(pk) * len(lw)], np.float64).reshape(len(lw), len(pk))
+        return dict(best_packet_rays=r.best_packet_rays, best_leaf_width=r.best_leaf_width, best_ms=r.best_ms,
+                    ms=grid, packet_rays=list(pk), leaf_widths=list(lw))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.lidar_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LidarReturn(torch.autograd.Function):
+    """(rho[nmat], k[nmat], pose_delta[6]) -> (intensity, range, valid, tri) of one noise-free scan.
+
+    The backward pass is the library's adjoint kernel with the hit triangles
+    of the forward pass held fixed; the pose gradient is with respect to
+    pose_delta = (dp, dw) with p = p0 + dp and R = Exp(dw) R0.
+    """
+
+    @staticmethod
+    def forward(ctx_, lidar_ctx: Context, rho, k, pose_delta, seed: int = 0, scan: int = 0):
+        out = lidar_ctx.simulate(seed, scan, out=alloc_outputs(lidar_ctx.n_beams, ("intensity", "range", "valid",
+                                                                                  "tri"), lidar_ctx.device),
+                                 params=dict(rho=rho.detach().contiguous(), angle_exp=k.detach().contiguous(),
+                                             pose_delta=pose_delta.detach().contiguous()))
+        ctx_.lidar = lidar_ctx
+        ctx_.save_for_backward(rho, k, pose_delta, out["tri"], out["valid"])
+        ctx_.mark_non_differentiable(out["valid"], out["tri"])
+        return out["intensity"], out["range"], out["valid"], out["tri"]
+
+    @staticmethod
+    def backward(ctx_, gI, gR, _gv, _gt):
+        rho, k, pose_delta, tri, valid = ctx_.saved_tensors
+        d_rho, d_k, d_pose = ctx_.lidar.backward(
+            tri, valid, None if gI is None else gI.contiguous(), None if gR is None else gR.contiguous(),
+            params=dict(rho=rho.detach().contiguous(), angle_exp=k.detach().contiguous(),
+                        pose_delta=pose_delta.detach().contiguous()))
+        return None, d_rho, d_k, d_pose, None, None

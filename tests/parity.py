@@ -1,0 +1,86 @@
+"""Element-by-element comparison of the GPU path's outputs with the FP64 oracle.
+
+Bars (FP32 GPU vs FP64 oracle, same seeded inputs, same Philox seed):
+  * hit triangle and instance label: bit-exact, except rays the oracle marks
+    ambiguous (second hit within 1e-6 m, edge graze, near miss, at the trace
+    limit), which are counted and excluded;
+  * detection flag: equal, except rays within 1e-5 relative of an eq.5 or
+    range threshold (oracle's ``marginal``) or ambiguous;
+  * depth (t, range, point coordinates): 1e-5 relative;
+  * intensity / R_lambda: 1e-4 relative (to max(I, R_lambda));
+  * depth and intensity tolerances skip grazing hits (cos < 0.01), where an
+    FP32 ray direction moves the hit by tan(theta) x 1e-7.
+"""
+import numpy as np
+
+NO = 0xFFFFFFFF
+
+
+def u32(t):
+    a = t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)
+    return a.view(np.uint32) if a.dtype == np.int32 else a.astype(np.uint32)
+
+
+def to_np(out: dict, beams=None) -> dict:
+    r = {}
+    for k, t in out.items():
+        a = t.detach().cpu().numpy()
+        if k in ("tri", "label"):
+            a = a.view(np.uint32)
+        if k == "material":
+            a = a.view(np.uint16)
+        if beams is not None:
+            a = a[..., beams]
+        r[k] = a
+    return r
+
+
+def compare(g: dict, o: dict, check_debug: bool = True) -> dict:
+    """g: GPU outputs (numpy, already restricted to o['beams']); o: oracle dict."""
+    amb = o["ambiguous"]
+    n = len(amb)
+    rep = {"n": n, "ambiguous": int(amb.sum()), "grazing": int(o["grazing"].sum()),
+           "marginal": int((o["marginal"] & ~amb).sum())}
+    ok = ~amb
+    if check_debug:
+        bad = ok & (g["tri"] != o["tri"])
+        rep["tri_mismatch"] = int(bad.sum())
+        assert not bad.any(), f"hit triangle differs on {bad.sum()} unambiguous rays, e.g. beams {o['beams'][bad][:8]}"
+        hit = ok & (o["tri"] != NO)
+        m_bad = hit & (g["material"] != o["material"])
+        assert not m_bad.any(), "material differs"
+    vcmp = ok & ~o["marginal"]
+    bad = vcmp & (g["valid"] != o["valid"])
+    rep["valid_mismatch"] = int(bad.sum())
+    assert not bad.any(), f"valid differs on {bad.sum()} rays, e.g. beams {o['beams'][bad][:8]}"
+    both = vcmp & (o["valid"] == 1)
+    assert np.array_equal(g["label"][both], o["label"][both]), "label differs"
+    nv = vcmp & (o["valid"] == 0)
+    assert np.all(g["label"][nv] == NO) and np.all(g["intensity"][nv] == 0) and np.all(g["range"][nv] == 0)
+    assert np.all(g["x"][nv] == 0) and np.all(g["y"][nv] == 0) and np.all(g["z"][nv] == 0)
+    fine = both & ~o["grazing"]
+    rng = o["range"][fine]
+    e_r = np.abs(g["range"][fine] - rng) / rng
+    rep["range_max_rel"] = float(e_r.max()) if e_r.size else 0.0
+    assert np.all(e_r <= 1e-5), f"range rel error {e_r.max():.3g}"
+    for k in ("x", "y", "z"):
+        e = np.abs(g[k][fine] - o[k][fine]) / rng
+        assert np.all(e <= 1e-5), f"{k} rel error {e.max():.3g}"
+    scale = np.maximum(np.abs(o["intensity"][fine]), o["r_lambda"][fine])
+    e_i = np.abs(g["intensity"][fine] - o["intensity"][fine]) / scale
+    rep["intensity_max_rel"] = float(e_i.max()) if e_i.size else 0.0
+    assert np.all(e_i <= 1e-4), f"intensity rel error {e_i.max():.3g}"
+    if check_debug:
+        h = ok & (o["tri"] != NO) & ~o["grazing"]
+        e_t = np.abs(g["t_hit"][h] - o["t_hit"][h]) / o["t_hit"][h]
+        rep["t_max_rel"] = float(e_t.max()) if e_t.size else 0.0
+        assert np.all(e_t <= 1e-5), f"t_hit rel error {e_t.max():.3g}"
+        e_l = np.abs(g["r_lambda"][h] - o["r_lambda"][h]) / o["r_lambda"][h]
+        assert np.all(e_l <= 1e-4), f"r_lambda rel error {e_l.max():.3g}"
+        e_n = np.abs(g["normal"][:, h] - o["normal"][h].T)
+        assert np.all(e_n <= 1e-5), f"normal error {e_n.max():.3g}"
+        miss = ok & (o["tri"] == NO)
+        assert np.all(g["t_hit"][miss] == 0) and np.all(g["material"][miss] == 0xFFFF)
+    rep["hits"] = int((o["tri"] != NO).sum())
+    rep["valid"] = int((o["valid"] == 1).sum())
+    return rep

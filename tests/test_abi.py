@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/lidar.h, the ctypes mirror matches the header, and the
+pure-host calls behave (no GPU compute)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lidar.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lidar_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2208_10295_amd import _abi
+    return _abi
+
+
+def test_every_declared_symbol_is_exported_and_bound(A):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(A.lib, n), f"{n} not exported by liblidar.so"
+        assert n in A.SIGNATURES, f"{n} missing from the ctypes mirror"
+    assert set(A.SIGNATURES) == set(names)
+
+
+def test_struct_layouts_match_header(A):
+    # sizes follow from the field lists in include/lidar.h on x86-64
+    assert C.sizeof(A.SceneDesc) == 8 + 8 + 4 * 8 + 4 + 4
+    assert C.sizeof(A.MaterialDesc) == 4 * 4 + 3 * 8
+    assert C.sizeof(A.SensorDesc) == 8 + 8 + 8 + 8 + 8 + 6 * 4
+    assert C.sizeof(A.Outputs) == 12 * 8
+    assert C.sizeof(A.Params) == 3 * 8
+    assert C.sizeof(A.TuneResult) == 12 + 64 * 4
+    assert C.sizeof(A.Stats) == 3 * 8 + 4 * 4 + 2 * 8 + 2 * 4
+
+
+def test_scene_bytes_host_only(A):
+    d = A.SceneDesc()
+    d.n_vertices, d.n_triangles = 100, 50
+    d.flags = A.SCENE_DEVICE_PTRS
+    p, s = C.c_uint64(), C.c_uint64()
+    assert A.lib.lidar_scene_bytes(C.byref(d), C.byref(p), C.byref(s)) == A.OK
+    assert p.value >= 50 * (128 + 48 + 4) and p.value % 256 == 0
+    d.flags = 0
+    p2, s2 = C.c_uint64(), C.c_uint64()
+    assert A.lib.lidar_scene_bytes(C.byref(d), C.byref(p2), C.byref(s2)) == A.OK
+    assert s2.value >= s.value + 100 * 12 + 50 * 18       # room for the host-array copies
+    d.n_triangles = 0
+    assert A.lib.lidar_scene_bytes(C.byref(d), C.byref(p), C.byref(s)) == A.ERR_INVALID_ARG
+    d.n_triangles = 1 << 28
+    assert A.lib.lidar_scene_bytes(C.byref(d), C.byref(p), C.byref(s)) == A.ERR_INVALID_ARG
+    assert A.lib.lidar_scene_bytes(None, C.byref(p), C.byref(s)) == A.ERR_INVALID_ARG
+
+
+def test_null_context_calls_are_rejected(A):
+    lib = A.lib
+    assert lib.lidar_destroy(None) == A.OK
+    assert lib.lidar_simulate(None, 0, 0, None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_sensor_set(None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_materials_set(None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_backward(None, None, None, None, None, None, None, None, None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_batch_destroy(None) == A.OK
+    assert lib.lidar_create(0, None) == A.ERR_INVALID_ARG
+
+
+def test_create_without_gpu_reports_error(A):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    st = A.lib.lidar_create(0, C.byref(h))
+    assert st in (A.ERR_HIP, A.ERR_INVALID_ARG)
+    assert h.value is None
+    assert len(A.lib.lidar_last_error(None)) > 0
+
+
+def test_binding_fails_loudly_without_library(A, tmp_path):
+    with pytest.raises(ImportError):
+        A.load(str(tmp_path / "liblidar.so"))

@@ -1,0 +1,159 @@
+"""GPU parity of the forward path (trace + return model) against the FP64 oracle.
+
+All calls go through the C ABI (liblidar.so) via the thin Python binding.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.lidar_oracle as O
+from lidar_inputs import scenes as S
+from tests.parity import compare, to_np
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x1234_5678_9ABC
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2208_10295_amd as lib
+    return lib
+
+
+def _ctx(L, scene, sensor, pose, leaf_width=4):
+    c = L.Context(0)
+    c.load(scene, leaf_width)
+    c.set_sensor(sensor)
+    c.set_pose(pose.p, pose.q)
+    return c
+
+
+def _report(name, rep):
+    print(f"[parity] {name}: " + ", ".join(f"{k}={v}" for k, v in rep.items()), flush=True)
+
+
+def test_config1_full_scan_matches_oracle(L):
+    scene, sensor, pose = S.config1()
+    c = _ctx(L, scene, sensor, pose)
+    g = to_np(c.simulate(SEED, scan=3, debug=True))
+    c.sync_check()
+    o = O.simulate(scene, sensor, pose, seed=SEED, scan=3)
+    rep = compare(g, o)
+    _report("config1 full", rep)
+    assert rep["valid"] > 3000 and rep["ambiguous"] < 0.01 * rep["n"]
+
+
+def test_config1_bvh_equals_bruteforce_and_is_deterministic(L):
+    scene, sensor, pose = S.config1()
+    c = _ctx(L, scene, sensor, pose)
+    a = to_np(c.simulate(SEED, 1, debug=True))
+    b = to_np(c.simulate(SEED, 1, debug=True, bruteforce=True))
+    a2 = to_np(c.simulate(SEED, 1, debug=True))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], a2[k]), k
+
+
+def test_leaf_widths_and_tile_shapes_do_not_change_results(L):
+    scene, sensor, pose = S.config1()
+    ref = None
+    for W in (1, 2, 3, 4, 8):
+        c = _ctx(L, scene, sensor, pose, leaf_width=W)
+        for tile in ((1, 8, 64) if W == 4 else (8,)):
+            c.set_tile_shape(tile)
+            g = to_np(c.simulate(SEED, 0, debug=True))
+            if ref is None:
+                ref = g
+            for k in ref:
+                assert np.array_equal(ref[k], g[k]), (W, tile, k)
+
+
+def test_config2_full_scan_sampled_oracle(L):
+    scene, sensor, pose = S.config2()
+    c = _ctx(L, scene, sensor, pose)
+    st = c.stats()
+    print("[bvh] config2", st, flush=True)
+    out = c.simulate(SEED, scan=0, debug=True)
+    c.sync_check()
+    rng = np.random.default_rng(7)
+    beams = np.sort(rng.choice(sensor.n_beams, 3072, replace=False))
+    # include whole rows at the ragged start/end of a tile row and the first/last beams
+    beams = np.unique(np.r_[beams, np.arange(0, 70), np.arange(sensor.n_beams - 70, sensor.n_beams)])
+    o = O.simulate(scene, sensor, pose, seed=SEED, scan=0, beams=beams)
+    rep = compare(to_np(out, beams), o)
+    _report("config2 sampled", rep)
+    assert rep["valid"] > 1000
+
+
+def test_config2_bvh_equals_bruteforce_full(L):
+    scene, sensor, pose = S.config2()
+    c = _ctx(L, scene, sensor, pose)
+    a = to_np(c.simulate(SEED, 0, debug=True))
+    b = to_np(c.simulate(SEED, 0, debug=True, bruteforce=True))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_ragged_sensor_and_offsets(L):
+    """Odd channel/azimuth counts, a partial FOV and a scene far from the origin."""
+    scene, _, _ = S.config1()
+    off = np.array([3000.0, -1500.0, 40.0])
+    sc2 = S.Scene((scene.vertices.astype(np.float64) + off).astype(np.float32), scene.indices, scene.material,
+                  scene.label, scene.spectra, scene.sigma_range, scene.angle_exp)
+    sensor = S.Sensor(np.array([-14.0, -9.5, -3.0, 0.5, 7.0]), 37, az0_deg=10.0, fov_h_deg=200.0, d_max=80.0)
+    pose = S.Pose((np.array([0.0, 0.0, 1.5]) + off).astype(np.float32), S.quat_from_ypr(0.3, 0.02, -0.01))
+    c = _ctx(L, sc2, sensor, pose)
+    for tile in (1, 4, 64):
+        c.set_tile_shape(tile)
+        g = to_np(c.simulate(99, 5, debug=True))
+        o = O.simulate(sc2, sensor, pose, seed=99, scan=5)
+        _report(f"ragged tile {tile}", compare(g, o))
+
+
+def test_single_triangle_scene(L):
+    v = np.array([[10, -5, -5], [10, 5, -5], [10, 0, 5]], np.float32)
+    scene = S.Scene(v, np.array([[0, 1, 2]], np.uint32), np.array([0], np.uint16), np.array([42], np.uint32),
+                    np.full((1, 61), 0.6, np.float32), np.array([0.0], np.float32), np.array([1.0], np.float32))
+    sensor = S.Sensor(np.array([-10.0, 0.0, 10.0]), 16, d_max=50.0, noise_on=False)
+    pose = S.Pose(np.zeros(3, np.float32), np.array([1, 0, 0, 0], np.float32))
+    c = _ctx(L, scene, sensor, pose)
+    assert c.stats()["n_nodes"] == 1
+    g = to_np(c.simulate(0, 0, debug=True))
+    o = O.simulate(scene, sensor, pose)
+    compare(g, o)
+    assert g["valid"][16 * 1 + 0] == 1 and g["label"][16] == 42
+    assert abs(g["range"][16] - 10.0) < 1e-5 and abs(g["intensity"][16] - 0.6) < 1e-6
+
+
+def test_config3_sequence_sampled(L):
+    scene, sensor, poses = S.config3()
+    c = L.Context(0)
+    st = c.load(scene)
+    print("[bvh] config3", st, flush=True)
+    c.set_sensor(sensor)
+    rng = np.random.default_rng(3)
+    for scan in (0, 57, 99):
+        pose = poses[scan]
+        c.set_pose(pose.p, pose.q)
+        out = c.simulate(SEED, scan, debug=True)
+        c.sync_check()
+        beams = np.sort(rng.choice(sensor.n_beams, 160, replace=False))
+        o = O.simulate(scene, sensor, pose, seed=SEED, scan=scan, beams=beams)
+        _report(f"config3 scan {scan}", compare(to_np(out, beams), o))
+
+
+def test_wavelength_clamp_warning_and_values(L):
+    scene, sensor, pose = S.config1()
+    s2 = S.Sensor(sensor.elev_deg, 64, wavelength_nm=1550.0, d_max=100.0)
+    c = L.Context(0)
+    c.load(scene)
+    with pytest.warns(RuntimeWarning):
+        c.set_sensor(s2)
+    c.set_pose(pose.p, pose.q)
+    g = to_np(c.simulate(5, 0, debug=True))
+    o = O.simulate(scene, s2, pose, seed=5)
+    assert o["wavelength_clamped"]
+    compare(g, o)

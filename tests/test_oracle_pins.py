@@ -238,9 +238,14 @@ def test_zero_return_beyond_max_range():
     r = O.simulate(_wall(dmax + 1e-3, 0.95), sensor0, pose)
     assert 0.8 / dmax * (dmax + 1e-3) <= 0.95
     assert r["valid"][0] == 0 and r["intensity"][0] == 0 and r["label"][0] == O.MISS_LABEL
-    # rho cos = R_L,max: detection up to d_max inclusive
-    r = O.simulate(_wall(dmax, 0.8), sensor0, pose)
-    assert r["valid"][0] == 1 and abs(r["intensity"][0] - 0.8) < 1e-7
+    # rho cos = R_L,max: detection up to d_max inclusive (powers of two make
+    # R_L(d_max) = R_L,max exact, so this pins the <= comparator and d <= d_max)
+    s64 = S.Sensor(np.array([0.0]), 4, d_max=64.0, r_l_max=0.5, noise_on=False)
+    r = O.simulate(_wall(64.0, 0.5), s64, pose)
+    assert r["t_hit"][0] == 64.0 and r["r_lambda"][0] == 0.5
+    assert r["valid"][0] == 1 and r["intensity"][0] == 0.5
+    r = O.simulate(_wall(64.0, 0.5 - 2 ** -20), s64, pose)
+    assert r["valid"][0] == 0
     r = O.simulate(_wall(dmax * 0.999, 0.8), sensor0, pose)
     assert r["valid"][0] == 1          # R_L(0.999 d_max) = 0.7992 <= 0.8
     r = O.simulate(_wall(dmax * 0.999, 0.79), sensor0, pose)
