@@ -221,11 +221,26 @@ lidar_status lidar_simulate_ex(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
 lidar_status lidar_simulate_bruteforce(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
                                        const lidar_outputs *out, void *stream);
 
-/* Wavefront ray tile: each 64-lane wavefront traces tile_az consecutive
- * azimuth steps of 64 / tile_az consecutive channels (tile_az a power of two
- * in 1..64; default 8).  Only affects speed, never results.  A batch keeps
- * the tile shape that was current when it was created. */
-lidar_status lidar_set_tile_shape(lidar_ctx *ctx, uint32_t tile_az);
+/* lidar_simulate that also writes, per beam, the number of 4-wide nodes the
+ * traversal fetched and the number of triangle records it tested
+ * (node_visits, tri_tests: caller-owned device [n_ch * n_az]).  Same results
+ * as lidar_simulate; used to count the bytes a scan reads.  Asynchronous. */
+lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_outputs *out,
+                                   uint32_t *node_visits, uint32_t *tri_tests, void *stream);
+
+/* Launch-shape options.  They change speed, never results.
+ *   LIDAR_OPT_TILE_AZ: beams are traced in 64-beam tiles of `value` azimuth
+ *     steps x 64 / value channels (power of two in 1..64; default 16).  A batch
+ *     keeps the tile shape that was current when it was created.
+ *   LIDAR_OPT_LANES_PER_RAY: 1 = one lane walks the BVH for a beam; 4 = the
+ *     four lanes of a quad share a beam, one child box or triangle each
+ *     (default 4).
+ *   LIDAR_OPT_XCD_REMAP: 1 = the thread blocks that run on one XCD take one
+ *     contiguous azimuth sector (default 1); 0 = blocks in launch order. */
+#define LIDAR_OPT_TILE_AZ        1u
+#define LIDAR_OPT_LANES_PER_RAY  2u
+#define LIDAR_OPT_XCD_REMAP      3u
+lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value);
 
 /* ------------------------------------------------------------------------ */
 /* Batched form: many sensors / poses in one persistent launch               */

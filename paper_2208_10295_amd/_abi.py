@@ -8,6 +8,10 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+# PyTorch ships its own HIP runtime; loading it before liblidar.so makes the
+# library bind to that same runtime (one HIP runtime per process).
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblidar.so")
 
@@ -26,6 +30,9 @@ NO_LABEL = 0xFFFFFFFF
 NO_TRIANGLE = 0xFFFFFFFF
 NO_MATERIAL = 0xFFFF
 SCENE_DEVICE_PTRS = 1
+OPT_TILE_AZ = 1
+OPT_LANES_PER_RAY = 2
+OPT_XCD_REMAP = 3
 
 STATUS_NAMES = {
     OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_NOT_READY: "ERR_NOT_READY",
@@ -96,10 +103,11 @@ SIGNATURES = {
     "lidar_materials_set": (C.c_int32, [P, C.POINTER(MaterialDesc)]),
     "lidar_sensor_set": (C.c_int32, [P, C.POINTER(SensorDesc)]),
     "lidar_pose_set": (C.c_int32, [P, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
-    "lidar_set_tile_shape": (C.c_int32, [P, C.c_uint32]),
+    "lidar_set_option": (C.c_int32, [P, C.c_uint32, C.c_int32]),
     "lidar_simulate": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P]),
     "lidar_simulate_ex": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Params), C.POINTER(Outputs), P]),
     "lidar_simulate_bruteforce": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P]),
+    "lidar_simulate_counts": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P, P, P]),
     "lidar_batch_create": (C.c_int32, [P, C.POINTER(Instance), C.c_uint32, C.c_uint32, C.POINTER(P)]),
     "lidar_batch_rays": (C.c_int32, [P, C.POINTER(C.c_uint64)]),
     "lidar_simulate_batch": (C.c_int32, [P, P, C.POINTER(Outputs), P]),

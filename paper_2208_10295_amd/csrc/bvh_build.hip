@@ -467,23 +467,24 @@ __global__ __launch_bounds__(256) void collapse_kernel(BinTree T, const TriRec *
         if (k < nc) {
             float lo[3], hi[3];
             child_box(T, recs, C[k], lo, hi);
-            nd.lox[k] = lo[0] - pad; nd.loy[k] = lo[1] - pad; nd.loz[k] = lo[2] - pad;
-            nd.hix[k] = hi[0] + pad; nd.hiy[k] = hi[1] + pad; nd.hiz[k] = hi[2] + pad;
+            for (int a = 0; a < 3; ++a) {
+                nd.c[k].lo[a] = lo[a] - pad;
+                nd.c[k].hi[a] = hi[a] + pad;
+            }
             uint32_t cnt = code_count(T, C[k]);
             if (cnt <= W) {
-                nd.child[k] = leaf_ref(code_first(T, C[k]), cnt);
+                nd.c[k].ref = leaf_ref(code_first(T, C[k]), cnt);
                 ++n_leaf;
             } else {
-                nd.child[k] = 0u;   // set by assign_kernel
+                nd.c[k].ref = 0u;   // set by assign_kernel
                 pending[4 * (size_t)f + n_int] = C[k] | ((uint32_t)k << 29);
                 ++n_int;
             }
         } else {
-            nd.lox[k] = nd.loy[k] = nd.loz[k] = 1e30f;
-            nd.hix[k] = nd.hiy[k] = nd.hiz[k] = 1e30f;
-            nd.child[k] = kEmptyRef;
+            for (int a = 0; a < 3; ++a) nd.c[k].lo[a] = nd.c[k].hi[a] = 1e30f;
+            nd.c[k].ref = kEmptyRef;
         }
-        nd.pad[k] = 0u;
+        nd.c[k].pad = 0u;
     }
     nodes[node_base + f] = nd;
     counts[f] = n_int;
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(256) void assign_kernel(const uint32_t *__restrict_
     for (uint32_t q = 0; q < cnt; ++q) {
         uint32_t e = pending[4 * (size_t)f + q];
         uint32_t slot = e >> 29, code = e & 0x1FFFFFFFu;
-        nodes[node_base + f].child[slot] = next_base + off + q;
+        nodes[node_base + f].c[slot].ref = next_base + off + q;
         next_frontier[off + q] = code;
     }
 }
@@ -518,13 +519,15 @@ __global__ void single_leaf_root_kernel(const TriRec *__restrict__ recs, uint32_
     }
     Node4 nd;
     for (int k = 0; k < 4; ++k) {
-        nd.lox[k] = nd.loy[k] = nd.loz[k] = nd.hix[k] = nd.hiy[k] = nd.hiz[k] = 1e30f;
-        nd.child[k] = kEmptyRef;
-        nd.pad[k] = 0;
+        for (int a = 0; a < 3; ++a) nd.c[k].lo[a] = nd.c[k].hi[a] = 1e30f;
+        nd.c[k].ref = kEmptyRef;
+        nd.c[k].pad = 0;
     }
-    nd.lox[0] = lo[0] - pad; nd.loy[0] = lo[1] - pad; nd.loz[0] = lo[2] - pad;
-    nd.hix[0] = hi[0] + pad; nd.hiy[0] = hi[1] + pad; nd.hiz[0] = hi[2] + pad;
-    nd.child[0] = leaf_ref(0, nt);
+    for (int a = 0; a < 3; ++a) {
+        nd.c[0].lo[a] = lo[a] - pad;
+        nd.c[0].hi[a] = hi[a] + pad;
+    }
+    nd.c[0].ref = leaf_ref(0, nt);
     nodes[0] = nd;
     stat[2] = 1;
 }

@@ -75,7 +75,11 @@ struct lidar_ctx {
     float q[4] = {1, 0, 0, 0};
     // device words: [0] error flags, [1] queue counter
     DevBuf words;
-    int tile_az_log2 = 3;
+    int tile_az_log2 = 4;
+    int lanes_per_ray = 4;
+    int xcd_remap = 1;
+
+    TraceOpts opts(int tile) const { return TraceOpts{stack, tile, lanes_per_ray, xcd_remap}; }
 
     lidar_status fail(lidar_status st, const std::string &msg) {
         err = msg;
@@ -96,7 +100,7 @@ struct lidar_batch {
     uint64_t n_rays = 0, n_padded = 0;
     uint32_t packet = 256;
     int tile_az_log2 = 3;      // tile shape fixed at creation (padded ray layout depends on it)
-    int graph_stack = -1;
+    TraceOpts graph_opts{-1, -1, -1, -1};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Outputs bound{};
@@ -177,6 +181,7 @@ InstanceDev make_instance(const lidar_ctx *ctx, int tile_az_log2, const lidar_se
     in.n_ch = d.n_ch;
     in.n_az = d.n_az;
     in.tiles_az = tiles_az(tile_az_log2, d.n_az);
+    in.tiles_ch = (d.n_ch + (64u >> tile_az_log2) - 1) / (64u >> tile_az_log2);
     in.ray_base = ray_base;
     in.out_base = out_base;
     for (int k = 0; k < 4; ++k) in.q[k] = q[k];
@@ -373,6 +378,7 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     ctx->slot_of = (const uint32_t *)((const char *)ctx->S.tris + persistent_recs_bytes(nt));
     ctx->S.root = br.root;
     ctx->S.n_tri = nt;
+    ctx->S.max_steps = br.n_nodes + br.n_leaves + 1;
     ctx->has_scene = true;
     return LIDAR_OK;
 }
@@ -458,7 +464,8 @@ lidar_status lidar_pose_set(lidar_ctx *ctx, const float p[3], const float q[4]) 
 }
 
 static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_params *params,
-                                    const lidar_outputs *out, void *stream, bool brute) {
+                                    const lidar_outputs *out, void *stream, bool brute, uint32_t *n_nodes = nullptr,
+                                    uint32_t *n_tris = nullptr) {
     lidar_status st = ready(ctx, true);
     if (st != LIDAR_OK) return st;
     if (!out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "outputs struct is null");
@@ -478,7 +485,8 @@ static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan
     hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     if (brute) launch_bruteforce(ctx->S, in, ctx->M, ov, o, ctx->tile_az_log2, np, s);
-    else launch_trace_scan(ctx->stack, ctx->S, in, ctx->M, ov, o, ctx->tile_az_log2, np, (uint32_t *)ctx->words.p, s);
+    else launch_trace_scan(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, ov, o, np, (uint32_t *)ctx->words.p,
+                           n_nodes, n_tris, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "trace launch");
     return wavelength_clamped(ctx, d.wavelength_nm) && !(params && params->rho) ? LIDAR_WARN_WAVELENGTH_CLAMPED
@@ -497,6 +505,13 @@ lidar_status lidar_simulate_ex(lidar_ctx *ctx, uint64_t seed, uint32_t scan, con
 lidar_status lidar_simulate_bruteforce(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_outputs *out,
                                        void *stream) {
     return simulate_common(ctx, seed, scan, nullptr, out, stream, true);
+}
+
+lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_outputs *out,
+                                   uint32_t *node_visits, uint32_t *tri_tests, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!node_visits || !tri_tests) return ctx->fail(LIDAR_ERR_INVALID_ARG, "count arrays are null");
+    return simulate_common(ctx, seed, scan, nullptr, out, stream, false, node_visits, tri_tests);
 }
 
 // ---------------------------------------------------------------------------
@@ -574,14 +589,15 @@ lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_ou
     if (!b || b->ctx != ctx || !out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "bad batch or outputs");
     hipSetDevice(ctx->device);
     Outputs o = to_outputs(out, b->n_rays);
-    if (!b->has_graph || !same_outputs(o, b->bound) || b->graph_stack != ctx->stack) {
+    TraceOpts t = ctx->opts(b->tile_az_log2);
+    if (!b->has_graph || !same_outputs(o, b->bound) || std::memcmp(&t, &b->graph_opts, sizeof t) != 0) {
         b->drop_graph();
-        uint32_t grid = (uint32_t)(ctx->n_cu * batch_blocks_per_cu(ctx->stack));
+        uint32_t grid = (uint32_t)(ctx->n_cu * batch_blocks_per_cu(t));
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return ctx->hip_fail(e, "graph capture begin");
         uint32_t *words = (uint32_t *)ctx->words.p;
-        launch_trace_batch(ctx->stack, ctx->S, (const InstanceDev *)b->d_insts.p, b->n_inst, ctx->M, o,
-                           b->tile_az_log2, b->n_padded, b->packet, words + 1, words, grid, b->cap_stream);
+        launch_trace_batch(t, ctx->S, (const InstanceDev *)b->d_insts.p, b->n_inst, ctx->M, o, b->n_padded,
+                           b->packet, words + 1, words, grid, b->cap_stream);
         e = hipStreamEndCapture(b->cap_stream, &b->graph);
         if (e != hipSuccess) return ctx->hip_fail(e, "graph capture end");
         e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
@@ -590,7 +606,7 @@ lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_ou
             return ctx->hip_fail(e, "graph instantiate");
         }
         b->bound = o;
-        b->graph_stack = ctx->stack;
+        b->graph_opts = t;
         b->has_graph = true;
     }
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
@@ -609,8 +625,8 @@ lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *b, con
     for (uint32_t k = 0; k < b->n_inst; ++k) {
         const InstanceDev &in = b->h_insts[k];
         uint64_t np = padded_rays(b->tile_az_log2, in.n_ch, in.n_az);
-        launch_trace_scan(ctx->stack, ctx->S, in, ctx->M, ov, o, b->tile_az_log2, np, (uint32_t *)ctx->words.p,
-                          (hipStream_t)stream);
+        launch_trace_scan(ctx->opts(b->tile_az_log2), ctx->S, in, ctx->M, ov, o, np, (uint32_t *)ctx->words.p,
+                          nullptr, nullptr, (hipStream_t)stream);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "sequential launches");
@@ -778,14 +794,28 @@ lidar_status lidar_debug_copy_bvh(lidar_ctx *ctx, void *host_nodes, uint64_t nod
     return LIDAR_OK;
 }
 
-lidar_status lidar_set_tile_shape(lidar_ctx *ctx, uint32_t tile_az) {
+lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
     if (!ctx) return LIDAR_ERR_INVALID_ARG;
-    int lg = -1;
-    for (int k = 0; k <= 6; ++k)
-        if ((1u << k) == tile_az) lg = k;
-    if (lg < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "tile_az must be a power of two in 1..64");
-    ctx->tile_az_log2 = lg;
-    return LIDAR_OK;
+    switch (option) {
+    case LIDAR_OPT_TILE_AZ: {
+        int lg = -1;
+        for (int k = 0; k <= 6; ++k)
+            if ((1 << k) == value) lg = k;
+        if (lg < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "tile_az must be a power of two in 1..64");
+        ctx->tile_az_log2 = lg;
+        return LIDAR_OK;
+    }
+    case LIDAR_OPT_LANES_PER_RAY:
+        if (value != 1 && value != 4) return ctx->fail(LIDAR_ERR_INVALID_ARG, "lanes per ray must be 1 or 4");
+        ctx->lanes_per_ray = value;
+        return LIDAR_OK;
+    case LIDAR_OPT_XCD_REMAP:
+        if (value != 0 && value != 1) return ctx->fail(LIDAR_ERR_INVALID_ARG, "xcd remap must be 0 or 1");
+        ctx->xcd_remap = value;
+        return LIDAR_OK;
+    default:
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "unknown option");
+    }
 }
 
 }  // extern "C"

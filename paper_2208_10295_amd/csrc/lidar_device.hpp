@@ -3,13 +3,14 @@
 //
 // Data layouts in device memory
 // -----------------------------
-// BVH node (128 B, one per 4-wide node), structure-of-arrays inside the node so
-// that one lane reads it with 7 dwordx4 loads:
-//   float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];  uint32 child[4]; uint32 pad[4]
+// BVH node (128 B, one per 4-wide node): four 32-byte child slots
+//   { float lo[3]; uint32 ref; float hi[3]; uint32 pad; }
+// so that one lane reads a whole node with 8 dwordx4 loads, or the four lanes
+// of a quad each read their child slot with 2 dwordx4 loads (one 128 B line).
 // child reference: bit 31 clear -> index of a 4-wide node;
 //                  bit 31 set   -> leaf: first triangle record = (ref >> 3) & 0x0FFFFFFF,
 //                                  count = (ref & 7) + 1;
-//                  0xFFFFFFFF   -> empty slot (its box is inverted, never hit).
+//                  0xFFFFFFFF   -> empty slot (its box sits at 1e30, beyond any trace limit).
 // Triangle record (48 B, leaf order = Morton order):
 //   float4 a = (v0.xyz, original index bits), float4 b = (v1.xyz, label bits),
 //   float4 c = (v2.xyz, material bits).
@@ -24,10 +25,15 @@ constexpr uint32_t kEmptyRef = 0xFFFFFFFFu;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr float kBoxMullerBound = 6.6605f;   // |z| <= sqrt(64 ln 2) = 6.66043..
 
+struct __align__(16) Child4 {
+    float lo[3];
+    uint32_t ref;
+    float hi[3];
+    uint32_t pad;
+};
+
 struct __align__(16) Node4 {
-    float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
-    uint32_t child[4];
-    uint32_t pad[4];
+    Child4 c[4];
 };
 static_assert(sizeof(Node4) == 128, "node must be 128 bytes");
 
@@ -52,7 +58,7 @@ struct InstanceDev {
     const double *az_cs;       // [2*n_az]: cos theta_i, sin theta_i interleaved
     uint32_t n_ch, n_az;
     uint32_t tiles_az;         // ceil(n_az / tile_az)
-    uint32_t pad0;
+    uint32_t tiles_ch;         // ceil(n_ch / tile_ch)
     uint64_t ray_base;         // first padded ray index of this instance (batch)
     uint64_t out_base;         // output offset of beam 0
     float q[4];                // pose quaternion (w, x, y, z), unit
@@ -239,6 +245,26 @@ __device__ inline RayBox prep_box_test(const Ray &r) {
     B.ix = 1.0f / dx; B.iy = 1.0f / dy; B.iz = 1.0f / dz;
     B.nox = -r.ox * B.ix; B.noy = -r.oy * B.iy; B.noz = -r.oz * B.iz;
     return B;
+}
+
+// ---------------------------------------------------------------------------
+// Quad (4-lane) exchanges through DPP quad_perm
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ inline uint32_t quad_bcast(uint32_t v) {
+    constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+}
+template <int K>
+__device__ inline float quad_bcast(float v) {
+    return __uint_as_float(quad_bcast<K>(__float_as_uint(v)));
+}
+// value of lane (lane ^ 1) / (lane ^ 2) within the quad
+__device__ inline uint32_t quad_xor1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+}
+__device__ inline uint32_t quad_xor2(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
 }
 
 // ---------------------------------------------------------------------------

@@ -12,6 +12,7 @@ struct SceneDev {
     const TriRec *tris;
     uint32_t root;
     uint32_t n_tri;
+    uint32_t max_steps;    // bound on traversal loop iterations (nodes + leaves)
 };
 
 // --- scan / sort utilities (bvh_build.hip) ---
@@ -53,17 +54,25 @@ size_t build_persistent_bytes(uint32_t nt);
 hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, BuildResult &res, hipStream_t s);
 
 // --- trace (trace.hip) ---
+struct TraceOpts {
+    int stack;            // traversal stack entries (32, 64 or 96)
+    int tile_az_log2;     // wavefront tile: 2^tile_az_log2 azimuth steps x 64 / that channels
+    int lanes_per_ray;    // 1 (lane per ray) or 4 (quad per ray)
+    int xcd_remap;        // 1: blocks of one XCD take one contiguous azimuth sector
+};
+
 void launch_dir_tables(const double *elev_deg, uint32_t n_ch, double az0_deg, double fov_h_deg,
                        uint32_t n_az, double *elev_cs, double *az_cs, hipStream_t s);
-void launch_trace_scan(int stack, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
-                       const Overrides &ov, const Outputs &out, int tile_az_log2, uint64_t n_padded,
-                       uint32_t *err, hipStream_t s);
+// n_nodes / n_tris: optional per-beam traversal counts (null = plain kernel)
+void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                       const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err, uint32_t *n_nodes,
+                       uint32_t *n_tris, hipStream_t s);
 void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
                        const Outputs &out, int tile_az_log2, uint64_t n_padded, hipStream_t s);
-void launch_trace_batch(int stack, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
-                        const MaterialsDev &M, const Outputs &out, int tile_az_log2, uint64_t n_padded,
-                        uint32_t packet, uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s);
-int batch_blocks_per_cu(int stack);
+void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
+                        const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
+                        uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s);
+int batch_blocks_per_cu(const TraceOpts &t);
 
 // --- adjoint (adjoint.hip) ---
 constexpr int kAdjBlock = 256;

@@ -1,11 +1,22 @@
 // trace.hip -- first-hit query and return model for every beam (gfx950).
 //
-// One lane traces one beam.  Wavefronts take 64-beam tiles of tile_ch
-// channels x tile_az azimuth steps (tile_ch * tile_az = 64) so that the rays
-// of a wave are close in angle and walk similar BVH paths.  The traversal
-// stack lives in LDS, one column per lane ([depth][lane], conflict-free).  The
-// hit's attributes and the return model are evaluated in the same kernel and
-// the per-beam outputs are written once.
+// Two traversal shapes share one intersection test and one epilogue:
+//   * lane-per-ray: one lane walks the 4-wide BVH for its beam and tests the
+//     four child boxes itself;
+//   * quad-per-ray: the four lanes of a DPP quad share a beam; lane s tests
+//     child box s (one 128-byte node line per quad) or triangles s, s+4 of a
+//     leaf, and the quad agrees on the traversal order through quad_perm
+//     exchanges.  This gives 4x the wavefronts for the same beams, which a
+//     single 131k-beam scan needs to hide the latency of dependent node
+//     fetches.
+// Both visit the same nodes in the same order and return bit-identical hits.
+//
+// Beams are grouped in 64-beam tiles of tile_ch channels x tile_az azimuth
+// steps, numbered column-major (all channel rows of an azimuth column, then
+// the next column).  With the XCD remap, blockIdx b runs logical block
+// (b % 8) * (nb / 8) + b / 8, so the blocks that the hardware places on one
+// XCD (b % 8 equal) cover one contiguous azimuth sector and share that XCD's
+// L2.
 //
 // Return model, per beam (paper Sections II-A to II-D):
 //   cos(theta) = |n . d| with n the hit triangle's unit normal (II-C),
@@ -46,7 +57,7 @@ void launch_dir_tables(const double *elev_deg, uint32_t n_ch, double az0_deg, do
 }
 
 // ---------------------------------------------------------------------------
-// BVH traversal: nearest hit with ties broken by the smaller original index.
+// common pieces
 // ---------------------------------------------------------------------------
 struct Hit {
     uint32_t slot;     // triangle record index, kNone if no hit
@@ -54,77 +65,162 @@ struct Hit {
     float t;
 };
 
+struct Counts {
+    uint32_t nodes, tris;
+};
+
+__device__ inline bool better(float t, uint32_t orig, float bt, uint32_t bo) {
+    return t < bt || (t == bt && orig < bo);
+}
+
 __device__ inline void csort(float &ka, uint32_t &va, float &kb, uint32_t &vb) {
     bool sw = kb < ka;
     float tk = sw ? kb : ka; kb = sw ? ka : kb; ka = tk;
     uint32_t tv = sw ? vb : va; vb = sw ? va : vb; va = tv;
 }
 
-__device__ inline void test_leaf(const TriRec *__restrict__ tris, uint32_t ref, const RayTri &T,
-                                 float t_lo, Hit &h) {
-    uint32_t first = leaf_first(ref), cnt = leaf_count(ref);
-    for (uint32_t k = 0; k < cnt; ++k) {
-        const TriRec *r = tris + first + k;
-        float4 a = r->a, b = r->b, c = r->c;
-        float t;
-        if (tri_hit(T, a, b, c, t_lo, t)) {
-            uint32_t orig = __float_as_uint(a.w);
-            if (t < h.t || (t == h.t && orig < h.orig)) {
-                h.t = t; h.orig = orig; h.slot = first + k;
-            }
-        }
-    }
+// entry distance of the ray into a child box, +inf if missed
+__device__ inline float slab(const RayBox &B, float4 lo, float4 hi, float t_lo, float tmax_lim) {
+    float x0 = fmaf(lo.x, B.ix, B.nox), x1 = fmaf(hi.x, B.ix, B.nox);
+    float y0 = fmaf(lo.y, B.iy, B.noy), y1 = fmaf(hi.y, B.iy, B.noy);
+    float z0 = fmaf(lo.z, B.iz, B.noz), z1 = fmaf(hi.z, B.iz, B.noz);
+    float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), t_lo));
+    float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmax_lim));
+    return (tn <= tf) ? tn : __builtin_inff();
 }
 
-template <int STACK, int BLOCK>
-__device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
-                               uint32_t root, const Ray &ray, float t_lo, float t_hi,
-                               uint32_t *__restrict__ stk, bool &overflow) {
+// Orders the four children nearest first; returns whether any was hit.  The
+// caller pushes c3, c2, c1 (those hit) and descends into c0.
+__device__ inline void sort4(float &k0, uint32_t &c0, float &k1, uint32_t &c1, float &k2, uint32_t &c2, float &k3,
+                             uint32_t &c3) {
+    csort(k0, c0, k1, c1);
+    csort(k2, c2, k3, c3);
+    csort(k0, c0, k2, c2);
+    csort(k1, c1, k3, c3);
+    csort(k1, c1, k2, c2);
+}
+
+// Bound on the box exit distance: a hair above the current best hit so that
+// a box whose computed entry equals the best distance is still opened (a tie
+// with a smaller original index may be inside).
+__device__ inline float box_limit(float best_t) { return best_t * 1.0000005f; }
+
+// ---------------------------------------------------------------------------
+// lane-per-ray traversal
+// ---------------------------------------------------------------------------
+// max_steps bounds the loop: a correct traversal visits every node and leaf
+// at most once, so exceeding it means a corrupt tree (flagged, never looped).
+template <int STACK, int NSLOT, bool COUNT>
+__device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris, uint32_t root,
+                               uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
+                               uint32_t *__restrict__ stk, bool &overflow, Counts &cnt) {
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
+    const float inf = __builtin_inff();
     Hit h{kNone, kNone, t_hi};
     uint32_t ref = root;
     int sp = 0;
-    const float inf = __builtin_inff();
+    uint32_t steps = 0;
     while (true) {
+        if (++steps > max_steps) { overflow = true; break; }
         if (ref & kLeafBit) {
-            test_leaf(tris, ref, T, t_lo, h);
-        } else {
-            const float4 *np = reinterpret_cast<const float4 *>(nodes + ref);
-            float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-            uint4 ch = reinterpret_cast<const uint4 *>(np)[6];
-            float tmax_lim = h.t * 1.0000005f;
-            float k0, k1, k2, k3;
-#define LIDAR_SLAB(K, LX, HX, LY, HY, LZ, HZ)                                   \
-            {                                                                   \
-                float x0 = fmaf(LX, B.ix, B.nox), x1 = fmaf(HX, B.ix, B.nox);   \
-                float y0 = fmaf(LY, B.iy, B.noy), y1 = fmaf(HY, B.iy, B.noy);   \
-                float z0 = fmaf(LZ, B.iz, B.noz), z1 = fmaf(HZ, B.iz, B.noz);   \
-                float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), t_lo)); \
-                float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmax_lim)); \
-                K = (tn <= tf) ? tn : inf;                                      \
+            uint32_t first = leaf_first(ref), n = leaf_count(ref);
+            if (COUNT) cnt.tris += n;
+            for (uint32_t k = 0; k < n; ++k) {
+                const TriRec *r = tris + first + k;
+                float4 a = r->a, b = r->b, c = r->c;
+                float t;
+                if (tri_hit(T, a, b, c, t_lo, t)) {
+                    uint32_t orig = __float_as_uint(a.w);
+                    if (better(t, orig, h.t, h.orig)) { h.t = t; h.orig = orig; h.slot = first + k; }
+                }
             }
-            LIDAR_SLAB(k0, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x)
-            LIDAR_SLAB(k1, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y)
-            LIDAR_SLAB(k2, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z)
-            LIDAR_SLAB(k3, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w)
-#undef LIDAR_SLAB
-            uint32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
-            csort(k0, c0, k1, c1);
-            csort(k2, c2, k3, c3);
-            csort(k0, c0, k2, c2);
-            csort(k1, c1, k3, c3);
-            csort(k1, c1, k2, c2);
+        } else {
+            if (COUNT) cnt.nodes += 1;
+            const float4 *np = reinterpret_cast<const float4 *>(nodes + ref);
+            float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3], a2 = np[4], b2 = np[5], a3 = np[6], b3 = np[7];
+            float lim = box_limit(h.t);
+            float k0 = slab(B, a0, b0, t_lo, lim), k1 = slab(B, a1, b1, t_lo, lim);
+            float k2 = slab(B, a2, b2, t_lo, lim), k3 = slab(B, a3, b3, t_lo, lim);
+            uint32_t c0 = __float_as_uint(a0.w), c1 = __float_as_uint(a1.w), c2 = __float_as_uint(a2.w),
+                     c3 = __float_as_uint(a3.w);
+            sort4(k0, c0, k1, c1, k2, c2, k3, c3);
             if (k0 != inf) {
-                if (k3 != inf) { if (sp < STACK) stk[(sp++) * BLOCK] = c3; else overflow = true; }
-                if (k2 != inf) { if (sp < STACK) stk[(sp++) * BLOCK] = c2; else overflow = true; }
-                if (k1 != inf) { if (sp < STACK) stk[(sp++) * BLOCK] = c1; else overflow = true; }
+                if (k3 != inf) { if (sp < STACK) stk[(sp++) * NSLOT] = c3; else overflow = true; }
+                if (k2 != inf) { if (sp < STACK) stk[(sp++) * NSLOT] = c2; else overflow = true; }
+                if (k1 != inf) { if (sp < STACK) stk[(sp++) * NSLOT] = c1; else overflow = true; }
                 ref = c0;
                 continue;
             }
         }
         if (sp == 0) break;
-        ref = stk[(--sp) * BLOCK];
+        ref = stk[(--sp) * NSLOT];
+    }
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// quad-per-ray traversal: lane s = threadIdx.x & 3 of the quad
+// ---------------------------------------------------------------------------
+template <int STACK, int NSLOT, bool COUNT>
+__device__ inline Hit traverse_quad(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
+                                    uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
+                                    uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt) {
+    const RayBox B = prep_box_test(ray);
+    const RayTri T = prep_tri_test(ray);
+    const float inf = __builtin_inff();
+    Hit h{kNone, kNone, t_hi};
+    uint32_t ref = root;
+    int sp = 0;
+    uint32_t steps = 0;
+    while (true) {
+        if (++steps > max_steps) { overflow = true; break; }
+        if (ref & kLeafBit) {
+            uint32_t first = leaf_first(ref), n = leaf_count(ref);
+            if (COUNT) cnt.tris += n;
+            float bt = inf;
+            uint32_t bo = kNone, bs = kNone;
+            for (uint32_t k = s; k < n; k += 4) {
+                const TriRec *r = tris + first + k;
+                float4 a = r->a, b = r->b, c = r->c;
+                float t;
+                if (tri_hit(T, a, b, c, t_lo, t)) {
+                    uint32_t orig = __float_as_uint(a.w);
+                    if (better(t, orig, bt, bo)) { bt = t; bo = orig; bs = first + k; }
+                }
+            }
+            // lexicographic (t, orig) minimum over the quad
+            {
+                float ot = __uint_as_float(quad_xor1(__float_as_uint(bt)));
+                uint32_t oo = quad_xor1(bo), os = quad_xor1(bs);
+                if (better(ot, oo, bt, bo)) { bt = ot; bo = oo; bs = os; }
+                ot = __uint_as_float(quad_xor2(__float_as_uint(bt)));
+                oo = quad_xor2(bo);
+                os = quad_xor2(bs);
+                if (better(ot, oo, bt, bo)) { bt = ot; bo = oo; bs = os; }
+            }
+            if (better(bt, bo, h.t, h.orig)) { h.t = bt; h.orig = bo; h.slot = bs; }
+        } else {
+            if (COUNT) cnt.nodes += 1;
+            const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 2 * s;
+            float4 a = np[0], b = np[1];
+            float key = slab(B, a, b, t_lo, box_limit(h.t));
+            uint32_t cref = __float_as_uint(a.w);
+            float k0 = quad_bcast<0>(key), k1 = quad_bcast<1>(key), k2 = quad_bcast<2>(key),
+                  k3 = quad_bcast<3>(key);
+            uint32_t c0 = quad_bcast<0>(cref), c1 = quad_bcast<1>(cref), c2 = quad_bcast<2>(cref),
+                     c3 = quad_bcast<3>(cref);
+            sort4(k0, c0, k1, c1, k2, c2, k3, c3);
+            if (k0 != inf) {
+                if (k3 != inf) { if (sp < STACK) { if (s == 0) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
+                if (k2 != inf) { if (sp < STACK) { if (s == 0) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
+                if (k1 != inf) { if (sp < STACK) { if (s == 0) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
+                ref = c0;
+                continue;
+            }
+        }
+        if (sp == 0) break;
+        ref = stk[(--sp) * NSLOT];
     }
     return h;
 }
@@ -206,34 +302,84 @@ __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev
     }
 }
 
-// tile mapping: padded ray r of an instance -> (channel j, azimuth i)
+// tile mapping: padded ray r of an instance -> (channel j, azimuth i);
+// tiles are numbered column-major (channel rows of one azimuth column first)
 __device__ inline bool ray_coords(uint64_t r, const InstanceDev &in, int tile_az_log2, uint32_t &j, uint32_t &i) {
     uint32_t tile = (uint32_t)(r >> 6), lane = (uint32_t)(r & 63);
-    uint32_t trow = tile / in.tiles_az, tcol = tile - trow * in.tiles_az;
+    uint32_t tcol = tile / in.tiles_ch, trow = tile - tcol * in.tiles_ch;
     uint32_t tile_ch = 64u >> tile_az_log2;
     j = trow * tile_ch + (lane >> tile_az_log2);
     i = (tcol << tile_az_log2) + (lane & ((1u << tile_az_log2) - 1u));
     return j < in.n_ch && i < in.n_az;
 }
 
+// blockIdx -> logical block; see the file header for the XCD remap
+__device__ inline uint32_t logical_block(int xcd_remap) {
+    uint32_t b = blockIdx.x;
+    if (!xcd_remap) return b;
+    uint32_t full = gridDim.x & ~7u;
+    if (b >= full) return b;
+    return (b & 7u) * (full >> 3) + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
-// Kernel 1: one scan, BVH traversal
+// Kernel 1: one scan, lane per ray
 // ---------------------------------------------------------------------------
-template <int STACK, int BLOCK>
+template <int STACK, int BLOCK, bool COUNT>
 __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
                                                            Overrides ov, Outputs out, int tile_az_log2,
-                                                           uint64_t n_padded, uint32_t *err) {
+                                                           uint64_t n_padded, int xcd_remap, uint32_t *err,
+                                                           uint32_t *__restrict__ n_nodes,
+                                                           uint32_t *__restrict__ n_tris) {
     __shared__ uint32_t stk[STACK * BLOCK];
-    uint64_t r = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+    uint64_t r = (uint64_t)logical_block(xcd_remap) * BLOCK + threadIdx.x;
     if (r >= n_padded) return;
     uint32_t j, i;
     if (!ray_coords(r, in, tile_az_log2, j, i)) return;
     Pose64 P = make_pose(in, ov.pose_delta);
     Ray ray = make_ray(in, P, j, i);
     bool overflow = false;
-    Hit h = traverse<STACK, BLOCK>(S.nodes, S.tris, S.root, ray, in.t_min, in.t_trace, stk + threadIdx.x, overflow);
+    Counts c{0u, 0u};
+    Hit h = traverse<STACK, BLOCK, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + threadIdx.x,
+                                          overflow, c);
     if (overflow) atomicOr(err, 1u);
     uint32_t beam = j * in.n_az + i;
+    if (COUNT) {
+        n_nodes[beam] = c.nodes;
+        n_tris[beam] = c.tris;
+    }
+    shade_and_write(in, M, ov, out, in.out_base + beam, beam, ray, S.tris, h);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1q: one scan, quad per ray (BLOCK threads = BLOCK / 4 rays)
+// ---------------------------------------------------------------------------
+template <int STACK, int BLOCK, bool COUNT>
+__global__ __launch_bounds__(BLOCK) void trace_scan_quad_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
+                                                                Overrides ov, Outputs out, int tile_az_log2,
+                                                                uint64_t n_padded, int xcd_remap, uint32_t *err,
+                                                                uint32_t *__restrict__ n_nodes,
+                                                                uint32_t *__restrict__ n_tris) {
+    constexpr int NR = BLOCK / 4;
+    __shared__ uint32_t stk[STACK * NR];
+    const uint32_t q = threadIdx.x >> 2, s = threadIdx.x & 3u;
+    uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
+    if (r >= n_padded) return;   // whole quad
+    uint32_t j, i;
+    if (!ray_coords(r, in, tile_az_log2, j, i)) return;   // whole quad
+    Pose64 P = make_pose(in, ov.pose_delta);
+    Ray ray = make_ray(in, P, j, i);
+    bool overflow = false;
+    Counts c{0u, 0u};
+    Hit h = traverse_quad<STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q, s,
+                                            overflow, c);
+    if (overflow) atomicOr(err, 1u);
+    if (s != 0) return;
+    uint32_t beam = j * in.n_az + i;
+    if (COUNT) {
+        n_nodes[beam] = c.nodes;
+        n_tris[beam] = c.tris;
+    }
     shade_and_write(in, M, ov, out, in.out_base + beam, beam, ray, S.tris, h);
 }
 
@@ -265,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void bruteforce_kernel(SceneDev S, InstanceD
                 float t;
                 if (tri_hit(T, a, b, c, in.t_min, t)) {
                     uint32_t orig = __float_as_uint(a.w);
-                    if (t < h.t || (t == h.t && orig < h.orig)) { h.t = t; h.orig = orig; h.slot = base + k; }
+                    if (better(t, orig, h.t, h.orig)) { h.t = t; h.orig = orig; h.slot = base + k; }
                 }
             }
         }
@@ -281,36 +427,52 @@ __global__ __launch_bounds__(BLOCK) void bruteforce_kernel(SceneDev S, InstanceD
 // packet may span instances, each lane finds its instance by binary search
 // over the instances' first padded ray.
 // ---------------------------------------------------------------------------
-template <int STACK, int BLOCK>
+__device__ inline uint32_t find_instance(const InstanceDev *__restrict__ insts, uint32_t n_inst, uint64_t r) {
+    uint32_t lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (insts[mid].ray_base <= r) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int STACK, int BLOCK, bool QUAD>
 __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts,
                                                             uint32_t n_inst, MaterialsDev M, Outputs out,
                                                             int tile_az_log2, uint64_t n_padded_total,
                                                             uint32_t packet, uint32_t *queue, uint32_t *err) {
-    __shared__ uint32_t stk[STACK * BLOCK];
+    constexpr int NSLOT = QUAD ? BLOCK / 4 : BLOCK;
+    constexpr uint32_t RAYS_PER_WAVE = QUAD ? 16u : 64u;
+    __shared__ uint32_t stk[STACK * NSLOT];
     const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t slot = QUAD ? (threadIdx.x >> 2) : threadIdx.x;
+    const uint32_t sub_lane = QUAD ? (lane >> 2) : lane;
+    const uint32_t s = threadIdx.x & 3u;
     const Overrides ov{nullptr, nullptr, nullptr};
     const uint64_t n_packets = (n_padded_total + packet - 1) / packet;
     bool overflow = false;
+    Counts cnt{0u, 0u};
     while (true) {
         uint32_t pk = 0;
         if (lane == 0) pk = atomicAdd(queue, 1u);
         pk = __shfl(pk, 0, 64);
         if ((uint64_t)pk >= n_packets) break;
-        for (uint32_t sub = 0; sub < packet; sub += 64) {
-            uint64_t r = (uint64_t)pk * packet + sub + lane;
-            if (r >= n_padded_total) break;   // uniform: padded totals are multiples of 64
-            // instance containing padded ray r
-            uint32_t lo = 0, hi = n_inst;
-            while (hi - lo > 1) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (insts[mid].ray_base <= r) lo = mid; else hi = mid;
-            }
-            const InstanceDev &in = insts[lo];
+        for (uint32_t sub = 0; sub < packet; sub += RAYS_PER_WAVE) {
+            uint64_t r = (uint64_t)pk * packet + sub + sub_lane;
+            if ((uint64_t)pk * packet + sub >= n_padded_total) break;   // uniform over the wave
+            const InstanceDev &in = insts[find_instance(insts, n_inst, r)];
             uint32_t j, i;
             if (!ray_coords(r - in.ray_base, in, tile_az_log2, j, i)) continue;
             Pose64 P = make_pose(in, nullptr);
             Ray ray = make_ray(in, P, j, i);
-            Hit h = traverse<STACK, BLOCK>(S.nodes, S.tris, S.root, ray, in.t_min, in.t_trace, stk + threadIdx.x, overflow);
+            Hit h;
+            if (QUAD)
+                h = traverse_quad<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + slot,
+                                                       s, overflow, cnt);
+            else
+                h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + slot,
+                                                  overflow, cnt);
+            if (QUAD && s != 0) continue;
             uint32_t beam = j * in.n_az + i;
             shade_and_write(in, M, ov, out, in.out_base + beam, beam, ray, S.tris, h);
         }
@@ -323,21 +485,38 @@ __global__ void reset_queue_kernel(uint32_t *queue) { *queue = 0u; }
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-constexpr int kBlock = 128;
+constexpr int kBlock = 128;       // lane-per-ray block (2 waves)
+constexpr int kQuadBlock = 256;   // quad-per-ray block (4 waves, 64 rays)
 
-template <int STACK>
-static void launch_scan_t(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
-                          const Outputs &out, int tile_az_log2, uint64_t n_padded, uint32_t *err, hipStream_t s) {
-    uint64_t blocks = (n_padded + kBlock - 1) / kBlock;
-    trace_scan_kernel<STACK, kBlock><<<(uint32_t)blocks, kBlock, 0, s>>>(S, in, M, ov, out, tile_az_log2, n_padded, err);
+template <int STACK, bool COUNT>
+static void launch_scan_t(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                          const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err,
+                          uint32_t *nn, uint32_t *nt, hipStream_t s) {
+    if (t.lanes_per_ray == 4) {
+        uint32_t blocks = (uint32_t)((n_padded * 4 + kQuadBlock - 1) / kQuadBlock);
+        trace_scan_quad_kernel<STACK, kQuadBlock, COUNT><<<blocks, kQuadBlock, 0, s>>>(
+            S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt);
+    } else {
+        uint32_t blocks = (uint32_t)((n_padded + kBlock - 1) / kBlock);
+        trace_scan_kernel<STACK, kBlock, COUNT><<<blocks, kBlock, 0, s>>>(S, in, M, ov, out, t.tile_az_log2,
+                                                                          n_padded, t.xcd_remap, err, nn, nt);
+    }
 }
 
-void launch_trace_scan(int stack, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
-                       const Overrides &ov, const Outputs &out, int tile_az_log2, uint64_t n_padded,
-                       uint32_t *err, hipStream_t s) {
-    if (stack <= 32) launch_scan_t<32>(S, in, M, ov, out, tile_az_log2, n_padded, err, s);
-    else if (stack <= 64) launch_scan_t<64>(S, in, M, ov, out, tile_az_log2, n_padded, err, s);
-    else launch_scan_t<96>(S, in, M, ov, out, tile_az_log2, n_padded, err, s);
+void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                       const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err, uint32_t *n_nodes,
+                       uint32_t *n_tris, hipStream_t s) {
+    bool count = n_nodes != nullptr;
+    if (t.stack <= 32) {
+        if (count) launch_scan_t<32, true>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
+        else launch_scan_t<32, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+    } else if (t.stack <= 64) {
+        if (count) launch_scan_t<64, true>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
+        else launch_scan_t<64, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+    } else {
+        if (count) launch_scan_t<96, true>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
+        else launch_scan_t<96, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+    }
 }
 
 void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
@@ -347,28 +526,41 @@ void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const Materials
     bruteforce_kernel<B, C><<<(uint32_t)blocks, B, 0, s>>>(S, in, M, ov, out, tile_az_log2, n_padded);
 }
 
-template <int STACK>
+template <int STACK, bool QUAD>
 static void launch_batch_t(const SceneDev &S, const InstanceDev *insts, uint32_t n_inst, const MaterialsDev &M,
                            const Outputs &out, int tile_az_log2, uint64_t n_padded, uint32_t packet,
                            uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
+    constexpr int B = QUAD ? kQuadBlock : kBlock;
     reset_queue_kernel<<<1, 1, 0, s>>>(queue);
-    trace_batch_kernel<STACK, kBlock><<<grid, kBlock, 0, s>>>(S, insts, n_inst, M, out, tile_az_log2, n_padded,
-                                                              packet, queue, err);
+    trace_batch_kernel<STACK, B, QUAD><<<grid, B, 0, s>>>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet,
+                                                          queue, err);
 }
 
-void launch_trace_batch(int stack, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
-                        const MaterialsDev &M, const Outputs &out, int tile_az_log2, uint64_t n_padded,
-                        uint32_t packet, uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
-    if (stack <= 32) launch_batch_t<32>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet, queue, err, grid, s);
-    else if (stack <= 64) launch_batch_t<64>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet, queue, err, grid, s);
-    else launch_batch_t<96>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet, queue, err, grid, s);
+void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
+                        const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
+                        uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
+    bool q = t.lanes_per_ray == 4;
+    if (t.stack <= 32) {
+        if (q) launch_batch_t<32, true>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+        else launch_batch_t<32, false>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+    } else if (t.stack <= 64) {
+        if (q) launch_batch_t<64, true>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+        else launch_batch_t<64, false>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+    } else {
+        if (q) launch_batch_t<96, true>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+        else launch_batch_t<96, false>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+    }
 }
 
-int batch_blocks_per_cu(int stack) {
-    // LDS per block = stack * kBlock * 4 bytes; 160 KB per CU on gfx950
-    int lds = (stack <= 32 ? 32 : stack <= 64 ? 64 : 96) * kBlock * 4;
-    int by_lds = (160 * 1024) / lds;
-    return by_lds < 8 ? by_lds : 8;
+int batch_blocks_per_cu(const TraceOpts &t) {
+    // LDS per block = stack entries x stack slots x 4 bytes; 160 KB per CU on gfx950
+    int st = t.stack <= 32 ? 32 : t.stack <= 64 ? 64 : 96;
+    int slots = t.lanes_per_ray == 4 ? kQuadBlock / 4 : kBlock;
+    int waves = t.lanes_per_ray == 4 ? kQuadBlock / 64 : kBlock / 64;
+    int by_lds = (160 * 1024) / (st * slots * 4);
+    int by_waves = 32 / waves;          // at most 8 waves per SIMD
+    int b = by_lds < by_waves ? by_lds : by_waves;
+    return b < 1 ? 1 : b;
 }
 
 }  // namespace lidar

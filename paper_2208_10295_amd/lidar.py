@@ -173,7 +173,13 @@ class Context:
         check(lib.lidar_pose_set(self.h, pa, qa), self.h)
 
     def set_tile_shape(self, tile_az: int):
-        check(lib.lidar_set_tile_shape(self.h, int(tile_az)), self.h)
+        check(lib.lidar_set_option(self.h, A.OPT_TILE_AZ, int(tile_az)), self.h)
+
+    def set_lanes_per_ray(self, lanes: int):
+        check(lib.lidar_set_option(self.h, A.OPT_LANES_PER_RAY, int(lanes)), self.h)
+
+    def set_xcd_remap(self, on: bool):
+        check(lib.lidar_set_option(self.h, A.OPT_XCD_REMAP, 1 if on else 0), self.h)
 
     # -- simulation ---------------------------------------------------------
     def simulate(self, seed: int = 0, scan: int = 0, debug: bool = False, out: dict | None = None,
@@ -195,6 +201,16 @@ class Context:
             st = lib.lidar_simulate(self.h, seed, scan, C.byref(o), _stream(stream))
         check(st, self.h)
         return out
+
+    def simulate_counts(self, seed: int = 0, scan: int = 0, stream=None):
+        """One scan plus per-beam (node visits, triangle tests) of the traversal."""
+        out = alloc_outputs(self.n_beams, POINT_OUTPUTS, self.device)
+        nn = torch.empty(self.n_beams, dtype=torch.int32, device=self.device)
+        nt = torch.empty(self.n_beams, dtype=torch.int32, device=self.device)
+        o = outputs_struct(out)
+        check(lib.lidar_simulate_counts(self.h, seed, scan, C.byref(o), _ptr(nn), _ptr(nt), _stream(stream)),
+              self.h)
+        return out, nn, nt
 
     def sync_check(self, stream=None):
         check(lib.lidar_sync_check(self.h, _stream(stream)), self.h)

@@ -57,18 +57,22 @@ def test_config1_bvh_equals_bruteforce_and_is_deterministic(L):
         assert np.array_equal(a[k], a2[k]), k
 
 
-def test_leaf_widths_and_tile_shapes_do_not_change_results(L):
+def test_launch_shapes_do_not_change_results(L):
+    """Leaf width, tile shape, lanes per ray and the XCD remap change speed only."""
     scene, sensor, pose = S.config1()
     ref = None
     for W in (1, 2, 3, 4, 8):
         c = _ctx(L, scene, sensor, pose, leaf_width=W)
-        for tile in ((1, 8, 64) if W == 4 else (8,)):
+        shapes = [(t, l, x) for t in (1, 8, 64) for l in (1, 4) for x in (0, 1)] if W == 4 else [(8, 4, 1), (8, 1, 0)]
+        for tile, lanes, xcd in shapes:
             c.set_tile_shape(tile)
+            c.set_lanes_per_ray(lanes)
+            c.set_xcd_remap(xcd)
             g = to_np(c.simulate(SEED, 0, debug=True))
             if ref is None:
                 ref = g
             for k in ref:
-                assert np.array_equal(ref[k], g[k]), (W, tile, k)
+                assert np.array_equal(ref[k], g[k]), (W, tile, lanes, xcd, k)
 
 
 def test_config2_full_scan_sampled_oracle(L):
@@ -91,10 +95,12 @@ def test_config2_full_scan_sampled_oracle(L):
 def test_config2_bvh_equals_bruteforce_full(L):
     scene, sensor, pose = S.config2()
     c = _ctx(L, scene, sensor, pose)
-    a = to_np(c.simulate(SEED, 0, debug=True))
     b = to_np(c.simulate(SEED, 0, debug=True, bruteforce=True))
-    for k in a:
-        assert np.array_equal(a[k], b[k]), k
+    for lanes in (1, 4):
+        c.set_lanes_per_ray(lanes)
+        a = to_np(c.simulate(SEED, 0, debug=True))
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (lanes, k)
 
 
 def test_ragged_sensor_and_offsets(L):
@@ -106,11 +112,13 @@ def test_ragged_sensor_and_offsets(L):
     sensor = S.Sensor(np.array([-14.0, -9.5, -3.0, 0.5, 7.0]), 37, az0_deg=10.0, fov_h_deg=200.0, d_max=80.0)
     pose = S.Pose((np.array([0.0, 0.0, 1.5]) + off).astype(np.float32), S.quat_from_ypr(0.3, 0.02, -0.01))
     c = _ctx(L, sc2, sensor, pose)
+    o = O.simulate(sc2, sensor, pose, seed=99, scan=5)
     for tile in (1, 4, 64):
-        c.set_tile_shape(tile)
-        g = to_np(c.simulate(99, 5, debug=True))
-        o = O.simulate(sc2, sensor, pose, seed=99, scan=5)
-        _report(f"ragged tile {tile}", compare(g, o))
+        for lanes in (1, 4):
+            c.set_tile_shape(tile)
+            c.set_lanes_per_ray(lanes)
+            g = to_np(c.simulate(99, 5, debug=True))
+            _report(f"ragged tile {tile} lanes {lanes}", compare(g, o))
 
 
 def test_single_triangle_scene(L):
