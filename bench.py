@@ -188,12 +188,15 @@ def main():
         nr = batch.n_rays
         bout = alloc_outputs(nr, POINT_OUTPUTS, ctx.device)
         log(f"batch: {len(insts)} instances, {nr} rays; tuning ...")
-        tune = batch.tune(packet_rays=(64, 128, 256, 512), leaf_widths=(2, 4, 8), reps=5, out=bout)
+        tune = batch.tune(packet_rays=(64, 256, 1024), leaf_widths=(2, 4, 8), lanes_per_ray=(1, 4), reps=5,
+                          out=bout)
         for _ in range(2):
             batch.simulate(bout)
         ctx.sync_check()
         reps = 10
         wall_b, ms_b = timed_launches(lambda k: batch.simulate(bout), reps, torch)
+        # the sequential baseline runs each instance as a plain scan with the plain-scan launch shape
+        ctx.set_lanes_per_ray(args.lanes)
         for _ in range(1):
             batch.simulate(bout, sequential=True)
         wall_s, ms_s = timed_launches(lambda k: batch.simulate(bout, sequential=True), 3, torch)
@@ -204,14 +207,18 @@ def main():
             "rays": nr, "batched_rays_per_s": nr / (float(np.median(ms_b)) * 1e-3),
             "sequential_rays_per_s": nr / (float(np.median(ms_s)) * 1e-3),
             "batched_ms": float(np.median(ms_b)), "sequential_ms": float(np.median(ms_s)),
+            "sequential_lanes_per_ray": args.lanes,
             "tuned_packet_rays": tune["best_packet_rays"], "tuned_leaf_width": tune["best_leaf_width"],
-            "tune_ms_grid": tune["ms"].round(4).tolist(), "tune_packets": [int(x) for x in tune["packet_rays"]],
-            "tune_leaf_widths": [int(x) for x in tune["leaf_widths"]]}
+            "tuned_lanes_per_ray": tune["best_lanes_per_ray"],
+            "tune_ms_grid_leaf_lanes_packet": tune["ms"].round(4).tolist(),
+            "tune_packets": [int(x) for x in tune["packet_rays"]],
+            "tune_leaf_widths": [int(x) for x in tune["leaf_widths"]],
+            "tune_lanes_per_ray": [int(x) for x in tune["lanes_per_ray"]]}
         result["batched"]["speedup_vs_sequential"] = (result["batched"]["batched_rays_per_s"]
                                                       / result["batched"]["sequential_rays_per_s"])
         log(f"batched {result['batched']['batched_rays_per_s']:.4g} rays/s vs sequential "
             f"{result['batched']['sequential_rays_per_s']:.4g} rays/s (tuned W={tune['best_leaf_width']}, "
-            f"P={tune['best_packet_rays']})")
+            f"P={tune['best_packet_rays']}, lanes={tune['best_lanes_per_ray']})")
         del batch, bout
 
     if "adjoint" in legs:

@@ -293,20 +293,24 @@ typedef struct {
     uint32_t n_packet;
     const uint32_t *leaf_widths;   /* host [n_leaf] candidates (1..8) */
     uint32_t n_leaf;
+    const uint32_t *lanes_per_ray; /* host [n_lanes] candidates (1 or 4); NULL = current only */
+    uint32_t n_lanes;
     uint32_t reps;                 /* timed repetitions per candidate (median) */
 } lidar_tune_desc;
 
 typedef struct {
     uint32_t best_packet_rays;
     uint32_t best_leaf_width;
+    uint32_t best_lanes_per_ray;
     float best_ms;
-    float ms[64];                  /* [n_leaf][n_packet] medians, row-major (<= 64 entries) */
+    float ms[64];                  /* [n_leaf][n_lanes][n_packet] medians, row-major (<= 64 entries) */
 } lidar_tune_result;
 
-/* Times lidar_simulate_batch for every (leaf width, packet size) candidate on
- * the batch, rebuilding the BVH per leaf width from `scene` into the given
- * buffers, then leaves the scene built with the best leaf width and the batch
- * set to the best packet size.  Synchronous. */
+/* Times lidar_simulate_batch for every (leaf width, lanes per ray, packet
+ * size) candidate on the batch, rebuilding the BVH per leaf width from
+ * `scene` into the given buffers, then leaves the scene built with the best
+ * leaf width, the context set to the best lanes per ray and the batch to the
+ * best packet size.  Results never depend on the choice.  Synchronous. */
 lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *persistent,
                         uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes,
                         lidar_batch *batch, const lidar_outputs *out, const lidar_tune_desc *desc,

@@ -11,8 +11,11 @@
 //   dL/dw_left += gamma (d x n),  gamma = g_I rho k |c|^(k-1) sgn(c) - g_t t / c
 // where w_left perturbs the rotation as R <- Exp(w) R.  The pose delta's
 // rotation gradient is J_l(dw)^T dL/dw_left (left Jacobian of Exp at dw).
-// Per-beam terms are FP32; every output is reduced in FP64 with a fixed tree
-// inside each block and a fixed sequential order across blocks.
+// Per-beam terms are FP32; every output is reduced in FP64 in a fixed order:
+// inside a wavefront, the beams of each material present (grouped by ballot)
+// are summed by a butterfly over the 64 lanes; the four wavefronts of a block
+// are added in order; the blocks' partial sums are added by one block per
+// output with a fixed stride pattern and tree.  Results are bit-reproducible.
 #include "lidar_kernels.hpp"
 
 namespace lidar {
@@ -30,15 +33,17 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(SceneDev S, const ui
                                                            const float *__restrict__ gI_in,
                                                            const float *__restrict__ gd_in,
                                                            double *__restrict__ partials) {
-    __shared__ double red[kAdjBlock / 64][2 * 256 + 6];
+    constexpr int NW = kAdjBlock / 64;
+    __shared__ double acc[NW][2 * 256 + 6];
     const uint32_t nmat = M.nmat;
     const uint32_t n_out = 2 * nmat + 6;
     const uint32_t nb = in.n_ch * in.n_az;
     const uint32_t b = blockIdx.x * kAdjBlock + threadIdx.x;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t o = lane; o < n_out; o += 64) acc[w][o] = 0.0;
 
     float a_rho = 0.f, a_k = 0.f, a_p[3] = {0.f, 0.f, 0.f}, a_w[3] = {0.f, 0.f, 0.f};
-    uint32_t m = 0xFFFFFFFFu;
+    uint32_t m = kNone;
     if (b < nb && valid[b] && tri[b] != kNone) {
         uint32_t j = b / in.n_az, i = b - j * in.n_az;
         Pose64 P = make_pose(in, ov.pose_delta);
@@ -73,7 +78,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(SceneDev S, const ui
         }
         float k = ov.angle_exp ? ov.angle_exp[m] : M.angle_exp[m];
         float lnc = logf(ac);
-        float ck = (k == 1.0f) ? ac : expf(k * lnc);           // |c|^k
+        float ck = (k == 1.0f) ? ac : expf(k * lnc);              // |c|^k
         float ck1 = (k == 1.0f) ? 1.0f : expf((k - 1.0f) * lnc);  // |c|^(k-1)
         float gI = gI_in ? gI_in[b] : 0.0f;
         float gt = gd_in ? gd_in[b] : 0.0f;
@@ -83,40 +88,61 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(SceneDev S, const ui
         a_p[0] = ginv * nx; a_p[1] = ginv * ny; a_p[2] = ginv * nz;
         float gamma = gI * rho * k * ck1 * copysignf(1.0f, c) - gt * t / c;
         // d x n
-        float dxn0 = fmaf(ray.dy, nz, -ray.dz * ny);
-        float dxn1 = fmaf(ray.dz, nx, -ray.dx * nz);
-        float dxn2 = fmaf(ray.dx, ny, -ray.dy * nx);
-        a_w[0] = gamma * dxn0; a_w[1] = gamma * dxn1; a_w[2] = gamma * dxn2;
+        a_w[0] = gamma * fmaf(ray.dy, nz, -ray.dz * ny);
+        a_w[1] = gamma * fmaf(ray.dz, nx, -ray.dx * nz);
+        a_w[2] = gamma * fmaf(ray.dx, ny, -ray.dy * nx);
     }
-    // fixed-order block reduction of every output
-    for (uint32_t o = 0; o < n_out; ++o) {
-        double v;
-        if (o < nmat) v = (m == o) ? (double)a_rho : 0.0;
-        else if (o < 2 * nmat) v = (m == o - nmat) ? (double)a_k : 0.0;
-        else if (o < 2 * nmat + 3) v = (m != 0xFFFFFFFFu) ? (double)a_p[o - 2 * nmat] : 0.0;
-        else v = (m != 0xFFFFFFFFu) ? (double)a_w[o - 2 * nmat - 3] : 0.0;
-        v = wave_sum(v);
-        if (lane == 0) red[w][o] = v;
+    __syncthreads();
+    // per-material sums over the lanes of this wavefront, one material at a time
+    uint64_t todo = __ballot(m != kNone);
+    while (todo) {
+        int leader = __ffsll((unsigned long long)todo) - 1;
+        uint32_t mm = __shfl(m, leader, 64);
+        bool mine = (m == mm);
+        uint64_t grp = __ballot(mine);
+        double vr = wave_sum(mine ? (double)a_rho : 0.0);
+        double vk = wave_sum(mine ? (double)a_k : 0.0);
+        if (lane == 0) {
+            acc[w][mm] = vr;
+            acc[w][nmat + mm] = vk;
+        }
+        todo &= ~grp;
+    }
+    for (int q = 0; q < 3; ++q) {
+        double vp = wave_sum((double)a_p[q]);
+        double vw = wave_sum((double)a_w[q]);
+        if (lane == 0) {
+            acc[w][2 * nmat + q] = vp;
+            acc[w][2 * nmat + 3 + q] = vw;
+        }
     }
     __syncthreads();
     for (uint32_t o = threadIdx.x; o < n_out; o += kAdjBlock) {
         double s = 0.0;
-        for (int q = 0; q < kAdjBlock / 64; ++q) s += red[q][o];
+        for (int q = 0; q < NW; ++q) s += acc[q][o];
         partials[(size_t)blockIdx.x * n_out + o] = s;
     }
 }
 
-__global__ __launch_bounds__(256) void adjoint_final_kernel(const double *__restrict__ partials, uint32_t nblocks,
-                                                            uint32_t nmat, const float *__restrict__ pose_delta,
-                                                            float *d_rho, float *d_k, float *d_pose6) {
-    __shared__ double tot[2 * 256 + 6];
-    const uint32_t n_out = 2 * nmat + 6;
-    for (uint32_t o = threadIdx.x; o < n_out; o += blockDim.x) {
-        double s = 0.0;
-        for (uint32_t q = 0; q < nblocks; ++q) s += partials[(size_t)q * n_out + o];
-        tot[o] = s;
-    }
+// one block per output: fixed-stride partial sums, then a fixed tree
+__global__ __launch_bounds__(256) void adjoint_sum_kernel(const double *__restrict__ partials, uint32_t nblocks,
+                                                          uint32_t n_out, double *__restrict__ tot) {
+    __shared__ double red[256];
+    const uint32_t o = blockIdx.x;
+    double s = 0.0;
+    for (uint32_t q = threadIdx.x; q < nblocks; q += 256) s += partials[(size_t)q * n_out + o];
+    red[threadIdx.x] = s;
     __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[o] = red[0];
+}
+
+__global__ __launch_bounds__(64) void adjoint_final_kernel(const double *__restrict__ tot, uint32_t nmat,
+                                                           const float *__restrict__ pose_delta, float *d_rho,
+                                                           float *d_k, float *d_pose6) {
     for (uint32_t o = threadIdx.x; o < nmat; o += blockDim.x) {
         if (d_rho) d_rho[o] = (float)tot[o];
         if (d_k) d_k[o] = (float)tot[nmat + o];
@@ -146,7 +172,7 @@ __global__ __launch_bounds__(256) void adjoint_final_kernel(const double *__rest
 
 size_t adjoint_partial_bytes(uint32_t n_beams, uint32_t nmat) {
     size_t nb = (n_beams + kAdjBlock - 1) / kAdjBlock;
-    return nb * (2 * (size_t)nmat + 6) * sizeof(double);
+    return (nb + 1) * (2 * (size_t)nmat + 6) * sizeof(double);
 }
 
 void launch_adjoint(const SceneDev &S, const uint32_t *slot_of, const InstanceDev &in, const MaterialsDev &M,
@@ -154,8 +180,11 @@ void launch_adjoint(const SceneDev &S, const uint32_t *slot_of, const InstanceDe
                     const float *gd, double *partials, float *d_rho, float *d_k, float *d_pose6, hipStream_t s) {
     uint32_t nb = in.n_ch * in.n_az;
     uint32_t blocks = (nb + kAdjBlock - 1) / kAdjBlock;
+    uint32_t n_out = 2 * M.nmat + 6;
+    double *tot = partials + (size_t)blocks * n_out;
     adjoint_kernel<<<blocks, kAdjBlock, 0, s>>>(S, slot_of, in, M, ov, tri, valid, gI, gd, partials);
-    adjoint_final_kernel<<<1, 256, 0, s>>>(partials, blocks, M.nmat, ov.pose_delta, d_rho, d_k, d_pose6);
+    adjoint_sum_kernel<<<n_out, 256, 0, s>>>(partials, blocks, n_out, tot);
+    adjoint_final_kernel<<<1, 64, 0, s>>>(tot, M.nmat, ov.pose_delta, d_rho, d_k, d_pose6);
 }
 
 }  // namespace lidar

@@ -650,15 +650,20 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
                         const lidar_tune_desc *desc, lidar_tune_result *res, void *stream) {
     if (!ctx) return LIDAR_ERR_INVALID_ARG;
     if (!scene || !b || !out || !desc || !res) return ctx->fail(LIDAR_ERR_INVALID_ARG, "null argument");
-    if (!desc->packet_rays || !desc->leaf_widths || desc->n_packet == 0 || desc->n_leaf == 0 ||
-        desc->n_packet * desc->n_leaf > 64)
-        return ctx->fail(LIDAR_ERR_INVALID_ARG, "need 1..64 candidate pairs");
+    uint32_t cur_lanes = (uint32_t)ctx->lanes_per_ray;
+    const uint32_t *lanes = desc->lanes_per_ray ? desc->lanes_per_ray : &cur_lanes;
+    uint32_t n_lanes = desc->lanes_per_ray ? desc->n_lanes : 1;
+    if (!desc->packet_rays || !desc->leaf_widths || desc->n_packet == 0 || desc->n_leaf == 0 || n_lanes == 0 ||
+        desc->n_packet * desc->n_leaf * n_lanes > 64)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "need 1..64 candidate combinations");
     for (uint32_t i = 0; i < desc->n_packet; ++i)
         if (desc->packet_rays[i] == 0 || desc->packet_rays[i] % 64 != 0 || desc->packet_rays[i] > 65536)
             return ctx->fail(LIDAR_ERR_INVALID_ARG, "packet sizes must be multiples of 64");
     for (uint32_t i = 0; i < desc->n_leaf; ++i)
         if (desc->leaf_widths[i] < 1 || desc->leaf_widths[i] > 8)
             return ctx->fail(LIDAR_ERR_INVALID_ARG, "leaf widths must be in 1..8");
+    for (uint32_t i = 0; i < n_lanes; ++i)
+        if (lanes[i] != 1 && lanes[i] != 4) return ctx->fail(LIDAR_ERR_INVALID_ARG, "lanes per ray must be 1 or 4");
     uint32_t reps = desc->reps ? desc->reps : 5;
     hipStream_t s = (hipStream_t)stream;
     std::memset(res, 0, sizeof *res);
@@ -667,47 +672,45 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     lidar_scene_desc sd = *scene;
-    for (uint32_t li = 0; li < desc->n_leaf; ++li) {
+    lidar_status st = LIDAR_OK;
+    for (uint32_t li = 0; li < desc->n_leaf && st == LIDAR_OK; ++li) {
         sd.leaf_width = desc->leaf_widths[li];
-        lidar_status st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
-        if (st != LIDAR_OK) {
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
-            return st;
-        }
-        for (uint32_t pi = 0; pi < desc->n_packet; ++pi) {
-            b->packet = desc->packet_rays[pi];
-            b->drop_graph();
-            std::vector<float> t;
-            for (uint32_t r = 0; r < reps + 1; ++r) {
-                hipEventRecord(e0, s);
-                st = lidar_simulate_batch(ctx, b, out, stream);
-                hipEventRecord(e1, s);
-                hipEventSynchronize(e1);
-                if (st != LIDAR_OK) {
-                    hipEventDestroy(e0);
-                    hipEventDestroy(e1);
-                    return st;
+        st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
+        for (uint32_t ni = 0; ni < n_lanes && st == LIDAR_OK; ++ni) {
+            ctx->lanes_per_ray = (int)lanes[ni];
+            for (uint32_t pi = 0; pi < desc->n_packet && st == LIDAR_OK; ++pi) {
+                b->packet = desc->packet_rays[pi];
+                b->drop_graph();
+                std::vector<float> t;
+                for (uint32_t r = 0; r < reps + 1 && st == LIDAR_OK; ++r) {
+                    hipEventRecord(e0, s);
+                    st = lidar_simulate_batch(ctx, b, out, stream);
+                    hipEventRecord(e1, s);
+                    hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (r > 0) t.push_back(ms);   // the first run includes the graph capture
                 }
-                float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
-                if (r > 0) t.push_back(ms);   // first run includes graph capture
-            }
-            std::sort(t.begin(), t.end());
-            float med = t[t.size() / 2];
-            res->ms[li * desc->n_packet + pi] = med;
-            if (med < res->best_ms) {
-                res->best_ms = med;
-                res->best_packet_rays = desc->packet_rays[pi];
-                res->best_leaf_width = desc->leaf_widths[li];
+                if (st != LIDAR_OK) break;
+                std::sort(t.begin(), t.end());
+                float med = t[t.size() / 2];
+                res->ms[(li * n_lanes + ni) * desc->n_packet + pi] = med;
+                if (med < res->best_ms) {
+                    res->best_ms = med;
+                    res->best_packet_rays = desc->packet_rays[pi];
+                    res->best_leaf_width = desc->leaf_widths[li];
+                    res->best_lanes_per_ray = lanes[ni];
+                }
             }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    sd.leaf_width = res->best_leaf_width;
-    lidar_status st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
     if (st != LIDAR_OK) return st;
+    sd.leaf_width = res->best_leaf_width;
+    st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
+    if (st != LIDAR_OK) return st;
+    ctx->lanes_per_ray = (int)res->best_lanes_per_ray;
     b->packet = res->best_packet_rays;
     b->drop_graph();
     return LIDAR_OK;

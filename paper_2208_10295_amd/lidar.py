@@ -275,14 +275,16 @@ class Batch:
         check(fn(self.ctx.h, self.h, C.byref(o), _stream(stream)), self.ctx.h)
         return out
 
-    def tune(self, packet_rays=(64, 128, 256, 512), leaf_widths=(2, 4, 8), reps=5, out=None, stream=None):
+    def tune(self, packet_rays=(64, 128, 256, 512), leaf_widths=(2, 4, 8), lanes_per_ray=(1, 4), reps=5, out=None,
+             stream=None):
         ctx = self.ctx
         if out is None:
             out = alloc_outputs(self.n_rays, POINT_OUTPUTS, ctx.device)
         o = outputs_struct(out)
         pk = np.ascontiguousarray(packet_rays, np.uint32)
         lw = np.ascontiguousarray(leaf_widths, np.uint32)
-        d = A.TuneDesc(pk.ctypes.data, len(pk), lw.ctypes.data, len(lw), int(reps))
+        ln = np.ascontiguousarray(lanes_per_ray, np.uint32)
+        d = A.TuneDesc(pk.ctypes.data, len(pk), lw.ctypes.data, len(lw), ln.ctypes.data, len(ln), int(reps))
         r = A.TuneResult()
         sd = ctx.scene_desc
         pb, sb = C.c_uint64(), C.c_uint64()
@@ -290,9 +292,10 @@ class Batch:
         scratch = torch.empty(sb.value, dtype=torch.uint8, device=ctx.device)
         check(lib.lidar_tune(ctx.h, C.byref(sd), _ptr(ctx.persistent), ctx.persistent.numel(), _ptr(scratch),
                              sb.value, self.h, C.byref(o), C.byref(d), C.byref(r), _stream(stream)), ctx.h)
-        grid = np.array(r.ms[:len(pk) * len(lw)], np.float64).reshape(len(lw), len(pk))
-        return dict(best_packet_rays=r.best_packet_rays, best_leaf_width=r.best_leaf_width, best_ms=r.best_ms,
-                    ms=grid, packet_rays=list(pk), leaf_widths=list(lw))
+        grid = np.array(r.ms[:len(pk) * len(lw) * len(ln)], np.float64).reshape(len(lw), len(ln), len(pk))
+        return dict(best_packet_rays=r.best_packet_rays, best_leaf_width=r.best_leaf_width,
+                    best_lanes_per_ray=r.best_lanes_per_ray, best_ms=r.best_ms, ms=grid, packet_rays=list(pk),
+                    leaf_widths=list(lw), lanes_per_ray=list(ln))
 
     def close(self):
         if getattr(self, "h", None):

@@ -33,15 +33,33 @@ def test_every_declared_symbol_is_exported_and_bound(A):
     assert set(A.SIGNATURES) == set(names)
 
 
-def test_struct_layouts_match_header(A):
-    # sizes follow from the field lists in include/lidar.h on x86-64
-    assert C.sizeof(A.SceneDesc) == 8 + 8 + 4 * 8 + 4 + 4
-    assert C.sizeof(A.MaterialDesc) == 4 * 4 + 3 * 8
-    assert C.sizeof(A.SensorDesc) == 8 + 8 + 8 + 8 + 8 + 6 * 4
-    assert C.sizeof(A.Outputs) == 12 * 8
-    assert C.sizeof(A.Params) == 3 * 8
-    assert C.sizeof(A.TuneResult) == 12 + 64 * 4
-    assert C.sizeof(A.Stats) == 3 * 8 + 4 * 4 + 2 * 8 + 2 * 4
+STRUCTS = {"SceneDesc": "lidar_scene_desc", "MaterialDesc": "lidar_material_desc", "SensorDesc": "lidar_sensor_desc",
+           "Outputs": "lidar_outputs", "Params": "lidar_params", "Instance": "lidar_instance",
+           "TuneDesc": "lidar_tune_desc", "TuneResult": "lidar_tune_result", "Stats": "lidar_stats"}
+
+
+def test_struct_layouts_match_header(A, tmp_path):
+    """Size and every field offset of the ctypes mirror equal what a C compiler sees in include/lidar.h."""
+    import subprocess
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lidar.h"', "int main(void) {"]
+    for py, cname in STRUCTS.items():
+        lines.append(f'printf("{py} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(A, py)._fields_:
+            lines.append(f'printf("{py} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        struct, field, val = line.split()
+        got[(struct, field)] = int(val)
+    for py in STRUCTS:
+        cls = getattr(A, py)
+        assert got[(py, "size")] == C.sizeof(cls), py
+        for fname, _ in cls._fields_:
+            assert got[(py, fname)] == getattr(cls, fname).offset, (py, fname)
 
 
 def test_scene_bytes_host_only(A):
