@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sequence or 'all'")
     ap.add_argument("--leaf-width", type=int, default=4)
+    ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
     ap.add_argument("--tile-az", type=int, default=16)
     ap.add_argument("--lanes", type=int, default=4, help="lanes per ray (1 or 4)")
     ap.add_argument("--xcd", type=int, default=1, help="XCD-aware block remap (0 or 1)")
@@ -125,7 +126,7 @@ def main():
     scene, sensor, pose = S.config2()
     log(f"config2: {scene.n_tri} triangles, {sensor.n_beams} beams")
     ctx = L.Context(0)
-    st = ctx.load(scene, args.leaf_width)
+    st = ctx.load(scene, args.leaf_width, builder=args.builder)
     ctx.set_sensor(sensor)
     ctx.set_pose(pose.p, pose.q)
     ctx.set_tile_shape(args.tile_az)
@@ -139,7 +140,7 @@ def main():
                                     "steps = 131,072 beams, procedural urban scene of 522,272 triangles "
                                     "(256x256 terrain cells, 400 buildings, 2,000 poles, 200 cars), 32 materials, "
                                     "905 nm, d_max 100 m, range noise 0.02 m",
-                        "beams": n, "triangles": scene.n_tri, "leaf_width": st["leaf_width"],
+                        "beams": n, "triangles": scene.n_tri, "leaf_width": st["leaf_width"], "bvh_builder": args.builder,
                         "tile_az": args.tile_az, "lanes_per_ray": args.lanes, "xcd_remap": args.xcd,
                         "bvh_nodes": st["n_nodes"], "bvh_depth": st["depth"]}
     result["bvh_build_ms"] = st["build_ms"]

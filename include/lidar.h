@@ -87,6 +87,7 @@ const char *lidar_last_error(const lidar_ctx *ctx);
 /* ------------------------------------------------------------------------ */
 
 #define LIDAR_SCENE_DEVICE_PTRS 1u   /* the four arrays below are device pointers */
+#define LIDAR_SCENE_BUILD_LBVH  2u   /* build the binary tree as an LBVH instead of by PLOC clustering */
 
 typedef struct {
     uint64_t n_vertices;
@@ -97,7 +98,7 @@ typedef struct {
     const uint32_t *label;     /* [n_triangles] instance label (the paper's per-object
                                   ground-truth id, Section II-B) */
     uint32_t leaf_width;       /* max triangles per BVH leaf, 1..8 (0 = 4) */
-    uint32_t flags;            /* LIDAR_SCENE_DEVICE_PTRS or 0 (host pointers) */
+    uint32_t flags;            /* LIDAR_SCENE_DEVICE_PTRS (else host pointers) | LIDAR_SCENE_BUILD_LBVH */
 } lidar_scene_desc;
 
 /* Sizes of the two caller-owned device buffers that lidar_scene_load needs:
@@ -107,9 +108,11 @@ typedef struct {
 lidar_status lidar_scene_bytes(const lidar_scene_desc *desc, uint64_t *persistent_bytes,
                                uint64_t *scratch_bytes);
 
-/* Builds the BVH on the GPU (Morton codes, radix sort, binary radix tree,
- * bounding-box refit, collapse to a 4-wide BVH with leaves of at most
- * leaf_width triangles) into `persistent`, replacing any previous scene.
+/* Builds the BVH on the GPU into `persistent`, replacing any previous scene:
+ * Morton codes and a radix sort, then a binary tree by PLOC clustering
+ * (default) or as an LBVH, then a collapse to a 4-wide BVH with leaves of at
+ * most leaf_width triangles.  Every build option gives the same simulation
+ * results (only the speed differs).
  * Validates every triangle index on the device.  Synchronises `stream` (it
  * reads back the tree size and depth).  Errors: INVALID_ARG (bad sizes,
  * index out of range), WORKSPACE_TOO_SMALL, STACK_OVERFLOW (tree deeper than

@@ -30,6 +30,7 @@ NO_LABEL = 0xFFFFFFFF
 NO_TRIANGLE = 0xFFFFFFFF
 NO_MATERIAL = 0xFFFF
 SCENE_DEVICE_PTRS = 1
+SCENE_BUILD_LBVH = 2
 OPT_TILE_AZ = 1
 OPT_LANES_PER_RAY = 2
 OPT_XCD_REMAP = 3

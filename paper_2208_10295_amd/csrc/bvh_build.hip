@@ -4,10 +4,19 @@
 // 2. 63-bit Morton code of the centroid (21 bits per axis) -> stable LSD radix
 //    sort of (code, triangle) pairs, 8 passes of 8 bits
 // 3. triangle records written in sorted order (leaves are contiguous ranges)
-// 4. binary radix tree over the sorted codes (Karras, HPG 2012), identical
-//    codes split by position
-// 5. bottom-up bounding-box refit; the second child to arrive at a node
-//    computes its box
+// 4. binary tree, either
+//    (a) PLOC (default; Meister and Bittner, "Parallel Locally-Ordered
+//        Clustering for Bounding Volume Hierarchy Construction", TVCG 2018):
+//        clusters in Morton order repeatedly find their nearest neighbour
+//        (smallest merged surface area) within +-16 positions; mutual nearest
+//        pairs merge into a new node; the survivors are compacted in order.
+//        Boxes are formed during the merges.  The leaves are then renumbered
+//        depth-first so that every subtree covers a contiguous range of
+//        triangle records; or
+//    (b) LBVH: binary radix tree over the sorted codes (Karras, HPG 2012),
+//        identical codes split by position, then a bottom-up bounding-box
+//        refit where the second child to arrive at a node computes its box
+// 5. (nothing: both trees have their boxes)
 // 6. level-synchronous collapse to 4 children: starting from the node's two
 //    children, the child with the largest surface area that holds more than
 //    leaf_width triangles is replaced by its two children until there are 4;
@@ -17,6 +26,8 @@
 // Child boxes are padded outward by 2^-20 of the largest vertex coordinate,
 // which exceeds the rounding error of the FP32 box and triangle tests for rays
 // starting inside the scene's extent.
+#include <vector>
+
 #include "lidar_kernels.hpp"
 
 namespace lidar {
@@ -533,12 +544,154 @@ __global__ void single_leaf_root_kernel(const TriRec *__restrict__ recs, uint32_
 }
 
 // ---------------------------------------------------------------------------
+// PLOC
+// ---------------------------------------------------------------------------
+constexpr int kPlocR = 16;       // search radius in Morton order
+constexpr int kPlocBlock = 256;
+
+__device__ inline float half_area(float lx, float ly, float lz, float hx, float hy, float hz) {
+    float ex = hx - lx, ey = hy - ly, ez = hz - lz;
+    return ex * ey + ey * ez + ez * ex;
+}
+
+// node ids: leaves 0..n-1 (Morton positions), internal nodes n..2n-2 in creation order
+__global__ __launch_bounds__(256) void ploc_init_kernel(const TriRec *__restrict__ recs, uint32_t n,
+                                                        float *__restrict__ nbox, uint32_t *__restrict__ ncount,
+                                                        uint32_t *__restrict__ C) {
+    uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    float lo[3], hi[3];
+    rec_box(recs, s, lo, hi);
+    float *b = nbox + 6 * (size_t)s;
+    for (int a = 0; a < 3; ++a) { b[a] = lo[a]; b[3 + a] = hi[a]; }
+    ncount[s] = 1;
+    C[s] = s;
+}
+
+__global__ __launch_bounds__(kPlocBlock) void ploc_nn_kernel(const uint32_t *__restrict__ C, uint32_t m,
+                                                             const float *__restrict__ nbox, uint32_t *__restrict__ nn) {
+    __shared__ float sb[(kPlocBlock + 2 * kPlocR) * 6];
+    const int base = (int)(blockIdx.x * kPlocBlock);
+    const int lo_i = base - kPlocR;
+    for (int k = threadIdx.x; k < kPlocBlock + 2 * kPlocR; k += kPlocBlock) {
+        int idx = lo_i + k;
+        if (idx >= 0 && idx < (int)m) {
+            const float *b = nbox + 6 * (size_t)C[idx];
+            for (int a = 0; a < 6; ++a) sb[k * 6 + a] = b[a];
+        }
+    }
+    __syncthreads();
+    const int i = base + (int)threadIdx.x;
+    if (i >= (int)m) return;
+    const int li = i - lo_i;
+    const float lx = sb[li * 6 + 0], ly = sb[li * 6 + 1], lz = sb[li * 6 + 2];
+    const float hx = sb[li * 6 + 3], hy = sb[li * 6 + 4], hz = sb[li * 6 + 5];
+    float best = __builtin_inff();
+    int bj = i == 0 ? 1 : i - 1;
+    for (int d = -kPlocR; d <= kPlocR; ++d) {
+        int j = i + d;
+        if (d == 0 || j < 0 || j >= (int)m) continue;
+        const float *o = sb + (li + d) * 6;
+        float a = half_area(fminf(lx, o[0]), fminf(ly, o[1]), fminf(lz, o[2]), fmaxf(hx, o[3]), fmaxf(hy, o[4]),
+                            fmaxf(hz, o[5]));
+        if (a < best) { best = a; bj = j; }    // ties keep the smaller j (ascending scan)
+    }
+    nn[i] = (uint32_t)bj;
+}
+
+__global__ __launch_bounds__(256) void ploc_flags_kernel(const uint32_t *__restrict__ nn, uint32_t m,
+                                                         uint32_t *__restrict__ leader, uint32_t *__restrict__ keep) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    uint32_t j = nn[i];
+    bool mutual = nn[j] == i;
+    leader[i] = (mutual && i < j) ? 1u : 0u;
+    keep[i] = (mutual && i > j) ? 0u : 1u;
+}
+
+__global__ __launch_bounds__(256) void ploc_merge_kernel(const uint32_t *__restrict__ C, const uint32_t *__restrict__ nn,
+                                                         uint32_t m, const uint32_t *__restrict__ leader,
+                                                         const uint32_t *__restrict__ loff,
+                                                         const uint32_t *__restrict__ keep,
+                                                         const uint32_t *__restrict__ koff, uint32_t next_id,
+                                                         uint32_t n, float *__restrict__ nbox,
+                                                         uint32_t *__restrict__ ncount, uint32_t *__restrict__ nleft,
+                                                         uint32_t *__restrict__ nright, uint32_t *__restrict__ C_out) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m || !keep[i]) return;
+    uint32_t c = C[i];
+    if (leader[i]) {
+        uint32_t a = C[i], b = C[nn[i]];
+        uint32_t id = next_id + loff[i];
+        const float *ba = nbox + 6 * (size_t)a, *bb = nbox + 6 * (size_t)b;
+        float *bo = nbox + 6 * (size_t)id;
+        for (int q = 0; q < 3; ++q) {
+            bo[q] = fminf(ba[q], bb[q]);
+            bo[3 + q] = fmaxf(ba[3 + q], bb[3 + q]);
+        }
+        ncount[id] = ncount[a] + ncount[b];
+        nleft[id - n] = a;
+        nright[id - n] = b;
+        c = id;
+    }
+    C_out[koff[i]] = c;
+}
+
+__global__ void set_u32_kernel(uint32_t *p, uint32_t v) { *p = v; }
+
+// top-down leaf offsets, one creation round at a time (parents before children)
+__global__ __launch_bounds__(256) void ploc_first_kernel(uint32_t id0, uint32_t cnt, uint32_t n,
+                                                         const uint32_t *__restrict__ nleft,
+                                                         const uint32_t *__restrict__ nright,
+                                                         const uint32_t *__restrict__ ncount,
+                                                         uint32_t *__restrict__ first) {
+    uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= cnt) return;
+    uint32_t id = id0 + k;
+    uint32_t l = nleft[id - n], r = nright[id - n];
+    uint32_t f = first[id];
+    first[l] = f;
+    first[r] = f + ncount[l];
+}
+
+// records into depth-first order; slot_of follows
+__global__ __launch_bounds__(256) void ploc_leaves_kernel(const TriRec *__restrict__ recs_m, uint32_t n,
+                                                          const uint32_t *__restrict__ first,
+                                                          TriRec *__restrict__ recs, uint32_t *__restrict__ slot_of) {
+    uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    uint32_t pos = first[s];
+    TriRec r = recs_m[s];
+    recs[pos] = r;
+    slot_of[__float_as_uint(r.a.w)] = pos;
+}
+
+// PLOC tree -> the binary-tree form the collapse reads (codes as in the LBVH path)
+__global__ __launch_bounds__(256) void ploc_bintree_kernel(uint32_t n, const uint32_t *__restrict__ nleft,
+                                                           const uint32_t *__restrict__ nright,
+                                                           const uint32_t *__restrict__ ncount,
+                                                           const uint32_t *__restrict__ first,
+                                                           const float *__restrict__ nbox, BinTree T) {
+    uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n - 1) return;
+    uint32_t id = n + k;
+    uint32_t l = nleft[k], r = nright[k];
+    T.left[k] = l < n ? (kLeafBit | first[l]) : (l - n);
+    T.right[k] = r < n ? (kLeafBit | first[r]) : (r - n);
+    T.first[k] = first[id];
+    T.last[k] = first[id] + ncount[id] - 1;
+    const float *b = nbox + 6 * (size_t)id;
+    for (int a = 0; a < 6; ++a) T.box[6 * (size_t)k + a] = b[a];
+}
+
+// ---------------------------------------------------------------------------
 // host orchestration
 // ---------------------------------------------------------------------------
 namespace {
 struct ScratchLayout {
     size_t cent, partials, keys, vals, keys2, vals2, sort_tmp, left, right, first, last, pint, pleaf, box,
-        visit, front_a, front_b, pending, counts, offsets, scan_tmp, stat, total;
+        visit, front_a, front_b, pending, counts, offsets, scan_tmp, stat, recs_m, nbox, ncount, nleft, nright,
+        nfirst, ca, cb, nn, leader, keep, loff, koff, total;
 };
 
 ScratchLayout scratch_layout(uint32_t nt) {
@@ -569,6 +722,19 @@ ScratchLayout scratch_layout(uint32_t nt) {
     L.offsets = take(4 * n);
     L.scan_tmp = take(scan_tmp_bytes(nt));
     L.stat = take(64);
+    L.recs_m = take(sizeof(TriRec) * n);
+    L.nbox = take(24 * 2 * n);
+    L.ncount = take(4 * 2 * n);
+    L.nleft = take(4 * n);
+    L.nright = take(4 * n);
+    L.nfirst = take(4 * 2 * n);
+    L.ca = take(4 * n);
+    L.cb = take(4 * n);
+    L.nn = take(4 * n);
+    L.leader = take(4 * n);
+    L.keep = take(4 * n);
+    L.loff = take(4 * n);
+    L.koff = take(4 * n);
     L.total = o;
     return L;
 }
@@ -606,12 +772,14 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
     uint32_t *slot_of = (uint32_t *)((char *)recs + persistent_recs_bytes(nt));
     const uint32_t nb = (nt + 255) / 256;
 
+    const bool ploc = in.builder == 0 && nt > in.leaf_width;
+    TriRec *recs_m = ploc ? (TriRec *)(sc + L.recs_m) : recs;   // Morton-order records
     HIP_TRY(hipMemsetAsync(stat, 0, 64, s));
     tri_prep_kernel<<<nb, 256, 0, s>>>(in, cent, partials, stat);
     bounds_reduce_kernel<<<1, 256, 0, s>>>(partials, nb);
     morton_kernel<<<nb, 256, 0, s>>>(cent, nt, partials, keys, vals);
     radix_sort_u64(keys, vals, (uint64_t *)(sc + L.keys2), (uint32_t *)(sc + L.vals2), nt, 63, sc + L.sort_tmp, s);
-    write_records_kernel<<<nb, 256, 0, s>>>(in, vals, recs, slot_of);
+    write_records_kernel<<<nb, 256, 0, s>>>(in, vals, recs_m, slot_of);
     HIP_TRY(hipGetLastError());
 
     uint32_t depth = 1, n_nodes = 1;
@@ -627,14 +795,61 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
         T.parent_leaf = (uint32_t *)(sc + L.pleaf);
         T.box = (float *)(sc + L.box);
         T.visit = (uint32_t *)(sc + L.visit);
-        HIP_TRY(hipMemsetAsync(T.visit, 0, 4 * (size_t)nt, s));
-        karras_kernel<<<nb, 256, 0, s>>>(keys, (int)nt, T);
-        refit_kernel<<<nb, 256, 0, s>>>(T, recs, (int)nt);
+        uint32_t *stmp = (uint32_t *)(sc + L.scan_tmp);
+        uint32_t root_code = 0;
+        if (ploc) {
+            float *nbox = (float *)(sc + L.nbox);
+            uint32_t *ncount = (uint32_t *)(sc + L.ncount), *nleft = (uint32_t *)(sc + L.nleft),
+                     *nright = (uint32_t *)(sc + L.nright), *nfirst = (uint32_t *)(sc + L.nfirst);
+            uint32_t *ca = (uint32_t *)(sc + L.ca), *cb = (uint32_t *)(sc + L.cb), *nn = (uint32_t *)(sc + L.nn);
+            uint32_t *leader = (uint32_t *)(sc + L.leader), *keep = (uint32_t *)(sc + L.keep);
+            uint32_t *loff = (uint32_t *)(sc + L.loff), *koff = (uint32_t *)(sc + L.koff);
+            ploc_init_kernel<<<nb, 256, 0, s>>>(recs_m, nt, nbox, ncount, ca);
+            std::vector<uint32_t> round_start, round_count;
+            uint32_t m = nt, next_id = nt;
+            while (m > 1) {
+                if (round_start.size() > 100000) return hipErrorIllegalState;
+                uint32_t g = (m + 255) / 256;
+                ploc_nn_kernel<<<(m + kPlocBlock - 1) / kPlocBlock, kPlocBlock, 0, s>>>(ca, m, nbox, nn);
+                ploc_flags_kernel<<<g, 256, 0, s>>>(nn, m, leader, keep);
+                scan_exclusive_u32(leader, loff, m, stmp, s);
+                scan_exclusive_u32(keep, koff, m, stmp, s);
+                uint32_t h[4];
+                HIP_TRY(hipMemcpyAsync(&h[0], leader + m - 1, 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(&h[1], loff + m - 1, 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(&h[2], keep + m - 1, 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(&h[3], koff + m - 1, 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                uint32_t merges = h[0] + h[1], survivors = h[2] + h[3];
+                if (merges == 0 || next_id + merges > 2 * nt - 1) return hipErrorIllegalState;
+                ploc_merge_kernel<<<g, 256, 0, s>>>(ca, nn, m, leader, loff, keep, koff, next_id, nt, nbox, ncount,
+                                                    nleft, nright, cb);
+                HIP_TRY(hipGetLastError());
+                round_start.push_back(next_id);
+                round_count.push_back(merges);
+                next_id += merges;
+                m = survivors;
+                uint32_t *t = ca; ca = cb; cb = t;
+            }
+            // depth-first leaf offsets: root first, then each creation round in reverse
+            const uint32_t root = 2 * nt - 2;
+            set_u32_kernel<<<1, 1, 0, s>>>(nfirst + root, 0u);
+            for (size_t r = round_start.size(); r-- > 0;)
+                ploc_first_kernel<<<(round_count[r] + 255) / 256, 256, 0, s>>>(round_start[r], round_count[r], nt, nleft,
+                                                                               nright, ncount, nfirst);
+            ploc_leaves_kernel<<<nb, 256, 0, s>>>(recs_m, nt, nfirst, recs, slot_of);
+            ploc_bintree_kernel<<<nb, 256, 0, s>>>(nt, nleft, nright, ncount, nfirst, nbox, T);
+            HIP_TRY(hipGetLastError());
+            root_code = root - nt;
+        } else {
+            HIP_TRY(hipMemsetAsync(T.visit, 0, 4 * (size_t)nt, s));
+            karras_kernel<<<nb, 256, 0, s>>>(keys, (int)nt, T);
+            refit_kernel<<<nb, 256, 0, s>>>(T, recs, (int)nt);
+        }
         uint32_t *fa = (uint32_t *)(sc + L.front_a), *fb = (uint32_t *)(sc + L.front_b);
         uint32_t *pending = (uint32_t *)(sc + L.pending);
         uint32_t *counts = (uint32_t *)(sc + L.counts), *offsets = (uint32_t *)(sc + L.offsets);
-        uint32_t *stmp = (uint32_t *)(sc + L.scan_tmp);
-        HIP_TRY(hipMemsetAsync(fa, 0, 4, s));   // frontier = [root internal node 0]
+        set_u32_kernel<<<1, 1, 0, s>>>(fa, root_code);   // frontier = [binary root]
         uint32_t n_front = 1, base = 0;
         depth = 0;
         n_nodes = 0;

@@ -325,6 +325,7 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     in.nv = desc->n_vertices;
     in.nt = nt;
     in.leaf_width = W;
+    in.builder = (desc->flags & LIDAR_SCENE_BUILD_LBVH) ? 1u : 0u;
     if (desc->flags & LIDAR_SCENE_DEVICE_PTRS) {
         in.vtx = desc->vertices;
         in.idx = desc->indices;

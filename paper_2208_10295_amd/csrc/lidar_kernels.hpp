@@ -32,6 +32,7 @@ struct BuildInputs {
     uint64_t nv;
     uint32_t nt;
     uint32_t leaf_width;
+    uint32_t builder;          // 0 = PLOC, 1 = LBVH (binary radix tree)
 };
 
 // Persistent layout: [nodes: Node4 x max(nt,1)] [records: TriRec x nt] [slot_of: u32 x nt]
