@@ -35,7 +35,8 @@ METRIC = "rays/sec, 64ch×2048 on 500k-tri scene; batched vs plain; backward/for
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, OUT_BYTES = 128, 48, 25     # per node fetch, per triangle record test, per beam written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_scan_config2_traffic.txt")
-KERNEL_SOURCES = ("paper_2208_10295_amd/csrc/trace.hip", "paper_2208_10295_amd/csrc/lidar_device.hpp")
+KERNEL_SOURCES = ("paper_2208_10295_amd/csrc/trace.hip", "paper_2208_10295_amd/csrc/lidar_device.hpp",
+                  "paper_2208_10295_amd/csrc/bvh_build.hip")
 
 
 def log(*a):
@@ -105,6 +106,7 @@ def main():
     ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sequence or 'all'")
     ap.add_argument("--leaf-width", type=int, default=4)
     ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
+    ap.add_argument("--ploc-radius", type=int, default=32)
     ap.add_argument("--tile-az", type=int, default=16)
     ap.add_argument("--lanes", type=int, default=4, help="lanes per ray (1 or 4)")
     ap.add_argument("--xcd", type=int, default=1, help="XCD-aware block remap (0 or 1)")
@@ -126,7 +128,7 @@ def main():
     scene, sensor, pose = S.config2()
     log(f"config2: {scene.n_tri} triangles, {sensor.n_beams} beams")
     ctx = L.Context(0)
-    st = ctx.load(scene, args.leaf_width, builder=args.builder)
+    st = ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius)
     ctx.set_sensor(sensor)
     ctx.set_pose(pose.p, pose.q)
     ctx.set_tile_shape(args.tile_az)
@@ -141,6 +143,7 @@ def main():
                                     "(256x256 terrain cells, 400 buildings, 2,000 poles, 200 cars), 32 materials, "
                                     "905 nm, d_max 100 m, range noise 0.02 m",
                         "beams": n, "triangles": scene.n_tri, "leaf_width": st["leaf_width"], "bvh_builder": args.builder,
+                        "ploc_radius": args.ploc_radius,
                         "tile_az": args.tile_az, "lanes_per_ray": args.lanes, "xcd_remap": args.xcd,
                         "bvh_nodes": st["n_nodes"], "bvh_depth": st["depth"]}
     result["bvh_build_ms"] = st["build_ms"]

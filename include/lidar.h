@@ -88,6 +88,7 @@ const char *lidar_last_error(const lidar_ctx *ctx);
 
 #define LIDAR_SCENE_DEVICE_PTRS 1u   /* the four arrays below are device pointers */
 #define LIDAR_SCENE_BUILD_LBVH  2u   /* build the binary tree as an LBVH instead of by PLOC clustering */
+/* flags bits 8-15: PLOC search radius in Morton order, 1..128 (0 = 32) */
 
 typedef struct {
     uint64_t n_vertices;

@@ -8,7 +8,8 @@
 //    (a) PLOC (default; Meister and Bittner, "Parallel Locally-Ordered
 //        Clustering for Bounding Volume Hierarchy Construction", TVCG 2018):
 //        clusters in Morton order repeatedly find their nearest neighbour
-//        (smallest merged surface area) within +-16 positions; mutual nearest
+//        (smallest merged surface area) within +-R positions (R = 32 by
+//        default, at most 128); mutual nearest
 //        pairs merge into a new node; the survivors are compacted in order.
 //        Boxes are formed during the merges.  The leaves are then renumbered
 //        depth-first so that every subtree covers a contiguous range of
@@ -546,7 +547,7 @@ __global__ void single_leaf_root_kernel(const TriRec *__restrict__ recs, uint32_
 // ---------------------------------------------------------------------------
 // PLOC
 // ---------------------------------------------------------------------------
-constexpr int kPlocR = 16;       // search radius in Morton order
+constexpr int kPlocRMax = 128;   // largest search radius in Morton order
 constexpr int kPlocBlock = 256;
 
 __device__ inline float half_area(float lx, float ly, float lz, float hx, float hy, float hz) {
@@ -569,11 +570,12 @@ __global__ __launch_bounds__(256) void ploc_init_kernel(const TriRec *__restrict
 }
 
 __global__ __launch_bounds__(kPlocBlock) void ploc_nn_kernel(const uint32_t *__restrict__ C, uint32_t m,
-                                                             const float *__restrict__ nbox, uint32_t *__restrict__ nn) {
-    __shared__ float sb[(kPlocBlock + 2 * kPlocR) * 6];
+                                                             const float *__restrict__ nbox, uint32_t *__restrict__ nn,
+                                                             int R) {
+    __shared__ float sb[(kPlocBlock + 2 * kPlocRMax) * 6];
     const int base = (int)(blockIdx.x * kPlocBlock);
-    const int lo_i = base - kPlocR;
-    for (int k = threadIdx.x; k < kPlocBlock + 2 * kPlocR; k += kPlocBlock) {
+    const int lo_i = base - R;
+    for (int k = threadIdx.x; k < kPlocBlock + 2 * R; k += kPlocBlock) {
         int idx = lo_i + k;
         if (idx >= 0 && idx < (int)m) {
             const float *b = nbox + 6 * (size_t)C[idx];
@@ -588,7 +590,7 @@ __global__ __launch_bounds__(kPlocBlock) void ploc_nn_kernel(const uint32_t *__r
     const float hx = sb[li * 6 + 3], hy = sb[li * 6 + 4], hz = sb[li * 6 + 5];
     float best = __builtin_inff();
     int bj = i == 0 ? 1 : i - 1;
-    for (int d = -kPlocR; d <= kPlocR; ++d) {
+    for (int d = -R; d <= R; ++d) {
         int j = i + d;
         if (d == 0 || j < 0 || j >= (int)m) continue;
         const float *o = sb + (li + d) * 6;
@@ -810,7 +812,8 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
             while (m > 1) {
                 if (round_start.size() > 100000) return hipErrorIllegalState;
                 uint32_t g = (m + 255) / 256;
-                ploc_nn_kernel<<<(m + kPlocBlock - 1) / kPlocBlock, kPlocBlock, 0, s>>>(ca, m, nbox, nn);
+                ploc_nn_kernel<<<(m + kPlocBlock - 1) / kPlocBlock, kPlocBlock, 0, s>>>(ca, m, nbox, nn,
+                                                                                         (int)in.ploc_radius);
                 ploc_flags_kernel<<<g, 256, 0, s>>>(nn, m, leader, keep);
                 scan_exclusive_u32(leader, loff, m, stmp, s);
                 scan_exclusive_u32(keep, koff, m, stmp, s);

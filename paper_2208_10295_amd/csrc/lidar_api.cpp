@@ -326,6 +326,9 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     in.nt = nt;
     in.leaf_width = W;
     in.builder = (desc->flags & LIDAR_SCENE_BUILD_LBVH) ? 1u : 0u;
+    in.ploc_radius = (desc->flags >> 8) & 0xFFu;
+    if (in.ploc_radius == 0) in.ploc_radius = 32;
+    if (in.ploc_radius > 128) return ctx->fail(LIDAR_ERR_INVALID_ARG, "PLOC radius (flags bits 8-15) must be <= 128");
     if (desc->flags & LIDAR_SCENE_DEVICE_PTRS) {
         in.vtx = desc->vertices;
         in.idx = desc->indices;

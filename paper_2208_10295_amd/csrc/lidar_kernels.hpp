@@ -33,6 +33,7 @@ struct BuildInputs {
     uint32_t nt;
     uint32_t leaf_width;
     uint32_t builder;          // 0 = PLOC, 1 = LBVH (binary radix tree)
+    uint32_t ploc_radius;      // PLOC search radius, 1..32
 };
 
 // Persistent layout: [nodes: Node4 x max(nt,1)] [records: TriRec x nt] [slot_of: u32 x nt]
