@@ -272,6 +272,15 @@ def simulate(scene, sensor, pose, seed: int = 0, scan: int = 0, inst: int = 0, b
         return _simulate(scene, sensor, pose, seed, scan, inst, beams, rho, angle_exp, R, p)
 
 
+def _rotate(R, s):
+    """d = R s for every row of s; R is [3, 3] or one matrix per row [n, 3, 3].
+    Each component is the plain three-term sum, left to right."""
+    R = np.asarray(R, dtype=np.float64)
+    if R.ndim == 2:
+        R = R[None]
+    return np.stack([R[:, r, 0] * s[:, 0] + R[:, r, 1] * s[:, 1] + R[:, r, 2] * s[:, 2] for r in range(3)], axis=1)
+
+
 def _simulate(scene, sensor, pose, seed, scan, inst, beams, rho, angle_exp, R, p):
     n_all = sensor.n_beams
     beams = np.arange(n_all, dtype=np.int64) if beams is None else np.asarray(beams, dtype=np.int64)
@@ -279,8 +288,12 @@ def _simulate(scene, sensor, pose, seed, scan, inst, beams, rho, angle_exp, R, p
     s = s_all[beams]
     Rm = rotation_from_quat(pose.q) if R is None else np.asarray(R, dtype=np.float64)
     o = np.asarray(pose.p, dtype=np.float64) if p is None else np.asarray(p, dtype=np.float64)
-    d = s @ Rm.T
+    return _trace_and_return(scene, sensor, beams, s, _rotate(Rm, s), o, seed, scan, inst, rho, angle_exp)
 
+
+def _trace_and_return(scene, sensor, beams, s, d, o, seed, scan, inst, rho, angle_exp):
+    """Steps 2-7 for beams with sensor-frame directions s, world directions d,
+    origins o ([3] or [n, 3]) and Philox scan counter `scan` (scalar or per beam)."""
     # step 2: first hit within the traceable range (traced a little beyond it
     # so that hits straddling the limit are seen and can be flagged)
     t_lim = trace_limit(scene, sensor)
@@ -344,6 +357,133 @@ def _simulate(scene, sensor, pose, seed, scan, inst, beams, rho, angle_exp, R, p
     out["marginal"] = hit & ((np.abs(r_lambda - r_l) <= 1e-5 * r_lambda)
                              | (np.abs(d_n - sensor.d_max) <= 1e-5 * sensor.d_max)
                              | (np.abs(d_n - sensor.t_min) <= 1e-5))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# partial sweep per simulation tick, rolling-shutter pose [II-A]
+# ----------------------------------------------------------------------------
+# Section II-A renders, at every engine tick, only the part of FOV_h that the
+# spinning head has covered since the previous tick (from the spin rate omega_l
+# and the tick length dt).  Here every column fired during the tick is traced
+# with the pose the sensor has at the moment that column fires: the pose moves
+# linearly in position and along the great arc (slerp) in orientation from the
+# pose at the tick start to the pose at the tick end.  With equal start and end
+# poses this is the paper's one-pose-per-tick model.
+
+SLERP_LINEAR_BELOW = 1e-6      # arc angle (rad) under which the interpolation is linear
+
+
+def sweep_window(head_deg_begin, spin_hz, dt_s):
+    """Head-angle interval [a, b) swept during one tick: b = a + 360 omega_l dt
+    (degrees, unwrapped: revolution s covers [360 s, 360 (s + 1)) + az0)."""
+    a = float(head_deg_begin)
+    return a, a + 360.0 * float(spin_hz) * float(dt_s)
+
+
+def column_coordinate(sensor, x, s):
+    """c_s(x) = ((x - az0) - 360 s) N_az / FOV_h: head angle x in units of
+    azimuth steps of revolution s, evaluated in exactly this order in FP64."""
+    return ((float(x) - sensor.az0_deg) - 360.0 * s) * sensor.n_az / sensor.fov_h_deg
+
+
+def sweep_columns(sensor, a, b):
+    """Columns fired while the head turns over [a, b) (degrees, b - a <= 360).
+
+    Column i of revolution (scan) s >= 0 points at head angle
+    A = 360 s + az0 + i FOV_h / N_az; it is fired iff a <= A < b, decided in
+    column coordinates as ceil(c_s(a)) <= i < ceil(c_s(b)).  A window of at
+    most one revolution can only reach revolutions s_a = floor((a - az0) / 360)
+    and s_a + 1.  Returns the non-empty runs [(s, i_begin, i_end), ...] in
+    firing order.
+    """
+    if not (b >= a and b - a <= 360.0):
+        raise ValueError("a tick sweeps between 0 and 360 degrees")
+    s_a = math.floor((float(a) - sensor.az0_deg) / 360.0)
+    runs = []
+    for s in (s_a, s_a + 1):
+        if s < 0:
+            continue
+        lo = max(0, math.ceil(column_coordinate(sensor, a, s)))
+        hi = min(sensor.n_az, math.ceil(column_coordinate(sensor, b, s)))
+        if hi > lo:
+            runs.append((int(s), int(lo), int(hi)))
+    return runs
+
+
+def column_time_fraction(sensor, s, i, a, b):
+    """tau = (A - a) / (b - a): the fraction of the tick at which column (s, i) fires,
+    with A = 360 s + (az0 + i FOV_h / N_az)."""
+    A = 360.0 * s + (sensor.az0_deg + i * (sensor.fov_h_deg / sensor.n_az))
+    return (A - a) / (b - a)
+
+
+def slerp(qa, qb, tau):
+    """Quaternion on the great arc from qa to qb at fraction tau (Shoemake, SIGGRAPH 1985).
+
+    Both ends are normalised and qb is negated when qa . qb < 0, so that the
+    shorter of the two arcs between the rotations is taken.  With arc angle
+    W = acos(qa . qb): q = sin((1 - tau) W) / sin W qa + sin(tau W) / sin W qb;
+    below SLERP_LINEAR_BELOW the arc is replaced by the chord qa + tau (qb - qa)
+    (unnormalised; rotation_from_quat normalises).
+    """
+    qa = np.asarray(qa, dtype=np.float64)
+    qb = np.asarray(qb, dtype=np.float64)
+    qa = qa / np.linalg.norm(qa)
+    qb = qb / np.linalg.norm(qb)
+    dot = float(np.dot(qa, qb))
+    if dot < 0.0:
+        qb, dot = -qb, -dot
+    w = math.acos(min(dot, 1.0))
+    if w < SLERP_LINEAR_BELOW:
+        return qa + tau * (qb - qa)
+    sw = math.sin(w)
+    return (math.sin((1.0 - tau) * w) / sw) * qa + (math.sin(tau * w) / sw) * qb
+
+
+def sweep_pose(pose_a, pose_b, tau):
+    """(R, p) at fraction tau of the tick: p = pa + tau (pb - pa), R from slerp."""
+    pa = np.asarray(pose_a.p, dtype=np.float64)
+    pb = np.asarray(pose_b.p, dtype=np.float64)
+    return rotation_from_quat(slerp(pose_a.q, pose_b.q, tau)), pa + tau * (pb - pa)
+
+
+def simulate_sweep(scene, sensor, pose_a, pose_b, head_deg_begin, spin_hz, dt_s, seed: int = 0,
+                   inst: int = 0, beams=None):
+    """Oracle for one tick of a spinning sensor.
+
+    The columns fired during the tick (``sweep_columns``) are traced with the
+    pose of their firing time; the Philox counter of beam (j, i) of revolution
+    s is (j N_az + i, s, inst, 0), so the ticks of one revolution together
+    reproduce ``simulate(..., scan=s)`` when the pose does not change.
+    beams: optional subset of range-image slots b = j N_az + i, which must lie
+    in fired columns.  Returns the ``simulate`` dict plus ``runs``, ``scan``
+    (per beam) and ``tau`` (per beam).
+    """
+    a, b = sweep_window(head_deg_begin, spin_hz, dt_s)
+    runs = sweep_columns(sensor, a, b)
+    col_scan = np.full(sensor.n_az, -1, dtype=np.int64)
+    for s_, lo, hi in runs:
+        col_scan[lo:hi] = s_
+    fired = np.flatnonzero(col_scan >= 0)
+    if beams is None:
+        beams = (np.arange(sensor.n_ch, dtype=np.int64)[:, None] * sensor.n_az + fired[None, :]).reshape(-1)
+        beams = np.sort(beams)
+    beams = np.asarray(beams, dtype=np.int64)
+    col = beams % sensor.n_az
+    if np.any(col_scan[col] < 0):
+        raise ValueError("beam outside the columns fired in this tick")
+    scan_b = col_scan[col]
+    tau_c = {int(i): column_time_fraction(sensor, int(col_scan[i]), int(i), a, b) for i in np.unique(col)}
+    poses = {i: sweep_pose(pose_a, pose_b, t) for i, t in tau_c.items()}
+    Rb = np.stack([poses[int(i)][0] for i in col]) if len(col) else np.zeros((0, 3, 3))
+    ob = np.stack([poses[int(i)][1] for i in col]) if len(col) else np.zeros((0, 3))
+    s = beam_directions(sensor).reshape(-1, 3)[beams]
+    with np.errstate(invalid="ignore", over="ignore"):
+        out = _trace_and_return(scene, sensor, beams, s, _rotate(Rb, s), ob, seed, scan_b, inst, None, None)
+    out["runs"] = runs
+    out["scan"] = scan_b
+    out["tau"] = np.array([tau_c[int(i)] for i in col], dtype=np.float64)
     return out
 
 
