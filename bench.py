@@ -24,6 +24,7 @@ Prints exactly one JSON line on stdout; progress goes to stderr.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -103,7 +104,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sequence or 'all'")
+    ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sweep,sequence or 'all'")
     ap.add_argument("--leaf-width", type=int, default=4)
     ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
     ap.add_argument("--ploc-radius", type=int, default=32)
@@ -116,7 +117,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": args.gpus}))
         sys.exit(2)
-    legs = {"plain", "cpu", "batch", "adjoint", "sequence"} if args.legs == "all" else set(args.legs.split(","))
+    legs = ({"plain", "cpu", "batch", "adjoint", "sweep", "sequence"} if args.legs == "all"
+            else set(args.legs.split(",")))
 
     import numpy as np
     import torch
@@ -292,6 +294,42 @@ def main():
             "pose_delta_final": [float(x) for x in pose_err]}
         log(f"adjoint: fwd {f_ms * 1e3:.1f} us, bwd {b_ms * 1e3:.1f} us; loss {losses[0]:.4g} -> {losses[-1]:.4g}")
         del cx
+
+    if "sweep" in legs:
+        # engine ticks at 60 Hz of a 10 Hz head: each tick traces the ~341 columns the head swept, with
+        # rolling-shutter poses of a sensor driving at 10 m/s and turning at 10 deg/s, for 1 s of sim time
+        spin, tick_hz, n_ticks = 10.0, 60.0, 60
+        dt = 1.0 / tick_hz
+        p0 = np.asarray(pose.p, np.float64)
+
+        def pose_at(t):
+            return ((p0 + np.array([10.0 * t, 0.0, 0.0])).astype(np.float32), S.quat_from_ypr(math.radians(10.0 * t)))
+        heads = [0.0]
+        for k in range(n_ticks):
+            heads.append(heads[-1] + 360.0 * spin * dt)      # each tick starts where the last one ended
+        ticks = [(heads[k], pose_at(k * dt), pose_at((k + 1) * dt)) for k in range(n_ticks)]
+        outs = alloc_outputs(n, POINT_OUTPUTS, ctx.device)
+        fired = []
+
+        def tick(k):
+            _, runs = ctx.simulate_sweep(seed, ticks[k][0], spin, dt, ticks[k][1], ticks[k][2], out=outs)
+            if len(fired) < n_ticks:
+                fired.append(sum(c for _, _, c in runs))
+        for k in range(min(args.warmup, n_ticks)):
+            tick(k)
+        fired.clear()
+        wall_s, ms_s = timed_launches(tick, n_ticks, torch)
+        ctx.sync_check()
+        rays = sensor.n_ch * sum(fired)
+        assert sum(fired) == n_ticks / tick_hz * spin * sensor.n_az
+        result["sweep"] = {"workload": "60 engine ticks at 60 Hz of a 10 Hz head (64ch x 2048, ~341 columns per "
+                                       "tick) on the 522k-triangle scene, rolling-shutter poses at 10 m/s and "
+                                       "10 deg/s yaw, 1 s of simulated time",
+                           "ticks": n_ticks, "rays": rays, "rays_per_s": rays / wall_s,
+                           "tick_us_mean": float(np.mean(ms_s)) * 1e3, "ticks_per_s": n_ticks / wall_s,
+                           "realtime_factor": (n_ticks / tick_hz) / wall_s}
+        log(f"sweep: {n_ticks} ticks in {wall_s * 1e3:.2f} ms ({np.mean(ms_s) * 1e3:.1f} us per tick, "
+            f"{rays / wall_s:.4g} rays/s, {(n_ticks / tick_hz) / wall_s:.0f}x real time)")
 
     if "sequence" in legs:
         sc3, s3, poses = S.config3()

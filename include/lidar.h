@@ -232,6 +232,63 @@ lidar_status lidar_simulate_bruteforce(lidar_ctx *ctx, uint64_t seed, uint32_t s
 lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_outputs *out,
                                    uint32_t *node_visits, uint32_t *tri_tests, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Partial sweep per engine tick, rolling-shutter pose (Section II-A)        */
+/* ------------------------------------------------------------------------ */
+
+/* One engine tick of a spinning head.  Section II-A simulates per tick only
+ * the part of the horizontal FOV that the head swept since the previous tick,
+ * from the spin rate omega_l and the tick length dt.  The head angle is
+ * unwrapped: revolution (scan) s >= 0 covers [360 s, 360 (s + 1)) + az0, and
+ * column i of revolution s fires at head angle A = 360 s + az0 + i fov_h / n_az.
+ * The tick covers the window [a, b) with a = head_deg and
+ * b = a + 360 * spin_hz * dt_s (computed in FP64 in this order).  Column i of
+ * revolution s is fired iff ceil(c_s(a)) <= i < ceil(c_s(b)), with
+ * c_s(x) = ((x - az0) - 360 s) * n_az / fov_h in FP64, for
+ * s in {floor((a - az0) / 360), that + 1}, s >= 0.  Consecutive ticks whose
+ * windows share their ends fire every column exactly once.
+ * Each fired column is traced with the pose at its firing fraction
+ * tau = (A - a) / (b - a) of the tick: p = p_begin + tau (p_end - p_begin),
+ * orientation on the great arc from q_begin to q_end (slerp, Shoemake 1985;
+ * the shorter arc; the chord q_begin + tau (q_end - q_begin) below an arc of
+ * 1e-6 rad).  Equal end poses reproduce lidar_simulate's pose exactly. */
+typedef struct {
+    double head_deg;           /* head angle at the tick start, degrees (unwrapped, finite) */
+    double spin_hz;            /* omega_l, revolutions per second (> 0) */
+    double dt_s;               /* tick length, seconds (>= 0; 360 * spin_hz * dt_s <= 360) */
+    float p_begin[3];          /* pose at the tick start: origin (world, metres) */
+    float q_begin[4];          /*   and unit quaternion (w, x, y, z) */
+    float p_end[3];            /* pose at the tick end */
+    float q_end[4];
+    uint64_t seed;             /* Philox key, as in lidar_simulate */
+} lidar_sweep_desc;
+
+/* The columns a tick fired: up to two runs, the second one revolution after
+ * the first (azimuth first[r] .. first[r] + count[r] - 1 of scan[r]). */
+typedef struct {
+    uint32_t n_runs;           /* 0, 1 or 2 */
+    uint32_t n_columns;        /* count[0] + count[1] */
+    uint32_t scan[2];
+    uint32_t first[2];
+    uint32_t count[2];
+} lidar_sweep_info;
+
+/* Simulates the columns fired in one tick with the current sensor.  Outputs
+ * use the layout of lidar_simulate ([n_ch][n_az] range image, one element per
+ * beam of the whole scan); only the beams of fired columns are written, the
+ * others keep their contents, so successive ticks fill the range image.  The
+ * Philox counter of beam (j, i) of revolution s is (j n_az + i, s, 0, 0):
+ * the ticks of revolution s with one fixed pose give bit for bit
+ * lidar_simulate(seed, scan = s) at that pose.  xyz are in the sensor frame
+ * at each column's firing time.  `info` (host, may be NULL) receives the
+ * fired columns.  Uses a context-owned pose table: sweeps on one context are
+ * ordered on one stream.  Errors: LIDAR_ERR_INVALID_ARG for a window longer
+ * than 360 degrees, non-finite values, non-unit quaternions (1e-4) or a
+ * revolution index >= 2^32 - 1; nothing is launched when no column fires.
+ * Asynchronous. */
+lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep, const lidar_outputs *out,
+                                  lidar_sweep_info *info, void *stream);
+
 /* Launch-shape options.  They change speed, never results.
  *   LIDAR_OPT_TILE_AZ: beams are traced in 64-beam tiles of `value` azimuth
  *     steps x 64 / value channels (power of two in 1..64; default 16).  A batch

@@ -421,24 +421,25 @@ def column_time_fraction(sensor, s, i, a, b):
 def slerp(qa, qb, tau):
     """Quaternion on the great arc from qa to qb at fraction tau (Shoemake, SIGGRAPH 1985).
 
-    Both ends are normalised and qb is negated when qa . qb < 0, so that the
-    shorter of the two arcs between the rotations is taken.  With arc angle
-    W = acos(qa . qb): q = sin((1 - tau) W) / sin W qa + sin(tau W) / sin W qb;
-    below SLERP_LINEAR_BELOW the arc is replaced by the chord qa + tau (qb - qa)
-    (unnormalised; rotation_from_quat normalises).
+    qb is negated when qa . qb < 0, so that the shorter of the two arcs between
+    the rotations is taken.  With unit ends ua, ub and arc angle W = acos(ua . ub):
+    q = sin((1 - tau) W) / sin W ua + sin(tau W) / sin W ub.  Below
+    SLERP_LINEAR_BELOW the arc is replaced by the chord qa + tau (qb - qa)
+    between the given quaternions (not renormalised: rotation_from_quat
+    normalises), so equal ends give back exactly the given quaternion.
     """
     qa = np.asarray(qa, dtype=np.float64)
     qb = np.asarray(qb, dtype=np.float64)
-    qa = qa / np.linalg.norm(qa)
-    qb = qb / np.linalg.norm(qb)
-    dot = float(np.dot(qa, qb))
+    ua = qa / np.linalg.norm(qa)
+    ub = qb / np.linalg.norm(qb)
+    dot = float(np.dot(ua, ub))
     if dot < 0.0:
-        qb, dot = -qb, -dot
+        qb, ub, dot = -qb, -ub, -dot
     w = math.acos(min(dot, 1.0))
     if w < SLERP_LINEAR_BELOW:
         return qa + tau * (qb - qa)
     sw = math.sin(w)
-    return (math.sin((1.0 - tau) * w) / sw) * qa + (math.sin(tau * w) / sw) * qb
+    return (math.sin((1.0 - tau) * w) / sw) * ua + (math.sin(tau * w) / sw) * ub
 
 
 def sweep_pose(pose_a, pose_b, tau):

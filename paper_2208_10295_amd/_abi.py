@@ -94,6 +94,17 @@ class Stats(C.Structure):
                 ("build_ms", C.c_float), ("box_pad", C.c_float)]
 
 
+class SweepDesc(C.Structure):
+    _fields_ = [("head_deg", C.c_double), ("spin_hz", C.c_double), ("dt_s", C.c_double),
+                ("p_begin", C.c_float * 3), ("q_begin", C.c_float * 4), ("p_end", C.c_float * 3),
+                ("q_end", C.c_float * 4), ("seed", C.c_uint64)]
+
+
+class SweepInfo(C.Structure):
+    _fields_ = [("n_runs", C.c_uint32), ("n_columns", C.c_uint32), ("scan", C.c_uint32 * 2),
+                ("first", C.c_uint32 * 2), ("count", C.c_uint32 * 2)]
+
+
 # name -> (restype, argtypes); every entry point declared in include/lidar.h
 SIGNATURES = {
     "lidar_create": (C.c_int32, [C.c_int, C.POINTER(P)]),
@@ -109,6 +120,7 @@ SIGNATURES = {
     "lidar_simulate_ex": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Params), C.POINTER(Outputs), P]),
     "lidar_simulate_bruteforce": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P]),
     "lidar_simulate_counts": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P, P, P]),
+    "lidar_simulate_sweep": (C.c_int32, [P, C.POINTER(SweepDesc), C.POINTER(Outputs), C.POINTER(SweepInfo), P]),
     "lidar_batch_create": (C.c_int32, [P, C.POINTER(Instance), C.c_uint32, C.c_uint32, C.POINTER(P)]),
     "lidar_batch_rays": (C.c_int32, [P, C.POINTER(C.c_uint64)]),
     "lidar_simulate_batch": (C.c_int32, [P, P, C.POINTER(Outputs), P]),

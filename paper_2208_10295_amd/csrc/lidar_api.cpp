@@ -69,6 +69,7 @@ struct lidar_ctx {
     bool has_sensor = false;
     SensorHost sensor;
     DevBuf sensor_tables;   // elev_cs then az_cs
+    DevBuf sweep_poses;     // [n_az][12] FP64 poses of a tick's fired columns
     DevBuf adj_partials;
     // pose
     float p[3] = {0, 0, 0};
@@ -197,6 +198,10 @@ InstanceDev make_instance(const lidar_ctx *ctx, int tile_az_log2, const lidar_se
     in.seed_hi = (uint32_t)(seed >> 32);
     in.scan = scan;
     in.inst_id = inst_id;
+    in.col_pose = nullptr;
+    in.n_cols = d.n_az;
+    in.seg_n0 = d.n_az;
+    in.seg_i0[0] = in.seg_i0[1] = 0;
     return in;
 }
 
@@ -275,6 +280,7 @@ lidar_status lidar_destroy(lidar_ctx *ctx) {
     hipDeviceSynchronize();
     ctx->mat_buf.release();
     ctx->sensor_tables.release();
+    ctx->sweep_poses.release();
     ctx->adj_partials.release();
     ctx->words.release();
     delete ctx;
@@ -444,6 +450,8 @@ lidar_status lidar_sensor_set(lidar_ctx *ctx, const lidar_sensor_desc *d) {
     double *elev_deg = az_cs + 2 * (size_t)d->n_az;
     if ((e = hipMemcpy(elev_deg, d->elev_deg, 8 * (size_t)d->n_ch, hipMemcpyHostToDevice)) != hipSuccess)
         return ctx->hip_fail(e, "sensor upload");
+    if ((e = ctx->sweep_poses.ensure(96 * (size_t)d->n_az)) != hipSuccess)
+        return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "sweep pose table allocation failed");
     launch_dir_tables(elev_deg, d->n_ch, d->az0_deg, d->fov_h_deg, d->n_az, elev_cs, az_cs, 0);
     if ((e = hipDeviceSynchronize()) != hipSuccess) return ctx->hip_fail(e, "direction tables");
     ctx->sensor.d = *d;
@@ -516,6 +524,96 @@ lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
     if (!ctx) return LIDAR_ERR_INVALID_ARG;
     if (!node_visits || !tri_tests) return ctx->fail(LIDAR_ERR_INVALID_ARG, "count arrays are null");
     return simulate_common(ctx, seed, scan, nullptr, out, stream, false, node_visits, tri_tests);
+}
+
+// ---------------------------------------------------------------------------
+// partial sweep per engine tick
+// ---------------------------------------------------------------------------
+lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, const lidar_outputs *out,
+                                  lidar_sweep_info *info, void *stream) {
+    lidar_status st = ready(ctx, true);
+    if (st != LIDAR_OK) return st;
+    if (!sw) return ctx->fail(LIDAR_ERR_INVALID_ARG, "sweep descriptor is null");
+    if (!out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "outputs struct is null");
+    if ((st = check_quat(ctx, sw->p_begin, sw->q_begin)) != LIDAR_OK) return st;
+    if ((st = check_quat(ctx, sw->p_end, sw->q_end)) != LIDAR_OK) return st;
+    if (!std::isfinite(sw->head_deg) || !std::isfinite(sw->spin_hz) || !(sw->spin_hz > 0.0) ||
+        !std::isfinite(sw->dt_s) || !(sw->dt_s >= 0.0))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "need finite head_deg, spin_hz > 0 and dt_s >= 0");
+    const lidar_sensor_desc &d = ctx->sensor.d;
+    const double a = sw->head_deg;
+    const double b = a + 360.0 * sw->spin_hz * sw->dt_s;
+    if (!(b - a <= 360.0)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "a tick may sweep at most 360 degrees");
+    const double s_a = std::floor((a - d.az0_deg) / 360.0);
+    if (s_a + 1.0 >= 4294967295.0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "revolution index out of range");
+    // fired columns: ceil(c_s(a)) <= i < ceil(c_s(b)), c_s(x) = ((x - az0) - 360 s) n_az / fov_h
+    uint32_t run_scan[2] = {0, 0}, run_first[2] = {0, 0}, run_count[2] = {0, 0}, n_runs = 0;
+    for (int r = 0; r < 2; ++r) {
+        double sr = s_a + r;
+        if (sr < 0.0) continue;
+        double ca = ((a - d.az0_deg) - 360.0 * sr) * (double)d.n_az / d.fov_h_deg;
+        double cb = ((b - d.az0_deg) - 360.0 * sr) * (double)d.n_az / d.fov_h_deg;
+        double lo = std::max(0.0, std::ceil(ca));
+        double hi = std::min((double)d.n_az, std::ceil(cb));
+        if (hi > lo) {
+            run_scan[n_runs] = (uint32_t)sr;
+            run_first[n_runs] = (uint32_t)lo;
+            run_count[n_runs] = (uint32_t)(hi - lo);
+            ++n_runs;
+        }
+    }
+    uint32_t n_cols = run_count[0] + run_count[1];
+    if (n_runs == 2 && run_scan[1] != run_scan[0] + 1)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "internal: runs are not in consecutive revolutions");
+    if (n_cols > d.n_az) return ctx->fail(LIDAR_ERR_INVALID_ARG, "internal: more columns than azimuth steps");
+    if (info) {
+        info->n_runs = n_runs;
+        info->n_columns = n_cols;
+        for (int r = 0; r < 2; ++r) {
+            info->scan[r] = run_scan[r];
+            info->first[r] = run_first[r];
+            info->count[r] = run_count[r];
+        }
+    }
+    lidar_status ok = wavelength_clamped(ctx, d.wavelength_nm) ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK;
+    if (n_cols == 0) return ok;
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    SweepPoseArgs A{};
+    A.a = a;
+    A.b = b;
+    A.az0 = d.az0_deg;
+    A.fov = d.fov_h_deg;
+    A.n_az = d.n_az;
+    A.n_cols = n_cols;
+    A.seg_n0 = run_count[0];
+    A.scan0 = run_scan[0];
+    A.seg_i0[0] = run_first[0];
+    A.seg_i0[1] = run_first[1];
+    std::memcpy(A.pa, sw->p_begin, 12);
+    std::memcpy(A.qa, sw->q_begin, 16);
+    std::memcpy(A.pb, sw->p_end, 12);
+    std::memcpy(A.qb, sw->q_end, 16);
+    double *poses = (double *)ctx->sweep_poses.p;
+    launch_sweep_poses(A, poses, s);
+    const double *elev_cs = (const double *)ctx->sensor_tables.p;
+    const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
+    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, sw->p_begin, sw->q_begin, sw->seed,
+                                   run_scan[0], 0, 0, 0);
+    in.col_pose = poses;
+    in.n_cols = n_cols;
+    in.seg_n0 = run_count[0];
+    in.seg_i0[0] = run_first[0];
+    in.seg_i0[1] = run_first[1];
+    in.tiles_az = tiles_az(ctx->tile_az_log2, n_cols);
+    uint64_t nb = (uint64_t)d.n_ch * d.n_az;
+    Outputs o = to_outputs(out, nb);
+    uint64_t np = padded_rays(ctx->tile_az_log2, d.n_ch, n_cols);
+    launch_trace_scan(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, Overrides{}, o, np,
+                      (uint32_t *)ctx->words.p, nullptr, nullptr, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "sweep launch");
+    return ok;
 }
 
 // ---------------------------------------------------------------------------

@@ -66,6 +66,15 @@ struct InstanceDev {
     float wavelength_nm, d_max, r_l_max, t_min, sigma_i, t_trace;
     uint32_t noise_on;
     uint32_t seed_lo, seed_hi, scan, inst_id;
+    // Columns traced by the launch.  A scan traces all n_az columns with one
+    // pose.  A partial sweep (one engine tick) traces n_cols fired columns in
+    // at most two runs: columns k < seg_n0 are azimuth seg_i0[0] + k of scan
+    // `scan`, the rest azimuth seg_i0[1] + (k - seg_n0) of scan + 1; column k
+    // takes the FP64 pose col_pose[12 k ..] (R row-major, then p).
+    const double *col_pose;    // null for a scan
+    uint32_t n_cols;
+    uint32_t seg_n0;
+    uint32_t seg_i0[2];
 };
 
 struct MaterialsDev {
@@ -104,7 +113,7 @@ struct Pose64 {
     double p[3];
 };
 
-__device__ inline void quat_to_rot(const float q[4], double R[9]) {
+__device__ inline void quat_to_rot(const double q[4], double R[9]) {
     double w = q[0], x = q[1], y = q[2], z = q[3];
     double n = sqrt(w * w + x * x + y * y + z * z);
     w /= n; x /= n; y /= n; z /= n;
@@ -129,7 +138,8 @@ __device__ inline void so3_exp(const double w[3], double E[9]) {
 
 __device__ inline Pose64 make_pose(const InstanceDev &in, const float *pose_delta) {
     Pose64 P;
-    quat_to_rot(in.q, P.R);
+    const double q[4] = {in.q[0], in.q[1], in.q[2], in.q[3]};
+    quat_to_rot(q, P.R);
     P.p[0] = in.p[0]; P.p[1] = in.p[1]; P.p[2] = in.p[2];
     if (pose_delta) {
         double w[3] = {pose_delta[3], pose_delta[4], pose_delta[5]};
@@ -141,6 +151,29 @@ __device__ inline Pose64 make_pose(const InstanceDev &in, const float *pose_delt
                 P.R[r * 3 + c] = E[r * 3 + 0] * R0[0 * 3 + c] + E[r * 3 + 1] * R0[1 * 3 + c] + E[r * 3 + 2] * R0[2 * 3 + c];
         P.p[0] += pose_delta[0]; P.p[1] += pose_delta[1]; P.p[2] += pose_delta[2];
     }
+    return P;
+}
+
+// Column k of a launch -> azimuth index, and the scan it belongs to.
+__device__ inline uint32_t column_azimuth(const InstanceDev &in, uint32_t k, uint32_t &scan) {
+    if (k < in.seg_n0) {
+        scan = in.scan;
+        return in.seg_i0[0] + k;
+    }
+    scan = in.scan + 1u;
+    return in.seg_i0[1] + (k - in.seg_n0);
+}
+
+// Pose of column k: the scan pose (with the calibration delta), or the
+// per-column pose of a partial sweep.
+__device__ inline Pose64 column_pose(const InstanceDev &in, const float *pose_delta, uint32_t k) {
+    if (!in.col_pose) return make_pose(in, pose_delta);
+    const double *c = in.col_pose + 12 * (size_t)k;
+    Pose64 P;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) P.R[e] = c[e];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) P.p[e] = c[9 + e];
     return P;
 }
 

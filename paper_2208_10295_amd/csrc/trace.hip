@@ -57,6 +57,72 @@ void launch_dir_tables(const double *elev_deg, uint32_t n_ch, double az0_deg, do
 }
 
 // ---------------------------------------------------------------------------
+// Partial sweep of one engine tick (Section II-A renders only the part of the
+// horizontal FOV swept since the previous tick): the pose of every fired
+// column at its firing time.  Column (scan s, azimuth i) fires when the head
+// reaches A = 360 s + (az0 + i FOV_h / N_az); over the tick's window [a, b)
+// that is the fraction tau = (A - a) / (b - a).  The position moves linearly,
+// the orientation along the great arc between the two quaternions (slerp,
+// Shoemake 1985), and along the chord below an arc of 1e-6 rad, so that equal
+// end poses give exactly the scan pose.
+// ---------------------------------------------------------------------------
+__global__ void sweep_pose_kernel(SweepPoseArgs A, double *__restrict__ out) {
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.n_cols) return;
+    uint32_t s, i;
+    if (k < A.seg_n0) {
+        s = A.scan0;
+        i = A.seg_i0[0] + k;
+    } else {
+        s = A.scan0 + 1u;
+        i = A.seg_i0[1] + (k - A.seg_n0);
+    }
+    double ang = 360.0 * (double)s + (A.az0 + (double)i * (A.fov / (double)A.n_az));
+    double tau = (ang - A.a) / (A.b - A.a);
+    double qa[4], qb[4], ua[4], ub[4];
+    double na = 0.0, nb = 0.0;
+    for (int e = 0; e < 4; ++e) {
+        qa[e] = A.qa[e];
+        qb[e] = A.qb[e];
+        na += qa[e] * qa[e];
+        nb += qb[e] * qb[e];
+    }
+    na = sqrt(na);
+    nb = sqrt(nb);
+    double dot = 0.0;
+    for (int e = 0; e < 4; ++e) {
+        ua[e] = qa[e] / na;
+        ub[e] = qb[e] / nb;
+        dot += ua[e] * ub[e];
+    }
+    if (dot < 0.0) {
+        for (int e = 0; e < 4; ++e) {
+            qb[e] = -qb[e];
+            ub[e] = -ub[e];
+        }
+        dot = -dot;
+    }
+    double w = acos(fmin(dot, 1.0));
+    double q[4];
+    if (w < 1e-6) {
+        for (int e = 0; e < 4; ++e) q[e] = qa[e] + tau * (qb[e] - qa[e]);
+    } else {
+        double sw = sin(w);
+        double ca = sin((1.0 - tau) * w) / sw, cb = sin(tau * w) / sw;
+        for (int e = 0; e < 4; ++e) q[e] = ca * ua[e] + cb * ub[e];
+    }
+    double R[9];
+    quat_to_rot(q, R);
+    double *o = out + 12 * (size_t)k;
+    for (int e = 0; e < 9; ++e) o[e] = R[e];
+    for (int e = 0; e < 3; ++e) o[9 + e] = (double)A.pa[e] + tau * ((double)A.pb[e] - (double)A.pa[e]);
+}
+
+void launch_sweep_poses(const SweepPoseArgs &A, double *out, hipStream_t s) {
+    sweep_pose_kernel<<<(A.n_cols + 127) / 128, 128, 0, s>>>(A, out);
+}
+
+// ---------------------------------------------------------------------------
 // common pieces
 // ---------------------------------------------------------------------------
 struct Hit {
@@ -229,8 +295,8 @@ __device__ inline Hit traverse_quad(const Node4 *__restrict__ nodes, const TriRe
 // Hit attributes + return model + output write (fused epilogue)
 // ---------------------------------------------------------------------------
 __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
-                                       const Outputs &out, uint64_t o, uint32_t beam, const Ray &ray,
-                                       const TriRec *__restrict__ tris, const Hit &h) {
+                                       const Outputs &out, uint64_t o, uint32_t beam, uint32_t scan,
+                                       const Ray &ray, const TriRec *__restrict__ tris, const Hit &h) {
     bool hit = h.slot != kNone;
     float nx = 0.f, ny = 0.f, nz = 0.f, rl = 0.f, dn = 0.f, inten = 0.f, tt = 0.f;
     uint32_t lab = kNone, orig = kNone;
@@ -271,7 +337,7 @@ __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev
         rl = (kx == 1.0f) ? r0 * cs : r0 * exp2f(kx * log2f(cs));
         float zd = 0.0f, zi = 0.0f, sig = 0.0f, sig_i = 0.0f;
         if (in.noise_on) {
-            uint4 x = philox4x32_10(make_uint4(beam, in.scan, in.inst_id, 0u), in.seed_lo, in.seed_hi);
+            uint4 x = philox4x32_10(make_uint4(beam, scan, in.inst_id, 0u), in.seed_lo, in.seed_hi);
             zd = box_muller(x.x, x.y);
             zi = box_muller(x.z, x.w);
             sig = M.sigma[m];
@@ -302,15 +368,15 @@ __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev
     }
 }
 
-// tile mapping: padded ray r of an instance -> (channel j, azimuth i);
-// tiles are numbered column-major (channel rows of one azimuth column first)
-__device__ inline bool ray_coords(uint64_t r, const InstanceDev &in, int tile_az_log2, uint32_t &j, uint32_t &i) {
+// tile mapping: padded ray r of an instance -> (channel j, launch column k);
+// tiles are numbered column-major (channel rows of one column first)
+__device__ inline bool ray_coords(uint64_t r, const InstanceDev &in, int tile_az_log2, uint32_t &j, uint32_t &k) {
     uint32_t tile = (uint32_t)(r >> 6), lane = (uint32_t)(r & 63);
     uint32_t tcol = tile / in.tiles_ch, trow = tile - tcol * in.tiles_ch;
     uint32_t tile_ch = 64u >> tile_az_log2;
     j = trow * tile_ch + (lane >> tile_az_log2);
-    i = (tcol << tile_az_log2) + (lane & ((1u << tile_az_log2) - 1u));
-    return j < in.n_ch && i < in.n_az;
+    k = (tcol << tile_az_log2) + (lane & ((1u << tile_az_log2) - 1u));
+    return j < in.n_ch && k < in.n_cols;
 }
 
 // blockIdx -> logical block; see the file header for the XCD remap
@@ -334,9 +400,10 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
     __shared__ uint32_t stk[STACK * BLOCK];
     uint64_t r = (uint64_t)logical_block(xcd_remap) * BLOCK + threadIdx.x;
     if (r >= n_padded) return;
-    uint32_t j, i;
-    if (!ray_coords(r, in, tile_az_log2, j, i)) return;
-    Pose64 P = make_pose(in, ov.pose_delta);
+    uint32_t j, k, scan;
+    if (!ray_coords(r, in, tile_az_log2, j, k)) return;
+    uint32_t i = column_azimuth(in, k, scan);
+    Pose64 P = column_pose(in, ov.pose_delta, k);
     Ray ray = make_ray(in, P, j, i);
     bool overflow = false;
     Counts c{0u, 0u};
@@ -348,7 +415,7 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
         n_nodes[beam] = c.nodes;
         n_tris[beam] = c.tris;
     }
-    shade_and_write(in, M, ov, out, in.out_base + beam, beam, ray, S.tris, h);
+    shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -365,9 +432,10 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_quad_kernel(SceneDev S, Inst
     const uint32_t q = threadIdx.x >> 2, s = threadIdx.x & 3u;
     uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
     if (r >= n_padded) return;   // whole quad
-    uint32_t j, i;
-    if (!ray_coords(r, in, tile_az_log2, j, i)) return;   // whole quad
-    Pose64 P = make_pose(in, ov.pose_delta);
+    uint32_t j, k, scan;
+    if (!ray_coords(r, in, tile_az_log2, j, k)) return;   // whole quad
+    uint32_t i = column_azimuth(in, k, scan);
+    Pose64 P = column_pose(in, ov.pose_delta, k);
     Ray ray = make_ray(in, P, j, i);
     bool overflow = false;
     Counts c{0u, 0u};
@@ -380,7 +448,7 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_quad_kernel(SceneDev S, Inst
         n_nodes[beam] = c.nodes;
         n_tris[beam] = c.tris;
     }
-    shade_and_write(in, M, ov, out, in.out_base + beam, beam, ray, S.tris, h);
+    shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,10 +461,12 @@ __global__ __launch_bounds__(BLOCK) void bruteforce_kernel(SceneDev S, InstanceD
                                                            uint64_t n_padded) {
     __shared__ float4 lds[CHUNK * 3];
     uint64_t r = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
-    uint32_t j = 0, i = 0;
-    bool active = r < n_padded && ray_coords(r, in, tile_az_log2, j, i);
-    Pose64 P = make_pose(in, ov.pose_delta);
-    Ray ray = make_ray(in, P, active ? j : 0, active ? i : 0);
+    uint32_t j = 0, k = 0, scan = in.scan;
+    bool active = r < n_padded && ray_coords(r, in, tile_az_log2, j, k);
+    if (!active) j = k = 0;
+    uint32_t i = column_azimuth(in, k, scan);
+    Pose64 P = column_pose(in, ov.pose_delta, k);
+    Ray ray = make_ray(in, P, j, i);
     RayTri T = prep_tri_test(ray);
     Hit h{kNone, kNone, in.t_trace};
     const float4 *src = reinterpret_cast<const float4 *>(S.tris);
@@ -418,7 +488,7 @@ __global__ __launch_bounds__(BLOCK) void bruteforce_kernel(SceneDev S, InstanceD
     }
     if (!active) return;
     uint32_t beam = j * in.n_az + i;
-    shade_and_write(in, M, ov, out, in.out_base + beam, beam, ray, S.tris, h);
+    shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,9 +531,10 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
             uint64_t r = (uint64_t)pk * packet + sub + sub_lane;
             if ((uint64_t)pk * packet + sub >= n_padded_total) break;   // uniform over the wave
             const InstanceDev &in = insts[find_instance(insts, n_inst, r)];
-            uint32_t j, i;
-            if (!ray_coords(r - in.ray_base, in, tile_az_log2, j, i)) continue;
-            Pose64 P = make_pose(in, nullptr);
+            uint32_t j, k, scan;
+            if (!ray_coords(r - in.ray_base, in, tile_az_log2, j, k)) continue;
+            uint32_t i = column_azimuth(in, k, scan);
+            Pose64 P = column_pose(in, nullptr, k);
             Ray ray = make_ray(in, P, j, i);
             Hit h;
             if (QUAD)
@@ -474,7 +545,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
                                                   overflow, cnt);
             if (QUAD && s != 0) continue;
             uint32_t beam = j * in.n_az + i;
-            shade_and_write(in, M, ov, out, in.out_base + beam, beam, ray, S.tris, h);
+            shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
         }
     }
     if (overflow) atomicOr(err, 1u);

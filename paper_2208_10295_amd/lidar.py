@@ -206,6 +206,31 @@ class Context:
         check(st, self.h)
         return out
 
+    def simulate_sweep(self, seed: int, head_deg: float, spin_hz: float, dt_s: float, pose_begin, pose_end,
+                       out: dict | None = None, debug: bool = False, stream=None):
+        """One engine tick: traces the columns the head fires over
+        [head_deg, head_deg + 360 spin_hz dt_s) with rolling-shutter poses
+        interpolated from pose_begin = (p, q) to pose_end = (p, q).  Writes the
+        fired columns' beams into the [n_ch][n_az] outputs `out` (allocated and
+        zero-filled if None) and returns (out, info) with info = the fired runs
+        [(scan, first_azimuth, count), ...]."""
+        if out is None:
+            out = alloc_outputs(self.n_beams, POINT_OUTPUTS + (DEBUG_OUTPUTS if debug else ()), self.device)
+            for t in out.values():
+                t.zero_()
+        d = A.SweepDesc()
+        d.head_deg, d.spin_hz, d.dt_s, d.seed = float(head_deg), float(spin_hz), float(dt_s), int(seed)
+        for name, val in (("p_begin", pose_begin[0]), ("q_begin", pose_begin[1]), ("p_end", pose_end[0]),
+                          ("q_end", pose_end[1])):
+            arr = getattr(d, name)
+            for k, x in enumerate(np.asarray(val, dtype=np.float32).reshape(-1)):
+                arr[k] = float(x)
+        info = A.SweepInfo()
+        o = outputs_struct(out)
+        check(lib.lidar_simulate_sweep(self.h, C.byref(d), C.byref(o), C.byref(info), _stream(stream)), self.h)
+        runs = [(int(info.scan[r]), int(info.first[r]), int(info.count[r])) for r in range(info.n_runs)]
+        return out, runs
+
     def simulate_counts(self, seed: int = 0, scan: int = 0, stream=None):
         """One scan plus per-beam (node visits, triangle tests) of the traversal."""
         out = alloc_outputs(self.n_beams, POINT_OUTPUTS, self.device)
