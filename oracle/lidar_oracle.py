@@ -198,6 +198,24 @@ def reflectance_at_wavelength(spectra, wavelength_nm, lambda0_nm=400.0, dlambda_
     return (1.0 - f) * T[:, i] + f * T[:, i + 1], False
 
 
+def spectral_weights(nbins, wavelength_nm, lambda0_nm=400.0, dlambda_nm=10.0) -> np.ndarray:
+    """w[nbins] such that R_lambda(0) = T w for every material row T: the linear
+    interpolation weights of ``reflectance_at_wavelength`` ((1 - f) on bin i,
+    f on bin i + 1; all weight on the end bin outside the table)."""
+    w = np.zeros(nbins)
+    q = (float(wavelength_nm) - lambda0_nm) / dlambda_nm
+    if q <= 0.0:
+        w[0] = 1.0
+    elif q >= nbins - 1:
+        w[nbins - 1] = 1.0
+    else:
+        i = int(math.floor(q))
+        f = q - i
+        w[i] = 1.0 - f
+        w[i + 1] = f
+    return w
+
+
 # ----------------------------------------------------------------------------
 # step 5: counter-based Gaussian noise [II-A]
 # ----------------------------------------------------------------------------
@@ -551,3 +569,18 @@ def calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_
     d_left = np.sum(gamma[:, None] * np.cross(d, n), axis=0)
     d_w = so3_left_jacobian(dw).T @ d_left
     return d_rho, d_k, np.concatenate([d_p, d_w])
+
+
+def calib_grad_spectral(scene, sensor, pose_ref, tri, beams, spectra, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0):
+    """Gradient of ``calib_loss`` with R_lambda(0) taken from the spectral table
+    at the sensor wavelength: returns (d_spectra[nmat, nbins], d_k, d_pose6).
+
+    R_lambda(0)_m = sum_b w_b T[m, b] with the interpolation weights w of the
+    sensor wavelength, so dL/dT[m, b] = w_b dL/dR_lambda(0)_m: only the one or
+    two bins around the wavelength receive gradient.
+    """
+    T = np.asarray(spectra, np.float64)
+    rho = reflectance_at_wavelength(T, sensor.wavelength_nm)[0]
+    d_rho, d_k, d_pose = calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d)
+    w = spectral_weights(T.shape[1], sensor.wavelength_nm)
+    return np.outer(d_rho, w), d_k, d_pose

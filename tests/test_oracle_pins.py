@@ -472,3 +472,35 @@ def test_adjoint_special_cases():
                                       np.array([0.4]), np.array([9.0]), lam_d=1.0)
     assert np.allclose(g_pose[:3], [0, 0, 2.0], atol=1e-9)
     assert np.allclose(g_pose[3:], 0, atol=1e-9)
+
+
+def test_spectral_adjoint_matches_central_differences_on_the_table():
+    """dL/dT[m, b] through the interpolation at the sensor wavelength, against
+    central differences of the loss with R_lambda(0) re-read from the perturbed
+    table: on a bin centre, between bins, and clamped below and above the table."""
+    import dataclasses
+    c5, beams, tri, I_t, t_t = _calib_problem(n_beams=1500, seed=1)
+    scene, pose = c5["scene"], c5["pose_true"]
+    T = scene.spectra.astype(np.float64)
+    kexp = c5["k0"].astype(np.float64) + 0.2
+    dp, dw = np.array(c5["dp0"]) * 0.05, np.array(c5["dw0"]) * 0.05
+    for lam, hot in ((900.0, (50,)), (905.0, (50, 51)), (931.0, (53, 54)), (380.0, (0,)), (1550.0, (60,))):
+        sensor = dataclasses.replace(c5["sensor"], wavelength_nm=lam)
+        args = (scene, sensor, pose, tri, beams)
+        g_T, g_k, g_pose = O.calib_grad_spectral(*args, T, kexp, dp, dw, I_t, t_t)
+        rho_of = lambda TT: O.reflectance_at_wavelength(TT, lam)[0]   # noqa: E731
+        g_rho, g_k2, g_pose2 = O.calib_grad(*args, rho_of(T), kexp, dp, dw, I_t, t_t)
+        assert np.array_equal(g_k, g_k2) and np.array_equal(g_pose, g_pose2)
+        cold = [b for b in (0, 10, 25, 49, 52, 55, 59, 60) if b not in hot]
+        h = 1e-6
+        for m in (0, 3, 11):
+            for b in list(hot) + cold[:3]:
+                Tp, Tm = T.copy(), T.copy()
+                Tp[m, b] += h
+                Tm[m, b] -= h
+                lp = O.calib_loss(*args, rho_of(Tp), kexp, dp, dw, I_t, t_t)
+                lm = O.calib_loss(*args, rho_of(Tm), kexp, dp, dw, I_t, t_t)
+                fd = (lp - lm) / (2 * h)
+                assert abs(g_T[m, b] - fd) <= 1e-6 * max(1.0, abs(fd)), (lam, m, b, g_T[m, b], fd)
+        assert np.count_nonzero(g_T.sum(axis=0)) == len(hot)
+        assert np.all(g_T[:, [b for b in range(61) if b not in hot]] == 0)
