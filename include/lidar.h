@@ -205,6 +205,8 @@ typedef struct {
     const float *rho;          /* [nmat] R_lambda(0) per material, used instead of the spectral table */
     const float *angle_exp;    /* [nmat] exponent k per material (cos^k) */
     const float *pose_delta;   /* [6] (dp, dw): p = p0 + dp, R = Exp(dw) R(q0) */
+    const float *spectra;      /* [nmat][nbins] spectral table used instead of the one of
+                                  lidar_materials_set (same lambda0, dlambda, nbins); not with rho */
 } lidar_params;
 
 /* One scan of the current sensor at the current pose.  Gaussian noise comes
@@ -293,9 +295,9 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep,
  *   LIDAR_OPT_TILE_AZ: beams are traced in 64-beam tiles of `value` azimuth
  *     steps x 64 / value channels (power of two in 1..64; default 16).  A batch
  *     keeps the tile shape that was current when it was created.
- *   LIDAR_OPT_LANES_PER_RAY: 1 = one lane walks the BVH for a beam; 4 = the
- *     four lanes of a quad share a beam, one child box or triangle each
- *     (default 4).
+ *   LIDAR_OPT_LANES_PER_RAY: 1 = one lane walks the BVH for a beam; 2 = two
+ *     lanes share a beam, two child boxes each; 4 = the four lanes of a quad
+ *     share a beam, one child box each (default 4).
  *   LIDAR_OPT_XCD_REMAP: 1 = the thread blocks that run on one XCD take one
  *     contiguous azimuth sector (default 1); 0 = blocks in launch order. */
 #define LIDAR_OPT_TILE_AZ        1u
@@ -354,7 +356,7 @@ typedef struct {
     uint32_t n_packet;
     const uint32_t *leaf_widths;   /* host [n_leaf] candidates (1..8) */
     uint32_t n_leaf;
-    const uint32_t *lanes_per_ray; /* host [n_lanes] candidates (1 or 4); NULL = current only */
+    const uint32_t *lanes_per_ray; /* host [n_lanes] candidates (1, 2 or 4); NULL = current only */
     uint32_t n_lanes;
     uint32_t reps;                 /* timed repetitions per candidate (median) */
 } lidar_tune_desc;
@@ -396,6 +398,21 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
 lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
                             const uint8_t *valid, const float *dL_dI, const float *dL_drange,
                             float *d_rho, float *d_k, float *d_pose6, void *stream);
+
+/* Full-spectrum adjoint: as lidar_backward, with R_lambda(0) read from the
+ * spectral table (params->spectra, else the table of lidar_materials_set) at
+ * the sensor wavelength.  Eq.4's R_lambda(0)_m = sum_b w_b T[m][b] with the
+ * linear interpolation weights w of the wavelength (Section II-C: the
+ * reflectance for the wavelength in use; clamped to the end bin outside the
+ * table), so dL/dT[m][b] = w_b dL/dR_lambda(0)_m.  Writes d_spectra[nmat][nbins]
+ * (device FP32; zero on bins the wavelength does not touch), d_k and d_pose6 as
+ * lidar_backward (either may be NULL).  Gradients of scans at several
+ * wavelengths add up to the multi-wavelength gradient.  Errors: INVALID_ARG if
+ * params->rho is set or d_spectra is NULL; otherwise as lidar_backward.
+ * Asynchronous. */
+lidar_status lidar_backward_spectra(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
+                                    const uint8_t *valid, const float *dL_dI, const float *dL_drange,
+                                    float *d_spectra, float *d_k, float *d_pose6, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Introspection                                                             */

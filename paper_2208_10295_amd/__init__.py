@@ -5,4 +5,4 @@ is its Python binding.  Importing it loads the library and raises if it has
 not been built (``python paper_2208_10295_amd/build.py``).
 """
 from ._abi import LidarError, NO_LABEL, NO_TRIANGLE, NO_MATERIAL  # noqa: F401
-from .lidar import Batch, Context, LidarReturn, alloc_outputs, as_u32  # noqa: F401
+from .lidar import Batch, Context, LidarReturn, LidarSpectralReturn, alloc_outputs, as_u32  # noqa: F401

@@ -69,7 +69,7 @@ class Outputs(C.Structure):
 
 
 class Params(C.Structure):
-    _fields_ = [("rho", P), ("angle_exp", P), ("pose_delta", P)]
+    _fields_ = [("rho", P), ("angle_exp", P), ("pose_delta", P), ("spectra", P)]
 
 
 class Instance(C.Structure):
@@ -129,6 +129,7 @@ SIGNATURES = {
     "lidar_tune": (C.c_int32, [P, C.POINTER(SceneDesc), P, C.c_uint64, P, C.c_uint64, P, C.POINTER(Outputs),
                                C.POINTER(TuneDesc), C.POINTER(TuneResult), P]),
     "lidar_backward": (C.c_int32, [P, C.POINTER(Params), P, P, P, P, P, P, P, P]),
+    "lidar_backward_spectra": (C.c_int32, [P, C.POINTER(Params), P, P, P, P, P, P, P, P]),
     "lidar_get_stats": (C.c_int32, [P, C.POINTER(Stats)]),
     "lidar_sync_check": (C.c_int32, [P, P]),
     "lidar_debug_copy_bvh": (C.c_int32, [P, P, C.c_uint64, P, C.c_uint64]),

@@ -62,20 +62,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(SceneDev S, const ui
               qz = (float)((double)r.a.z - P.p[2]);
         float t = fmaf(nx, qx, fmaf(ny, qy, nz * qz)) / c;
         float ac = fabsf(c);
-        float rho;
-        if (ov.rho) {
-            rho = ov.rho[m];
-        } else {
-            float q = (in.wavelength_nm - M.lambda0) / M.dlambda;
-            const float *T = M.spectra + (size_t)m * M.nbins;
-            if (q <= 0.0f) rho = T[0];
-            else if (q >= (float)(M.nbins - 1)) rho = T[M.nbins - 1];
-            else {
-                int i0 = (int)floorf(q);
-                float f = q - (float)i0;
-                rho = fmaf(f, T[i0 + 1], (1.0f - f) * T[i0]);
-            }
-        }
+        float rho = reflectance0(ov, M, in.wavelength_nm, m);
         float k = ov.angle_exp ? ov.angle_exp[m] : M.angle_exp[m];
         float lnc = logf(ac);
         float ck = (k == 1.0f) ? ac : expf(k * lnc);              // |c|^k
@@ -140,12 +127,35 @@ __global__ __launch_bounds__(256) void adjoint_sum_kernel(const double *__restri
     if (threadIdx.x == 0) tot[o] = red[0];
 }
 
+// Spectral form (d_spectra non-null): dL/dT[m][b] = w_b dL/dR_lambda(0)_m with
+// the interpolation weights w of the wavelength, computed as in the forward.
 __global__ __launch_bounds__(64) void adjoint_final_kernel(const double *__restrict__ tot, uint32_t nmat,
                                                            const float *__restrict__ pose_delta, float *d_rho,
-                                                           float *d_k, float *d_pose6) {
+                                                           float *d_k, float *d_pose6, float *d_spectra,
+                                                           MaterialsDev M, float wavelength_nm) {
     for (uint32_t o = threadIdx.x; o < nmat; o += blockDim.x) {
         if (d_rho) d_rho[o] = (float)tot[o];
         if (d_k) d_k[o] = (float)tot[nmat + o];
+    }
+    if (d_spectra) {
+        float q = (wavelength_nm - M.lambda0) / M.dlambda;
+        int b0, b1;
+        float w0, w1;
+        if (q <= 0.0f) { b0 = b1 = 0; w0 = 1.0f; w1 = 0.0f; }
+        else if (q >= (float)(M.nbins - 1)) { b0 = b1 = (int)M.nbins - 1; w0 = 1.0f; w1 = 0.0f; }
+        else {
+            b0 = (int)floorf(q);
+            b1 = b0 + 1;
+            w1 = q - (float)b0;
+            w0 = 1.0f - w1;
+        }
+        const uint32_t n = nmat * M.nbins;
+        for (uint32_t o = threadIdx.x; o < n; o += blockDim.x) {
+            uint32_t m = o / M.nbins, b = o - m * M.nbins;
+            double g = tot[m];
+            double v = (b == (uint32_t)b0 ? (double)w0 * g : 0.0) + (b == (uint32_t)b1 && b1 != b0 ? (double)w1 * g : 0.0);
+            d_spectra[o] = (float)v;
+        }
     }
     if (threadIdx.x == 0 && d_pose6) {
         const double *g = tot + 2 * nmat;
@@ -177,14 +187,16 @@ size_t adjoint_partial_bytes(uint32_t n_beams, uint32_t nmat) {
 
 void launch_adjoint(const SceneDev &S, const uint32_t *slot_of, const InstanceDev &in, const MaterialsDev &M,
                     const Overrides &ov, const uint32_t *tri, const uint8_t *valid, const float *gI,
-                    const float *gd, double *partials, float *d_rho, float *d_k, float *d_pose6, hipStream_t s) {
+                    const float *gd, double *partials, float *d_rho, float *d_k, float *d_pose6, float *d_spectra,
+                    hipStream_t s) {
     uint32_t nb = in.n_ch * in.n_az;
     uint32_t blocks = (nb + kAdjBlock - 1) / kAdjBlock;
     uint32_t n_out = 2 * M.nmat + 6;
     double *tot = partials + (size_t)blocks * n_out;
     adjoint_kernel<<<blocks, kAdjBlock, 0, s>>>(S, slot_of, in, M, ov, tri, valid, gI, gd, partials);
     adjoint_sum_kernel<<<n_out, 256, 0, s>>>(partials, blocks, n_out, tot);
-    adjoint_final_kernel<<<1, 64, 0, s>>>(tot, M.nmat, ov.pose_delta, d_rho, d_k, d_pose6);
+    adjoint_final_kernel<<<1, 64, 0, s>>>(tot, M.nmat, ov.pose_delta, d_rho, d_k, d_pose6, d_spectra, M,
+                                          in.wavelength_nm);
 }
 
 }  // namespace lidar

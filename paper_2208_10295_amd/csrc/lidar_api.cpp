@@ -487,9 +487,12 @@ static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan
     InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, ctx->p, ctx->q, seed, scan, 0, 0, 0);
     Overrides ov{};
     if (params) {
+        if (params->rho && params->spectra)
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "params: give rho or spectra, not both");
         ov.rho = params->rho;
         ov.angle_exp = params->angle_exp;
         ov.pose_delta = params->pose_delta;
+        ov.spectra = params->spectra;
     }
     uint64_t nb = (uint64_t)d.n_ch * d.n_az;
     Outputs o = to_outputs(out, nb);
@@ -765,7 +768,8 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
         if (desc->leaf_widths[i] < 1 || desc->leaf_widths[i] > 8)
             return ctx->fail(LIDAR_ERR_INVALID_ARG, "leaf widths must be in 1..8");
     for (uint32_t i = 0; i < n_lanes; ++i)
-        if (lanes[i] != 1 && lanes[i] != 4) return ctx->fail(LIDAR_ERR_INVALID_ARG, "lanes per ray must be 1 or 4");
+        if (lanes[i] != 1 && lanes[i] != 2 && lanes[i] != 4)
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "lanes per ray must be 1, 2 or 4");
     uint32_t reps = desc->reps ? desc->reps : 5;
     hipStream_t s = (hipStream_t)stream;
     std::memset(res, 0, sizeof *res);
@@ -821,14 +825,16 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
 // ---------------------------------------------------------------------------
 // adjoint
 // ---------------------------------------------------------------------------
-lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri, const uint8_t *valid,
-                            const float *dL_dI, const float *dL_drange, float *d_rho, float *d_k, float *d_pose6,
-                            void *stream) {
+static lidar_status backward_common(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
+                                    const uint8_t *valid, const float *dL_dI, const float *dL_drange, float *d_rho,
+                                    float *d_k, float *d_pose6, float *d_spectra, void *stream) {
     lidar_status st = ready(ctx, true);
     if (st != LIDAR_OK) return st;
     if (!tri) return ctx->fail(LIDAR_ERR_NO_FORWARD_STATE, "backward needs the forward's triangle ids (tri)");
     if (!valid) return ctx->fail(LIDAR_ERR_NO_FORWARD_STATE, "backward needs the forward's valid mask");
     if (ctx->M.nmat > kMaxAdjMaterials) return ctx->fail(LIDAR_ERR_INVALID_ARG, "backward supports nmat <= 256");
+    if (params && params->rho && params->spectra)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "params: give rho or spectra, not both");
     const lidar_sensor_desc &d = ctx->sensor.d;
     size_t pb = adjoint_partial_bytes(d.n_ch * d.n_az, ctx->M.nmat);
     if (ctx->adj_partials.n < pb) return ctx->fail(LIDAR_ERR_NOT_READY, "adjoint buffer not allocated");
@@ -840,13 +846,30 @@ lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const ui
         ov.rho = params->rho;
         ov.angle_exp = params->angle_exp;
         ov.pose_delta = params->pose_delta;
+        ov.spectra = params->spectra;
     }
     hipSetDevice(ctx->device);
     launch_adjoint(ctx->S, ctx->slot_of, in, ctx->M, ov, tri, valid, dL_dI, dL_drange, (double *)ctx->adj_partials.p,
-                   d_rho, d_k, d_pose6, (hipStream_t)stream);
+                   d_rho, d_k, d_pose6, d_spectra, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "adjoint launch");
     return LIDAR_OK;
+}
+
+lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri, const uint8_t *valid,
+                            const float *dL_dI, const float *dL_drange, float *d_rho, float *d_k, float *d_pose6,
+                            void *stream) {
+    return backward_common(ctx, params, tri, valid, dL_dI, dL_drange, d_rho, d_k, d_pose6, nullptr, stream);
+}
+
+lidar_status lidar_backward_spectra(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
+                                    const uint8_t *valid, const float *dL_dI, const float *dL_drange,
+                                    float *d_spectra, float *d_k, float *d_pose6, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (params && params->rho) return ctx->fail(LIDAR_ERR_INVALID_ARG, "the spectral adjoint reads R_lambda(0) "
+                                                                       "from the table: params->rho must be NULL");
+    if (!d_spectra) return ctx->fail(LIDAR_ERR_INVALID_ARG, "d_spectra is null");
+    return backward_common(ctx, params, tri, valid, dL_dI, dL_drange, nullptr, d_k, d_pose6, d_spectra, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -911,7 +934,8 @@ lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
         return LIDAR_OK;
     }
     case LIDAR_OPT_LANES_PER_RAY:
-        if (value != 1 && value != 4) return ctx->fail(LIDAR_ERR_INVALID_ARG, "lanes per ray must be 1 or 4");
+        if (value != 1 && value != 2 && value != 4)
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "lanes per ray must be 1, 2 or 4");
         ctx->lanes_per_ray = value;
         return LIDAR_OK;
     case LIDAR_OPT_XCD_REMAP:

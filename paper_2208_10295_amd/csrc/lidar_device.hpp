@@ -89,7 +89,21 @@ struct Overrides {
     const float *rho;          // [nmat] or null
     const float *angle_exp;    // [nmat] or null
     const float *pose_delta;   // [6] or null
+    const float *spectra;      // [nmat][nbins] or null (replaces the material table)
 };
+
+// R_lambda(0) of material m: the override, else the spectral table at the
+// wavelength, interpolated linearly between bins and clamped at the ends.
+__device__ inline float reflectance0(const Overrides &ov, const MaterialsDev &M, float wavelength_nm, uint32_t m) {
+    if (ov.rho) return ov.rho[m];
+    float q = (wavelength_nm - M.lambda0) / M.dlambda;
+    const float *T = (ov.spectra ? ov.spectra : M.spectra) + (size_t)m * M.nbins;
+    if (q <= 0.0f) return T[0];
+    if (q >= (float)(M.nbins - 1)) return T[M.nbins - 1];
+    int i0 = (int)floorf(q);
+    float f = q - (float)i0;
+    return fmaf(f, T[i0 + 1], (1.0f - f) * T[i0]);
+}
 
 struct Outputs {
     float *x, *y, *z, *intensity;

@@ -92,6 +92,7 @@ constexpr int kAdjBlock = 256;
 size_t adjoint_partial_bytes(uint32_t n_beams, uint32_t nmat);
 void launch_adjoint(const SceneDev &S, const uint32_t *slot_of, const InstanceDev &in, const MaterialsDev &M,
                     const Overrides &ov,
-                    const uint32_t *tri, const uint8_t *valid, const float *gI, const float *gd, double *partials, float *d_rho, float *d_k, float *d_pose6, hipStream_t s);
+                    const uint32_t *tri, const uint8_t *valid, const float *gI, const float *gd, double *partials,
+                    float *d_rho, float *d_k, float *d_pose6, float *d_spectra, hipStream_t s);
 
 }  // namespace lidar

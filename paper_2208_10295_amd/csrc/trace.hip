@@ -226,12 +226,18 @@ __device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__
 }
 
 // ---------------------------------------------------------------------------
-// quad-per-ray traversal: lane s = threadIdx.x & 3 of the quad
+// multi-lane traversal: LANES (2 or 4) adjacent lanes of one DPP quad share a
+// beam; lane s = lane % LANES tests child boxes s * 4 / LANES .. (one 32-byte
+// slot each, so the lanes of a beam read one 128-byte node line together) and
+// the triangles s, s + LANES, ... of a leaf.  The lanes exchange their keys
+// through quad_perm DPP moves, put the four children in node order and run the
+// same sorting network, so they agree on the order without further exchanges.
 // ---------------------------------------------------------------------------
-template <int STACK, int NSLOT, bool COUNT>
-__device__ inline Hit traverse_quad(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
-                                    uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
-                                    uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt) {
+template <int LANES, int STACK, int NSLOT, bool COUNT>
+__device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
+                                     uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
+                                     uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt) {
+    static_assert(LANES == 2 || LANES == 4, "2 or 4 lanes per beam");
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
     const float inf = __builtin_inff();
@@ -246,7 +252,7 @@ __device__ inline Hit traverse_quad(const Node4 *__restrict__ nodes, const TriRe
             if (COUNT) cnt.tris += n;
             float bt = inf;
             uint32_t bo = kNone, bs = kNone;
-            for (uint32_t k = s; k < n; k += 4) {
+            for (uint32_t k = s; k < n; k += LANES) {
                 const TriRec *r = tris + first + k;
                 float4 a = r->a, b = r->b, c = r->c;
                 float t;
@@ -255,27 +261,45 @@ __device__ inline Hit traverse_quad(const Node4 *__restrict__ nodes, const TriRe
                     if (better(t, orig, bt, bo)) { bt = t; bo = orig; bs = first + k; }
                 }
             }
-            // lexicographic (t, orig) minimum over the quad
+            // lexicographic (t, orig) minimum over the beam's lanes
             {
                 float ot = __uint_as_float(quad_xor1(__float_as_uint(bt)));
                 uint32_t oo = quad_xor1(bo), os = quad_xor1(bs);
                 if (better(ot, oo, bt, bo)) { bt = ot; bo = oo; bs = os; }
-                ot = __uint_as_float(quad_xor2(__float_as_uint(bt)));
-                oo = quad_xor2(bo);
-                os = quad_xor2(bs);
-                if (better(ot, oo, bt, bo)) { bt = ot; bo = oo; bs = os; }
+                if (LANES == 4) {
+                    ot = __uint_as_float(quad_xor2(__float_as_uint(bt)));
+                    oo = quad_xor2(bo);
+                    os = quad_xor2(bs);
+                    if (better(ot, oo, bt, bo)) { bt = ot; bo = oo; bs = os; }
+                }
             }
             if (better(bt, bo, h.t, h.orig)) { h.t = bt; h.orig = bo; h.slot = bs; }
         } else {
             if (COUNT) cnt.nodes += 1;
-            const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 2 * s;
-            float4 a = np[0], b = np[1];
-            float key = slab(B, a, b, t_lo, box_limit(h.t));
-            uint32_t cref = __float_as_uint(a.w);
-            float k0 = quad_bcast<0>(key), k1 = quad_bcast<1>(key), k2 = quad_bcast<2>(key),
-                  k3 = quad_bcast<3>(key);
-            uint32_t c0 = quad_bcast<0>(cref), c1 = quad_bcast<1>(cref), c2 = quad_bcast<2>(cref),
-                     c3 = quad_bcast<3>(cref);
+            float k0, k1, k2, k3;
+            uint32_t c0, c1, c2, c3;
+            if (LANES == 4) {
+                const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 2 * s;
+                float4 a = np[0], b = np[1];
+                float key = slab(B, a, b, t_lo, box_limit(h.t));
+                uint32_t cref = __float_as_uint(a.w);
+                k0 = quad_bcast<0>(key); k1 = quad_bcast<1>(key); k2 = quad_bcast<2>(key); k3 = quad_bcast<3>(key);
+                c0 = quad_bcast<0>(cref); c1 = quad_bcast<1>(cref); c2 = quad_bcast<2>(cref); c3 = quad_bcast<3>(cref);
+            } else {
+                const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 4 * s;
+                float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3];
+                float lim = box_limit(h.t);
+                float ka = slab(B, a0, b0, t_lo, lim), kb = slab(B, a1, b1, t_lo, lim);
+                uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
+                float oa = __uint_as_float(quad_xor1(__float_as_uint(ka)));
+                float ob = __uint_as_float(quad_xor1(__float_as_uint(kb)));
+                uint32_t oca = quad_xor1(ca), ocb = quad_xor1(cb);
+                const bool lo = (s == 0);   // lane 0 holds children 0, 1; lane 1 children 2, 3
+                k0 = lo ? ka : oa; c0 = lo ? ca : oca;
+                k1 = lo ? kb : ob; c1 = lo ? cb : ocb;
+                k2 = lo ? oa : ka; c2 = lo ? oca : ca;
+                k3 = lo ? ob : kb; c3 = lo ? ocb : cb;
+            }
             sort4(k0, c0, k1, c1, k2, c2, k3, c3);
             if (k0 != inf) {
                 if (k3 != inf) { if (sp < STACK) { if (s == 0) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
@@ -318,21 +342,7 @@ __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev
         nx = cx / len; ny = cy / len; nz = cz / len;
         float cd = fmaf(nx, ray.dx, fmaf(ny, ray.dy, nz * ray.dz));
         float cs = fabsf(cd);
-        // R_lambda(0): per-material override, else spectral table at lambda
-        float r0;
-        if (ov.rho) {
-            r0 = ov.rho[m];
-        } else {
-            float q = (in.wavelength_nm - M.lambda0) / M.dlambda;
-            const float *T = M.spectra + (size_t)m * M.nbins;
-            if (q <= 0.0f) r0 = T[0];
-            else if (q >= (float)(M.nbins - 1)) r0 = T[M.nbins - 1];
-            else {
-                int i0 = (int)floorf(q);
-                float f = q - (float)i0;
-                r0 = fmaf(f, T[i0 + 1], (1.0f - f) * T[i0]);
-            }
-        }
+        float r0 = reflectance0(ov, M, in.wavelength_nm, m);
         float kx = ov.angle_exp ? ov.angle_exp[m] : M.angle_exp[m];
         rl = (kx == 1.0f) ? r0 * cs : r0 * exp2f(kx * log2f(cs));
         float zd = 0.0f, zi = 0.0f, sig = 0.0f, sig_i = 0.0f;
@@ -391,7 +401,22 @@ __device__ inline uint32_t logical_block(int xcd_remap) {
 // ---------------------------------------------------------------------------
 // Kernel 1: one scan, lane per ray
 // ---------------------------------------------------------------------------
-template <int STACK, int BLOCK, bool COUNT>
+// The beam of padded ray r: channel j, azimuth i, scan counter and pose.  A
+// scan uses the instance pose (with the calibration delta); a sweep maps the
+// launch column to (azimuth, scan) and reads the column's pose.
+template <bool SWEEP>
+__device__ inline Ray beam_ray(const InstanceDev &in, const Overrides &ov, uint32_t j, uint32_t k, uint32_t &i,
+                               uint32_t &scan) {
+    if (SWEEP) {
+        i = column_azimuth(in, k, scan);
+        return make_ray(in, column_pose(in, nullptr, k), j, i);
+    }
+    i = k;
+    scan = in.scan;
+    return make_ray(in, make_pose(in, ov.pose_delta), j, i);
+}
+
+template <int STACK, int BLOCK, bool COUNT, bool SWEEP>
 __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
                                                            Overrides ov, Outputs out, int tile_az_log2,
                                                            uint64_t n_padded, int xcd_remap, uint32_t *err,
@@ -400,11 +425,9 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
     __shared__ uint32_t stk[STACK * BLOCK];
     uint64_t r = (uint64_t)logical_block(xcd_remap) * BLOCK + threadIdx.x;
     if (r >= n_padded) return;
-    uint32_t j, k, scan;
+    uint32_t j, k, i, scan;
     if (!ray_coords(r, in, tile_az_log2, j, k)) return;
-    uint32_t i = column_azimuth(in, k, scan);
-    Pose64 P = column_pose(in, ov.pose_delta, k);
-    Ray ray = make_ray(in, P, j, i);
+    Ray ray = beam_ray<SWEEP>(in, ov, j, k, i, scan);
     bool overflow = false;
     Counts c{0u, 0u};
     Hit h = traverse<STACK, BLOCK, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + threadIdx.x,
@@ -419,28 +442,26 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
 }
 
 // ---------------------------------------------------------------------------
-// Kernel 1q: one scan, quad per ray (BLOCK threads = BLOCK / 4 rays)
+// Kernel 1m: one scan, LANES (2 or 4) lanes per ray (BLOCK / LANES rays)
 // ---------------------------------------------------------------------------
-template <int STACK, int BLOCK, bool COUNT>
-__global__ __launch_bounds__(BLOCK) void trace_scan_quad_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
-                                                                Overrides ov, Outputs out, int tile_az_log2,
-                                                                uint64_t n_padded, int xcd_remap, uint32_t *err,
-                                                                uint32_t *__restrict__ n_nodes,
-                                                                uint32_t *__restrict__ n_tris) {
-    constexpr int NR = BLOCK / 4;
+template <int STACK, int BLOCK, int LANES, bool COUNT, bool SWEEP>
+__global__ __launch_bounds__(BLOCK) void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
+                                                                 Overrides ov, Outputs out, int tile_az_log2,
+                                                                 uint64_t n_padded, int xcd_remap, uint32_t *err,
+                                                                 uint32_t *__restrict__ n_nodes,
+                                                                 uint32_t *__restrict__ n_tris) {
+    constexpr int NR = BLOCK / LANES;
     __shared__ uint32_t stk[STACK * NR];
-    const uint32_t q = threadIdx.x >> 2, s = threadIdx.x & 3u;
+    const uint32_t q = threadIdx.x / LANES, s = threadIdx.x % LANES;
     uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
-    if (r >= n_padded) return;   // whole quad
-    uint32_t j, k, scan;
-    if (!ray_coords(r, in, tile_az_log2, j, k)) return;   // whole quad
-    uint32_t i = column_azimuth(in, k, scan);
-    Pose64 P = column_pose(in, ov.pose_delta, k);
-    Ray ray = make_ray(in, P, j, i);
+    if (r >= n_padded) return;   // all lanes of the beam
+    uint32_t j, k, i, scan;
+    if (!ray_coords(r, in, tile_az_log2, j, k)) return;   // all lanes of the beam
+    Ray ray = beam_ray<SWEEP>(in, ov, j, k, i, scan);
     bool overflow = false;
     Counts c{0u, 0u};
-    Hit h = traverse_quad<STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q, s,
-                                            overflow, c);
+    Hit h = traverse_multi<LANES, STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace,
+                                                    stk + q, s, overflow, c);
     if (overflow) atomicOr(err, 1u);
     if (s != 0) return;
     uint32_t beam = j * in.n_az + i;
@@ -506,19 +527,19 @@ __device__ inline uint32_t find_instance(const InstanceDev *__restrict__ insts, 
     return lo;
 }
 
-template <int STACK, int BLOCK, bool QUAD>
+template <int STACK, int BLOCK, int LANES>
 __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts,
                                                             uint32_t n_inst, MaterialsDev M, Outputs out,
                                                             int tile_az_log2, uint64_t n_padded_total,
                                                             uint32_t packet, uint32_t *queue, uint32_t *err) {
-    constexpr int NSLOT = QUAD ? BLOCK / 4 : BLOCK;
-    constexpr uint32_t RAYS_PER_WAVE = QUAD ? 16u : 64u;
+    constexpr int NSLOT = BLOCK / LANES;
+    constexpr uint32_t RAYS_PER_WAVE = 64u / LANES;
     __shared__ uint32_t stk[STACK * NSLOT];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t slot = QUAD ? (threadIdx.x >> 2) : threadIdx.x;
-    const uint32_t sub_lane = QUAD ? (lane >> 2) : lane;
-    const uint32_t s = threadIdx.x & 3u;
-    const Overrides ov{nullptr, nullptr, nullptr};
+    const uint32_t slot = threadIdx.x / LANES;
+    const uint32_t sub_lane = lane / LANES;
+    const uint32_t s = threadIdx.x % LANES;
+    const Overrides ov{nullptr, nullptr, nullptr, nullptr};
     const uint64_t n_packets = (n_padded_total + packet - 1) / packet;
     bool overflow = false;
     Counts cnt{0u, 0u};
@@ -531,19 +552,17 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
             uint64_t r = (uint64_t)pk * packet + sub + sub_lane;
             if ((uint64_t)pk * packet + sub >= n_padded_total) break;   // uniform over the wave
             const InstanceDev &in = insts[find_instance(insts, n_inst, r)];
-            uint32_t j, k, scan;
+            uint32_t j, k, i, scan;
             if (!ray_coords(r - in.ray_base, in, tile_az_log2, j, k)) continue;
-            uint32_t i = column_azimuth(in, k, scan);
-            Pose64 P = column_pose(in, nullptr, k);
-            Ray ray = make_ray(in, P, j, i);
+            Ray ray = beam_ray<false>(in, ov, j, k, i, scan);   // batch instances are whole scans
             Hit h;
-            if (QUAD)
-                h = traverse_quad<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + slot,
-                                                       s, overflow, cnt);
+            if constexpr (LANES == 1)
+                h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace,
+                                                  stk + slot, overflow, cnt);
             else
-                h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + slot,
-                                                  overflow, cnt);
-            if (QUAD && s != 0) continue;
+                h = traverse_multi<LANES, STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
+                                                               in.t_trace, stk + slot, s, overflow, cnt);
+            if (s != 0) continue;
             uint32_t beam = j * in.n_az + i;
             shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
         }
@@ -556,37 +575,47 @@ __global__ void reset_queue_kernel(uint32_t *queue) { *queue = 0u; }
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-constexpr int kBlock = 128;       // lane-per-ray block (2 waves)
+constexpr int kBlock = 128;       // lane-per-ray block (2 waves, 128 rays)
+constexpr int kPairBlock = 128;   // pair-per-ray block (2 waves, 64 rays)
 constexpr int kQuadBlock = 256;   // quad-per-ray block (4 waves, 64 rays)
 
-template <int STACK, bool COUNT>
+template <int STACK, bool COUNT, bool SWEEP>
 static void launch_scan_t(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
                           const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err,
                           uint32_t *nn, uint32_t *nt, hipStream_t s) {
     if (t.lanes_per_ray == 4) {
         uint32_t blocks = (uint32_t)((n_padded * 4 + kQuadBlock - 1) / kQuadBlock);
-        trace_scan_quad_kernel<STACK, kQuadBlock, COUNT><<<blocks, kQuadBlock, 0, s>>>(
+        trace_scan_multi_kernel<STACK, kQuadBlock, 4, COUNT, SWEEP><<<blocks, kQuadBlock, 0, s>>>(
+            S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt);
+    } else if (t.lanes_per_ray == 2) {
+        uint32_t blocks = (uint32_t)((n_padded * 2 + kPairBlock - 1) / kPairBlock);
+        trace_scan_multi_kernel<STACK, kPairBlock, 2, COUNT, SWEEP><<<blocks, kPairBlock, 0, s>>>(
             S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt);
     } else {
         uint32_t blocks = (uint32_t)((n_padded + kBlock - 1) / kBlock);
-        trace_scan_kernel<STACK, kBlock, COUNT><<<blocks, kBlock, 0, s>>>(S, in, M, ov, out, t.tile_az_log2,
-                                                                          n_padded, t.xcd_remap, err, nn, nt);
+        trace_scan_kernel<STACK, kBlock, COUNT, SWEEP><<<blocks, kBlock, 0, s>>>(S, in, M, ov, out, t.tile_az_log2,
+                                                                                 n_padded, t.xcd_remap, err, nn, nt);
     }
 }
 
 void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
                        const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err, uint32_t *n_nodes,
                        uint32_t *n_tris, hipStream_t s) {
-    bool count = n_nodes != nullptr;
-    if (t.stack <= 32) {
-        if (count) launch_scan_t<32, true>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
-        else launch_scan_t<32, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+    const bool count = n_nodes != nullptr;
+    const bool sweep = in.col_pose != nullptr;
+    if (sweep) {   // sweeps do not count
+        if (t.stack <= 32) launch_scan_t<32, false, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+        else if (t.stack <= 64) launch_scan_t<64, false, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+        else launch_scan_t<96, false, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+    } else if (t.stack <= 32) {
+        if (count) launch_scan_t<32, true, false>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
+        else launch_scan_t<32, false, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
     } else if (t.stack <= 64) {
-        if (count) launch_scan_t<64, true>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
-        else launch_scan_t<64, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+        if (count) launch_scan_t<64, true, false>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
+        else launch_scan_t<64, false, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
     } else {
-        if (count) launch_scan_t<96, true>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
-        else launch_scan_t<96, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
+        if (count) launch_scan_t<96, true, false>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
+        else launch_scan_t<96, false, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
     }
 }
 
@@ -597,37 +626,43 @@ void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const Materials
     bruteforce_kernel<B, C><<<(uint32_t)blocks, B, 0, s>>>(S, in, M, ov, out, tile_az_log2, n_padded);
 }
 
-template <int STACK, bool QUAD>
+template <int STACK, int LANES>
 static void launch_batch_t(const SceneDev &S, const InstanceDev *insts, uint32_t n_inst, const MaterialsDev &M,
                            const Outputs &out, int tile_az_log2, uint64_t n_padded, uint32_t packet,
                            uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
-    constexpr int B = QUAD ? kQuadBlock : kBlock;
+    constexpr int B = LANES == 4 ? kQuadBlock : LANES == 2 ? kPairBlock : kBlock;
     reset_queue_kernel<<<1, 1, 0, s>>>(queue);
-    trace_batch_kernel<STACK, B, QUAD><<<grid, B, 0, s>>>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet,
-                                                          queue, err);
+    trace_batch_kernel<STACK, B, LANES><<<grid, B, 0, s>>>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet,
+                                                           queue, err);
+}
+
+template <int STACK>
+static void launch_batch_s(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
+                           const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
+                           uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
+    if (t.lanes_per_ray == 4)
+        launch_batch_t<STACK, 4>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+    else if (t.lanes_per_ray == 2)
+        launch_batch_t<STACK, 2>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+    else
+        launch_batch_t<STACK, 1>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
 }
 
 void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
                         const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
                         uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
-    bool q = t.lanes_per_ray == 4;
-    if (t.stack <= 32) {
-        if (q) launch_batch_t<32, true>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
-        else launch_batch_t<32, false>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
-    } else if (t.stack <= 64) {
-        if (q) launch_batch_t<64, true>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
-        else launch_batch_t<64, false>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
-    } else {
-        if (q) launch_batch_t<96, true>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
-        else launch_batch_t<96, false>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
-    }
+    if (t.stack <= 32) launch_batch_s<32>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
+    else if (t.stack <= 64) launch_batch_s<64>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
+    else launch_batch_s<96>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
 }
 
 int batch_blocks_per_cu(const TraceOpts &t) {
     // LDS per block = stack entries x stack slots x 4 bytes; 160 KB per CU on gfx950
     int st = t.stack <= 32 ? 32 : t.stack <= 64 ? 64 : 96;
-    int slots = t.lanes_per_ray == 4 ? kQuadBlock / 4 : kBlock;
-    int waves = t.lanes_per_ray == 4 ? kQuadBlock / 64 : kBlock / 64;
+    int lanes = t.lanes_per_ray;
+    int block = lanes == 4 ? kQuadBlock : lanes == 2 ? kPairBlock : kBlock;
+    int slots = block / lanes;
+    int waves = block / 64;
     int by_lds = (160 * 1024) / (st * slots * 4);
     int by_waves = 32 / waves;          // at most 8 waves per SIMD
     int b = by_lds < by_waves ? by_lds : by_waves;

@@ -164,6 +164,7 @@ class Context:
         d.angle_exp = None if ke is None else ke.ctypes.data
         check(lib.lidar_materials_set(self.h, C.byref(d)), self.h)
         self.nmat = int(d.nmat)
+        self.nbins = int(d.nbins)
 
     def set_sensor(self, sensor) -> int:
         d, keep = sensor_struct(sensor)
@@ -195,7 +196,7 @@ class Context:
             st = lib.lidar_simulate_bruteforce(self.h, seed, scan, C.byref(o), _stream(stream))
         elif params:
             p = A.Params()
-            for k in ("rho", "angle_exp", "pose_delta"):
+            for k in ("rho", "angle_exp", "pose_delta", "spectra"):
                 t = params.get(k)
                 if t is not None:
                     assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
@@ -249,14 +250,20 @@ class Context:
         d_rho = torch.empty(nmat, dtype=torch.float32, device=self.device)
         d_k = torch.empty(nmat, dtype=torch.float32, device=self.device)
         d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
-        p = A.Params()
-        for k in ("rho", "angle_exp", "pose_delta"):
-            t = (params or {}).get(k)
-            if t is not None:
-                setattr(p, k, t.data_ptr())
+        p = _params_struct(params)
         check(lib.lidar_backward(self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(dL_dI), _ptr(dL_drange),
                                  _ptr(d_rho), _ptr(d_k), _ptr(d_pose), _stream(stream)), self.h)
         return d_rho, d_k, d_pose
+
+    def backward_spectra(self, tri, valid, dL_dI=None, dL_drange=None, params: dict | None = None, stream=None):
+        """Full-spectrum adjoint: (d_spectra[nmat, nbins], d_k[nmat], d_pose6) at the sensor wavelength."""
+        d_T = torch.empty((self.nmat, self.nbins), dtype=torch.float32, device=self.device)
+        d_k = torch.empty(self.nmat, dtype=torch.float32, device=self.device)
+        d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
+        p = _params_struct(params)
+        check(lib.lidar_backward_spectra(self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(dL_dI), _ptr(dL_drange),
+                                         _ptr(d_T), _ptr(d_k), _ptr(d_pose), _stream(stream)), self.h)
+        return d_T, d_k, d_pose
 
     def batch(self, instances, packet_rays: int = 0) -> "Batch":
         return Batch(self, instances, packet_rays)
@@ -338,6 +345,16 @@ class Batch:
             pass
 
 
+def _params_struct(params: dict | None) -> A.Params:
+    p = A.Params()
+    for k in ("rho", "angle_exp", "pose_delta", "spectra"):
+        t = (params or {}).get(k)
+        if t is not None:
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+            setattr(p, k, t.data_ptr())
+    return p
+
+
 class LidarReturn(torch.autograd.Function):
     """(rho[nmat], k[nmat], pose_delta[6]) -> (intensity, range, valid, tri) of one noise-free scan.
 
@@ -365,3 +382,35 @@ class LidarReturn(torch.autograd.Function):
             params=dict(rho=rho.detach().contiguous(), angle_exp=k.detach().contiguous(),
                         pose_delta=pose_delta.detach().contiguous()))
         return None, d_rho, d_k, d_pose, None, None
+
+
+class LidarSpectralReturn(torch.autograd.Function):
+    """(spectra[nmat, nbins], k[nmat], pose_delta[6]) -> (intensity, range, valid, tri) of one
+    noise-free scan at the context's sensor wavelength.
+
+    R_lambda(0) is read from `spectra` at the wavelength (linear between bins),
+    so the backward pass (the library's full-spectrum adjoint, hit triangles
+    fixed) gives gradient to the one or two bins around it; scans at several
+    wavelengths, each through its own call, add up in autograd.
+    """
+
+    @staticmethod
+    def forward(ctx_, lidar_ctx: Context, spectra, k, pose_delta, seed: int = 0, scan: int = 0):
+        prm = dict(spectra=spectra.detach().contiguous(), angle_exp=k.detach().contiguous(),
+                   pose_delta=pose_delta.detach().contiguous())
+        out = lidar_ctx.simulate(seed, scan, out=alloc_outputs(lidar_ctx.n_beams, ("intensity", "range", "valid",
+                                                                                  "tri"), lidar_ctx.device),
+                                 params=prm)
+        ctx_.lidar = lidar_ctx
+        ctx_.save_for_backward(spectra, k, pose_delta, out["tri"], out["valid"])
+        ctx_.mark_non_differentiable(out["valid"], out["tri"])
+        return out["intensity"], out["range"], out["valid"], out["tri"]
+
+    @staticmethod
+    def backward(ctx_, gI, gR, _gv, _gt):
+        spectra, k, pose_delta, tri, valid = ctx_.saved_tensors
+        d_T, d_k, d_pose = ctx_.lidar.backward_spectra(
+            tri, valid, None if gI is None else gI.contiguous(), None if gR is None else gR.contiguous(),
+            params=dict(spectra=spectra.detach().contiguous(), angle_exp=k.detach().contiguous(),
+                        pose_delta=pose_delta.detach().contiguous()))
+        return None, d_T, d_k, d_pose, None, None

@@ -75,7 +75,7 @@ def test_batch_packet_sizes_identical(L):
     ctx.load(scene)
     ref = None
     for pk in (64, 128, 1024):
-        for lanes in (1, 4):
+        for lanes in (1, 2, 4):
             ctx.set_lanes_per_ray(lanes)
             b = ctx.batch(insts, pk)
             g = to_np(b.simulate(debug=True))
@@ -97,9 +97,9 @@ def test_tuner_picks_a_candidate_and_keeps_results(L):
     ctx.load(scene)
     b = ctx.batch(insts, 64)
     before = to_np(b.simulate(debug=True))
-    res = b.tune(packet_rays=(64, 256), leaf_widths=(1, 4), lanes_per_ray=(1, 4), reps=3)
+    res = b.tune(packet_rays=(64, 256), leaf_widths=(1, 4), lanes_per_ray=(1, 2, 4), reps=3)
     assert res["best_packet_rays"] in (64, 256) and res["best_leaf_width"] in (1, 4)
-    assert res["best_lanes_per_ray"] in (1, 4) and res["ms"].shape == (2, 2, 2)
+    assert res["best_lanes_per_ray"] in (1, 2, 4) and res["ms"].shape == (2, 3, 2)
     assert np.all(res["ms"] > 0)
     assert ctx.stats()["leaf_width"] == res["best_leaf_width"]
     after = to_np(b.simulate(debug=True))

@@ -63,7 +63,8 @@ def test_launch_shapes_do_not_change_results(L):
     ref = None
     for W in (1, 2, 3, 4, 8):
         c = _ctx(L, scene, sensor, pose, leaf_width=W)
-        shapes = [(t, l, x) for t in (1, 8, 64) for l in (1, 4) for x in (0, 1)] if W == 4 else [(8, 4, 1), (8, 1, 0)]
+        shapes = ([(t, l, x) for t in (1, 8, 64) for l in (1, 2, 4) for x in (0, 1)] if W == 4
+                  else [(8, 4, 1), (8, 1, 0), (4, 2, 1)])
         for tile, lanes, xcd in shapes:
             c.set_tile_shape(tile)
             c.set_lanes_per_ray(lanes)
@@ -101,7 +102,7 @@ def test_config2_bvh_equals_bruteforce_full(L):
         st = c.load(scene, builder=builder)
         print(f"[bvh] config2 {builder}: nodes {st['n_nodes']} leaves {st['n_leaves']} depth {st['depth']} "
               f"build {st['build_ms']:.2f} ms", flush=True)
-        for lanes in (1, 4):
+        for lanes in (1, 2, 4):
             c.set_lanes_per_ray(lanes)
             a = to_np(c.simulate(SEED, 0, debug=True))
             for k in a:
@@ -156,7 +157,7 @@ def test_ragged_sensor_and_offsets(L):
     c = _ctx(L, sc2, sensor, pose)
     o = O.simulate(sc2, sensor, pose, seed=99, scan=5)
     for tile in (1, 4, 64):
-        for lanes in (1, 4):
+        for lanes in (1, 2, 4):
             c.set_tile_shape(tile)
             c.set_lanes_per_ray(lanes)
             g = to_np(c.simulate(99, 5, debug=True))

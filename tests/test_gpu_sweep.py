@@ -121,7 +121,7 @@ def test_sweep_launch_shapes_and_lbvh_do_not_change_results(L):
     ref = None
     for builder in ("ploc", "lbvh"):
         c.load(scene, builder=builder)
-        for tile, lanes in ((16, 4), (1, 1), (64, 4), (4, 1)):
+        for tile, lanes in ((16, 4), (1, 1), (64, 4), (4, 1), (16, 2), (2, 2)):
             c.set_tile_shape(tile)
             c.set_lanes_per_ray(lanes)
             out, _ = c.simulate_sweep(9, 30.0, 10.0, 0.07, (pa.p, pa.q), (pb.p, pb.q), debug=True)
