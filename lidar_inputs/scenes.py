@@ -21,6 +21,8 @@ Workloads (stand-ins for the paper's Unreal scenes, which are not available):
   in the config2 scene.
 * ``config5``: config2 geometry with 20 materials and hidden per-material
   reflectance / angle exponent / pose for calibration.
+* ``dynamic_config``: the config2 scene plus 200 moving cars (three car meshes)
+  and 100 walking, deforming pedestrians placed by rigid transforms.
 
 The spectral tables stand in for the ECOSTRESS library (paper, Section II-C):
 61 bins from 400 nm to 1000 nm in 10 nm steps, values i.i.d. U(0.05, 0.9)
@@ -643,3 +645,128 @@ def config5(seed: int = 5005):
     dang = np.deg2rad(rng.uniform(-1.0, 1.0, size=3))
     return dict(scene=scene, sensor=sensor, pose_true=pose_true, rho_true=rho_true, k_true=k_true,
                 dp0=dp, dw0=dang, rho0=np.full(20, 0.3, np.float32), k0=np.ones(20, np.float32))
+
+
+# ----------------------------------------------------------------------------
+# dynamic scenes: meshes placed by moving actors
+# ----------------------------------------------------------------------------
+@dataclass
+class Mesh:
+    vertices: np.ndarray          # float32 [nv, 3], object space
+    indices: np.ndarray           # uint32 [nt, 3]
+    material: np.ndarray          # uint16 [nt]
+
+    @property
+    def n_tri(self) -> int:
+        return int(self.indices.shape[0])
+
+
+@dataclass
+class Actor:
+    mesh: int                     # index into the mesh list
+    label: int                    # instance label of every triangle of this actor
+    p: np.ndarray                 # float32 [3] object origin in the world
+    q: np.ndarray                 # float32 [4] orientation (w, x, y, z)
+
+
+def _wheel(cx, cy, r, w, seg=24):
+    """Cylinder with its axis along y, centre (cx, cy, r): ring vertices then the two cap centres."""
+    ang = 2.0 * np.pi * np.arange(seg) / seg
+    v = []
+    for y in (cy - w / 2, cy + w / 2):
+        for a in ang:
+            v.append([cx + r * math.cos(a), y, r + r * math.sin(a)])
+    v.append([cx, cy - w / 2, r])
+    v.append([cx, cy + w / 2, r])
+    return np.array(v), cylinder_topology(seg, 1)
+
+
+def _assemble(parts):
+    vs, ts, ms = [], [], []
+    base = 0
+    for v, t, m in parts:
+        vs.append(np.asarray(v, np.float64))
+        ts.append(np.asarray(t, np.int64) + base)
+        ms.append(np.full(len(t), m, np.uint16))
+        base += len(v)
+    return Mesh(np.concatenate(vs).astype(np.float32), np.concatenate(ts).astype(np.uint32), np.concatenate(ms))
+
+
+def car_mesh(length=4.5, width=1.8, height=1.5, mats=(3, 7, 11)):
+    """A car in object space (x forward, base at z = 0): body, cabin and four wheels; 408 triangles."""
+    L, W, H = length, width, height
+    parts = []
+    v, t = box_mesh([-L / 2, -W / 2, 0.3], [L / 2, W / 2, 0.3 + 0.55 * H])
+    parts.append((v, t, mats[0]))
+    v, t = box_mesh([-0.3 * L, -0.45 * W, 0.3 + 0.55 * H], [0.25 * L, 0.45 * W, H])
+    parts.append((v, t, mats[1]))
+    for sx in (-0.32 * L, 0.32 * L):
+        for sy in (-W / 2 + 0.11, W / 2 - 0.11):
+            v, t = _wheel(sx, sy, 0.33, 0.22)
+            parts.append((v, t, mats[2]))
+    return _assemble(parts)
+
+
+def pedestrian_mesh(mats=(5, 9)):
+    """A pedestrian in object space: torso cylinder and head sphere; 304 triangles."""
+    v, t = cylinders(np.array([[0.0, 0.0, 0.0]]), np.array([0.2]), np.array([1.45]), seg=16, stacks=4)
+    parts = [(v[0], t, mats[0])]
+    v, t = uv_sphere([0.0, 0.0, 1.6], 0.13, 12, 7)
+    parts.append((v, t, mats[1]))
+    return _assemble(parts)
+
+
+def pedestrian_pose_vertices(mesh: Mesh, phase: float) -> np.ndarray:
+    """Deformed (walking sway) object-space vertices of ``pedestrian_mesh``, same topology."""
+    v = mesh.vertices.astype(np.float64).copy()
+    z = v[:, 2] / 1.75
+    v[:, 0] += 0.15 * math.sin(phase) * z * z
+    v[:, 1] += 0.05 * math.cos(phase) * z
+    return v.astype(np.float32)
+
+
+def dynamic_config(seed: int = 6006, n_cars: int = 200, n_peds: int = 100):
+    """Moving actors in the 522k-triangle urban scene.
+
+    Three car meshes (408 triangles each) and one deformable pedestrian mesh
+    (304 triangles); cars drive along the road lanes at U(5, 15) m/s,
+    pedestrians walk along the sidewalks at 1.4 m/s.  Returns a dict with the
+    static scene, sensor, sensor pose, meshes, and ``actors_at(t)`` giving the
+    actor list at time t (labels 100000 + k).
+    """
+    scene = urban_small(32, 2002)
+    _, sensor, pose = config2()
+    meshes = [car_mesh(4.5, 1.8, 1.5), car_mesh(4.0, 1.7, 1.45, mats=(4, 7, 11)),
+              car_mesh(5.2, 2.0, 1.9, mats=(13, 7, 11)), pedestrian_mesh()]
+    rng = np.random.default_rng(seed)
+    half = 256 * 2.0 / 2.0 - 8.0
+    kmin, kmax = math.ceil(-half / ROAD_PITCH), math.floor(half / ROAD_PITCH)
+    specs = []
+    for k in range(n_cars + n_peds):
+        car = k < n_cars
+        road = int(rng.integers(kmin, kmax + 1))
+        axis = int(rng.integers(0, 2))             # 0: road along y (x = const), 1: along x
+        side = float(rng.choice([-1.0, 1.0]))
+        off = side * (2.5 if car else 6.5)
+        along0 = float(rng.uniform(-half, half))
+        speed = float(rng.uniform(5.0, 15.0)) if car else 1.4
+        # right-hand traffic: the lane at +offset drives in +direction
+        direction = side
+        mesh = int(rng.integers(0, 3)) if car else 3
+        # keep the origin clearing free at t = 0
+        if abs(along0) < 12.0 and abs(road) == 0:
+            along0 += 24.0
+        specs.append((mesh, road * ROAD_PITCH + off, axis, along0, speed * direction))
+
+    def actors_at(t: float):
+        out = []
+        for k, (mesh, c, axis, a0, v) in enumerate(specs):
+            a = a0 + v * t
+            a = (a + half) % (2 * half) - half     # wrap inside the scene
+            x, y = (c, a) if axis == 0 else (a, c)
+            yaw = (math.pi / 2 if axis == 0 else 0.0) + (0.0 if v >= 0 else math.pi)
+            z = float(scene.heights(x, y)) - (0.05 if mesh < 3 else 0.0)
+            out.append(Actor(mesh, 100000 + k, np.array([x, y, z], np.float32), quat_from_ypr(yaw)))
+        return out
+
+    return dict(scene=scene, sensor=sensor, pose=pose, meshes=meshes, actors_at=actors_at)

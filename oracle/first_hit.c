@@ -24,7 +24,8 @@
  *   near_t    smallest t over triangles that the ray misses by less than
  *             edge_abs + edge_rel * t (measured the same way, outside the
  *             triangle) -- a "near miss" that rounding could turn into a hit.
- * Vertices are float32 and are promoted exactly to double.
+ * Vertices are given in double (oracle_first_hit_d) or float32
+ * (oracle_first_hit, promoted exactly to double).
  */
 #include <math.h>
 #include <stdint.h>
@@ -46,11 +47,11 @@ static inline double dot3(const double a[3], const double b[3]) {
 static inline double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
 
 /* Returns 0 on success, -1 on allocation failure. */
-int oracle_first_hit(int64_t n_rays, const double *orig, const double *dir,
-                     int64_t n_tri, const float *vtx, const uint32_t *idx,
-                     double t_min, double t_max, double edge_abs, double edge_rel,
-                     int64_t *hit_tri, double *hit_t, double *t_second,
-                     double *edge_in, double *near_t)
+int oracle_first_hit_d(int64_t n_rays, const double *orig, const double *dir,
+                       int64_t n_tri, const double *vtx, const uint32_t *idx,
+                       double t_min, double t_max, double edge_abs, double edge_rel,
+                       int64_t *hit_tri, double *hit_t, double *t_second,
+                       double *edge_in, double *near_t)
 {
     tri64 *T = (tri64 *)malloc(sizeof(tri64) * (size_t)(n_tri > 0 ? n_tri : 1));
     if (!T) return -1;
@@ -58,7 +59,7 @@ int oracle_first_hit(int64_t n_rays, const double *orig, const double *dir,
         double v[3][3];
         for (int c = 0; c < 3; ++c)
             for (int a = 0; a < 3; ++a)
-                v[c][a] = (double)vtx[3 * (size_t)idx[3 * k + c] + a];
+                v[c][a] = vtx[3 * (size_t)idx[3 * k + c] + a];
         double e12[3], n[3];
         for (int a = 0; a < 3; ++a) {
             T[k].v0[a] = v[0][a];
@@ -128,4 +129,23 @@ int oracle_first_hit(int64_t n_rays, const double *orig, const double *dir,
     }
     free(T);
     return 0;
+}
+
+/* The same query with float32 vertices (promoted exactly to double). */
+int oracle_first_hit(int64_t n_rays, const double *orig, const double *dir,
+                     int64_t n_tri, const float *vtx, const uint32_t *idx,
+                     double t_min, double t_max, double edge_abs, double edge_rel,
+                     int64_t *hit_tri, double *hit_t, double *t_second,
+                     double *edge_in, double *near_t)
+{
+    int64_t nv = 0;
+    for (int64_t k = 0; k < 3 * n_tri; ++k)
+        if ((int64_t)idx[k] + 1 > nv) nv = (int64_t)idx[k] + 1;
+    double *v = (double *)malloc(sizeof(double) * 3 * (size_t)(nv > 0 ? nv : 1));
+    if (!v) return -1;
+    for (int64_t k = 0; k < 3 * nv; ++k) v[k] = (double)vtx[k];
+    int rc = oracle_first_hit_d(n_rays, orig, dir, n_tri, v, idx, t_min, t_max, edge_abs, edge_rel,
+                                hit_tri, hit_t, t_second, edge_in, near_t);
+    free(v);
+    return rc;
 }

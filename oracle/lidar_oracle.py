@@ -68,6 +68,8 @@ def _load():
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, P, P, P, P, P]
         lib.oracle_first_hit.restype = ctypes.c_int
+        lib.oracle_first_hit_d.argtypes = lib.oracle_first_hit.argtypes
+        lib.oracle_first_hit_d.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -157,11 +159,14 @@ def first_hit(scene, orig, dirs, t_min, t_max):
     orig = np.ascontiguousarray(np.broadcast_to(orig, dirs.shape), dtype=np.float64)
     dirs = np.ascontiguousarray(dirs, dtype=np.float64)
     n = dirs.shape[0]
-    vtx = np.ascontiguousarray(scene.vertices, dtype=np.float32)
+    # FP64 vertices (actors placed by a rigid transform) are used as given; FP32 ones are promoted
+    f64 = np.asarray(scene.vertices).dtype == np.float64
+    vtx = np.ascontiguousarray(scene.vertices, dtype=np.float64 if f64 else np.float32)
     idx = np.ascontiguousarray(scene.indices, dtype=np.uint32)
     out = dict(tri=np.empty(n, np.int64), t=np.empty(n), t_second=np.empty(n),
                edge_in=np.empty(n), near_t=np.empty(n))
-    rc = lib.oracle_first_hit(n, orig.ctypes.data, dirs.ctypes.data, idx.shape[0], vtx.ctypes.data,
+    fn = lib.oracle_first_hit_d if f64 else lib.oracle_first_hit
+    rc = fn(n, orig.ctypes.data, dirs.ctypes.data, idx.shape[0], vtx.ctypes.data,
                               idx.ctypes.data, float(t_min), float(t_max), EDGE_ABS_M, EDGE_REL,
                               out["tri"].ctypes.data, out["t"].ctypes.data, out["t_second"].ctypes.data,
                               out["edge_in"].ctypes.data, out["near_t"].ctypes.data)
@@ -503,6 +508,61 @@ def simulate_sweep(scene, sensor, pose_a, pose_b, head_deg_begin, spin_hz, dt_s,
     out["runs"] = runs
     out["scan"] = scan_b
     out["tau"] = np.array([tau_c[int(i)] for i in col], dtype=np.float64)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# dynamic scenes: meshes placed in the world by moving actors [II-B]
+# ----------------------------------------------------------------------------
+# An actor places a mesh (object-space triangles with per-triangle materials)
+# in the world with a rigid transform x_world = R(q) x_object + p and gives all
+# of its triangles one instance label (Section II-B labels every object
+# instance).  The first hit is taken over one triangle soup: the static
+# triangles first, then every actor's triangles in actor order, with FP64
+# world vertices, so ties are broken by that order.
+
+def actor_vertices(mesh, actor) -> np.ndarray:
+    """World vertices R(q) v + p (FP64) of the mesh placed by the actor."""
+    R = rotation_from_quat(actor.q)
+    v = np.asarray(mesh.vertices, dtype=np.float64)
+    return v @ R.T + np.asarray(actor.p, dtype=np.float64)
+
+
+def scene_with_actors(scene, meshes, actors, mesh_vertices=None):
+    """The static scene and the placed actors as one soup (FP64 vertices).
+
+    mesh_vertices: optional per-mesh replacement vertex arrays (deformed meshes,
+    same topology).  Returns (soup, tri_base) with tri_base[a] the index of
+    actor a's first triangle in the soup.
+    """
+    from dataclasses import replace
+    verts = [np.asarray(scene.vertices, dtype=np.float64)]
+    idx = [np.asarray(scene.indices, dtype=np.int64)]
+    mat = [np.asarray(scene.material)]
+    lab = [np.asarray(scene.label)]
+    nv, nt = len(verts[0]), scene.n_tri
+    tri_base = []
+    for a in actors:
+        m = meshes[a.mesh]
+        mv = m if mesh_vertices is None or mesh_vertices[a.mesh] is None else replace(m, vertices=mesh_vertices[a.mesh])
+        verts.append(actor_vertices(mv, a))
+        idx.append(np.asarray(m.indices, dtype=np.int64) + nv)
+        mat.append(np.asarray(m.material))
+        lab.append(np.full(m.n_tri, a.label, dtype=np.uint32))
+        tri_base.append(nt)
+        nv += len(m.vertices)
+        nt += m.n_tri
+    soup = replace(scene, vertices=np.concatenate(verts), indices=np.concatenate(idx).astype(np.uint32),
+                   material=np.concatenate(mat).astype(np.uint16), label=np.concatenate(lab).astype(np.uint32))
+    return soup, np.array(tri_base, dtype=np.int64)
+
+
+def simulate_actors(scene, meshes, actors, sensor, pose, seed: int = 0, scan: int = 0, beams=None,
+                    mesh_vertices=None):
+    """Oracle for one scan of a dynamic scene; the ``simulate`` dict plus ``tri_base``."""
+    soup, tri_base = scene_with_actors(scene, meshes, actors, mesh_vertices)
+    out = simulate(soup, sensor, pose, seed=seed, scan=scan, beams=beams)
+    out["tri_base"] = tri_base
     return out
 
 
