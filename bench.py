@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sweep,sequence or 'all'")
+    ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sweep,dynamic,sequence or 'all'")
     ap.add_argument("--leaf-width", type=int, default=4)
     ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
     ap.add_argument("--ploc-radius", type=int, default=32)
@@ -131,7 +131,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": args.gpus}))
         sys.exit(2)
-    legs = ({"plain", "cpu", "batch", "adjoint", "sweep", "sequence"} if args.legs == "all"
+    legs = ({"plain", "cpu", "batch", "adjoint", "sweep", "dynamic", "sequence"} if args.legs == "all"
             else set(args.legs.split(",")))
 
     import numpy as np
@@ -394,6 +394,41 @@ def main():
                            "realtime_factor": (n_ticks / tick_hz) / wall_s}
         log(f"sweep: {n_ticks} ticks in {wall_s * 1e3:.2f} ms ({np.mean(ms_s) * 1e3:.1f} us per tick, "
             f"{rays / wall_s:.4g} rays/s, {(n_ticks / tick_hz) / wall_s:.0f}x real time)")
+
+    if "dynamic" in legs:
+        # 300 moving actors (200 cars, 100 walking pedestrians) in the 522k scene: per 10 Hz frame the
+        # pedestrian mesh is refit to its walking pose, the actors' top-level BVH is refit, and one scan runs
+        dc = S.dynamic_config()
+        ids = [ctx.load_mesh(m) for m in dc["meshes"]]
+        n_frames = 20
+        frames = [ctx.actor_array(dc["actors_at"](0.1 * f)) for f in range(n_frames + 1)]
+        sways = [torch.tensor(S.pedestrian_pose_vertices(dc["meshes"][3], 0.9 * f), device=ctx.device)
+                 for f in range(n_frames + 1)]
+        t0 = time.perf_counter()
+        ctx.set_actors(dc["actors_at"](0.0))
+        torch.cuda.synchronize()
+        set_ms = (time.perf_counter() - t0) * 1e3
+        outd = alloc_outputs(n, POINT_OUTPUTS, ctx.device)
+        ctx.simulate(seed, 0, out=outd)
+
+        def frame(f):
+            ctx.refit_mesh(ids[3], sways[f + 1])
+            ctx.update_actors(frames[f + 1])
+            ctx.simulate(seed, f, out=outd)
+        wall_d, ms_d = timed_launches(frame, n_frames, torch)
+        ctx.sync_check()
+        _, ms_scan = timed_launches(lambda k: ctx.simulate(seed, k, out=outd), 50, torch)
+        n_act = int((outd["label"].view(torch.int32) >= 100000).sum())
+        result["dynamic"] = {
+            "workload": "522k-triangle scene + 300 actors (200 cars of 408 triangles, 100 deforming pedestrians of "
+                        "304 triangles) moving at 10 Hz; per frame: pedestrian mesh refit, actor BVH refit, "
+                        "64ch x 2048 scan",
+            "frames": n_frames, "frame_ms_mean": float(np.mean(ms_d)), "rays_per_s_with_updates": n_frames * n / wall_d,
+            "scan_ms_mean": float(np.mean(ms_scan)), "rays_per_s_scan": n / (float(np.mean(ms_scan)) * 1e-3),
+            "actors_set_ms": set_ms, "beams_on_actors_last_frame": n_act}
+        log(f"dynamic: {np.mean(ms_d) * 1e3:.1f} us per frame (refits + scan), scan {np.mean(ms_scan) * 1e3:.1f} us, "
+            f"actor BVH build {set_ms:.2f} ms, {n_act} beams on actors")
+        ctx.clear_actors()
 
     if "sequence" in legs:
         sc3, s3, poses = S.config3()

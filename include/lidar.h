@@ -235,6 +235,70 @@ lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
                                    uint32_t *node_visits, uint32_t *tri_tests, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Dynamic scenes: meshes placed by moving actors (Section II-B)             */
+/* ------------------------------------------------------------------------ */
+
+/* Section II-B gives every object instance its own label.  A dynamic scene
+ * adds, to the static scene of lidar_scene_load, actors: each places a mesh
+ * (object-space triangles with per-triangle materials) in the world with a
+ * rigid transform x_world = R(q) x_object + p and gives all of the mesh's
+ * triangles the actor's label.  Every mesh has its own BVH; a top-level BVH
+ * over the actors' world boxes is built by lidar_actors_set and refit by
+ * lidar_actors_update each frame.  The first hit is taken over the static
+ * triangles and all placed meshes as one soup, ties broken by the index in
+ * the combined ordering: static triangles 0 .. n_static - 1, then the
+ * triangles of actor 0, actor 1, ... (outputs.tri reports that index).
+ * lidar_simulate, lidar_simulate_ex and lidar_simulate_sweep see the actors;
+ * the brute-force reference, traversal counting, the batched form and the
+ * adjoint cover the static scene only and return LIDAR_ERR_INVALID_ARG while
+ * actors are set. */
+
+/* Workspace sizes of a mesh (lidar_scene_desc with label ignored, may be NULL;
+ * the workspaces hold the mesh BVH and a copy of the indices). */
+lidar_status lidar_mesh_bytes(const lidar_scene_desc *mesh, uint64_t *persistent_bytes, uint64_t *scratch_bytes);
+
+/* Builds a mesh's BVH into caller-owned workspaces (256-byte aligned; the
+ * persistent one must stay allocated while the context uses the mesh, the
+ * scratch one only during the call) and returns its id (0, 1, ... in load
+ * order; at most 4096 meshes).  Synchronises `stream`. */
+lidar_status lidar_mesh_load(lidar_ctx *ctx, const lidar_scene_desc *mesh, void *persistent,
+                             uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes, void *stream,
+                             uint32_t *mesh_id);
+
+/* Deformed mesh: new object-space vertices (device [n_vertices][3], same
+ * topology) replace the mesh's triangles and its BVH boxes are refit.  Call
+ * lidar_actors_update afterwards (simulating before returns
+ * LIDAR_ERR_NOT_READY).  Asynchronous; `vertices` must stay valid until the
+ * stream reaches the call. */
+lidar_status lidar_mesh_refit(lidar_ctx *ctx, uint32_t mesh_id, const float *vertices, void *stream);
+
+typedef struct {
+    uint32_t mesh;             /* mesh id from lidar_mesh_load */
+    uint32_t label;            /* instance label of every triangle of the actor */
+    float p[3];                /* object origin in the world, metres */
+    float q_wxyz[4];           /* orientation, unit quaternion (1e-4) */
+} lidar_actor;
+
+/* Workspace sizes for n_actors actors (1 .. 2^20). */
+lidar_status lidar_actors_bytes(uint32_t n_actors, uint64_t *persistent_bytes, uint64_t *scratch_bytes);
+
+/* Sets the actors (host array) and builds the top-level BVH over their world
+ * boxes into caller-owned workspaces (256-byte aligned; persistent kept while
+ * the actors are in use, scratch only during the call).  n_actors = 0 clears
+ * them.  Synchronises `stream`. */
+lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_t n_actors, void *persistent,
+                              uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* Per-frame update: the same actors (count and meshes) at new poses.  Uploads
+ * the transforms through a pinned buffer, recomputes the world boxes and refits
+ * the top-level BVH (no rebuild: call lidar_actors_set again when the tree has
+ * degraded).  Asynchronous; waits only for the previous update's upload. */
+lidar_status lidar_actors_update(lidar_ctx *ctx, const lidar_actor *actors, uint32_t n_actors, void *stream);
+
+/* Removes the actors (the workspaces are the caller's). */
+lidar_status lidar_actors_clear(lidar_ctx *ctx);
+
+/* ------------------------------------------------------------------------ */
 /* Partial sweep per engine tick, rolling-shutter pose (Section II-A)        */
 /* ------------------------------------------------------------------------ */
 

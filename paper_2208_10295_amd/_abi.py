@@ -94,6 +94,10 @@ class Stats(C.Structure):
                 ("build_ms", C.c_float), ("box_pad", C.c_float)]
 
 
+class Actor(C.Structure):
+    _fields_ = [("mesh", C.c_uint32), ("label", C.c_uint32), ("p", C.c_float * 3), ("q_wxyz", C.c_float * 4)]
+
+
 class SweepDesc(C.Structure):
     _fields_ = [("head_deg", C.c_double), ("spin_hz", C.c_double), ("dt_s", C.c_double),
                 ("p_begin", C.c_float * 3), ("q_begin", C.c_float * 4), ("p_end", C.c_float * 3),
@@ -121,6 +125,14 @@ SIGNATURES = {
     "lidar_simulate_bruteforce": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P]),
     "lidar_simulate_counts": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P, P, P]),
     "lidar_simulate_sweep": (C.c_int32, [P, C.POINTER(SweepDesc), C.POINTER(Outputs), C.POINTER(SweepInfo), P]),
+    "lidar_mesh_bytes": (C.c_int32, [C.POINTER(SceneDesc), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "lidar_mesh_load": (C.c_int32, [P, C.POINTER(SceneDesc), P, C.c_uint64, P, C.c_uint64, P,
+                                    C.POINTER(C.c_uint32)]),
+    "lidar_mesh_refit": (C.c_int32, [P, C.c_uint32, P, P]),
+    "lidar_actors_bytes": (C.c_int32, [C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "lidar_actors_set": (C.c_int32, [P, C.POINTER(Actor), C.c_uint32, P, C.c_uint64, P, C.c_uint64, P]),
+    "lidar_actors_update": (C.c_int32, [P, C.POINTER(Actor), C.c_uint32, P]),
+    "lidar_actors_clear": (C.c_int32, [P]),
     "lidar_batch_create": (C.c_int32, [P, C.POINTER(Instance), C.c_uint32, C.c_uint32, C.POINTER(P)]),
     "lidar_batch_rays": (C.c_int32, [P, C.POINTER(C.c_uint64)]),
     "lidar_simulate_batch": (C.c_int32, [P, P, C.POINTER(Outputs), P]),

@@ -344,7 +344,8 @@ __global__ __launch_bounds__(256) void write_records_kernel(BuildInputs in, cons
     const float *v = in.vtx;
     TriRec r;
     r.a = make_float4(v[3 * (size_t)i0], v[3 * (size_t)i0 + 1], v[3 * (size_t)i0 + 2], __uint_as_float(k));
-    r.b = make_float4(v[3 * (size_t)i1], v[3 * (size_t)i1 + 1], v[3 * (size_t)i1 + 2], __uint_as_float(in.label[k]));
+    r.b = make_float4(v[3 * (size_t)i1], v[3 * (size_t)i1 + 1], v[3 * (size_t)i1 + 2],
+                      __uint_as_float(in.label ? in.label[k] : 0u));
     r.c = make_float4(v[3 * (size_t)i2], v[3 * (size_t)i2 + 1], v[3 * (size_t)i2 + 2], __uint_as_float((uint32_t)in.mat[k]));
     recs[s] = r;
     slot_of[k] = s;
@@ -858,6 +859,7 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
         n_nodes = 0;
         while (n_front > 0) {
             if (depth >= 1024 || n_nodes + n_front > (nt > 1 ? nt : 1)) return hipErrorIllegalState;
+            if (depth <= (uint32_t)kMaxLevels) res.level_base[depth] = base;
             uint32_t g = (n_front + 255) / 256;
             collapse_kernel<<<g, 256, 0, s>>>(T, recs, fa, n_front, base, in.leaf_width, partials, nodes,
                                               pending, counts, stat);
@@ -883,6 +885,8 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
     HIP_TRY(hipMemcpyAsync(&hb, partials, sizeof(Bounds), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
+    if (nt <= in.leaf_width) res.level_base[0] = 0;
+    if (depth <= (uint32_t)kMaxLevels) res.level_base[depth] = n_nodes;
     res.root = 0;
     res.n_nodes = n_nodes;
     res.n_leaves = hstat[2];

@@ -1,0 +1,218 @@
+// dynamic.hip -- dynamic scenes on gfx950: meshes placed in the world by
+// moving actors (Section II-B labels every object instance; an actor is one
+// labelled instance of a mesh).
+//
+// * A mesh has its own 4-wide BVH over object-space triangles (built by the
+//   scene builder).  A deformed mesh (same topology, new vertices) is refit:
+//   its records are rewritten from the new vertices and every node's child
+//   boxes are recomputed level by level, deepest level first.
+// * The actors' world boxes (the mesh root box, its 8 corners transformed in
+//   FP64, rounded outward) are the primitives of a top-level BVH, built by the
+//   same builder from degenerate triangles (lo, hi, lo) whose bounding box is
+//   exactly the actor box.  A per-frame update rewrites those records from the
+//   new boxes and refits the tree; a rebuild (new actor set) builds it again.
+// Refit reproduces the builder's boxes exactly for unchanged inputs: a leaf
+// slot is the union of its records' vertices minus/plus the pad, an inner slot
+// the union of its child node's (padded) slots, and the pad is 2^-20 of the
+// largest coordinate as in the build.
+#include "lidar_kernels.hpp"
+
+namespace lidar {
+
+namespace {
+
+constexpr float kInf = __builtin_inff();
+
+// word[0] = bits of max |x| over the values (non-negative floats order like their bits)
+__global__ __launch_bounds__(256) void maxabs_kernel(const float *__restrict__ v, uint64_t n, uint32_t *word) {
+    float m = 0.0f;
+    for (uint64_t k = blockIdx.x * 256ull + threadIdx.x; k < n; k += (uint64_t)gridDim.x * 256ull)
+        m = fmaxf(m, fabsf(v[k]));
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(word, __float_as_uint(m));
+}
+
+__global__ void zero_words_kernel(uint32_t *word) {
+    word[0] = 0u;
+    word[1] = 0u;
+}
+
+// word[1] = bits of the box pad 2^-20 max |x| + 1e-20 (the builder's formula)
+__global__ void pad_kernel(uint32_t *word) {
+    word[1] = __float_as_uint(__uint_as_float(word[0]) * 9.5367431640625e-07f + 1e-20f);
+}
+
+__global__ __launch_bounds__(256) void mesh_records_kernel(TriRec *__restrict__ recs, uint32_t nt,
+                                                           const uint32_t *__restrict__ idx,
+                                                           const float *__restrict__ v) {
+    uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= nt) return;
+    TriRec r = recs[s];
+    uint32_t k = __float_as_uint(r.a.w);
+    uint32_t i0 = idx[3 * (size_t)k], i1 = idx[3 * (size_t)k + 1], i2 = idx[3 * (size_t)k + 2];
+    r.a.x = v[3 * (size_t)i0]; r.a.y = v[3 * (size_t)i0 + 1]; r.a.z = v[3 * (size_t)i0 + 2];
+    r.b.x = v[3 * (size_t)i1]; r.b.y = v[3 * (size_t)i1 + 1]; r.b.z = v[3 * (size_t)i1 + 2];
+    r.c.x = v[3 * (size_t)i2]; r.c.y = v[3 * (size_t)i2 + 1]; r.c.z = v[3 * (size_t)i2 + 2];
+    recs[s] = r;
+}
+
+__device__ inline float round_down(double x) {
+    float f = (float)x;
+    return ((double)f > x) ? nextafterf(f, -kInf) : f;
+}
+__device__ inline float round_up(double x) {
+    float f = (float)x;
+    return ((double)f < x) ? nextafterf(f, kInf) : f;
+}
+
+// world box of each actor: the mesh root box (union of the root's slots) with
+// its 8 corners transformed; also max |coordinate| of all boxes into word[0]
+__global__ __launch_bounds__(256) void actor_boxes_kernel(const ActorDev *__restrict__ actors, uint32_t n,
+                                                          const MeshDev *__restrict__ meshes, float *__restrict__ lohi,
+                                                          uint32_t *word) {
+    uint32_t a = blockIdx.x * 256 + threadIdx.x;
+    float m = 0.0f;
+    if (a < n) {
+        const ActorDev A = actors[a];
+        const Node4 root = meshes[A.mesh].nodes[0];
+        float lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+        for (int k = 0; k < 4; ++k) {
+            if (root.c[k].ref == kEmptyRef) continue;
+            for (int e = 0; e < 3; ++e) {
+                lo[e] = fminf(lo[e], root.c[k].lo[e]);
+                hi[e] = fmaxf(hi[e], root.c[k].hi[e]);
+            }
+        }
+        double wl[3] = {1e300, 1e300, 1e300}, wh[3] = {-1e300, -1e300, -1e300};
+        for (int c = 0; c < 8; ++c) {
+            const double x = (c & 1) ? hi[0] : lo[0], y = (c & 2) ? hi[1] : lo[1], z = (c & 4) ? hi[2] : lo[2];
+            for (int e = 0; e < 3; ++e) {
+                const double w = A.R[3 * e] * x + A.R[3 * e + 1] * y + A.R[3 * e + 2] * z + A.p[e];
+                wl[e] = fmin(wl[e], w);
+                wh[e] = fmax(wh[e], w);
+            }
+        }
+        for (int e = 0; e < 3; ++e) {
+            const float l = round_down(wl[e]), h = round_up(wh[e]);
+            lohi[6 * (size_t)a + e] = l;
+            lohi[6 * (size_t)a + 3 + e] = h;
+            m = fmaxf(m, fmaxf(fabsf(l), fabsf(h)));
+        }
+    }
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(word, __float_as_uint(m));
+}
+
+// builder input for the top-level BVH: vertices 2a = lo, 2a + 1 = hi, triangle (lo, hi, lo)
+__global__ __launch_bounds__(256) void actor_prims_kernel(const float *__restrict__ lohi, uint32_t n,
+                                                          float *__restrict__ vtx, uint32_t *__restrict__ idx,
+                                                          uint16_t *__restrict__ mat) {
+    uint32_t a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= n) return;
+    for (int e = 0; e < 6; ++e) vtx[6 * (size_t)a + e] = lohi[6 * (size_t)a + e];
+    idx[3 * (size_t)a] = 2 * a;
+    idx[3 * (size_t)a + 1] = 2 * a + 1;
+    idx[3 * (size_t)a + 2] = 2 * a;
+    mat[a] = 0;
+}
+
+__global__ __launch_bounds__(256) void tlas_records_kernel(TriRec *__restrict__ recs, uint32_t n,
+                                                           const float *__restrict__ lohi) {
+    uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    TriRec r = recs[s];
+    const uint32_t a = __float_as_uint(r.a.w);
+    const float *b = lohi + 6 * (size_t)a;
+    r.a.x = b[0]; r.a.y = b[1]; r.a.z = b[2];
+    r.b.x = b[3]; r.b.y = b[4]; r.b.z = b[5];
+    r.c.x = b[0]; r.c.y = b[1]; r.c.z = b[2];
+    recs[s] = r;
+}
+
+__global__ __launch_bounds__(256) void refit_level_kernel(Node4 *__restrict__ nodes, const TriRec *__restrict__ recs,
+                                                          uint32_t first, uint32_t count,
+                                                          const uint32_t *__restrict__ word) {
+    uint32_t n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= count) return;
+    n += first;
+    const float pad = __uint_as_float(word[1]);
+    Node4 nd = nodes[n];
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t ref = nd.c[k].ref;
+        if (ref == kEmptyRef) continue;
+        float lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+        if (ref & kLeafBit) {
+            const uint32_t f = leaf_first(ref), c = leaf_count(ref);
+            for (uint32_t r = 0; r < c; ++r) {
+                const TriRec t = recs[f + r];
+                lo[0] = fminf(lo[0], fminf(t.a.x, fminf(t.b.x, t.c.x)));
+                lo[1] = fminf(lo[1], fminf(t.a.y, fminf(t.b.y, t.c.y)));
+                lo[2] = fminf(lo[2], fminf(t.a.z, fminf(t.b.z, t.c.z)));
+                hi[0] = fmaxf(hi[0], fmaxf(t.a.x, fmaxf(t.b.x, t.c.x)));
+                hi[1] = fmaxf(hi[1], fmaxf(t.a.y, fmaxf(t.b.y, t.c.y)));
+                hi[2] = fmaxf(hi[2], fmaxf(t.a.z, fmaxf(t.b.z, t.c.z)));
+            }
+            for (int e = 0; e < 3; ++e) {
+                lo[e] = lo[e] - pad;
+                hi[e] = hi[e] + pad;
+            }
+        } else {
+            const Node4 &ch = nodes[ref];
+            for (int j = 0; j < 4; ++j) {
+                if (ch.c[j].ref == kEmptyRef) continue;
+                for (int e = 0; e < 3; ++e) {
+                    lo[e] = fminf(lo[e], ch.c[j].lo[e]);
+                    hi[e] = fmaxf(hi[e], ch.c[j].hi[e]);
+                }
+            }
+        }
+        for (int e = 0; e < 3; ++e) {
+            nd.c[k].lo[e] = lo[e];
+            nd.c[k].hi[e] = hi[e];
+        }
+    }
+    nodes[n] = nd;
+}
+
+inline uint32_t grid_of(uint64_t n) { return (uint32_t)((n + 255) / 256); }
+
+// child boxes of every node, deepest level first
+void refit_tree(Node4 *nodes, const TriRec *recs, const BuildResult &br, const uint32_t *word, hipStream_t s) {
+    for (int L = (int)br.depth - 1; L >= 0; --L) {
+        const uint32_t first = br.level_base[L], count = br.level_base[L + 1] - first;
+        if (count) refit_level_kernel<<<grid_of(count), 256, 0, s>>>(nodes, recs, first, count, word);
+    }
+}
+
+}  // namespace
+
+bool refit_supported(const BuildResult &br) { return br.depth >= 1 && br.depth <= (uint32_t)kMaxLevels; }
+
+void refit_mesh(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t nt, const uint32_t *idx,
+                const float *vertices, uint64_t nv, uint32_t *word, hipStream_t s) {
+    zero_words_kernel<<<1, 1, 0, s>>>(word);
+    uint32_t g = grid_of(3 * nv);
+    maxabs_kernel<<<g < 1024 ? g : 1024, 256, 0, s>>>(vertices, 3 * nv, word);
+    pad_kernel<<<1, 1, 0, s>>>(word);
+    mesh_records_kernel<<<grid_of(nt), 256, 0, s>>>(recs, nt, idx, vertices);
+    refit_tree(nodes, recs, br, word, s);
+}
+
+void actor_boxes(const ActorDev *actors, uint32_t n, const MeshDev *meshes, float *lohi, uint32_t *word,
+                 hipStream_t s) {
+    zero_words_kernel<<<1, 1, 0, s>>>(word);
+    actor_boxes_kernel<<<grid_of(n), 256, 0, s>>>(actors, n, meshes, lohi, word);
+}
+
+void actor_prims(const float *lohi, uint32_t n, float *vtx, uint32_t *idx, uint16_t *mat, hipStream_t s) {
+    actor_prims_kernel<<<grid_of(n), 256, 0, s>>>(lohi, n, vtx, idx, mat);
+}
+
+void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,
+                hipStream_t s) {
+    pad_kernel<<<1, 1, 0, s>>>(word);
+    tlas_records_kernel<<<grid_of(n), 256, 0, s>>>(recs, n, lohi);
+    refit_tree(nodes, recs, br, word, s);
+}
+
+}  // namespace lidar

@@ -46,6 +46,18 @@ struct SensorHost {
     std::vector<double> elev;
 };
 
+struct MeshHost {
+    MeshDev dev;
+    BuildResult br;
+    Node4 *nodes;
+    TriRec *recs;
+    const uint32_t *idx;    // device copy of the indices (in the mesh workspace)
+    uint64_t nv;
+};
+
+constexpr uint32_t kMaxMeshes = 4096;
+constexpr uint32_t kMaxActors = 1u << 20;
+
 }  // namespace
 
 struct lidar_ctx {
@@ -74,13 +86,31 @@ struct lidar_ctx {
     // pose
     float p[3] = {0, 0, 0};
     float q[4] = {1, 0, 0, 0};
-    // device words: [0] error flags, [1] queue counter
+    // device words: [0] error flags, [1] queue counter, [2..3] refit scratch
     DevBuf words;
     int tile_az_log2 = 4;
     int lanes_per_ray = 4;
     int xcd_remap = 1;
+    // dynamic scene: meshes and the actors placing them
+    std::vector<MeshHost> meshes;
+    DevBuf mesh_table;        // MeshDev[kMaxMeshes]
+    bool has_actors = false;
+    bool tlas_stale = false;  // a mesh was refit after the actors' boxes were computed
+    ActorsDev A{};
+    BuildResult tlas_br{};
+    TriRec *tlas_recs = nullptr;
+    ActorDev *actors_dev = nullptr;
+    float *actor_lohi = nullptr;
+    std::vector<uint32_t> actor_mesh;
+    std::vector<ActorDev> actor_host;
+    ActorDev *staging = nullptr;   // pinned upload buffer of lidar_actors_update
+    size_t staging_n = 0;
+    hipEvent_t staging_ev = nullptr;
+    int actor_stack = 0;
 
-    TraceOpts opts(int tile) const { return TraceOpts{stack, tile, lanes_per_ray, xcd_remap}; }
+    int trace_stack() const { return has_actors && actor_stack > stack ? actor_stack : stack; }
+    TraceOpts opts(int tile) const { return TraceOpts{trace_stack(), tile, lanes_per_ray, xcd_remap}; }
+    uint32_t *refit_word() const { return (uint32_t *)words.p + 2; }
 
     lidar_status fail(lidar_status st, const std::string &msg) {
         err = msg;
@@ -222,6 +252,19 @@ lidar_status ready(lidar_ctx *ctx, bool need_sensor) {
     if (need_sensor && !ctx->has_sensor) return ctx->fail(LIDAR_ERR_NOT_READY, "no sensor set");
     if (ctx->br.max_material >= ctx->M.nmat)
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "scene uses a material id >= nmat");
+    if (ctx->has_actors) {
+        if (ctx->tlas_stale)
+            return ctx->fail(LIDAR_ERR_NOT_READY, "a mesh was refit: call lidar_actors_update before simulating");
+        for (uint32_t m : ctx->actor_mesh)
+            if (ctx->meshes[m].br.max_material >= ctx->M.nmat)
+                return ctx->fail(LIDAR_ERR_INVALID_ARG, "a mesh uses a material id >= nmat");
+    }
+    return LIDAR_OK;
+}
+
+lidar_status no_actors(lidar_ctx *ctx, const char *what) {
+    if (ctx->has_actors)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, std::string(what) + " covers the static scene only: clear the actors");
     return LIDAR_OK;
 }
 
@@ -282,6 +325,9 @@ lidar_status lidar_destroy(lidar_ctx *ctx) {
     ctx->sensor_tables.release();
     ctx->sweep_poses.release();
     ctx->adj_partials.release();
+    ctx->mesh_table.release();
+    if (ctx->staging) hipHostFree(ctx->staging);
+    if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
     ctx->words.release();
     delete ctx;
     return LIDAR_OK;
@@ -481,6 +527,8 @@ static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan
     lidar_status st = ready(ctx, true);
     if (st != LIDAR_OK) return st;
     if (!out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "outputs struct is null");
+    if (brute && (st = no_actors(ctx, "the brute-force reference")) != LIDAR_OK) return st;
+    if (n_nodes && (st = no_actors(ctx, "traversal counting")) != LIDAR_OK) return st;
     const lidar_sensor_desc &d = ctx->sensor.d;
     const double *elev_cs = (const double *)ctx->sensor_tables.p;
     const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
@@ -501,7 +549,7 @@ static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan
     hipStream_t s = (hipStream_t)stream;
     if (brute) launch_bruteforce(ctx->S, in, ctx->M, ov, o, ctx->tile_az_log2, np, s);
     else launch_trace_scan(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, ov, o, np, (uint32_t *)ctx->words.p,
-                           n_nodes, n_tris, s);
+                           n_nodes, n_tris, ctx->has_actors ? &ctx->A : nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "trace launch");
     return wavelength_clamped(ctx, d.wavelength_nm) && !(params && params->rho) ? LIDAR_WARN_WAVELENGTH_CLAMPED
@@ -613,10 +661,277 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, co
     Outputs o = to_outputs(out, nb);
     uint64_t np = padded_rays(ctx->tile_az_log2, d.n_ch, n_cols);
     launch_trace_scan(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, Overrides{}, o, np,
-                      (uint32_t *)ctx->words.p, nullptr, nullptr, s);
+                      (uint32_t *)ctx->words.p, nullptr, nullptr, ctx->has_actors ? &ctx->A : nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "sweep launch");
     return ok;
+}
+
+// ---------------------------------------------------------------------------
+// dynamic scenes: meshes placed by actors
+// ---------------------------------------------------------------------------
+static uint64_t al256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+static void host_rotation(const float q[4], double R[9]) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    double n = std::sqrt(w * w + x * x + y * y + z * z);
+    w /= n; x /= n; y /= n; z /= n;
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static int stack_for_need(int need) {
+    if (need <= 32) return 32;
+    if (need <= 64) return 64;
+    if (need <= 96) return 96;
+    return -1;
+}
+
+static int entries_for_depth(uint32_t depth) { return 3 * (int)(depth > 0 ? depth - 1 : 0) + 1; }
+
+lidar_status lidar_mesh_bytes(const lidar_scene_desc *mesh, uint64_t *persistent_bytes, uint64_t *scratch_bytes) {
+    if (!mesh || !persistent_bytes || !scratch_bytes) return LIDAR_ERR_INVALID_ARG;
+    uint64_t p = 0, sc = 0;
+    lidar_status st = lidar_scene_bytes(mesh, &p, &sc);
+    if (st != LIDAR_OK) return st;
+    *persistent_bytes = al256(p) + al256(12 * mesh->n_triangles);
+    *scratch_bytes = sc;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_mesh_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void *persistent,
+                             uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes, void *stream,
+                             uint32_t *mesh_id) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!desc || !mesh_id) return ctx->fail(LIDAR_ERR_INVALID_ARG, "mesh descriptor or mesh_id is null");
+    if (!desc->vertices || !desc->indices || !desc->material)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "mesh array pointer is null");
+    if (ctx->meshes.size() >= kMaxMeshes) return ctx->fail(LIDAR_ERR_INVALID_ARG, "too many meshes");
+    uint32_t W = desc->leaf_width ? desc->leaf_width : 4u;
+    if (W < 1 || W > 8) return ctx->fail(LIDAR_ERR_INVALID_ARG, "leaf_width must be in 1..8");
+    uint64_t need_p = 0, need_s = 0;
+    if (lidar_mesh_bytes(desc, &need_p, &need_s) != LIDAR_OK)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "triangle/vertex count out of range");
+    if (!persistent || !scratch) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace pointer is null");
+    if (((uintptr_t)persistent & 255) || ((uintptr_t)scratch & 255))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspaces must be 256-byte aligned");
+    if (persistent_bytes < need_p || scratch_bytes < need_s)
+        return ctx->fail(LIDAR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than lidar_mesh_bytes()");
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!ctx->mesh_table.p && (e = ctx->mesh_table.ensure(sizeof(MeshDev) * kMaxMeshes)) != hipSuccess)
+        return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "mesh table allocation failed");
+    const uint32_t nt = (uint32_t)desc->n_triangles;
+    BuildInputs in{};
+    in.nv = desc->n_vertices;
+    in.nt = nt;
+    in.leaf_width = W;
+    in.builder = (desc->flags & LIDAR_SCENE_BUILD_LBVH) ? 1u : 0u;
+    in.ploc_radius = (desc->flags >> 8) & 0xFFu;
+    if (in.ploc_radius == 0) in.ploc_radius = 32;
+    if (in.ploc_radius > 128) return ctx->fail(LIDAR_ERR_INVALID_ARG, "PLOC radius (flags bits 8-15) must be <= 128");
+    if (desc->flags & LIDAR_SCENE_DEVICE_PTRS) {
+        in.vtx = desc->vertices;
+        in.idx = desc->indices;
+        in.mat = desc->material;
+    } else {
+        char *base = (char *)scratch + build_scratch_bytes(nt);
+        float *v = (float *)base;
+        uint32_t *ix = (uint32_t *)(base + al256(12 * in.nv));
+        uint16_t *m = (uint16_t *)((char *)ix + al256(12 * (uint64_t)nt));
+        if ((e = hipMemcpyAsync(v, desc->vertices, 12 * in.nv, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(ix, desc->indices, 12 * (uint64_t)nt, hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(m, desc->material, 2 * (uint64_t)nt, hipMemcpyHostToDevice, s)) != hipSuccess)
+            return ctx->hip_fail(e, "mesh upload");
+        in.vtx = v;
+        in.idx = ix;
+        in.mat = m;
+    }
+    in.label = nullptr;
+    uint32_t *idx_copy = (uint32_t *)((char *)persistent + al256(build_persistent_bytes(nt)));
+    if ((e = hipMemcpyAsync(idx_copy, in.idx, 12 * (uint64_t)nt, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return ctx->hip_fail(e, "mesh index copy");
+    BuildResult br{};
+    if ((e = build_bvh(in, persistent, scratch, br, s)) != hipSuccess) return ctx->hip_fail(e, "mesh BVH build");
+    if (br.bad_index) return ctx->fail(LIDAR_ERR_INVALID_ARG, "a triangle index is >= n_vertices");
+    if (!refit_supported(br) || stack_for_need(entries_for_depth(br.depth)) < 0)
+        return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "mesh BVH too deep");
+    MeshHost mh{};
+    mh.nodes = (Node4 *)persistent;
+    mh.recs = (TriRec *)((char *)persistent + persistent_nodes_bytes(nt));
+    mh.dev.nodes = mh.nodes;
+    mh.dev.tris = mh.recs;
+    mh.dev.max_steps = br.n_nodes + br.n_leaves + 1;
+    mh.dev.n_tri = nt;
+    mh.br = br;
+    mh.idx = idx_copy;
+    mh.nv = desc->n_vertices;
+    ctx->meshes.push_back(mh);
+    const uint32_t id = (uint32_t)ctx->meshes.size() - 1;
+    if ((e = hipMemcpy((MeshDev *)ctx->mesh_table.p + id, &mh.dev, sizeof(MeshDev), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+        return ctx->hip_fail(e, "mesh table upload");
+    *mesh_id = id;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_mesh_refit(lidar_ctx *ctx, uint32_t mesh_id, const float *vertices, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (mesh_id >= ctx->meshes.size()) return ctx->fail(LIDAR_ERR_INVALID_ARG, "mesh id out of range");
+    if (!vertices) return ctx->fail(LIDAR_ERR_INVALID_ARG, "vertices are null");
+    hipSetDevice(ctx->device);
+    MeshHost &m = ctx->meshes[mesh_id];
+    refit_mesh(m.nodes, m.recs, m.br, m.dev.n_tri, m.idx, vertices, m.nv, ctx->refit_word(), (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "mesh refit");
+    if (ctx->has_actors)
+        for (uint32_t am : ctx->actor_mesh)
+            if (am == mesh_id) ctx->tlas_stale = true;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_actors_bytes(uint32_t n_actors, uint64_t *persistent_bytes, uint64_t *scratch_bytes) {
+    if (!persistent_bytes || !scratch_bytes || n_actors < 1 || n_actors > kMaxActors) return LIDAR_ERR_INVALID_ARG;
+    const uint64_t n = n_actors;
+    *persistent_bytes = al256(build_persistent_bytes(n_actors)) + al256(sizeof(ActorDev) * n) + al256(24 * n);
+    *scratch_bytes = al256(build_scratch_bytes(n_actors)) + al256(24 * n) + al256(12 * n) + al256(2 * n);
+    return LIDAR_OK;
+}
+
+static lidar_status actor_table(lidar_ctx *ctx, const lidar_actor *actors, uint32_t n, std::vector<ActorDev> &out) {
+    out.resize(n);
+    uint64_t base = ctx->S.n_tri;
+    for (uint32_t k = 0; k < n; ++k) {
+        const lidar_actor &a = actors[k];
+        if (a.mesh >= ctx->meshes.size()) return ctx->fail(LIDAR_ERR_INVALID_ARG, "actor mesh id out of range");
+        lidar_status st = check_quat(ctx, a.p, a.q_wxyz);
+        if (st != LIDAR_OK) return st;
+        ActorDev d{};
+        host_rotation(a.q_wxyz, d.R);
+        for (int e = 0; e < 3; ++e) d.p[e] = a.p[e];
+        d.mesh = a.mesh;
+        d.label = a.label;
+        d.tri_base = (uint32_t)base;
+        base += ctx->meshes[a.mesh].dev.n_tri;
+        if (base >= 0xFFFFFFFFull) return ctx->fail(LIDAR_ERR_INVALID_ARG, "too many triangles in the scene");
+        out[k] = d;
+    }
+    return LIDAR_OK;
+}
+
+lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_t n_actors, void *persistent,
+                              uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!ctx->has_scene) return ctx->fail(LIDAR_ERR_NOT_READY, "load the static scene before the actors");
+    if (n_actors == 0) return lidar_actors_clear(ctx);
+    if (!actors) return ctx->fail(LIDAR_ERR_INVALID_ARG, "actors are null");
+    uint64_t need_p = 0, need_s = 0;
+    if (lidar_actors_bytes(n_actors, &need_p, &need_s) != LIDAR_OK)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "actor count out of range");
+    if (!persistent || !scratch) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace pointer is null");
+    if (((uintptr_t)persistent & 255) || ((uintptr_t)scratch & 255))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspaces must be 256-byte aligned");
+    if (persistent_bytes < need_p || scratch_bytes < need_s)
+        return ctx->fail(LIDAR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than lidar_actors_bytes()");
+    std::vector<ActorDev> h;
+    lidar_status st = actor_table(ctx, actors, n_actors, h);
+    if (st != LIDAR_OK) return st;
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t n = n_actors;
+    char *P = (char *)persistent, *Sc = (char *)scratch;
+    ActorDev *ad = (ActorDev *)(P + al256(build_persistent_bytes(n_actors)));
+    float *lohi = (float *)((char *)ad + al256(sizeof(ActorDev) * n));
+    float *vtx = (float *)(Sc + al256(build_scratch_bytes(n_actors)));
+    uint32_t *idx = (uint32_t *)((char *)vtx + al256(24 * n));
+    uint16_t *mat = (uint16_t *)((char *)idx + al256(12 * n));
+    ctx->has_actors = false;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ad, h.data(), sizeof(ActorDev) * n, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return ctx->hip_fail(e, "actor upload");
+    actor_boxes(ad, n_actors, (const MeshDev *)ctx->mesh_table.p, lohi, ctx->refit_word(), s);
+    actor_prims(lohi, n_actors, vtx, idx, mat, s);
+    BuildInputs in{};
+    in.vtx = vtx;
+    in.idx = idx;
+    in.mat = mat;
+    in.label = nullptr;
+    in.nv = 2 * n;
+    in.nt = n_actors;
+    in.leaf_width = 4;
+    in.builder = 0;
+    in.ploc_radius = 32;
+    BuildResult br{};
+    if ((e = build_bvh(in, persistent, scratch, br, s)) != hipSuccess) return ctx->hip_fail(e, "actor BVH build");
+    if (!refit_supported(br)) return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "actor BVH too deep");
+    int mesh_need = 0;
+    for (const ActorDev &d : h) mesh_need = std::max(mesh_need, entries_for_depth(ctx->meshes[d.mesh].br.depth));
+    const int stack = stack_for_need(entries_for_depth(br.depth) + mesh_need);
+    if (stack < 0) return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "actor and mesh BVHs too deep for the traversal stack");
+    if (ctx->staging_n < n_actors) {
+        if (ctx->staging) hipHostFree(ctx->staging);
+        ctx->staging = nullptr;
+        ctx->staging_n = 0;
+        if ((e = hipHostMalloc((void **)&ctx->staging, sizeof(ActorDev) * n)) != hipSuccess)
+            return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "pinned staging allocation failed");
+        ctx->staging_n = n_actors;
+    }
+    if (!ctx->staging_ev && (e = hipEventCreateWithFlags(&ctx->staging_ev, hipEventDisableTiming)) != hipSuccess)
+        return ctx->hip_fail(e, "event");
+    if ((e = hipEventRecord(ctx->staging_ev, s)) != hipSuccess) return ctx->hip_fail(e, "event record");
+    ctx->tlas_br = br;
+    ctx->tlas_recs = (TriRec *)(P + persistent_nodes_bytes(n_actors));
+    ctx->actors_dev = ad;
+    ctx->actor_lohi = lohi;
+    ctx->A.nodes = (const Node4 *)P;
+    ctx->A.recs = ctx->tlas_recs;
+    ctx->A.actors = ad;
+    ctx->A.meshes = (const MeshDev *)ctx->mesh_table.p;
+    ctx->A.max_steps = br.n_nodes + br.n_leaves + 1;
+    ctx->A.n_actors = n_actors;
+    ctx->actor_mesh.resize(n_actors);
+    for (uint32_t k = 0; k < n_actors; ++k) ctx->actor_mesh[k] = actors[k].mesh;
+    ctx->actor_stack = stack;
+    ctx->tlas_stale = false;
+    ctx->has_actors = true;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_actors_update(lidar_ctx *ctx, const lidar_actor *actors, uint32_t n_actors, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!ctx->has_actors) return ctx->fail(LIDAR_ERR_NOT_READY, "no actors set");
+    if (!actors || n_actors != ctx->A.n_actors)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "update needs the actor count of lidar_actors_set");
+    for (uint32_t k = 0; k < n_actors; ++k)
+        if (actors[k].mesh != ctx->actor_mesh[k])
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "update keeps every actor's mesh (use lidar_actors_set)");
+    lidar_status st = actor_table(ctx, actors, n_actors, ctx->actor_host);
+    if (st != LIDAR_OK) return st;
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = hipEventSynchronize(ctx->staging_ev)) != hipSuccess) return ctx->hip_fail(e, "staging wait");
+    std::memcpy(ctx->staging, ctx->actor_host.data(), sizeof(ActorDev) * n_actors);
+    if ((e = hipMemcpyAsync(ctx->actors_dev, ctx->staging, sizeof(ActorDev) * n_actors, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipEventRecord(ctx->staging_ev, s)) != hipSuccess)
+        return ctx->hip_fail(e, "actor upload");
+    actor_boxes(ctx->actors_dev, n_actors, (const MeshDev *)ctx->mesh_table.p, ctx->actor_lohi, ctx->refit_word(), s);
+    refit_tlas((Node4 *)ctx->A.nodes, ctx->tlas_recs, ctx->tlas_br, n_actors, ctx->actor_lohi, ctx->refit_word(), s);
+    if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "actor update");
+    ctx->tlas_stale = false;
+    return LIDAR_OK;
+}
+
+lidar_status lidar_actors_clear(lidar_ctx *ctx) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    ctx->has_actors = false;
+    ctx->tlas_stale = false;
+    ctx->A = ActorsDev{};
+    ctx->actor_mesh.clear();
+    return LIDAR_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -691,6 +1006,7 @@ lidar_status lidar_batch_rays(const lidar_batch *b, uint64_t *n) {
 lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_outputs *out, void *stream) {
     lidar_status st = ready(ctx, false);
     if (st != LIDAR_OK) return st;
+    if ((st = no_actors(ctx, "the batched form")) != LIDAR_OK) return st;
     if (!b || b->ctx != ctx || !out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "bad batch or outputs");
     hipSetDevice(ctx->device);
     Outputs o = to_outputs(out, b->n_rays);
@@ -723,6 +1039,7 @@ lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *b, con
                                              void *stream) {
     lidar_status st = ready(ctx, false);
     if (st != LIDAR_OK) return st;
+    if ((st = no_actors(ctx, "the batched form")) != LIDAR_OK) return st;
     if (!b || b->ctx != ctx || !out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "bad batch or outputs");
     hipSetDevice(ctx->device);
     Outputs o = to_outputs(out, b->n_rays);
@@ -731,7 +1048,7 @@ lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *b, con
         const InstanceDev &in = b->h_insts[k];
         uint64_t np = padded_rays(b->tile_az_log2, in.n_ch, in.n_az);
         launch_trace_scan(ctx->opts(b->tile_az_log2), ctx->S, in, ctx->M, ov, o, np, (uint32_t *)ctx->words.p,
-                          nullptr, nullptr, (hipStream_t)stream);
+                          nullptr, nullptr, nullptr, (hipStream_t)stream);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "sequential launches");
@@ -835,6 +1152,7 @@ static lidar_status backward_common(lidar_ctx *ctx, const lidar_params *params, 
     if (ctx->M.nmat > kMaxAdjMaterials) return ctx->fail(LIDAR_ERR_INVALID_ARG, "backward supports nmat <= 256");
     if (params && params->rho && params->spectra)
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "params: give rho or spectra, not both");
+    if ((st = no_actors(ctx, "the adjoint")) != LIDAR_OK) return st;
     const lidar_sensor_desc &d = ctx->sensor.d;
     size_t pb = adjoint_partial_bytes(d.n_ch * d.n_az, ctx->M.nmat);
     if (ctx->adj_partials.n < pb) return ctx->fail(LIDAR_ERR_NOT_READY, "adjoint buffer not allocated");

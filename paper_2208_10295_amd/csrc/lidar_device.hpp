@@ -77,6 +77,36 @@ struct InstanceDev {
     uint32_t seg_i0[2];
 };
 
+// ---------------------------------------------------------------------------
+// Dynamic scenes: meshes (own BVH over object-space triangles) placed in the
+// world by actors, and a top-level BVH over the actors' world boxes whose
+// leaf records carry the actor index in a.w.
+// ---------------------------------------------------------------------------
+struct ActorDev {
+    double R[9];               // world <- object rotation, row-major
+    double p[3];               // world position of the object origin
+    uint32_t mesh;             // index into the mesh table
+    uint32_t label;            // instance label of all its triangles
+    uint32_t tri_base;         // index of its first triangle in the combined ordering
+    uint32_t pad_;
+};
+
+struct MeshDev {
+    const Node4 *nodes;
+    const TriRec *tris;
+    uint32_t max_steps;
+    uint32_t n_tri;
+};
+
+struct ActorsDev {
+    const Node4 *nodes;        // top-level BVH (root 0)
+    const TriRec *recs;        // its leaf records: a.w = actor index
+    const ActorDev *actors;
+    const MeshDev *meshes;
+    uint32_t max_steps;
+    uint32_t n_actors;
+};
+
 struct MaterialsDev {
     const float *spectra;      // [nmat][nbins]
     const float *sigma;        // [nmat]
@@ -209,6 +239,23 @@ __device__ inline Ray make_ray(const InstanceDev &in, const Pose64 &P, uint32_t 
     r.dy = (float)(P.R[3] * s0 + P.R[4] * s1 + P.R[5] * s2);
     r.dz = (float)(P.R[6] * s0 + P.R[7] * s1 + P.R[8] * s2);
     r.ox = (float)P.p[0]; r.oy = (float)P.p[1]; r.oz = (float)P.p[2];
+    return r;
+}
+
+// The object-space ray of an actor: o' = R^T (o - p), d' = R^T d in FP64,
+// rounded once.  R is a rotation, so the ray parameter t is the same in both
+// spaces.
+__device__ inline Ray object_ray(const ActorDev &A, const Ray &w) {
+    const double ox = (double)w.ox - A.p[0], oy = (double)w.oy - A.p[1], oz = (double)w.oz - A.p[2];
+    const double dx = w.dx, dy = w.dy, dz = w.dz;
+    Ray r;
+    r.ox = (float)(A.R[0] * ox + A.R[3] * oy + A.R[6] * oz);
+    r.oy = (float)(A.R[1] * ox + A.R[4] * oy + A.R[7] * oz);
+    r.oz = (float)(A.R[2] * ox + A.R[5] * oy + A.R[8] * oz);
+    r.dx = (float)(A.R[0] * dx + A.R[3] * dy + A.R[6] * dz);
+    r.dy = (float)(A.R[1] * dx + A.R[4] * dy + A.R[7] * dz);
+    r.dz = (float)(A.R[2] * dx + A.R[5] * dy + A.R[8] * dz);
+    r.sx = w.sx; r.sy = w.sy; r.sz = w.sz;
     return r;
 }
 

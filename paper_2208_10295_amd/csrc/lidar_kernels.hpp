@@ -28,7 +28,7 @@ struct BuildInputs {
     const float *vtx;          // device [nv][3]
     const uint32_t *idx;       // device [nt][3]
     const uint16_t *mat;       // device [nt]
-    const uint32_t *label;     // device [nt]
+    const uint32_t *label;     // device [nt], or null (label 0)
     uint64_t nv;
     uint32_t nt;
     uint32_t leaf_width;
@@ -40,6 +40,8 @@ struct BuildInputs {
 size_t persistent_nodes_bytes(uint32_t nt);
 size_t persistent_recs_bytes(uint32_t nt);
 
+constexpr int kMaxLevels = 64;   // refit supports trees up to this depth
+
 struct BuildResult {
     uint32_t root;
     uint32_t n_nodes;
@@ -48,6 +50,7 @@ struct BuildResult {
     uint32_t max_material;
     uint32_t bad_index;
     float box_pad;
+    uint32_t level_base[kMaxLevels + 1];   // nodes of level L: [level_base[L], level_base[L + 1])
 };
 
 size_t build_scratch_bytes(uint32_t nt);
@@ -76,16 +79,28 @@ struct SweepPoseArgs {
 };
 // writes 12 doubles (R row-major, p) per fired column to `out`
 void launch_sweep_poses(const SweepPoseArgs &A, double *out, hipStream_t s);
-// n_nodes / n_tris: optional per-beam traversal counts (null = plain kernel)
+// n_nodes / n_tris: optional per-beam traversal counts (null = plain kernel);
+// actors: the dynamic part of the scene, or null
 void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
                        const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err, uint32_t *n_nodes,
-                       uint32_t *n_tris, hipStream_t s);
+                       uint32_t *n_tris, const ActorsDev *actors, hipStream_t s);
 void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
                        const Outputs &out, int tile_az_log2, uint64_t n_padded, hipStream_t s);
 void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
                         const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
                         uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s);
 int batch_blocks_per_cu(const TraceOpts &t);
+
+// --- dynamic scenes (dynamic.hip) ---
+// word: two device words of scratch (max |coordinate| bits, pad bits)
+bool refit_supported(const BuildResult &br);
+void refit_mesh(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t nt, const uint32_t *idx,
+                const float *vertices, uint64_t nv, uint32_t *word, hipStream_t s);
+void actor_boxes(const ActorDev *actors, uint32_t n, const MeshDev *meshes, float *lohi, uint32_t *word,
+                 hipStream_t s);
+void actor_prims(const float *lohi, uint32_t n, float *vtx, uint32_t *idx, uint16_t *mat, hipStream_t s);
+void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,
+                hipStream_t s);
 
 // --- adjoint (adjoint.hip) ---
 constexpr int kAdjBlock = 256;

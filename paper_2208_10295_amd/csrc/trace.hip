@@ -127,8 +127,9 @@ void launch_sweep_poses(const SweepPoseArgs &A, double *out, hipStream_t s) {
 // ---------------------------------------------------------------------------
 struct Hit {
     uint32_t slot;     // triangle record index, kNone if no hit
-    uint32_t orig;     // original triangle index
+    uint32_t orig;     // original triangle index (actors: in the combined ordering)
     float t;
+    uint32_t actor;    // kNone: static scene; else the actor whose mesh holds the record
 };
 
 struct Counts {
@@ -179,11 +180,11 @@ __device__ inline float box_limit(float best_t) { return best_t * 1.0000005f; }
 template <int STACK, int NSLOT, bool COUNT>
 __device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris, uint32_t root,
                                uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
-                               uint32_t *__restrict__ stk, bool &overflow, Counts &cnt) {
+                               uint32_t *__restrict__ stk, bool &overflow, Counts &cnt, int cap = STACK) {
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
     const float inf = __builtin_inff();
-    Hit h{kNone, kNone, t_hi};
+    Hit h{kNone, kNone, t_hi, kNone};
     uint32_t ref = root;
     int sp = 0;
     uint32_t steps = 0;
@@ -212,9 +213,9 @@ __device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__
                      c3 = __float_as_uint(a3.w);
             sort4(k0, c0, k1, c1, k2, c2, k3, c3);
             if (k0 != inf) {
-                if (k3 != inf) { if (sp < STACK) stk[(sp++) * NSLOT] = c3; else overflow = true; }
-                if (k2 != inf) { if (sp < STACK) stk[(sp++) * NSLOT] = c2; else overflow = true; }
-                if (k1 != inf) { if (sp < STACK) stk[(sp++) * NSLOT] = c1; else overflow = true; }
+                if (k3 != inf) { if (sp < cap) stk[(sp++) * NSLOT] = c3; else overflow = true; }
+                if (k2 != inf) { if (sp < cap) stk[(sp++) * NSLOT] = c2; else overflow = true; }
+                if (k1 != inf) { if (sp < cap) stk[(sp++) * NSLOT] = c1; else overflow = true; }
                 ref = c0;
                 continue;
             }
@@ -236,12 +237,13 @@ __device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__
 template <int LANES, int STACK, int NSLOT, bool COUNT>
 __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
                                      uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
-                                     uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt) {
+                                     uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt,
+                                     int cap = STACK) {
     static_assert(LANES == 2 || LANES == 4, "2 or 4 lanes per beam");
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
     const float inf = __builtin_inff();
-    Hit h{kNone, kNone, t_hi};
+    Hit h{kNone, kNone, t_hi, kNone};
     uint32_t ref = root;
     int sp = 0;
     uint32_t steps = 0;
@@ -302,9 +304,9 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
             }
             sort4(k0, c0, k1, c1, k2, c2, k3, c3);
             if (k0 != inf) {
-                if (k3 != inf) { if (sp < STACK) { if (s == 0) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
-                if (k2 != inf) { if (sp < STACK) { if (s == 0) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
-                if (k1 != inf) { if (sp < STACK) { if (s == 0) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
+                if (k3 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
+                if (k2 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
+                if (k1 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
                 ref = c0;
                 continue;
             }
@@ -316,11 +318,94 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
 }
 
 // ---------------------------------------------------------------------------
+// Dynamic scenes: the top-level BVH over the actors.  Its nodes are tested
+// like any 4-wide node (LANES lanes per beam); at a leaf, each actor's ray is
+// taken to object space and the actor's mesh BVH is walked with the stack
+// entries above the top-level ones, with the best distance so far as its
+// limit.  Candidates are compared by (t, index in the combined ordering), the
+// static scene's triangles first, so ties resolve as in one flat soup.
+// ---------------------------------------------------------------------------
+template <int LANES, int STACK, int NSLOT>
+__device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float t_lo, Hit &h,
+                                       uint32_t *__restrict__ stk, uint32_t s, bool &overflow) {
+    const RayBox B = prep_box_test(ray);
+    const float inf = __builtin_inff();
+    Counts cnt{0u, 0u};
+    uint32_t ref = 0;
+    int sp = 0;
+    uint32_t steps = 0;
+    while (true) {
+        if (++steps > A.max_steps) { overflow = true; break; }
+        if (ref & kLeafBit) {
+            const uint32_t first = leaf_first(ref), n = leaf_count(ref);
+            for (uint32_t k = 0; k < n; ++k) {
+                const uint32_t a = __float_as_uint(A.recs[first + k].a.w);
+                const ActorDev &act = A.actors[a];
+                const Ray ro = object_ray(act, ray);
+                const MeshDev m = A.meshes[act.mesh];
+                Hit hb;
+                if constexpr (LANES == 1)
+                    hb = traverse<STACK, NSLOT, false>(m.nodes, m.tris, 0u, m.max_steps, ro, t_lo, h.t,
+                                                       stk + sp * NSLOT, overflow, cnt, STACK - sp);
+                else
+                    hb = traverse_multi<LANES, STACK, NSLOT, false>(m.nodes, m.tris, 0u, m.max_steps, ro, t_lo, h.t,
+                                                                    stk + sp * NSLOT, s, overflow, cnt, STACK - sp);
+                if (hb.slot != kNone) {
+                    const uint32_t g = act.tri_base + hb.orig;
+                    if (better(hb.t, g, h.t, h.orig)) { h.t = hb.t; h.orig = g; h.slot = hb.slot; h.actor = a; }
+                }
+            }
+        } else {
+            const float lim = box_limit(h.t);
+            float k0, k1, k2, k3;
+            uint32_t c0, c1, c2, c3;
+            const float4 *np = reinterpret_cast<const float4 *>(A.nodes + ref);
+            if constexpr (LANES == 1) {
+                float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3], a2 = np[4], b2 = np[5], a3 = np[6], b3 = np[7];
+                k0 = slab(B, a0, b0, t_lo, lim); k1 = slab(B, a1, b1, t_lo, lim);
+                k2 = slab(B, a2, b2, t_lo, lim); k3 = slab(B, a3, b3, t_lo, lim);
+                c0 = __float_as_uint(a0.w); c1 = __float_as_uint(a1.w); c2 = __float_as_uint(a2.w); c3 = __float_as_uint(a3.w);
+            } else if constexpr (LANES == 4) {
+                float4 a = np[2 * s], b = np[2 * s + 1];
+                float key = slab(B, a, b, t_lo, lim);
+                uint32_t cref = __float_as_uint(a.w);
+                k0 = quad_bcast<0>(key); k1 = quad_bcast<1>(key); k2 = quad_bcast<2>(key); k3 = quad_bcast<3>(key);
+                c0 = quad_bcast<0>(cref); c1 = quad_bcast<1>(cref); c2 = quad_bcast<2>(cref); c3 = quad_bcast<3>(cref);
+            } else {
+                float4 a0 = np[4 * s], b0 = np[4 * s + 1], a1 = np[4 * s + 2], b1 = np[4 * s + 3];
+                float ka = slab(B, a0, b0, t_lo, lim), kb = slab(B, a1, b1, t_lo, lim);
+                uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
+                float oa = __uint_as_float(quad_xor1(__float_as_uint(ka)));
+                float ob = __uint_as_float(quad_xor1(__float_as_uint(kb)));
+                uint32_t oca = quad_xor1(ca), ocb = quad_xor1(cb);
+                const bool lo = (s == 0);
+                k0 = lo ? ka : oa; c0 = lo ? ca : oca;
+                k1 = lo ? kb : ob; c1 = lo ? cb : ocb;
+                k2 = lo ? oa : ka; c2 = lo ? oca : ca;
+                k3 = lo ? ob : kb; c3 = lo ? ocb : cb;
+            }
+            sort4(k0, c0, k1, c1, k2, c2, k3, c3);
+            if (k0 != inf) {
+                const bool w = (LANES == 1) || s == 0;
+                if (k3 != inf) { if (sp < STACK) { if (w) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
+                if (k2 != inf) { if (sp < STACK) { if (w) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
+                if (k1 != inf) { if (sp < STACK) { if (w) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
+                ref = c0;
+                continue;
+            }
+        }
+        if (sp == 0) break;
+        ref = stk[(--sp) * NSLOT];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Hit attributes + return model + output write (fused epilogue)
 // ---------------------------------------------------------------------------
 __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
                                        const Outputs &out, uint64_t o, uint32_t beam, uint32_t scan,
-                                       const Ray &ray, const TriRec *__restrict__ tris, const Hit &h) {
+                                       const Ray &ray, const TriRec *__restrict__ tris, const Hit &h,
+                                       const ActorDev *act = nullptr) {
     bool hit = h.slot != kNone;
     float nx = 0.f, ny = 0.f, nz = 0.f, rl = 0.f, dn = 0.f, inten = 0.f, tt = 0.f;
     uint32_t lab = kNone, orig = kNone;
@@ -329,8 +414,10 @@ __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev
     if (hit) {
         const TriRec *r = tris + h.slot;
         float4 a = r->a, b = r->b, c = r->c;
-        orig = __float_as_uint(a.w);
-        uint32_t label = __float_as_uint(b.w);
+        // an actor's record is in object space: its label is the actor's, its
+        // index the combined one, and its normal is rotated to the world
+        orig = act ? h.orig : __float_as_uint(a.w);
+        uint32_t label = act ? act->label : __float_as_uint(b.w);
         uint32_t m = __float_as_uint(c.w);
         mat16 = (uint16_t)m;
         float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
@@ -340,6 +427,12 @@ __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev
         float cz = fmaf(e1x, e2y, -e1y * e2x);
         float len = __fsqrt_rn(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
         nx = cx / len; ny = cy / len; nz = cz / len;
+        if (act) {
+            const double X = nx, Y = ny, Z = nz;
+            nx = (float)(act->R[0] * X + act->R[1] * Y + act->R[2] * Z);
+            ny = (float)(act->R[3] * X + act->R[4] * Y + act->R[5] * Z);
+            nz = (float)(act->R[6] * X + act->R[7] * Y + act->R[8] * Z);
+        }
         float cd = fmaf(nx, ray.dx, fmaf(ny, ray.dy, nz * ray.dz));
         float cs = fabsf(cd);
         float r0 = reflectance0(ov, M, in.wavelength_nm, m);
@@ -416,12 +509,12 @@ __device__ inline Ray beam_ray(const InstanceDev &in, const Overrides &ov, uint3
     return make_ray(in, make_pose(in, ov.pose_delta), j, i);
 }
 
-template <int STACK, int BLOCK, bool COUNT, bool SWEEP>
+template <int STACK, int BLOCK, bool COUNT, bool SWEEP, bool ACTORS>
 __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
                                                            Overrides ov, Outputs out, int tile_az_log2,
                                                            uint64_t n_padded, int xcd_remap, uint32_t *err,
                                                            uint32_t *__restrict__ n_nodes,
-                                                           uint32_t *__restrict__ n_tris) {
+                                                           uint32_t *__restrict__ n_tris, ActorsDev A) {
     __shared__ uint32_t stk[STACK * BLOCK];
     uint64_t r = (uint64_t)logical_block(xcd_remap) * BLOCK + threadIdx.x;
     if (r >= n_padded) return;
@@ -432,24 +525,33 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
     Counts c{0u, 0u};
     Hit h = traverse<STACK, BLOCK, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + threadIdx.x,
                                           overflow, c);
+    const ActorDev *act = nullptr;
+    const TriRec *tris = S.tris;
+    if constexpr (ACTORS) {
+        traverse_actors<1, STACK, BLOCK>(A, ray, in.t_min, h, stk + threadIdx.x, 0u, overflow);
+        if (h.actor != kNone) {
+            act = A.actors + h.actor;
+            tris = A.meshes[act->mesh].tris;
+        }
+    }
     if (overflow) atomicOr(err, 1u);
     uint32_t beam = j * in.n_az + i;
     if (COUNT) {
         n_nodes[beam] = c.nodes;
         n_tris[beam] = c.tris;
     }
-    shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
+    shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, tris, h, act);
 }
 
 // ---------------------------------------------------------------------------
 // Kernel 1m: one scan, LANES (2 or 4) lanes per ray (BLOCK / LANES rays)
 // ---------------------------------------------------------------------------
-template <int STACK, int BLOCK, int LANES, bool COUNT, bool SWEEP>
+template <int STACK, int BLOCK, int LANES, bool COUNT, bool SWEEP, bool ACTORS>
 __global__ __launch_bounds__(BLOCK) void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
                                                                  Overrides ov, Outputs out, int tile_az_log2,
                                                                  uint64_t n_padded, int xcd_remap, uint32_t *err,
                                                                  uint32_t *__restrict__ n_nodes,
-                                                                 uint32_t *__restrict__ n_tris) {
+                                                                 uint32_t *__restrict__ n_tris, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
     __shared__ uint32_t stk[STACK * NR];
     const uint32_t q = threadIdx.x / LANES, s = threadIdx.x % LANES;
@@ -462,6 +564,15 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_multi_kernel(SceneDev S, Ins
     Counts c{0u, 0u};
     Hit h = traverse_multi<LANES, STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace,
                                                     stk + q, s, overflow, c);
+    const ActorDev *act = nullptr;
+    const TriRec *tris = S.tris;
+    if constexpr (ACTORS) {
+        traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
+        if (h.actor != kNone) {
+            act = A.actors + h.actor;
+            tris = A.meshes[act->mesh].tris;
+        }
+    }
     if (overflow) atomicOr(err, 1u);
     if (s != 0) return;
     uint32_t beam = j * in.n_az + i;
@@ -469,7 +580,7 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_multi_kernel(SceneDev S, Ins
         n_nodes[beam] = c.nodes;
         n_tris[beam] = c.tris;
     }
-    shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
+    shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, tris, h, act);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,7 +600,7 @@ __global__ __launch_bounds__(BLOCK) void bruteforce_kernel(SceneDev S, InstanceD
     Pose64 P = column_pose(in, ov.pose_delta, k);
     Ray ray = make_ray(in, P, j, i);
     RayTri T = prep_tri_test(ray);
-    Hit h{kNone, kNone, in.t_trace};
+    Hit h{kNone, kNone, in.t_trace, kNone};
     const float4 *src = reinterpret_cast<const float4 *>(S.tris);
     for (uint32_t base = 0; base < S.n_tri; base += CHUNK) {
         uint32_t cnt = min((uint32_t)CHUNK, S.n_tri - base);
@@ -579,44 +690,49 @@ constexpr int kBlock = 128;       // lane-per-ray block (2 waves, 128 rays)
 constexpr int kPairBlock = 128;   // pair-per-ray block (2 waves, 64 rays)
 constexpr int kQuadBlock = 256;   // quad-per-ray block (4 waves, 64 rays)
 
-template <int STACK, bool COUNT, bool SWEEP>
+template <int STACK, bool COUNT, bool SWEEP, bool ACTORS>
 static void launch_scan_t(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
                           const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err,
-                          uint32_t *nn, uint32_t *nt, hipStream_t s) {
+                          uint32_t *nn, uint32_t *nt, const ActorsDev &A, hipStream_t s) {
     if (t.lanes_per_ray == 4) {
         uint32_t blocks = (uint32_t)((n_padded * 4 + kQuadBlock - 1) / kQuadBlock);
-        trace_scan_multi_kernel<STACK, kQuadBlock, 4, COUNT, SWEEP><<<blocks, kQuadBlock, 0, s>>>(
-            S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt);
+        trace_scan_multi_kernel<STACK, kQuadBlock, 4, COUNT, SWEEP, ACTORS><<<blocks, kQuadBlock, 0, s>>>(
+            S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt, A);
     } else if (t.lanes_per_ray == 2) {
         uint32_t blocks = (uint32_t)((n_padded * 2 + kPairBlock - 1) / kPairBlock);
-        trace_scan_multi_kernel<STACK, kPairBlock, 2, COUNT, SWEEP><<<blocks, kPairBlock, 0, s>>>(
-            S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt);
+        trace_scan_multi_kernel<STACK, kPairBlock, 2, COUNT, SWEEP, ACTORS><<<blocks, kPairBlock, 0, s>>>(
+            S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt, A);
     } else {
         uint32_t blocks = (uint32_t)((n_padded + kBlock - 1) / kBlock);
-        trace_scan_kernel<STACK, kBlock, COUNT, SWEEP><<<blocks, kBlock, 0, s>>>(S, in, M, ov, out, t.tile_az_log2,
-                                                                                 n_padded, t.xcd_remap, err, nn, nt);
+        trace_scan_kernel<STACK, kBlock, COUNT, SWEEP, ACTORS><<<blocks, kBlock, 0, s>>>(
+            S, in, M, ov, out, t.tile_az_log2, n_padded, t.xcd_remap, err, nn, nt, A);
+    }
+}
+
+template <int STACK>
+static void launch_scan_s(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                          const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err,
+                          uint32_t *nn, uint32_t *nt, const ActorsDev *A, hipStream_t s) {
+    const bool sweep = in.col_pose != nullptr;
+    const ActorsDev none{};
+    if (A) {   // dynamic scene (never counted)
+        if (sweep) launch_scan_t<STACK, false, true, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, *A, s);
+        else launch_scan_t<STACK, false, false, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, *A, s);
+    } else if (sweep) {
+        launch_scan_t<STACK, false, true, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, none, s);
+    } else if (nn) {
+        launch_scan_t<STACK, true, false, false>(t, S, in, M, ov, out, n_padded, err, nn, nt, none, s);
+    } else {
+        launch_scan_t<STACK, false, false, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, none, s);
     }
 }
 
 void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
                        const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err, uint32_t *n_nodes,
-                       uint32_t *n_tris, hipStream_t s) {
-    const bool count = n_nodes != nullptr;
-    const bool sweep = in.col_pose != nullptr;
-    if (sweep) {   // sweeps do not count
-        if (t.stack <= 32) launch_scan_t<32, false, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
-        else if (t.stack <= 64) launch_scan_t<64, false, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
-        else launch_scan_t<96, false, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
-    } else if (t.stack <= 32) {
-        if (count) launch_scan_t<32, true, false>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
-        else launch_scan_t<32, false, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
-    } else if (t.stack <= 64) {
-        if (count) launch_scan_t<64, true, false>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
-        else launch_scan_t<64, false, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
-    } else {
-        if (count) launch_scan_t<96, true, false>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, s);
-        else launch_scan_t<96, false, false>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, s);
-    }
+                       uint32_t *n_tris, const ActorsDev *actors, hipStream_t s) {
+    if (t.stack <= 32) launch_scan_s<32>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
+    else if (t.stack <= 64) launch_scan_s<64>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
+    else launch_scan_s<96>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
 }
 
 void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,

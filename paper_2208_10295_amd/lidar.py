@@ -145,6 +145,76 @@ class Context:
         self.set_materials(scene.spectra, scene.sigma_range, scene.angle_exp)
         return st
 
+    # -- dynamic scenes -----------------------------------------------------
+    def load_mesh(self, mesh, leaf_width: int = 4, stream=None) -> int:
+        """Builds the BVH of a mesh (object-space vertices/indices/material); returns its id."""
+        dev = self.device
+        v = torch.as_tensor(np.ascontiguousarray(mesh.vertices, np.float32)).to(dev)
+        i = torch.as_tensor(np.ascontiguousarray(mesh.indices, np.uint32).view(np.int32)).to(dev)
+        m = torch.as_tensor(np.ascontiguousarray(mesh.material, np.uint16).view(np.int16)).to(dev)
+        d = A.SceneDesc()
+        d.n_vertices, d.n_triangles = v.shape[0], i.shape[0]
+        d.vertices, d.indices, d.material = v.data_ptr(), i.data_ptr(), m.data_ptr()
+        d.leaf_width = int(leaf_width)
+        d.flags = A.SCENE_DEVICE_PTRS
+        pb, sb = C.c_uint64(), C.c_uint64()
+        check(lib.lidar_mesh_bytes(C.byref(d), C.byref(pb), C.byref(sb)), self.h)
+        persistent = torch.empty(pb.value, dtype=torch.uint8, device=dev)
+        scratch = torch.empty(sb.value, dtype=torch.uint8, device=dev)
+        mid = C.c_uint32()
+        check(lib.lidar_mesh_load(self.h, C.byref(d), _ptr(persistent), pb.value, _ptr(scratch), sb.value,
+                                  _stream(stream), C.byref(mid)), self.h)
+        if not hasattr(self, "_meshes"):
+            self._meshes = []
+        self._meshes.append((persistent, int(v.shape[0])))
+        return int(mid.value)
+
+    def refit_mesh(self, mesh_id: int, vertices, stream=None):
+        """New object-space vertices for a loaded mesh (same topology); call update_actors afterwards."""
+        t = vertices if torch.is_tensor(vertices) else torch.as_tensor(np.ascontiguousarray(vertices, np.float32))
+        t = t.to(self.device, torch.float32).contiguous()
+        assert t.shape == (self._meshes[mesh_id][1], 3)
+        check(lib.lidar_mesh_refit(self.h, int(mesh_id), _ptr(t), _stream(stream)), self.h)
+        self._refit_keep = t      # alive until the stream has used it
+
+    @staticmethod
+    def _actor_array(actors):
+        arr = (A.Actor * len(actors))()
+        for k, a in enumerate(actors):
+            arr[k].mesh, arr[k].label = int(a.mesh), int(a.label)
+            for e in range(3):
+                arr[k].p[e] = float(a.p[e])
+            for e in range(4):
+                arr[k].q_wxyz[e] = float(a.q[e])
+        return arr
+
+    def set_actors(self, actors, stream=None):
+        """Places meshes by actors (objects with mesh, label, p, q) and builds the top-level BVH."""
+        n = len(actors)
+        if n == 0:
+            self.clear_actors()
+            return
+        pb, sb = C.c_uint64(), C.c_uint64()
+        check(lib.lidar_actors_bytes(n, C.byref(pb), C.byref(sb)), self.h)
+        persistent = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+        scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+        arr = self._actor_array(actors)
+        check(lib.lidar_actors_set(self.h, arr, n, _ptr(persistent), pb.value, _ptr(scratch), sb.value,
+                                   _stream(stream)), self.h)
+        self._actors_persistent = persistent
+
+    def update_actors(self, actors, stream=None):
+        """Same actors at new poses: top-level BVH refit (asynchronous).  `actors` may be a
+        prebuilt array from actor_array()."""
+        arr = actors if isinstance(actors, C.Array) else self._actor_array(actors)
+        check(lib.lidar_actors_update(self.h, arr, len(arr), _stream(stream)), self.h)
+
+    actor_array = _actor_array
+
+    def clear_actors(self):
+        check(lib.lidar_actors_clear(self.h), self.h)
+        self._actors_persistent = None
+
     def stats(self) -> dict:
         s = A.Stats()
         check(lib.lidar_get_stats(self.h, C.byref(s)), self.h)

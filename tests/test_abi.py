@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported_and_bound(A):
 STRUCTS = {"SceneDesc": "lidar_scene_desc", "MaterialDesc": "lidar_material_desc", "SensorDesc": "lidar_sensor_desc",
            "Outputs": "lidar_outputs", "Params": "lidar_params", "Instance": "lidar_instance",
            "TuneDesc": "lidar_tune_desc", "TuneResult": "lidar_tune_result", "Stats": "lidar_stats",
-           "SweepDesc": "lidar_sweep_desc", "SweepInfo": "lidar_sweep_info"}
+           "SweepDesc": "lidar_sweep_desc", "SweepInfo": "lidar_sweep_info", "Actor": "lidar_actor"}
 
 
 def test_struct_layouts_match_header(A, tmp_path):
@@ -86,6 +86,11 @@ def test_null_context_calls_are_rejected(A):
     assert lib.lidar_destroy(None) == A.OK
     assert lib.lidar_simulate(None, 0, 0, None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_simulate_sweep(None, None, None, None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_mesh_load(None, None, None, 0, None, 0, None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_mesh_refit(None, 0, None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_actors_set(None, None, 0, None, 0, None, 0, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_actors_update(None, None, 0, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_actors_clear(None) == A.ERR_INVALID_ARG
     assert lib.lidar_sensor_set(None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_materials_set(None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_backward(None, None, None, None, None, None, None, None, None, None) == A.ERR_INVALID_ARG
@@ -107,3 +112,15 @@ def test_create_without_gpu_reports_error(A):
 def test_binding_fails_loudly_without_library(A, tmp_path):
     with pytest.raises(ImportError):
         A.load(str(tmp_path / "liblidar.so"))
+
+
+def test_actor_workspace_sizes_host_only(A):
+    p, s = C.c_uint64(), C.c_uint64()
+    assert A.lib.lidar_actors_bytes(300, C.byref(p), C.byref(s)) == A.OK
+    assert p.value >= 300 * (128 + 48 + 112 + 24) and p.value % 256 == 0 and s.value > 300 * 38
+    assert A.lib.lidar_actors_bytes(0, C.byref(p), C.byref(s)) == A.ERR_INVALID_ARG
+    assert A.lib.lidar_actors_bytes((1 << 20) + 1, C.byref(p), C.byref(s)) == A.ERR_INVALID_ARG
+    d = A.SceneDesc()
+    d.n_vertices, d.n_triangles, d.flags = 100, 50, A.SCENE_DEVICE_PTRS
+    assert A.lib.lidar_mesh_bytes(C.byref(d), C.byref(p), C.byref(s)) == A.OK
+    assert p.value >= 50 * (128 + 48 + 4 + 12)
