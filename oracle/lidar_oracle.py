@@ -260,13 +260,15 @@ def box_muller(xa, xb):
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
 
 
-def beam_normals(seed: int, scan: int, inst: int, beams):
-    """(z_range, z_intensity) for beams, from Philox counter (beam, scan, inst, 0), key = seed."""
+def beam_normals(seed: int, scan: int, inst: int, beams, word3=0):
+    """(z_range, z_intensity) for beams, from Philox counter (beam, scan, inst, word3), key = seed
+    (word3 = 0 for the single return; the echo index for multi-echo returns)."""
     beams = np.asarray(beams, dtype=np.uint64)
     ctr = np.zeros((len(beams), 4), dtype=np.uint64)
     ctr[:, 0] = beams
     ctr[:, 1] = scan
     ctr[:, 2] = inst
+    ctr[:, 3] = word3
     x = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
     return box_muller(x[:, 0], x[:, 1]), box_muller(x[:, 2], x[:, 3])
 
@@ -380,6 +382,157 @@ def _trace_and_return(scene, sensor, beams, s, d, o, seed, scan, inst, rho, angl
     out["marginal"] = hit & ((np.abs(r_lambda - r_l) <= 1e-5 * r_lambda)
                              | (np.abs(d_n - sensor.d_max) <= 1e-5 * sensor.d_max)
                              | (np.abs(d_n - sensor.t_min) <= 1e-5))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# beam divergence and multi-echo returns [IV, named there as future work]
+# ----------------------------------------------------------------------------
+# The paper's conclusion names beam divergence and multi-echo LiDAR as the next
+# physical effects to model, without a model.  Reading used here:
+#  * a beam is a cone of full angle delta around its axis s, sampled by K
+#    sub-rays of equal power 1/K: sub-ray 0 is the axis, sub-ray k >= 1 is the
+#    axis turned by r_k = (delta / 2) sqrt(k / (K - 1)) towards the direction
+#    cos(b_k) e_theta + sin(b_k) e_phi, b_k = k * pi (3 - sqrt 5) (a Vogel
+#    spiral over the cone's disk), with e_theta, e_phi the unit azimuth and
+#    elevation tangents at s;
+#  * every sub-ray gets its first hit and its noise-free R_lambda (eq.4);
+#  * the hits, ordered by (t, k), form echoes: a gap larger than the range
+#    resolution starts a new echo;
+#  * an echo's strength is P = (1/K) sum R_lambda,k over its sub-rays (the
+#    returned power fraction), its range the R_lambda-weighted mean
+#    t = t_first + sum R_k (t_k - t_first) / sum R_k (plain mean if all R are
+#    0), its label and material those of its strongest sub-ray (smallest k on
+#    ties);
+#  * echo e gets range noise and intensity noise from Philox counter
+#    (beam, scan, instance, e) and the eq.5 test with P in place of R_lambda;
+#  * the first E echoes in range order are reported.
+# With K = 1 and delta = 0, echo 0 is exactly the single return of simulate().
+
+GOLDEN_ANGLE = math.pi * (3.0 - math.sqrt(5.0))
+
+
+def subray_pattern(n_sub: int, divergence_rad: float):
+    """(r_k, b_k) for k = 0..K-1: angle from the beam axis and direction around it."""
+    k = np.arange(n_sub, dtype=np.float64)
+    r = np.zeros(n_sub) if n_sub == 1 else (0.5 * float(divergence_rad)) * np.sqrt(k / (n_sub - 1))
+    return r, k * GOLDEN_ANGLE
+
+
+def subray_directions(sensor, beams, n_sub: int, divergence_rad: float) -> np.ndarray:
+    """Sensor-frame unit directions [n_beams, K, 3] of the sub-rays of the given beams."""
+    theta, phi = beam_angles(sensor)
+    beams = np.asarray(beams, dtype=np.int64)
+    th = theta[beams % sensor.n_az][:, None]
+    ph = phi[beams // sensor.n_az][:, None]
+    ct, st, cp, sp = np.cos(th), np.sin(th), np.cos(ph), np.sin(ph)
+    axis = np.stack([cp * ct, cp * st, sp * np.ones_like(ct)], axis=-1)          # [n, 1, 3]
+    e_th = np.stack([-st, ct, np.zeros_like(ct)], axis=-1)
+    e_ph = np.stack([-sp * ct, -sp * st, cp], axis=-1)
+    r, b = subray_pattern(n_sub, divergence_rad)
+    r, b = r[None, :, None], b[None, :, None]
+    return np.cos(r) * axis + np.sin(r) * (np.cos(b) * e_th + np.sin(b) * e_ph)
+
+
+def simulate_echoes(scene, sensor, pose, n_sub: int, max_echoes: int, divergence_rad: float, echo_sep_m: float,
+                    seed: int = 0, scan: int = 0, inst: int = 0, beams=None):
+    """Oracle for one scan with divergent beams and multi-echo returns.
+
+    Returns per-echo arrays [E, n] (valid, range, intensity, label, x, y, z,
+    tri, t_hit, material, r_lambda (= P)), ``n_echoes`` [n] (echoes formed),
+    the per-sub-ray hits, and ``ambiguous`` [n] (a sub-ray is ambiguous in
+    the sense of simulate(), or two of its hits straddle the echo separation
+    or the ordering within 1e-6 m) and ``marginal`` [E, n].
+    """
+    with np.errstate(invalid="ignore", over="ignore", divide="ignore"):
+        return _simulate_echoes(scene, sensor, pose, n_sub, max_echoes, divergence_rad, echo_sep_m, seed, scan,
+                                inst, beams)
+
+
+def _simulate_echoes(scene, sensor, pose, n_sub, max_echoes, divergence_rad, echo_sep_m, seed, scan, inst, beams):
+    n_all = sensor.n_beams
+    beams = np.arange(n_all, dtype=np.int64) if beams is None else np.asarray(beams, dtype=np.int64)
+    n, K, E = len(beams), int(n_sub), int(max_echoes)
+    sdir = subray_directions(sensor, beams, K, divergence_rad).reshape(-1, 3)
+    R = rotation_from_quat(pose.q)
+    o = np.asarray(pose.p, dtype=np.float64)
+    d = _rotate(R, sdir)
+    t_lim = trace_limit(scene, sensor)
+    fh = first_hit(scene, o, d, sensor.t_min, t_lim * (1 + 1e-5) + 1e-3)
+    tri = fh["tri"]
+    t1 = fh["t"]
+    hit = (tri >= 0) & (t1 <= t_lim)
+    safe = np.where(hit, tri, 0)
+    nrm = face_normals(scene, safe)
+    cos_t = np.abs(np.einsum("ij,ij->i", nrm, d))
+    m = scene.material[safe].astype(np.int64)
+    r0_tab, clamped = reflectance_at_wavelength(scene.spectra, sensor.wavelength_nm)
+    kexp = np.asarray(scene.angle_exp, dtype=np.float64)[m]
+    r_l = r0_tab[m] * np.where(kexp == 1.0, cos_t, cos_t ** kexp)
+    has = tri >= 0
+    eps_e = EDGE_ABS_M + EDGE_REL * np.where(has, t1, 0.0)
+    amb_sub = ((has & (fh["t_second"] - t1 < TIE_MARGIN_M)) | (has & (fh["edge_in"] < eps_e))
+               | np.where(has, fh["near_t"] <= t1 + TIE_MARGIN_M, np.isfinite(fh["near_t"]))
+               | (has & (np.abs(t1 - t_lim) <= 1e-6 * (1.0 + t_lim))))
+    shape = (n, K)
+    hit, t1, tri, r_l, m, amb_sub, cos_t = (a.reshape(shape) for a in (hit, t1, tri, r_l, m, amb_sub, cos_t))
+    label = scene.label[np.where(hit, tri, 0)].astype(np.int64)
+
+    out = {k: np.zeros((E, n)) for k in ("range", "intensity", "x", "y", "z", "t_hit", "r_lambda")}
+    out["valid"] = np.zeros((E, n), np.uint8)
+    out["label"] = np.full((E, n), MISS_LABEL, np.uint32)
+    out["tri"] = np.full((E, n), MISS_TRI, np.uint32)
+    out["material"] = np.full((E, n), 0xFFFF, np.uint16)
+    out["marginal"] = np.zeros((E, n), bool)
+    out["grazing"] = np.zeros((E, n), bool)
+    n_echo = np.zeros(n, np.int64)
+    ambiguous = amb_sub.any(axis=1)
+    sig_all = scene.sigma_range.astype(np.float64)
+    axis = sdir.reshape(n, K, 3)[:, 0, :]
+    zs = [beam_normals(seed, scan, inst, beams, word3=e) for e in range(E)]
+    for b in range(n):
+        ks = [k for k in range(K) if hit[b, k]]
+        ks.sort(key=lambda k: (t1[b, k], k))
+        groups = []
+        for idx, k in enumerate(ks):
+            if idx == 0 or t1[b, k] - t1[b, ks[idx - 1]] > echo_sep_m:
+                groups.append([k])
+            else:
+                groups.append(groups.pop() + [k])
+            if idx > 0:
+                gap = t1[b, k] - t1[b, ks[idx - 1]]
+                if abs(gap - echo_sep_m) <= 1e-6 * (1.0 + t1[b, k]) or gap <= TIE_MARGIN_M:
+                    ambiguous[b] = True
+        n_echo[b] = len(groups)
+        for e, g in enumerate(groups[:E]):
+            rs = np.array([r_l[b, k] for k in g])
+            ts = np.array([t1[b, k] for k in g])
+            P = rs.sum() / K
+            t0 = ts[0]
+            te = t0 + (np.sum(rs * (ts - t0)) / rs.sum() if rs.sum() > 0 else np.mean(ts - t0))
+            dom = g[int(np.argmax(rs))]                 # first maximum = smallest k among equal
+            mm = int(m[b, dom])
+            z_d, z_i = zs[e][0][b], zs[e][1][b]
+            sig = sig_all[mm] if sensor.noise_on else 0.0
+            sig_i = float(sensor.sigma_intensity) if sensor.noise_on else 0.0
+            dn = te + sig * z_d
+            rlim = (sensor.r_l_max / sensor.d_max) * dn
+            det = (dn > sensor.t_min) and (dn <= sensor.d_max) and (rlim <= P)
+            out["t_hit"][e, b] = te
+            out["r_lambda"][e, b] = P
+            out["tri"][e, b] = tri[b, dom]
+            out["material"][e, b] = mm
+            out["marginal"][e, b] = ((abs(P - rlim) <= 1e-5 * max(P, 1e-30)) or abs(dn - sensor.d_max) <= 1e-5 * sensor.d_max
+                                     or abs(dn - sensor.t_min) <= 1e-5)
+            out["grazing"][e, b] = bool(np.any(np.array([cos_t[b, k] for k in g]) < 0.01))
+            if det:
+                out["valid"][e, b] = 1
+                out["range"][e, b] = dn
+                out["intensity"][e, b] = max(0.0, P + sig_i * z_i)
+                out["label"][e, b] = label[b, dom]
+                out["x"][e, b], out["y"][e, b], out["z"][e, b] = dn * axis[b]
+    out.update(beams=beams, n_echoes=n_echo, ambiguous=ambiguous, wavelength_clamped=clamped,
+               sub_hit=hit, sub_t=t1, sub_tri=tri, sub_r_lambda=r_l, sub_dir_sensor=sdir.reshape(n, K, 3))
     return out
 
 
