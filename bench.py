@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sweep,dynamic,sequence or 'all'")
+    ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sweep,echo,dynamic,sequence or 'all'")
     ap.add_argument("--leaf-width", type=int, default=4)
     ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
     ap.add_argument("--ploc-radius", type=int, default=32)
@@ -131,7 +131,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": args.gpus}))
         sys.exit(2)
-    legs = ({"plain", "cpu", "batch", "adjoint", "sweep", "dynamic", "sequence"} if args.legs == "all"
+    legs = ({"plain", "cpu", "batch", "adjoint", "sweep", "echo", "dynamic", "sequence"} if args.legs == "all"
             else set(args.legs.split(",")))
 
     import numpy as np
@@ -394,6 +394,25 @@ def main():
                            "realtime_factor": (n_ticks / tick_hz) / wall_s}
         log(f"sweep: {n_ticks} ticks in {wall_s * 1e3:.2f} ms ({np.mean(ms_s) * 1e3:.1f} us per tick, "
             f"{rays / wall_s:.4g} rays/s, {(n_ticks / tick_hz) / wall_s:.0f}x real time)")
+
+    if "echo" in legs:
+        # divergent beams: 7 sub-rays in a 3 mrad cone per beam of the 64 x 2048 scan, up to 3 echoes
+        K, E = 7, 3
+        e_out = alloc_outputs(n * E, POINT_OUTPUTS, ctx.device)
+        ws = None
+        for _ in range(3):
+            r = ctx.simulate_echoes(seed, 0, K, E, 0.003, 0.5, out=e_out, workspace=ws)
+            ws = ctx._echo_workspace
+        wall_e, ms_e = timed_launches(lambda k: ctx.simulate_echoes(seed, k, K, E, 0.003, 0.5, out=e_out,
+                                                                    workspace=ws), 50, torch)
+        ctx.sync_check()
+        det = [int(r["valid"][e].sum()) for e in range(E)]
+        result["echo"] = {"workload": "64ch x 2048 scan of the 522k scene, 7 sub-rays per beam in a 3 mrad cone, "
+                                      "echo separation 0.5 m, up to 3 echoes per beam",
+                          "ms_per_scan": float(np.mean(ms_e)), "beams_per_s": n / (float(np.mean(ms_e)) * 1e-3),
+                          "subrays_per_s": K * n / (float(np.mean(ms_e)) * 1e-3), "detected_per_echo": det}
+        log(f"echo: {np.mean(ms_e) * 1e3:.1f} us per scan ({K * n / (np.mean(ms_e) * 1e-3):.4g} sub-rays/s), "
+            f"detected per echo {det}")
 
     if "dynamic" in legs:
         # 300 moving actors (200 cars, 100 walking pedestrians) in the 522k scene: per 10 Hz frame the

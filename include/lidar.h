@@ -235,6 +235,51 @@ lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
                                    uint32_t *node_visits, uint32_t *tri_tests, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Divergent beams and multi-echo returns (Section IV: named future work)    */
+/* ------------------------------------------------------------------------ */
+
+/* The paper's conclusion names beam divergence and multi-echo LiDAR as the
+ * next physical effects; the model here is this library's reading.  A beam is
+ * a cone of full angle divergence_rad sampled by n_sub equal-power sub-rays:
+ * sub-ray 0 is the beam axis s, sub-ray k >= 1 is s turned by
+ * r_k = (divergence_rad / 2) sqrt(k / (n_sub - 1)) towards
+ * cos(b_k) e_theta + sin(b_k) e_phi with b_k = k pi (3 - sqrt 5) and e_theta,
+ * e_phi the unit azimuth and elevation tangents at s (FP64, rounded once).
+ * Each sub-ray takes its first hit and its noise-free R_lambda (eq.4).  Hits
+ * ordered by (t, k) form echoes, a new echo starting where consecutive ranges
+ * differ by more than echo_sep_m.  Echo e: strength
+ * P = (1/n_sub) sum R_k, range t_first + sum R_k (t_k - t_first) / sum R_k
+ * (plain mean if every R is 0), label, material and triangle of its strongest
+ * sub-ray (smallest k on ties); range and intensity noise from Philox counter
+ * (beam, scan, 0, e); detected iff t_min < d <= d_max and
+ * (r_l_max / d_max) d <= P (eq.5 with P for R_lambda); intensity
+ * max(0, P + sigma_I z).  With n_sub = 1 and divergence_rad = 0, echo 0 is
+ * lidar_simulate's return bit for bit. */
+typedef struct {
+    uint32_t n_sub;            /* sub-rays per beam, 1..16 */
+    uint32_t max_echoes;       /* echoes reported per beam, 1..4 (first ones in range order) */
+    float divergence_rad;      /* full cone angle, >= 0 and < 0.5 */
+    float echo_sep_m;          /* range resolution (> 0) */
+} lidar_echo_desc;
+
+/* Device workspace for lidar_simulate_echoes with the current sensor: 24 bytes
+ * per sub-ray. */
+lidar_status lidar_echo_bytes(lidar_ctx *ctx, const lidar_echo_desc *echo, uint64_t *workspace_bytes);
+
+/* One scan with divergent beams.  Every output array (caller-owned device
+ * memory) holds max_echoes planes of n_ch * n_az elements, echo e of beam b at
+ * e * n_ch * n_az + b, laid out like lidar_simulate's; unformed or undetected
+ * echoes read as misses.  Diagnostics per echo: tri / material of the
+ * strongest sub-ray (LIDAR_NO_TRIANGLE / LIDAR_NO_MATERIAL if the echo was not
+ * formed), t_hit = noise-free echo range, r_lambda = strength P; normal is
+ * not produced (must be NULL).  Sees the actors of a dynamic scene.
+ * Asynchronous; the workspace (>= lidar_echo_bytes, 256-byte aligned) is used
+ * until the stream has passed the call. */
+lidar_status lidar_simulate_echoes(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_echo_desc *echo,
+                                   void *workspace, uint64_t workspace_bytes, const lidar_outputs *out,
+                                   void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Dynamic scenes: meshes placed by moving actors (Section II-B)             */
 /* ------------------------------------------------------------------------ */
 

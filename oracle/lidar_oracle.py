@@ -485,6 +485,7 @@ def _simulate_echoes(scene, sensor, pose, n_sub, max_echoes, divergence_rad, ech
     out["material"] = np.full((E, n), 0xFFFF, np.uint16)
     out["marginal"] = np.zeros((E, n), bool)
     out["grazing"] = np.zeros((E, n), bool)
+    out["amb_dom"] = np.zeros((E, n), bool)
     n_echo = np.zeros(n, np.int64)
     ambiguous = amb_sub.any(axis=1)
     sig_all = scene.sigma_range.astype(np.float64)
@@ -500,8 +501,10 @@ def _simulate_echoes(scene, sensor, pose, n_sub, max_echoes, divergence_rad, ech
             else:
                 groups.append(groups.pop() + [k])
             if idx > 0:
+                # a 32-bit range is good to about 1e-6 relative: gaps that close to the separation
+                # (or to zero, where the order decides the first range) may group differently
                 gap = t1[b, k] - t1[b, ks[idx - 1]]
-                if abs(gap - echo_sep_m) <= 1e-6 * (1.0 + t1[b, k]) or gap <= TIE_MARGIN_M:
+                if abs(gap - echo_sep_m) <= 1e-5 * (1.0 + t1[b, k]) or gap <= TIE_MARGIN_M:
                     ambiguous[b] = True
         n_echo[b] = len(groups)
         for e, g in enumerate(groups[:E]):
@@ -510,7 +513,11 @@ def _simulate_echoes(scene, sensor, pose, n_sub, max_echoes, divergence_rad, ech
             P = rs.sum() / K
             t0 = ts[0]
             te = t0 + (np.sum(rs * (ts - t0)) / rs.sum() if rs.sum() > 0 else np.mean(ts - t0))
-            dom = g[int(np.argmax(rs))]                 # first maximum = smallest k among equal
+            order = np.argsort(-rs, kind="stable")
+            dom = min(g[q] for q in range(len(g)) if rs[q] == rs.max())     # strongest, smallest k on ties
+            # strongest sub-ray decided within 32-bit rounding: another one within 1e-5 relative
+            if len(g) > 1 and rs[order[1]] >= rs[order[0]] * (1.0 - 1e-5):
+                out["amb_dom"][e, b] = True
             mm = int(m[b, dom])
             z_d, z_i = zs[e][0][b], zs[e][1][b]
             sig = sig_all[mm] if sensor.noise_on else 0.0

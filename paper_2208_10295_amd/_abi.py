@@ -98,6 +98,11 @@ class Actor(C.Structure):
     _fields_ = [("mesh", C.c_uint32), ("label", C.c_uint32), ("p", C.c_float * 3), ("q_wxyz", C.c_float * 4)]
 
 
+class EchoDesc(C.Structure):
+    _fields_ = [("n_sub", C.c_uint32), ("max_echoes", C.c_uint32), ("divergence_rad", C.c_float),
+                ("echo_sep_m", C.c_float)]
+
+
 class SweepDesc(C.Structure):
     _fields_ = [("head_deg", C.c_double), ("spin_hz", C.c_double), ("dt_s", C.c_double),
                 ("p_begin", C.c_float * 3), ("q_begin", C.c_float * 4), ("p_end", C.c_float * 3),
@@ -125,6 +130,9 @@ SIGNATURES = {
     "lidar_simulate_bruteforce": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P]),
     "lidar_simulate_counts": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P, P, P]),
     "lidar_simulate_sweep": (C.c_int32, [P, C.POINTER(SweepDesc), C.POINTER(Outputs), C.POINTER(SweepInfo), P]),
+    "lidar_echo_bytes": (C.c_int32, [P, C.POINTER(EchoDesc), C.POINTER(C.c_uint64)]),
+    "lidar_simulate_echoes": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(EchoDesc), P, C.c_uint64,
+                                          C.POINTER(Outputs), P]),
     "lidar_mesh_bytes": (C.c_int32, [C.POINTER(SceneDesc), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "lidar_mesh_load": (C.c_int32, [P, C.POINTER(SceneDesc), P, C.c_uint64, P, C.c_uint64, P,
                                     C.POINTER(C.c_uint32)]),

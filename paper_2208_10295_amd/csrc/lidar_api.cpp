@@ -668,6 +668,74 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, co
 }
 
 // ---------------------------------------------------------------------------
+// divergent beams and multi-echo returns
+// ---------------------------------------------------------------------------
+static lidar_status check_echo(lidar_ctx *ctx, const lidar_echo_desc *d) {
+    if (!d) return ctx->fail(LIDAR_ERR_INVALID_ARG, "echo descriptor is null");
+    if (d->n_sub < 1 || d->n_sub > (uint32_t)kMaxSub) return ctx->fail(LIDAR_ERR_INVALID_ARG, "n_sub must be in 1..16");
+    if (d->max_echoes < 1 || d->max_echoes > (uint32_t)kMaxEchoes)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "max_echoes must be in 1..4");
+    if (!std::isfinite(d->divergence_rad) || !(d->divergence_rad >= 0.0f) || !(d->divergence_rad < 0.5f))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "divergence_rad must be in [0, 0.5)");
+    if (!std::isfinite(d->echo_sep_m) || !(d->echo_sep_m > 0.0f))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "echo_sep_m must be > 0");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_echo_bytes(lidar_ctx *ctx, const lidar_echo_desc *echo, uint64_t *workspace_bytes) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!workspace_bytes) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace_bytes is null");
+    if (!ctx->has_sensor) return ctx->fail(LIDAR_ERR_NOT_READY, "no sensor set");
+    lidar_status st = check_echo(ctx, echo);
+    if (st != LIDAR_OK) return st;
+    *workspace_bytes = (uint64_t)ctx->sensor.d.n_ch * ctx->sensor.d.n_az * echo->n_sub * sizeof(SubHit);
+    return LIDAR_OK;
+}
+
+lidar_status lidar_simulate_echoes(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_echo_desc *echo,
+                                   void *workspace, uint64_t workspace_bytes, const lidar_outputs *out,
+                                   void *stream) {
+    lidar_status st = ready(ctx, true);
+    if (st != LIDAR_OK) return st;
+    if ((st = check_echo(ctx, echo)) != LIDAR_OK) return st;
+    if (!out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "outputs struct is null");
+    if (out->normal) return ctx->fail(LIDAR_ERR_INVALID_ARG, "echo outputs have no normal (pass NULL)");
+    uint64_t need = 0;
+    lidar_echo_bytes(ctx, echo, &need);
+    if (!workspace || ((uintptr_t)workspace & 255)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need) return ctx->fail(LIDAR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than lidar_echo_bytes()");
+    const lidar_sensor_desc &d = ctx->sensor.d;
+    const double *elev_cs = (const double *)ctx->sensor_tables.p;
+    const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
+    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, ctx->p, ctx->q, seed, scan, 0, 0, 0);
+    SubrayPattern pat{};
+    pat.n_sub = echo->n_sub;
+    const double golden = 3.14159265358979323846 * (3.0 - std::sqrt(5.0));
+    for (uint32_t k = 0; k < echo->n_sub; ++k) {
+        const double r = echo->n_sub == 1 ? 0.0
+                                          : (0.5 * (double)echo->divergence_rad) *
+                                                std::sqrt((double)k / (double)(echo->n_sub - 1));
+        const double b = (double)k * golden;
+        pat.c[k][0] = std::cos(r);
+        pat.c[k][1] = std::sin(r);
+        pat.c[k][2] = std::cos(b);
+        pat.c[k][3] = std::sin(b);
+    }
+    const uint64_t nb = (uint64_t)d.n_ch * d.n_az;
+    Outputs o = to_outputs(out, nb);
+    const uint64_t np = padded_rays(ctx->tile_az_log2, d.n_ch, d.n_az);
+    hipSetDevice(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    SubHit *sub = (SubHit *)workspace;
+    launch_trace_subrays(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, pat, sub, np, (uint32_t *)ctx->words.p,
+                         ctx->has_actors ? &ctx->A : nullptr, s);
+    launch_echoes(in, ctx->M, sub, echo->n_sub, echo->max_echoes, echo->echo_sep_m, o, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "echo launch");
+    return wavelength_clamped(ctx, d.wavelength_nm) ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // dynamic scenes: meshes placed by actors
 // ---------------------------------------------------------------------------
 static uint64_t al256(uint64_t x) { return (x + 255) / 256 * 256; }

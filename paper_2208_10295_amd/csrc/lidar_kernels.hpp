@@ -91,6 +91,27 @@ void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev
                         uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s);
 int batch_blocks_per_cu(const TraceOpts &t);
 
+// --- divergent beams and multi-echo returns (trace.hip) ---
+constexpr int kMaxSub = 16;      // sub-rays per beam
+constexpr int kMaxEchoes = 4;
+struct SubrayPattern {
+    double c[kMaxSub][4];        // cos r_k, sin r_k, cos b_k, sin b_k
+    uint32_t n_sub;
+};
+struct SubHit {                  // first hit of one sub-ray (t = +inf: none)
+    float t;
+    uint32_t orig;
+    float rl;                    // noise-free R_lambda (eq.4)
+    uint32_t label;
+    uint32_t mat;
+    uint32_t pad_;
+};
+void launch_trace_subrays(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                          const SubrayPattern &pat, SubHit *sub, uint64_t n_padded, uint32_t *err,
+                          const ActorsDev *actors, hipStream_t s);
+void launch_echoes(const InstanceDev &in, const MaterialsDev &M, const SubHit *sub, uint32_t n_sub,
+                   uint32_t max_echoes, float echo_sep, const Outputs &out, hipStream_t s);
+
 // --- dynamic scenes (dynamic.hip) ---
 // word: two device words of scratch (max |coordinate| bits, pad bits)
 bool refit_supported(const BuildResult &br);

@@ -402,6 +402,43 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
 // ---------------------------------------------------------------------------
 // Hit attributes + return model + output write (fused epilogue)
 // ---------------------------------------------------------------------------
+// Attributes of a hit: unit world normal, noise-free eq.4 reflectance
+// R_lambda = R_lambda(0) |n . d|^k, label, material and triangle index.  An
+// actor's record is in object space: its label is the actor's, its index the
+// combined one, and its normal is rotated to the world.
+struct Shade {
+    float nx, ny, nz, rl;
+    uint32_t orig, label, mat;
+};
+
+__device__ inline Shade shade_hit(const MaterialsDev &M, const Overrides &ov, float wavelength_nm, const Ray &ray,
+                                  const TriRec *__restrict__ r, const Hit &h, const ActorDev *act) {
+    Shade S;
+    float4 a = r->a, b = r->b, c = r->c;
+    S.orig = act ? h.orig : __float_as_uint(a.w);
+    S.label = act ? act->label : __float_as_uint(b.w);
+    S.mat = __float_as_uint(c.w);
+    float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
+    float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
+    float cx = fmaf(e1y, e2z, -e1z * e2y);
+    float cy = fmaf(e1z, e2x, -e1x * e2z);
+    float cz = fmaf(e1x, e2y, -e1y * e2x);
+    float len = __fsqrt_rn(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
+    S.nx = cx / len; S.ny = cy / len; S.nz = cz / len;
+    if (act) {
+        const double X = S.nx, Y = S.ny, Z = S.nz;
+        S.nx = (float)(act->R[0] * X + act->R[1] * Y + act->R[2] * Z);
+        S.ny = (float)(act->R[3] * X + act->R[4] * Y + act->R[5] * Z);
+        S.nz = (float)(act->R[6] * X + act->R[7] * Y + act->R[8] * Z);
+    }
+    float cd = fmaf(S.nx, ray.dx, fmaf(S.ny, ray.dy, S.nz * ray.dz));
+    float cs = fabsf(cd);
+    float r0 = reflectance0(ov, M, wavelength_nm, S.mat);
+    float kx = ov.angle_exp ? ov.angle_exp[S.mat] : M.angle_exp[S.mat];
+    S.rl = (kx == 1.0f) ? r0 * cs : r0 * exp2f(kx * log2f(cs));
+    return S;
+}
+
 __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
                                        const Outputs &out, uint64_t o, uint32_t beam, uint32_t scan,
                                        const Ray &ray, const TriRec *__restrict__ tris, const Hit &h,
@@ -412,32 +449,12 @@ __device__ inline void shade_and_write(const InstanceDev &in, const MaterialsDev
     uint16_t mat16 = 0xFFFFu;
     bool det = false;
     if (hit) {
-        const TriRec *r = tris + h.slot;
-        float4 a = r->a, b = r->b, c = r->c;
-        // an actor's record is in object space: its label is the actor's, its
-        // index the combined one, and its normal is rotated to the world
-        orig = act ? h.orig : __float_as_uint(a.w);
-        uint32_t label = act ? act->label : __float_as_uint(b.w);
-        uint32_t m = __float_as_uint(c.w);
+        const Shade sh = shade_hit(M, ov, in.wavelength_nm, ray, tris + h.slot, h, act);
+        nx = sh.nx; ny = sh.ny; nz = sh.nz;
+        rl = sh.rl;
+        orig = sh.orig;
+        const uint32_t label = sh.label, m = sh.mat;
         mat16 = (uint16_t)m;
-        float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
-        float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
-        float cx = fmaf(e1y, e2z, -e1z * e2y);
-        float cy = fmaf(e1z, e2x, -e1x * e2z);
-        float cz = fmaf(e1x, e2y, -e1y * e2x);
-        float len = __fsqrt_rn(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
-        nx = cx / len; ny = cy / len; nz = cz / len;
-        if (act) {
-            const double X = nx, Y = ny, Z = nz;
-            nx = (float)(act->R[0] * X + act->R[1] * Y + act->R[2] * Z);
-            ny = (float)(act->R[3] * X + act->R[4] * Y + act->R[5] * Z);
-            nz = (float)(act->R[6] * X + act->R[7] * Y + act->R[8] * Z);
-        }
-        float cd = fmaf(nx, ray.dx, fmaf(ny, ray.dy, nz * ray.dz));
-        float cs = fabsf(cd);
-        float r0 = reflectance0(ov, M, in.wavelength_nm, m);
-        float kx = ov.angle_exp ? ov.angle_exp[m] : M.angle_exp[m];
-        rl = (kx == 1.0f) ? r0 * cs : r0 * exp2f(kx * log2f(cs));
         float zd = 0.0f, zi = 0.0f, sig = 0.0f, sig_i = 0.0f;
         if (in.noise_on) {
             uint4 x = philox4x32_10(make_uint4(beam, scan, in.inst_id, 0u), in.seed_lo, in.seed_hi);
@@ -581,6 +598,200 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_multi_kernel(SceneDev S, Ins
         n_tris[beam] = c.tris;
     }
     shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, tris, h, act);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1e: divergent beams.  Sub-ray k of beam (j, i) is the beam axis s
+// turned by r_k towards cos(b_k) e_theta + sin(b_k) e_phi (unit azimuth and
+// elevation tangents at s), in FP64 and rounded once after the rotation to the
+// world: s_k = cos(r_k) s + sin(r_k) (cos(b_k) e_theta + sin(b_k) e_phi).
+// Sub-ray 0 (r = 0) is exactly the beam of the single return.  The launch
+// covers the beams once per sub-ray (slice k = padded ray / n_padded), and
+// each sub-ray's first hit and noise-free R_lambda go to sub[beam][k].
+// ---------------------------------------------------------------------------
+__device__ inline Ray make_subray(const InstanceDev &in, const Pose64 &P, uint32_t j, uint32_t i, const double *pc) {
+    const double cp = in.elev_cs[2 * j], sp = in.elev_cs[2 * j + 1];
+    const double ct = in.az_cs[2 * i], st = in.az_cs[2 * i + 1];
+    const double a0 = cp * ct, a1 = cp * st, a2 = sp;           // axis
+    const double t0 = -st, t1 = ct, t2 = 0.0;                   // e_theta
+    const double p0 = -sp * ct, p1 = -sp * st, p2 = cp;         // e_phi
+    const double cr = pc[0], sr = pc[1], cb = pc[2], sb = pc[3];
+    const double s0 = cr * a0 + sr * (cb * t0 + sb * p0);
+    const double s1 = cr * a1 + sr * (cb * t1 + sb * p1);
+    const double s2 = cr * a2 + sr * (cb * t2 + sb * p2);
+    Ray r;
+    r.sx = (float)a0; r.sy = (float)a1; r.sz = (float)a2;
+    r.dx = (float)(P.R[0] * s0 + P.R[1] * s1 + P.R[2] * s2);
+    r.dy = (float)(P.R[3] * s0 + P.R[4] * s1 + P.R[5] * s2);
+    r.dz = (float)(P.R[6] * s0 + P.R[7] * s1 + P.R[8] * s2);
+    r.ox = (float)P.p[0]; r.oy = (float)P.p[1]; r.oz = (float)P.p[2];
+    return r;
+}
+
+template <int STACK, int BLOCK, int LANES, bool ACTORS>
+__global__ __launch_bounds__(BLOCK) void trace_subrays_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
+                                                              SubrayPattern pat, SubHit *__restrict__ sub,
+                                                              int tile_az_log2, uint64_t n_padded, int xcd_remap,
+                                                              uint32_t *err, ActorsDev A) {
+    constexpr int NR = BLOCK / LANES;
+    __shared__ uint32_t stk[STACK * NR];
+    const uint32_t q = threadIdx.x / LANES, s = threadIdx.x % LANES;
+    const uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
+    if (r >= n_padded * pat.n_sub) return;     // all lanes of the sub-ray
+    const uint32_t k = (uint32_t)(r / n_padded);
+    uint32_t j, i;
+    if (!ray_coords(r - (uint64_t)k * n_padded, in, tile_az_log2, j, i)) return;
+    const Overrides ov{nullptr, nullptr, nullptr, nullptr};
+    const Ray ray = make_subray(in, make_pose(in, nullptr), j, i, pat.c[k]);
+    bool overflow = false;
+    Counts c{0u, 0u};
+    Hit h;
+    if constexpr (LANES == 1)
+        h = traverse<STACK, NR, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q,
+                                       overflow, c);
+    else
+        h = traverse_multi<LANES, STACK, NR, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
+                                                    in.t_trace, stk + q, s, overflow, c);
+    const ActorDev *act = nullptr;
+    const TriRec *tris = S.tris;
+    if constexpr (ACTORS) {
+        traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
+        if (h.actor != kNone) {
+            act = A.actors + h.actor;
+            tris = A.meshes[act->mesh].tris;
+        }
+    }
+    if (overflow) atomicOr(err, 1u);
+    if (s != 0) return;
+    SubHit o{__builtin_inff(), kNone, 0.0f, kNone, 0xFFFFu, 0u};
+    if (h.slot != kNone) {
+        const Shade sh = shade_hit(M, ov, in.wavelength_nm, ray, tris + h.slot, h, act);
+        o = SubHit{h.t, sh.orig, sh.rl, sh.label, sh.mat, 0u};
+    }
+    sub[(size_t)(j * in.n_az + i) * pat.n_sub + k] = o;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1f: echoes of one beam from its sub-ray hits.  The hits, ordered by
+// (t, k) with an odd-even transposition network over KMAX registers, form
+// echoes split where consecutive ranges differ by more than echo_sep.  Echo e:
+// strength P = (1/K) sum R_k, range t_first + sum R_k (t_k - t_first) / sum R_k
+// (plain mean if every R is 0), label/material/index of its strongest sub-ray
+// (smallest k on ties), Philox counter (beam, scan, instance, e) for the range
+// and intensity noise, then the eq.5 test with P in place of R_lambda.
+// Outputs: plane e of every array holds echo e; unformed echoes read as
+// misses.  With K = 1 the first echo is the single return, bit for bit.
+// ---------------------------------------------------------------------------
+template <int KMAX>
+__global__ __launch_bounds__(128) void echo_kernel(InstanceDev in, MaterialsDev M, const SubHit *__restrict__ sub,
+                                                   uint32_t K, uint32_t E, float sep, Outputs out) {
+    const uint32_t nb = in.n_ch * in.n_az;
+    const uint32_t beam = blockIdx.x * 128 + threadIdx.x;
+    if (beam >= nb) return;
+    float t[KMAX], rl[KMAX];
+    uint32_t kk[KMAX], orig[KMAX], lab[KMAX], mat[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        kk[q] = (uint32_t)q;
+        if ((uint32_t)q < K) {
+            const SubHit h = sub[(size_t)beam * K + q];
+            t[q] = h.t; rl[q] = h.rl; orig[q] = h.orig; lab[q] = h.label; mat[q] = h.mat;
+        } else {
+            t[q] = __builtin_inff(); rl[q] = 0.0f; orig[q] = kNone; lab[q] = kNone; mat[q] = 0xFFFFu;
+        }
+    }
+#pragma unroll
+    for (int round = 0; round < KMAX; ++round) {
+#pragma unroll
+        for (int q = round & 1; q + 1 < KMAX; q += 2) {
+            const bool sw = t[q + 1] < t[q] || (t[q + 1] == t[q] && kk[q + 1] < kk[q]);
+#define LIDAR_CSWAP(A)                                  \
+            {                                           \
+                auto lo_ = sw ? A[q + 1] : A[q];        \
+                auto hi_ = sw ? A[q] : A[q + 1];        \
+                A[q] = lo_;                             \
+                A[q + 1] = hi_;                         \
+            }
+            LIDAR_CSWAP(t) LIDAR_CSWAP(rl) LIDAR_CSWAP(kk) LIDAR_CSWAP(orig) LIDAR_CSWAP(lab) LIDAR_CSWAP(mat)
+#undef LIDAR_CSWAP
+        }
+    }
+    const uint32_t j = beam / in.n_az, i = beam - j * in.n_az;
+    const double cp = in.elev_cs[2 * j], sp = in.elev_cs[2 * j + 1];
+    const double ct = in.az_cs[2 * i], st = in.az_cs[2 * i + 1];
+    const float sx = (float)(cp * ct), sy = (float)(cp * st), sz = (float)sp;
+    const uint64_t plane = nb;
+    // running group: first range, sums, strongest sub-ray
+    uint32_t e = 0;
+    int n_in = 0;
+    float t0 = 0.0f, t_prev = 0.0f, sum_r = 0.0f, sum_rt = 0.0f, sum_dt = 0.0f, best_r = -1.0f;
+    uint32_t best_k = kNone, best_orig = kNone, best_lab = kNone, best_mat = 0xFFFFu;
+    auto emit = [&]() {
+        if (e >= E) return;
+        const float P = sum_r / (float)K;
+        const float te = (sum_r > 0.0f) ? t0 + sum_rt / sum_r : t0 + sum_dt / (float)n_in;
+        float zd = 0.0f, zi = 0.0f, sig = 0.0f, sig_i = 0.0f;
+        if (in.noise_on) {
+            const uint4 x = philox4x32_10(make_uint4(beam, in.scan, in.inst_id, e), in.seed_lo, in.seed_hi);
+            zd = box_muller(x.x, x.y);
+            zi = box_muller(x.z, x.w);
+            sig = M.sigma[best_mat];
+            sig_i = in.sigma_i;
+        }
+        const float dn = fmaf(sig, zd, te);
+        const float rlim = (in.r_l_max / in.d_max) * dn;
+        const bool det = (dn > in.t_min) && (dn <= in.d_max) && (rlim <= P);
+        const float inten = fmaxf(0.0f, fmaf(sig_i, zi, P));
+        const uint64_t o = in.out_base + (uint64_t)e * plane + beam;
+        if (out.valid) out.valid[o] = det ? 1 : 0;
+        if (out.label) out.label[o] = det ? best_lab : kNone;
+        if (out.x) out.x[o] = det ? dn * sx : 0.0f;
+        if (out.y) out.y[o] = det ? dn * sy : 0.0f;
+        if (out.z) out.z[o] = det ? dn * sz : 0.0f;
+        if (out.intensity) out.intensity[o] = det ? inten : 0.0f;
+        if (out.range) out.range[o] = det ? dn : 0.0f;
+        if (out.tri) out.tri[o] = best_orig;
+        if (out.t_hit) out.t_hit[o] = te;
+        if (out.material) out.material[o] = (uint16_t)best_mat;
+        if (out.r_lambda) out.r_lambda[o] = P;
+        ++e;
+    };
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+        if (t[q] != __builtin_inff()) {
+            if (n_in > 0 && t[q] - t_prev > sep) {
+                emit();
+                n_in = 0;
+            }
+            if (n_in == 0) {
+                t0 = t[q];
+                sum_r = 0.0f; sum_rt = 0.0f; sum_dt = 0.0f; best_r = -1.0f; best_k = kNone;
+            }
+            sum_r += rl[q];
+            sum_rt = fmaf(rl[q], t[q] - t0, sum_rt);
+            sum_dt += t[q] - t0;
+            if (rl[q] > best_r || (rl[q] == best_r && kk[q] < best_k)) {
+                best_r = rl[q]; best_k = kk[q]; best_orig = orig[q]; best_lab = lab[q]; best_mat = mat[q];
+            }
+            t_prev = t[q];
+            ++n_in;
+        }
+    }
+    if (n_in > 0) emit();
+    for (; e < E; ++e) {
+        const uint64_t o = in.out_base + (uint64_t)e * plane + beam;
+        if (out.valid) out.valid[o] = 0;
+        if (out.label) out.label[o] = kNone;
+        if (out.x) out.x[o] = 0.0f;
+        if (out.y) out.y[o] = 0.0f;
+        if (out.z) out.z[o] = 0.0f;
+        if (out.intensity) out.intensity[o] = 0.0f;
+        if (out.range) out.range[o] = 0.0f;
+        if (out.tri) out.tri[o] = kNone;
+        if (out.t_hit) out.t_hit[o] = 0.0f;
+        if (out.material) out.material[o] = 0xFFFFu;
+        if (out.r_lambda) out.r_lambda[o] = 0.0f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -733,6 +944,50 @@ void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev 
     if (t.stack <= 32) launch_scan_s<32>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
     else if (t.stack <= 64) launch_scan_s<64>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
     else launch_scan_s<96>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
+}
+
+template <int STACK, bool ACTORS>
+static void launch_subrays_t(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                             const SubrayPattern &pat, SubHit *sub, uint64_t n_padded, uint32_t *err,
+                             const ActorsDev &A, hipStream_t s) {
+    const uint64_t rays = n_padded * pat.n_sub;
+    if (t.lanes_per_ray == 4) {
+        uint32_t blocks = (uint32_t)((rays * 4 + kQuadBlock - 1) / kQuadBlock);
+        trace_subrays_kernel<STACK, kQuadBlock, 4, ACTORS><<<blocks, kQuadBlock, 0, s>>>(
+            S, in, M, pat, sub, t.tile_az_log2, n_padded, t.xcd_remap, err, A);
+    } else if (t.lanes_per_ray == 2) {
+        uint32_t blocks = (uint32_t)((rays * 2 + kPairBlock - 1) / kPairBlock);
+        trace_subrays_kernel<STACK, kPairBlock, 2, ACTORS><<<blocks, kPairBlock, 0, s>>>(
+            S, in, M, pat, sub, t.tile_az_log2, n_padded, t.xcd_remap, err, A);
+    } else {
+        uint32_t blocks = (uint32_t)((rays + kBlock - 1) / kBlock);
+        trace_subrays_kernel<STACK, kBlock, 1, ACTORS><<<blocks, kBlock, 0, s>>>(
+            S, in, M, pat, sub, t.tile_az_log2, n_padded, t.xcd_remap, err, A);
+    }
+}
+
+void launch_trace_subrays(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
+                          const SubrayPattern &pat, SubHit *sub, uint64_t n_padded, uint32_t *err,
+                          const ActorsDev *actors, hipStream_t s) {
+    const ActorsDev none{};
+    if (actors) {
+        if (t.stack <= 32) launch_subrays_t<32, true>(t, S, in, M, pat, sub, n_padded, err, *actors, s);
+        else if (t.stack <= 64) launch_subrays_t<64, true>(t, S, in, M, pat, sub, n_padded, err, *actors, s);
+        else launch_subrays_t<96, true>(t, S, in, M, pat, sub, n_padded, err, *actors, s);
+    } else {
+        if (t.stack <= 32) launch_subrays_t<32, false>(t, S, in, M, pat, sub, n_padded, err, none, s);
+        else if (t.stack <= 64) launch_subrays_t<64, false>(t, S, in, M, pat, sub, n_padded, err, none, s);
+        else launch_subrays_t<96, false>(t, S, in, M, pat, sub, n_padded, err, none, s);
+    }
+}
+
+void launch_echoes(const InstanceDev &in, const MaterialsDev &M, const SubHit *sub, uint32_t n_sub,
+                   uint32_t max_echoes, float echo_sep, const Outputs &out, hipStream_t s) {
+    const uint32_t nb = in.n_ch * in.n_az;
+    const uint32_t blocks = (nb + 127) / 128;
+    if (n_sub <= 4) echo_kernel<4><<<blocks, 128, 0, s>>>(in, M, sub, n_sub, max_echoes, echo_sep, out);
+    else if (n_sub <= 8) echo_kernel<8><<<blocks, 128, 0, s>>>(in, M, sub, n_sub, max_echoes, echo_sep, out);
+    else echo_kernel<kMaxSub><<<blocks, 128, 0, s>>>(in, M, sub, n_sub, max_echoes, echo_sep, out);
 }
 
 void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,

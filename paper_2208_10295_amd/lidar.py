@@ -302,6 +302,26 @@ class Context:
         runs = [(int(info.scan[r]), int(info.first[r]), int(info.count[r])) for r in range(info.n_runs)]
         return out, runs
 
+    def simulate_echoes(self, seed: int, scan: int, n_sub: int, max_echoes: int, divergence_rad: float,
+                        echo_sep_m: float, debug: bool = False, out: dict | None = None, workspace=None,
+                        stream=None):
+        """One scan with divergent beams (n_sub sub-rays in a cone of full angle divergence_rad) and
+        up to max_echoes echoes per beam.  Returns a dict of [max_echoes, n_beams] tensors."""
+        d = A.EchoDesc(int(n_sub), int(max_echoes), float(divergence_rad), float(echo_sep_m))
+        nbytes = C.c_uint64()
+        check(lib.lidar_echo_bytes(self.h, C.byref(d), C.byref(nbytes)), self.h)
+        if workspace is None or workspace.numel() < nbytes.value:
+            workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        names = POINT_OUTPUTS + (tuple(k for k in DEBUG_OUTPUTS if k != "normal") if debug else ())
+        if out is None:
+            out = alloc_outputs(self.n_beams * int(max_echoes), names, self.device)
+        o = outputs_struct(out)
+        st = lib.lidar_simulate_echoes(self.h, int(seed), int(scan), C.byref(d), _ptr(workspace), workspace.numel(),
+                                       C.byref(o), _stream(stream))
+        check(st, self.h)
+        self._echo_workspace = workspace
+        return {k: v.view(int(max_echoes), self.n_beams) for k, v in out.items()}
+
     def simulate_counts(self, seed: int = 0, scan: int = 0, stream=None):
         """One scan plus per-beam (node visits, triangle tests) of the traversal."""
         out = alloc_outputs(self.n_beams, POINT_OUTPUTS, self.device)

@@ -84,3 +84,51 @@ def compare(g: dict, o: dict, check_debug: bool = True) -> dict:
     rep["hits"] = int((o["tri"] != NO).sum())
     rep["valid"] = int((o["valid"] == 1).sum())
     return rep
+
+
+def compare_echoes(g: dict, o: dict) -> dict:
+    """g: GPU echo outputs as numpy [E, n] (restricted to o['beams']); o: oracle simulate_echoes dict.
+
+    Beams the oracle marks ambiguous (a sub-ray ambiguous as in compare(), or a
+    gap within 1e-5 relative of the separation) are excluded; per echo, the
+    detection flag skips marginal echoes, triangle / material (and the label,
+    when it differs between them) skip echoes whose two strongest sub-rays are
+    within 1e-5, and the range / intensity tolerances skip echoes with a
+    grazing sub-ray.  Tolerances as in compare().
+    """
+    E, n = o["valid"].shape
+    ok = ~o["ambiguous"]
+    rep = {"n": n, "ambiguous": int((~ok).sum()), "echoes_formed": [int((o["tri"][e] != NO).sum()) for e in range(E)],
+           "detected": [int(o["valid"][e].sum()) for e in range(E)], "range_max_rel": 0.0, "intensity_max_rel": 0.0}
+    for e in range(E):
+        formed = ok & (o["tri"][e] != NO)
+        assert np.all(g["tri"][e][ok & ~formed] == NO) and np.all(g["valid"][e][ok & ~formed] == 0), e
+        dom = o["amb_dom"][e]
+        sel = formed & ~dom
+        bad = sel & ((g["tri"][e] != o["tri"][e]) | (g["material"][e] != o["material"][e]))
+        assert not bad.any(), f"echo {e}: strongest sub-ray differs on {bad.sum()} beams"
+        vcmp = ok & ~o["marginal"][e]
+        bad = vcmp & (g["valid"][e] != o["valid"][e])
+        assert not bad.any(), f"echo {e}: valid differs on {bad.sum()} beams, e.g. {o['beams'][bad][:8]}"
+        both = vcmp & (o["valid"][e] == 1)
+        bad = both & ~dom & (g["label"][e] != o["label"][e])
+        assert not bad.any(), f"echo {e}: label differs on {bad.sum()} beams"
+        fine = both & ~o["grazing"][e]
+        rng = o["range"][e][fine]
+        e_r = np.abs(g["range"][e][fine] - rng) / rng
+        assert np.all(e_r <= 1e-5), f"echo {e}: range rel error {e_r.max():.3g}"
+        for k in ("x", "y", "z"):
+            assert np.all(np.abs(g[k][e][fine] - o[k][e][fine]) / rng <= 1e-5), (e, k)
+        scale = np.maximum(np.abs(o["intensity"][e][fine]), o["r_lambda"][e][fine])
+        e_i = np.abs(g["intensity"][e][fine] - o["intensity"][e][fine]) / scale
+        assert np.all(e_i <= 1e-4), f"echo {e}: intensity rel error {e_i.max():.3g}"
+        fz = formed & ~o["grazing"][e]
+        e_t = np.abs(g["t_hit"][e][fz] - o["t_hit"][e][fz]) / o["t_hit"][e][fz]
+        assert np.all(e_t <= 1e-5), f"echo {e}: echo range rel error {e_t.max():.3g}"
+        e_p = np.abs(g["r_lambda"][e][fz] - o["r_lambda"][e][fz]) / np.maximum(o["r_lambda"][e][fz], 1e-30)
+        assert np.all(e_p <= 1e-4), f"echo {e}: strength rel error {e_p.max():.3g}"
+        if e_r.size:
+            rep["range_max_rel"] = max(rep["range_max_rel"], float(e_r.max()))
+        if e_i.size:
+            rep["intensity_max_rel"] = max(rep["intensity_max_rel"], float(e_i.max()))
+    return rep

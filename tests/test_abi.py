@@ -36,7 +36,8 @@ def test_every_declared_symbol_is_exported_and_bound(A):
 STRUCTS = {"SceneDesc": "lidar_scene_desc", "MaterialDesc": "lidar_material_desc", "SensorDesc": "lidar_sensor_desc",
            "Outputs": "lidar_outputs", "Params": "lidar_params", "Instance": "lidar_instance",
            "TuneDesc": "lidar_tune_desc", "TuneResult": "lidar_tune_result", "Stats": "lidar_stats",
-           "SweepDesc": "lidar_sweep_desc", "SweepInfo": "lidar_sweep_info", "Actor": "lidar_actor"}
+           "SweepDesc": "lidar_sweep_desc", "SweepInfo": "lidar_sweep_info", "Actor": "lidar_actor",
+           "EchoDesc": "lidar_echo_desc"}
 
 
 def test_struct_layouts_match_header(A, tmp_path):
@@ -91,6 +92,8 @@ def test_null_context_calls_are_rejected(A):
     assert lib.lidar_actors_set(None, None, 0, None, 0, None, 0, None) == A.ERR_INVALID_ARG
     assert lib.lidar_actors_update(None, None, 0, None) == A.ERR_INVALID_ARG
     assert lib.lidar_actors_clear(None) == A.ERR_INVALID_ARG
+    assert lib.lidar_simulate_echoes(None, 0, 0, None, None, 0, None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_echo_bytes(None, None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_sensor_set(None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_materials_set(None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_backward(None, None, None, None, None, None, None, None, None, None) == A.ERR_INVALID_ARG
