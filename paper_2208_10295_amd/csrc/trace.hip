@@ -526,6 +526,37 @@ __device__ inline Ray beam_ray(const InstanceDev &in, const Overrides &ov, uint3
     return make_ray(in, make_pose(in, ov.pose_delta), j, i);
 }
 
+// The pose of a scan is the same for every beam: thread 0 of the block builds
+// it (make_pose, FP64) into LDS once, instead of every lane.  Must be reached
+// by all threads of the block (it holds a barrier).
+__device__ inline void block_pose(const InstanceDev &in, const Overrides &ov, double *lds) {
+    if (threadIdx.x == 0) {
+        const Pose64 P = make_pose(in, ov.pose_delta);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) lds[e] = P.R[e];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) lds[9 + e] = P.p[e];
+    }
+    __syncthreads();
+}
+
+template <bool SWEEP>
+__device__ inline Ray beam_ray_lds(const InstanceDev &in, const double *lds, uint32_t j, uint32_t k, uint32_t &i,
+                                   uint32_t &scan) {
+    if (SWEEP) {
+        i = column_azimuth(in, k, scan);
+        return make_ray(in, column_pose(in, nullptr, k), j, i);
+    }
+    i = k;
+    scan = in.scan;
+    Pose64 P;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) P.R[e] = lds[e];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) P.p[e] = lds[9 + e];
+    return make_ray(in, P, j, i);
+}
+
 template <int STACK, int BLOCK, bool COUNT, bool SWEEP, bool ACTORS>
 __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
                                                            Overrides ov, Outputs out, int tile_az_log2,
@@ -533,11 +564,13 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
                                                            uint32_t *__restrict__ n_nodes,
                                                            uint32_t *__restrict__ n_tris, ActorsDev A) {
     __shared__ uint32_t stk[STACK * BLOCK];
+    __shared__ double pose[12];
+    if (!SWEEP) block_pose(in, ov, pose);
     uint64_t r = (uint64_t)logical_block(xcd_remap) * BLOCK + threadIdx.x;
     if (r >= n_padded) return;
     uint32_t j, k, i, scan;
     if (!ray_coords(r, in, tile_az_log2, j, k)) return;
-    Ray ray = beam_ray<SWEEP>(in, ov, j, k, i, scan);
+    Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
     bool overflow = false;
     Counts c{0u, 0u};
     Hit h = traverse<STACK, BLOCK, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + threadIdx.x,
@@ -571,12 +604,14 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_multi_kernel(SceneDev S, Ins
                                                                  uint32_t *__restrict__ n_tris, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
     __shared__ uint32_t stk[STACK * NR];
+    __shared__ double pose[12];
+    if (!SWEEP) block_pose(in, ov, pose);
     const uint32_t q = threadIdx.x / LANES, s = threadIdx.x % LANES;
     uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
     if (r >= n_padded) return;   // all lanes of the beam
     uint32_t j, k, i, scan;
     if (!ray_coords(r, in, tile_az_log2, j, k)) return;   // all lanes of the beam
-    Ray ray = beam_ray<SWEEP>(in, ov, j, k, i, scan);
+    Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
     bool overflow = false;
     Counts c{0u, 0u};
     Hit h = traverse_multi<LANES, STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace,
@@ -635,14 +670,21 @@ __global__ __launch_bounds__(BLOCK) void trace_subrays_kernel(SceneDev S, Instan
                                                               uint32_t *err, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
     __shared__ uint32_t stk[STACK * NR];
+    __shared__ double pose[12];
+    const Overrides ov{nullptr, nullptr, nullptr, nullptr};
+    block_pose(in, ov, pose);
     const uint32_t q = threadIdx.x / LANES, s = threadIdx.x % LANES;
     const uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
     if (r >= n_padded * pat.n_sub) return;     // all lanes of the sub-ray
     const uint32_t k = (uint32_t)(r / n_padded);
     uint32_t j, i;
     if (!ray_coords(r - (uint64_t)k * n_padded, in, tile_az_log2, j, i)) return;
-    const Overrides ov{nullptr, nullptr, nullptr, nullptr};
-    const Ray ray = make_subray(in, make_pose(in, nullptr), j, i, pat.c[k]);
+    Pose64 P;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) P.R[e] = pose[e];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) P.p[e] = pose[9 + e];
+    const Ray ray = make_subray(in, P, j, i, pat.c[k]);
     bool overflow = false;
     Counts c{0u, 0u};
     Hit h;
