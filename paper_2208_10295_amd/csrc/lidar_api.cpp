@@ -88,7 +88,7 @@ struct lidar_ctx {
     float q[4] = {1, 0, 0, 0};
     // device words: [0] error flags, [1] queue counter, [2..3] refit scratch
     DevBuf words;
-    int tile_az_log2 = 4;
+    int tile_az_log2 = 1;     // 2 azimuth steps x 32 channels per 64-beam tile
     int lanes_per_ray = 4;
     int xcd_remap = 1;
     // dynamic scene: meshes and the actors placing them
