@@ -304,9 +304,21 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
             }
             sort4(k0, c0, k1, c1, k2, c2, k3, c3);
             if (k0 != inf) {
-                if (k3 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
-                if (k2 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
-                if (k1 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
+                if (LANES == 4) {
+                    // the h further children hit go on the stack farthest first: lane s = 1..3 of the
+                    // quad writes c_s to entry sp + h - s, one store per lane
+                    const int nh = (k1 != inf) + (k2 != inf) + (k3 != inf);
+                    if (sp + nh <= cap) {
+                        if (s >= 1 && (int)s <= nh) stk[(sp + nh - (int)s) * NSLOT] = (s == 1) ? c1 : (s == 2) ? c2 : c3;
+                        sp += nh;
+                    } else {
+                        overflow = true;
+                    }
+                } else {
+                    if (k3 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
+                    if (k2 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
+                    if (k1 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
+                }
                 ref = c0;
                 continue;
             }
