@@ -122,8 +122,7 @@ def main():
     ap.add_argument("--leaf-width", type=int, default=4)
     ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
     ap.add_argument("--ploc-radius", type=int, default=32)
-    ap.add_argument("--tile-az", type=int, default=2)
-    ap.add_argument("--batch-tile-az", type=int, default=16)
+    ap.add_argument("--tile-az", type=int, default=0, help="64-beam tile width in azimuth steps; 0 = automatic")
     ap.add_argument("--lanes", type=int, default=4, help="lanes per ray (1, 2 or 4)")
     ap.add_argument("--xcd", type=int, default=1, help="XCD-aware block remap (0 or 1)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
@@ -161,8 +160,8 @@ def main():
                                     "905 nm, d_max 100 m, range noise 0.02 m",
                         "beams": n, "triangles": scene.n_tri, "leaf_width": st["leaf_width"], "bvh_builder": args.builder,
                         "ploc_radius": args.ploc_radius,
-                        "tile_az": args.tile_az, "batch_tile_az": args.batch_tile_az, "lanes_per_ray": args.lanes,
-                        "xcd_remap": args.xcd,
+                        "tile_az": args.tile_az or "auto (2; 16 for the batch, 8 with actors)",
+                        "lanes_per_ray": args.lanes, "xcd_remap": args.xcd,
                         "bvh_nodes": st["n_nodes"], "bvh_depth": st["depth"]}
     result["bvh_build_ms"] = st["build_ms"]
 
@@ -206,9 +205,7 @@ def main():
     if "batch" in legs:
         sc4, insts = S.config4()
         assert sc4 is scene
-        ctx.set_tile_shape(args.batch_tile_az)     # the batch keeps the tile shape current at its creation
         batch = ctx.batch(insts, 256)
-        ctx.set_tile_shape(args.tile_az)
         nr = batch.n_rays
         bout = alloc_outputs(nr, POINT_OUTPUTS, ctx.device)
         log(f"batch: {len(insts)} instances, {nr} rays; tuning ...")

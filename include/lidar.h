@@ -402,8 +402,10 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep,
 
 /* Launch-shape options.  They change speed, never results.
  *   LIDAR_OPT_TILE_AZ: beams are traced in 64-beam tiles of `value` azimuth
- *     steps x 64 / value channels (power of two in 1..64; default 2).  A batch
- *     keeps the tile shape that was current when it was created.
+ *     steps x 64 / value channels (power of two in 1..64), or 0 = automatic
+ *     (default): 2 for the static scene, 8 while actors are set, 16 for a
+ *     batch.  A batch keeps the tile shape that was current when it was
+ *     created.
  *   LIDAR_OPT_LANES_PER_RAY: 1 = one lane walks the BVH for a beam; 2 = two
  *     lanes share a beam, two child boxes each; 4 = the four lanes of a quad
  *     share a beam, one child box each (default 4).

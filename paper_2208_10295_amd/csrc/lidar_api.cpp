@@ -88,7 +88,7 @@ struct lidar_ctx {
     float q[4] = {1, 0, 0, 0};
     // device words: [0] error flags, [1] queue counter, [2..3] refit scratch
     DevBuf words;
-    int tile_az_log2 = 1;     // 2 azimuth steps x 32 channels per 64-beam tile
+    int tile_az_log2 = -1;    // -1: automatic (tile_log2())
     int lanes_per_ray = 4;
     int xcd_remap = 1;
     // dynamic scene: meshes and the actors placing them
@@ -109,6 +109,10 @@ struct lidar_ctx {
     int actor_stack = 0;
 
     int trace_stack() const { return has_actors && actor_stack > stack ? actor_stack : stack; }
+    // automatic tile shape (measured on the 64 x 2048 scan): 2 azimuth steps x 32 channels for the
+    // static scene, 8 x 8 with actors (their nested mesh walks diverge less), 16 x 4 for batches
+    int tile_log2() const { return tile_az_log2 >= 0 ? tile_az_log2 : (has_actors ? 3 : 1); }
+    int batch_tile_log2() const { return tile_az_log2 >= 0 ? tile_az_log2 : 4; }
     TraceOpts opts(int tile) const { return TraceOpts{trace_stack(), tile, lanes_per_ray, xcd_remap}; }
     uint32_t *refit_word() const { return (uint32_t *)words.p + 2; }
 
@@ -532,7 +536,7 @@ static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan
     const lidar_sensor_desc &d = ctx->sensor.d;
     const double *elev_cs = (const double *)ctx->sensor_tables.p;
     const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
-    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, ctx->p, ctx->q, seed, scan, 0, 0, 0);
+    InstanceDev in = make_instance(ctx, ctx->tile_log2(), d, elev_cs, az_cs, ctx->p, ctx->q, seed, scan, 0, 0, 0);
     Overrides ov{};
     if (params) {
         if (params->rho && params->spectra)
@@ -544,11 +548,11 @@ static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan
     }
     uint64_t nb = (uint64_t)d.n_ch * d.n_az;
     Outputs o = to_outputs(out, nb);
-    uint64_t np = padded_rays(ctx->tile_az_log2, d.n_ch, d.n_az);
+    uint64_t np = padded_rays(ctx->tile_log2(), d.n_ch, d.n_az);
     hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
-    if (brute) launch_bruteforce(ctx->S, in, ctx->M, ov, o, ctx->tile_az_log2, np, s);
-    else launch_trace_scan(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, ov, o, np, (uint32_t *)ctx->words.p,
+    if (brute) launch_bruteforce(ctx->S, in, ctx->M, ov, o, ctx->tile_log2(), np, s);
+    else launch_trace_scan(ctx->opts(ctx->tile_log2()), ctx->S, in, ctx->M, ov, o, np, (uint32_t *)ctx->words.p,
                            n_nodes, n_tris, ctx->has_actors ? &ctx->A : nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "trace launch");
@@ -649,18 +653,18 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, co
     launch_sweep_poses(A, poses, s);
     const double *elev_cs = (const double *)ctx->sensor_tables.p;
     const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
-    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, sw->p_begin, sw->q_begin, sw->seed,
+    InstanceDev in = make_instance(ctx, ctx->tile_log2(), d, elev_cs, az_cs, sw->p_begin, sw->q_begin, sw->seed,
                                    run_scan[0], 0, 0, 0);
     in.col_pose = poses;
     in.n_cols = n_cols;
     in.seg_n0 = run_count[0];
     in.seg_i0[0] = run_first[0];
     in.seg_i0[1] = run_first[1];
-    in.tiles_az = tiles_az(ctx->tile_az_log2, n_cols);
+    in.tiles_az = tiles_az(ctx->tile_log2(), n_cols);
     uint64_t nb = (uint64_t)d.n_ch * d.n_az;
     Outputs o = to_outputs(out, nb);
-    uint64_t np = padded_rays(ctx->tile_az_log2, d.n_ch, n_cols);
-    launch_trace_scan(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, Overrides{}, o, np,
+    uint64_t np = padded_rays(ctx->tile_log2(), d.n_ch, n_cols);
+    launch_trace_scan(ctx->opts(ctx->tile_log2()), ctx->S, in, ctx->M, Overrides{}, o, np,
                       (uint32_t *)ctx->words.p, nullptr, nullptr, ctx->has_actors ? &ctx->A : nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "sweep launch");
@@ -707,7 +711,7 @@ lidar_status lidar_simulate_echoes(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
     const lidar_sensor_desc &d = ctx->sensor.d;
     const double *elev_cs = (const double *)ctx->sensor_tables.p;
     const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
-    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, ctx->p, ctx->q, seed, scan, 0, 0, 0);
+    InstanceDev in = make_instance(ctx, ctx->tile_log2(), d, elev_cs, az_cs, ctx->p, ctx->q, seed, scan, 0, 0, 0);
     SubrayPattern pat{};
     pat.n_sub = echo->n_sub;
     const double golden = 3.14159265358979323846 * (3.0 - std::sqrt(5.0));
@@ -723,11 +727,11 @@ lidar_status lidar_simulate_echoes(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
     }
     const uint64_t nb = (uint64_t)d.n_ch * d.n_az;
     Outputs o = to_outputs(out, nb);
-    const uint64_t np = padded_rays(ctx->tile_az_log2, d.n_ch, d.n_az);
+    const uint64_t np = padded_rays(ctx->tile_log2(), d.n_ch, d.n_az);
     hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     SubHit *sub = (SubHit *)workspace;
-    launch_trace_subrays(ctx->opts(ctx->tile_az_log2), ctx->S, in, ctx->M, pat, sub, np, (uint32_t *)ctx->words.p,
+    launch_trace_subrays(ctx->opts(ctx->tile_log2()), ctx->S, in, ctx->M, pat, sub, np, (uint32_t *)ctx->words.p,
                          ctx->has_actors ? &ctx->A : nullptr, s);
     launch_echoes(in, ctx->M, sub, echo->n_sub, echo->max_echoes, echo->echo_sep_m, o, s);
     hipError_t e = hipGetLastError();
@@ -1029,7 +1033,7 @@ lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint
     b->ctx = ctx;
     b->n_inst = n_inst;
     b->packet = packet_rays ? packet_rays : 256;
-    b->tile_az_log2 = ctx->tile_az_log2;
+    b->tile_az_log2 = ctx->batch_tile_log2();
     hipSetDevice(ctx->device);
     if (b->tables.ensure(table_doubles * 8) != hipSuccess || b->d_insts.ensure(sizeof(InstanceDev) * n_inst) != hipSuccess) {
         delete b;
@@ -1226,7 +1230,7 @@ static lidar_status backward_common(lidar_ctx *ctx, const lidar_params *params, 
     if (ctx->adj_partials.n < pb) return ctx->fail(LIDAR_ERR_NOT_READY, "adjoint buffer not allocated");
     const double *elev_cs = (const double *)ctx->sensor_tables.p;
     const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
-    InstanceDev in = make_instance(ctx, ctx->tile_az_log2, d, elev_cs, az_cs, ctx->p, ctx->q, 0, 0, 0, 0, 0);
+    InstanceDev in = make_instance(ctx, ctx->tile_log2(), d, elev_cs, az_cs, ctx->p, ctx->q, 0, 0, 0, 0, 0);
     Overrides ov{};
     if (params) {
         ov.rho = params->rho;
@@ -1312,10 +1316,14 @@ lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
     if (!ctx) return LIDAR_ERR_INVALID_ARG;
     switch (option) {
     case LIDAR_OPT_TILE_AZ: {
+        if (value == 0) {   // automatic
+            ctx->tile_az_log2 = -1;
+            return LIDAR_OK;
+        }
         int lg = -1;
         for (int k = 0; k <= 6; ++k)
             if ((1 << k) == value) lg = k;
-        if (lg < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "tile_az must be a power of two in 1..64");
+        if (lg < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "tile_az must be 0 (automatic) or a power of two in 1..64");
         ctx->tile_az_log2 = lg;
         return LIDAR_OK;
     }

@@ -315,9 +315,15 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                         overflow = true;
                     }
                 } else {
-                    if (k3 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
-                    if (k2 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
-                    if (k1 != inf) { if (sp < cap) { if (s == 0) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
+                    // pair: lane s writes c_(s+1) to entry sp + h - (s + 1); lane 1 also writes c3 when h = 3
+                    const int nh = (k1 != inf) + (k2 != inf) + (k3 != inf);
+                    if (sp + nh <= cap) {
+                        if ((int)s + 1 <= nh) stk[(sp + nh - 1 - (int)s) * NSLOT] = (s == 0) ? c1 : c2;
+                        if (nh == 3 && s == 1) stk[sp * NSLOT] = c3;
+                        sp += nh;
+                    } else {
+                        overflow = true;
+                    }
                 }
                 ref = c0;
                 continue;
