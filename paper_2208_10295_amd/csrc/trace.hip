@@ -624,35 +624,57 @@ __global__ __launch_bounds__(BLOCK, ACTORS ? 1 : 8) void trace_scan_multi_kernel
                                                                  uint32_t *__restrict__ n_nodes,
                                                                  uint32_t *__restrict__ n_tris, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
+    static_assert(NR == 64, "one 64-beam tile per block; its epilogue runs in the first wavefront");
     __shared__ uint32_t stk[STACK * NR];
     __shared__ double pose[12];
+    // hits of the block's beams, handed from the walking lanes to the epilogue wavefront:
+    // (j << 20 | launch column), record slot, triangle index, t bits, actor, beam active
+    __shared__ uint32_t hand[6][NR];
     if (!SWEEP) block_pose(in, ov, pose);
     const uint32_t q = threadIdx.x / LANES, s = threadIdx.x % LANES;
-    uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
-    if (r >= n_padded) return;   // all lanes of the beam
-    uint32_t j, k, i, scan;
-    if (!ray_coords(r, in, tile_az_log2, j, k)) return;   // all lanes of the beam
-    Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
-    bool overflow = false;
-    Counts c{0u, 0u};
-    Hit h = traverse_multi<LANES, STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace,
-                                                    stk + q, s, overflow, c);
-    const ActorDev *act = nullptr;
-    const TriRec *tris = S.tris;
-    if constexpr (ACTORS) {
-        traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
-        if (h.actor != kNone) {
-            act = A.actors + h.actor;
-            tris = A.meshes[act->mesh].tris;
+    const uint64_t r = (uint64_t)logical_block(xcd_remap) * NR + q;
+    uint32_t j = 0, k = 0;
+    const bool active = r < n_padded && ray_coords(r, in, tile_az_log2, j, k);
+    if (active) {
+        uint32_t i, scan;
+        const Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
+        bool overflow = false;
+        Counts c{0u, 0u};
+        Hit h = traverse_multi<LANES, STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
+                                                        in.t_trace, stk + q, s, overflow, c);
+        if constexpr (ACTORS) traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
+        if (overflow) atomicOr(err, 1u);
+        if (s == 0) {
+            if (COUNT) {
+                const uint32_t beam = j * in.n_az + i;
+                n_nodes[beam] = c.nodes;
+                n_tris[beam] = c.tris;
+            }
+            hand[0][q] = (j << 20) | k;
+            hand[1][q] = h.slot;
+            hand[2][q] = h.orig;
+            hand[3][q] = __float_as_uint(h.t);
+            hand[4][q] = h.actor;
         }
     }
-    if (overflow) atomicOr(err, 1u);
-    if (s != 0) return;
-    uint32_t beam = j * in.n_az + i;
-    if (COUNT) {
-        n_nodes[beam] = c.nodes;
-        n_tris[beam] = c.tris;
+    if (s == 0) hand[5][q] = active ? 1u : 0u;
+    __syncthreads();
+    // Epilogue: the block's 64 beams, one per lane of the first wavefront, instead
+    // of one lane in LANES of every wavefront.
+    if (threadIdx.x >= (unsigned)NR || !hand[5][threadIdx.x]) return;
+    const uint32_t e = threadIdx.x;
+    j = hand[0][e] >> 20;
+    k = hand[0][e] & 0xFFFFFu;
+    uint32_t i, scan;
+    const Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
+    const Hit h{hand[1][e], hand[2][e], __uint_as_float(hand[3][e]), hand[4][e]};
+    const ActorDev *act = nullptr;
+    const TriRec *tris = S.tris;
+    if (ACTORS && h.actor != kNone) {
+        act = A.actors + h.actor;
+        tris = A.meshes[act->mesh].tris;
     }
+    const uint32_t beam = j * in.n_az + i;
     shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, tris, h, act);
 }
 
