@@ -385,6 +385,19 @@ def _trace_and_return(scene, sensor, beams, s, d, o, seed, scan, inst, rho, angl
     return out
 
 
+def point_cloud(out, fields=("x", "y", "z", "intensity", "label", "range")):
+    """Step 7 [Fig.1 caption]: the labelled point cloud lists the detected
+    returns only; a miss or a dropped return has no point.  Points keep the
+    beam order of the range image (b = j * n_az + i); `beam` gives each
+    point's beam index (the dense index when `out` has no `beams` entry)."""
+    valid = np.asarray(out["valid"]).reshape(-1)
+    keep = np.flatnonzero(valid != 0)
+    pc = {k: np.asarray(out[k]).reshape(-1)[keep] for k in fields}
+    beams = np.asarray(out["beams"]) if "beams" in out else np.arange(len(valid))
+    pc["beam"] = beams[keep]
+    return pc
+
+
 # ----------------------------------------------------------------------------
 # beam divergence and multi-echo returns [IV, named there as future work]
 # ----------------------------------------------------------------------------

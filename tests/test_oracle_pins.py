@@ -140,6 +140,29 @@ def test_ground_plane_closed_form_config1_numbers():
     assert r["valid"][3 * n_az] == 1 and r["valid"][2 * n_az] == 0     # -9 kept, -8 dropped
 
 
+def test_point_cloud_of_ground_plane_closed_form():
+    """Point cloud over a ground plane: exactly the channels below the eq.5 cutoff elevation
+    (sin^2|phi| >= R_L,max h / (d_max rho), |phi| >= 8.91 deg here) give points, every azimuth
+    of them, in beam order, each at range h / sin|phi| with z = -h in the sensor frame."""
+    h, rho = 1.5, 0.5
+    scene = _ground(spectra=np.full((1, 61), rho, np.float32))
+    elev = np.array([-15.0, 10.0, -7.0, -9.0, -8.0, -11.0, 0.0])
+    sensor = S.Sensor(elev, 12, d_max=100.0, r_l_max=0.8, noise_on=False)
+    pose = S.Pose(np.array([0, 0, h], np.float32), np.array([1, 0, 0, 0], np.float32))
+    pc = O.point_cloud(O.simulate(scene, sensor, pose))
+    cut = math.asin(math.sqrt(0.8 * h / (100.0 * rho)))
+    kept = [j for j, e in enumerate(elev) if e < 0 and math.radians(-e) >= cut]
+    assert kept == [0, 3, 5]
+    expect_beams = np.array([j * 12 + i for j in kept for i in range(12)])
+    np.testing.assert_array_equal(pc["beam"], expect_beams)
+    phi = np.radians(-elev[expect_beams // 12])
+    np.testing.assert_allclose(pc["range"], h / np.sin(phi), rtol=1e-12)
+    np.testing.assert_allclose(pc["z"], -h, rtol=1e-12)
+    np.testing.assert_allclose(np.hypot(pc["x"], pc["y"]), h / np.tan(phi), rtol=1e-12)
+    # triangle 0 (label 1) is the half y < x of the square, triangle 1 (label 2) the half y > x
+    np.testing.assert_array_equal(pc["label"], np.where(pc["y"] < pc["x"], 1, 2))
+
+
 def test_tilted_plane_distance_and_angle():
     """Plane n.x = h at arbitrary orientation: t = (h - n.o)/(n.d), cos = |n.d|, I = rho cos^k."""
     rng = np.random.default_rng(5)
