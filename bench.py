@@ -81,6 +81,21 @@ def timed_launches(fn, n, torch):
     return wall, [a.elapsed_time(b) for a, b in evs]
 
 
+def timed_region(fn, n, torch):
+    """Run fn(k) for k < n back to back between two HIP events recorded on the current stream (the stream
+    the kernels are launched on); returns (wall_s, mean ms per call from the events)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for k in range(n):
+        fn(k)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / n
+
+
 def O_weights(nbins, wavelength_nm, lambda0_nm=400.0, dlambda_nm=10.0):
     """Linear interpolation weights of a spectral table at a wavelength (for reporting only)."""
     w = [0.0] * nbins
@@ -174,12 +189,12 @@ def main():
 
     if "plain" in legs:
         out = alloc_outputs(n, POINT_OUTPUTS, ctx.device)
+        scan = ctx.scan_launcher(seed, out)      # argument structs built once: one ctypes call per scan
         for w in range(args.warmup):
-            ctx.simulate(seed, w, out=out)
+            scan(w)
         ctx.sync_check()
-        wall, ms = timed_launches(lambda k: ctx.simulate(seed, k, out=out), args.steps, torch)
+        wall, kernel_ms = timed_region(scan, args.steps, torch)
         ctx.sync_check()
-        kernel_ms = float(np.mean(ms))
         result["value"] = args.steps * n / wall
         result["ms_per_step"] = 1e3 * wall / args.steps
         result["kernel_ms"] = kernel_ms
@@ -196,6 +211,16 @@ def main():
                                "kernel_source_sha256_16": kernel_source_hash()}
         log(f"plain: {result['value']:.4g} rays/s, kernel {kernel_ms * 1e3:.1f} us, "
             f"{n_nodes / n:.1f} nodes + {n_tris / n:.1f} tris per ray, {achieved:.0f} GB/s algorithmic")
+        # order-preserving compaction of the scan's point cloud (detected beams only)
+        comp, _, cnt = ctx.compact_launcher(out, alloc_outputs(n, POINT_OUTPUTS, ctx.device))
+        for _ in range(3):
+            comp()
+        _, c_ms = timed_region(comp, 50, torch)
+        n_pts = int(cnt.item())
+        result["compact"] = {"workload": "detected points of the 64ch x 2048 scan, x/y/z/intensity/label/valid/range "
+                                         "+ beam index, in beam order",
+                             "us_per_scan": c_ms * 1e3, "points": n_pts, "beams": n}
+        log(f"compact: {n_pts} points of {n} beams in {c_ms * 1e3:.1f} us")
 
     if "cpu" in legs:
         log("cpu baseline (FP64 oracle) ...")
@@ -273,9 +298,10 @@ def main():
         gR = torch.randn(n, **f32)
         for _ in range(3):
             cx.backward(fo["tri"], fo["valid"], gI, gR, params=fwd_args)
-        _, ms_f = timed_launches(lambda k: cx.simulate(0, 0, out=fo, params=fwd_args), 50, torch)
-        _, ms_bw = timed_launches(lambda k: cx.backward(fo["tri"], fo["valid"], gI, gR, params=fwd_args), 50, torch)
-        f_ms, b_ms = float(np.median(ms_f)), float(np.median(ms_bw))
+        fwd = cx.scan_launcher(0, fo, params=fwd_args)
+        bwd, _ = cx.backward_launcher(fo["tri"], fo["valid"], gI, gR, params=fwd_args)
+        _, f_ms = timed_region(lambda k: fwd(0), 50, torch)
+        _, b_ms = timed_region(bwd, 50, torch)
         # 200 steps of calibration (Adam) on rho, k, pose
         opt = torch.optim.Adam([{"params": [rho], "lr": 0.01}, {"params": [kk], "lr": 0.02},
                                 {"params": [pose6], "lr": 0.002}])
@@ -328,8 +354,8 @@ def main():
         cxs[1].simulate(0, 0, out=fo, params=sp_args)
         for _ in range(3):
             cxs[1].backward_spectra(fo["tri"], fo["valid"], gI, gR, params=sp_args)
-        _, ms_bs = timed_launches(lambda k: cxs[1].backward_spectra(fo["tri"], fo["valid"], gI, gR, params=sp_args),
-                                  50, torch)
+        bws, _ = cxs[1].backward_launcher(fo["tri"], fo["valid"], gI, gR, params=sp_args, spectra=True)
+        _, bs_ms = timed_region(bws, 50, torch)
         opt = torch.optim.Adam([Tt], lr=0.02)
         sl = []
         t0 = time.perf_counter()
@@ -354,10 +380,10 @@ def main():
             r_err.append(((Tt.detach() - T_true) @ w).abs().cpu().numpy()[used])
         result["adjoint"]["spectral"] = {
             "workload": "same scene and pose, 20 x 61 spectral table, scans at 850 / 905 / 940 nm, intensity MSE",
-            "backward_spectra_ms": float(np.median(ms_bs)), "calibration_steps": 100, "calibration_s": sp_s,
+            "backward_spectra_ms": bs_ms, "calibration_steps": 100, "calibration_s": sp_s,
             "loss_first": sl[0], "loss_last": sl[-1],
             "r_lambda0_abs_err_median": float(np.median(np.concatenate(r_err)))}
-        log(f"spectral adjoint: bwd {np.median(ms_bs) * 1e3:.1f} us; 3-wavelength loss {sl[0]:.4g} -> {sl[-1]:.4g}")
+        log(f"spectral adjoint: bwd {bs_ms * 1e3:.1f} us; 3-wavelength loss {sl[0]:.4g} -> {sl[-1]:.4g}")
         del cxs
 
     if "sweep" in legs:
@@ -437,16 +463,16 @@ def main():
             ctx.simulate(seed, f, out=outd)
         wall_d, ms_d = timed_launches(frame, n_frames, torch)
         ctx.sync_check()
-        _, ms_scan = timed_launches(lambda k: ctx.simulate(seed, k, out=outd), 50, torch)
+        _, scan_ms = timed_region(ctx.scan_launcher(seed, outd), 50, torch)
         n_act = int((outd["label"].view(torch.int32) >= 100000).sum())
         result["dynamic"] = {
             "workload": "522k-triangle scene + 300 actors (200 cars of 408 triangles, 100 deforming pedestrians of "
                         "304 triangles) moving at 10 Hz; per frame: pedestrian mesh refit, actor BVH refit, "
                         "64ch x 2048 scan",
             "frames": n_frames, "frame_ms_mean": float(np.mean(ms_d)), "rays_per_s_with_updates": n_frames * n / wall_d,
-            "scan_ms_mean": float(np.mean(ms_scan)), "rays_per_s_scan": n / (float(np.mean(ms_scan)) * 1e-3),
+            "scan_ms_mean": scan_ms, "rays_per_s_scan": n / (scan_ms * 1e-3),
             "actors_set_ms": set_ms, "beams_on_actors_last_frame": n_act}
-        log(f"dynamic: {np.mean(ms_d) * 1e3:.1f} us per frame (refits + scan), scan {np.mean(ms_scan) * 1e3:.1f} us, "
+        log(f"dynamic: {np.mean(ms_d) * 1e3:.1f} us per frame (refits + scan), scan {scan_ms * 1e3:.1f} us, "
             f"actor BVH build {set_ms:.2f} ms, {n_act} beams on actors")
         ctx.clear_actors()
 

@@ -235,6 +235,33 @@ lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
                                    uint32_t *node_visits, uint32_t *tri_tests, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Point cloud: detected points only (Fig.1: the labelled point cloud)       */
+/* ------------------------------------------------------------------------ */
+
+/* Size of the caller-owned device workspace of lidar_compact_points for
+ * n_beams dense elements (4 bytes per 256 beams, at least 256).  Errors:
+ * INVALID_ARG (NULL pointer, n_beams > 2^31). */
+lidar_status lidar_compact_bytes(uint64_t n_beams, uint64_t *workspace_bytes);
+
+/* Order-preserving compaction of dense outputs: the elements b with
+ * dense->valid[b] != 0 are copied, in increasing b, to elements 0, 1, ... of
+ * every non-NULL array of `compact`; beam_index (device [n_beams], or NULL)
+ * receives b, and *count (one device uint32) the number of detected points.
+ * `dense` holds n_beams elements per array (the outputs of lidar_simulate,
+ * lidar_simulate_batch, lidar_simulate_sweep, or of lidar_simulate_echoes with
+ * n_beams = beams x echoes); it must have `valid`, and every array requested in
+ * `compact` (normal: [3][n_beams] in both).  Every array of `compact` must
+ * hold n_beams elements (the worst case); elements at and beyond *count are
+ * left untouched.  Workspace: device, 256-byte aligned, at least
+ * lidar_compact_bytes(n_beams).  Ballot and prefix sum per 256-beam block, no
+ * atomics: the result is deterministic.  Asynchronous.  Errors: INVALID_ARG
+ * (missing valid or source array, NULL count, misaligned workspace),
+ * WORKSPACE_TOO_SMALL, HIP. */
+lidar_status lidar_compact_points(lidar_ctx *ctx, const lidar_outputs *dense, uint64_t n_beams,
+                                  const lidar_outputs *compact, uint32_t *beam_index, uint32_t *count,
+                                  void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Divergent beams and multi-echo returns (Section IV: named future work)    */
 /* ------------------------------------------------------------------------ */
 

@@ -129,6 +129,9 @@ SIGNATURES = {
     "lidar_simulate_ex": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Params), C.POINTER(Outputs), P]),
     "lidar_simulate_bruteforce": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P]),
     "lidar_simulate_counts": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P, P, P]),
+    "lidar_compact_bytes": (C.c_int32, [C.c_uint64, C.POINTER(C.c_uint64)]),
+    "lidar_compact_points": (C.c_int32, [P, C.POINTER(Outputs), C.c_uint64, C.POINTER(Outputs), P, P, P, C.c_uint64,
+                                         P]),
     "lidar_simulate_sweep": (C.c_int32, [P, C.POINTER(SweepDesc), C.POINTER(Outputs), C.POINTER(SweepInfo), P]),
     "lidar_echo_bytes": (C.c_int32, [P, C.POINTER(EchoDesc), C.POINTER(C.c_uint64)]),
     "lidar_simulate_echoes": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(EchoDesc), P, C.c_uint64,

@@ -582,6 +582,45 @@ lidar_status lidar_simulate_counts(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
 }
 
 // ---------------------------------------------------------------------------
+// point-cloud compaction
+// ---------------------------------------------------------------------------
+constexpr uint64_t kMaxCompactBeams = 1ull << 31;
+
+lidar_status lidar_compact_bytes(uint64_t n_beams, uint64_t *workspace_bytes) {
+    if (!workspace_bytes || n_beams > kMaxCompactBeams) return LIDAR_ERR_INVALID_ARG;
+    *workspace_bytes = std::max<uint64_t>(256, (4 * compact_blocks(n_beams) + 255) / 256 * 256);
+    return LIDAR_OK;
+}
+
+lidar_status lidar_compact_points(lidar_ctx *ctx, const lidar_outputs *dense, uint64_t n_beams,
+                                  const lidar_outputs *compact, uint32_t *beam_index, uint32_t *count,
+                                  void *workspace, uint64_t workspace_bytes, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!dense || !compact) return ctx->fail(LIDAR_ERR_INVALID_ARG, "outputs struct is null");
+    if (!dense->valid && n_beams) return ctx->fail(LIDAR_ERR_INVALID_ARG, "dense outputs need the valid array");
+    if (!count) return ctx->fail(LIDAR_ERR_INVALID_ARG, "count pointer is null");
+    if (n_beams > kMaxCompactBeams) return ctx->fail(LIDAR_ERR_INVALID_ARG, "more than 2^31 beams");
+    const void *pairs[][2] = {{compact->x, dense->x}, {compact->y, dense->y}, {compact->z, dense->z},
+                              {compact->intensity, dense->intensity}, {compact->label, dense->label},
+                              {compact->valid, dense->valid}, {compact->range, dense->range},
+                              {compact->tri, dense->tri}, {compact->t_hit, dense->t_hit},
+                              {compact->material, dense->material}, {compact->normal, dense->normal},
+                              {compact->r_lambda, dense->r_lambda}};
+    for (const auto &pr : pairs)
+        if (pr[0] && !pr[1]) return ctx->fail(LIDAR_ERR_INVALID_ARG, "a compact field has no dense source");
+    uint64_t need = 0;
+    lidar_compact_bytes(n_beams, &need);
+    if (!workspace || ((uintptr_t)workspace & 255)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need) return ctx->fail(LIDAR_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than lidar_compact_bytes()");
+    hipSetDevice(ctx->device);
+    launch_compact(to_outputs(dense, n_beams), to_outputs(compact, n_beams), beam_index, count, n_beams,
+                   (uint32_t *)workspace, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "compaction launch");
+    return LIDAR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // partial sweep per engine tick
 // ---------------------------------------------------------------------------
 lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, const lidar_outputs *out,

@@ -123,6 +123,12 @@ void actor_prims(const float *lohi, uint32_t n, float *vtx, uint32_t *idx, uint1
 void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,
                 hipStream_t s);
 
+// --- point-cloud compaction (compact.hip) ---
+// counts: compact_blocks(n) device words of scratch; count: one device word
+uint64_t compact_blocks(uint64_t n);
+void launch_compact(const Outputs &dense, const Outputs &comp, uint32_t *beam_index, uint32_t *count, uint64_t n,
+                    uint32_t *counts, hipStream_t s);
+
 // --- adjoint (adjoint.hip) ---
 constexpr int kAdjBlock = 256;
 size_t adjoint_partial_bytes(uint32_t n_beams, uint32_t nmat);

@@ -277,6 +277,111 @@ class Context:
         check(st, self.h)
         return out
 
+    def scan_launcher(self, seed: int, out: dict, params: dict | None = None, stream=None):
+        """A callable f(scan) that runs lidar_simulate (lidar_simulate_ex with `params`) on fixed
+        outputs and stream.
+
+        The argument structs are built once, so a loop of f(k) costs one ctypes
+        call per scan on the host (for back-to-back launches that keep the GPU
+        queue full)."""
+        o = outputs_struct(out)
+        ob = C.byref(o)
+        sp = _stream(stream)
+        h = self.h
+        seed = int(seed)
+        if params:
+            p = _params_struct(params)
+            pb = C.byref(p)
+            fn = lib.lidar_simulate_ex
+
+            def run(scan: int):
+                st = fn(h, seed, scan, pb, ob, sp)
+                if st < 0:
+                    check(st, h)
+            run._keep = (o, out, p, params)
+            return run
+        fn = lib.lidar_simulate
+
+        def run(scan: int):
+            st = fn(h, seed, scan, ob, sp)
+            if st < 0:
+                check(st, h)
+        run._keep = (o, out)
+        return run
+
+    def backward_launcher(self, tri, valid, dL_dI, dL_drange, params: dict | None = None, spectra: bool = False,
+                          stream=None):
+        """A callable f() that runs lidar_backward (lidar_backward_spectra if `spectra`) with fixed
+        arguments, writing into the returned (d_rho or d_spectra, d_k, d_pose6) tensors."""
+        nmat = self.nmat
+        shape = (nmat, self.nbins) if spectra else (nmat,)
+        d_a = torch.empty(shape, dtype=torch.float32, device=self.device)
+        d_k = torch.empty(nmat, dtype=torch.float32, device=self.device)
+        d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
+        p = _params_struct(params)
+        args = (self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(dL_dI), _ptr(dL_drange), _ptr(d_a), _ptr(d_k),
+                _ptr(d_pose), _stream(stream))
+        fn = lib.lidar_backward_spectra if spectra else lib.lidar_backward
+        h = self.h
+
+        def run(*_):
+            st = fn(*args)
+            if st < 0:
+                check(st, h)
+        run._keep = (p, params, tri, valid, dL_dI, dL_drange)
+        return run, (d_a, d_k, d_pose)
+
+    def compact(self, dense: dict, names=None, out: dict | None = None, workspace=None, stream=None,
+                read_count: bool = True):
+        """Order-preserving compaction of dense outputs (any number of beams) to the detected points.
+
+        Returns (points, beam_index, count): `points` maps each requested name (default: every dense
+        array) to a tensor of capacity n whose first `count` elements are the detected points in beam
+        order, `beam_index` their dense indices, `count` the device count tensor, or its value (a host
+        int, after a synchronisation) if read_count is True; then the tensors are cut to that length."""
+        v = dense.get("valid")
+        n = int(v.numel()) if v is not None else int(next(t for t in dense.values() if t is not None).shape[-1])
+        dense = {k: t for k, t in dense.items() if t is not None}
+        names = tuple(dense.keys()) if names is None else tuple(names)
+        if out is None:
+            out = alloc_outputs(n, names, self.device)
+        nbytes = C.c_uint64()
+        check(lib.lidar_compact_bytes(n, C.byref(nbytes)), self.h)
+        if workspace is None or workspace.numel() < nbytes.value:
+            workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        beam_index = torch.empty(n, dtype=torch.int32, device=self.device)
+        count = torch.zeros(1, dtype=torch.int32, device=self.device)
+        di, co = outputs_struct(dense), outputs_struct({k: out[k] for k in names})
+        check(lib.lidar_compact_points(self.h, C.byref(di), n, C.byref(co), _ptr(beam_index), _ptr(count),
+                                       _ptr(workspace), workspace.numel(), _stream(stream)), self.h)
+        self._compact_workspace = workspace
+        if not read_count:
+            return out, beam_index, count
+        c = int(count.item())
+        pts = {k: (v[:, :c] if k == "normal" else v[:c]) for k, v in out.items()}
+        return pts, beam_index[:c], c
+
+    def compact_launcher(self, dense: dict, out: dict, stream=None):
+        """A callable f() that runs lidar_compact_points on fixed arrays; returns (f, beam_index, count)
+        with count a one-element device tensor."""
+        n = int(dense["valid"].numel())
+        nbytes = C.c_uint64()
+        check(lib.lidar_compact_bytes(n, C.byref(nbytes)), self.h)
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        beam_index = torch.empty(n, dtype=torch.int32, device=self.device)
+        count = torch.zeros(1, dtype=torch.int32, device=self.device)
+        di, co = outputs_struct(dense), outputs_struct(out)
+        args = (self.h, C.byref(di), n, C.byref(co), _ptr(beam_index), _ptr(count), _ptr(ws), ws.numel(),
+                _stream(stream))
+        fn, h = lib.lidar_compact_points, self.h
+
+        def run(*_):
+            st = fn(*args)
+            if st < 0:
+                check(st, h)
+        run._keep = (di, co, ws, dense, out)
+        return run, beam_index, count
+
     def simulate_sweep(self, seed: int, head_deg: float, spin_hz: float, dt_s: float, pose_begin, pose_end,
                        out: dict | None = None, debug: bool = False, stream=None):
         """One engine tick: traces the columns the head fires over

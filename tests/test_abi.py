@@ -98,7 +98,17 @@ def test_null_context_calls_are_rejected(A):
     assert lib.lidar_materials_set(None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_backward(None, None, None, None, None, None, None, None, None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_batch_destroy(None) == A.OK
+    assert lib.lidar_compact_points(None, None, 0, None, None, None, None, 0, None) == A.ERR_INVALID_ARG
     assert lib.lidar_create(0, None) == A.ERR_INVALID_ARG
+
+
+def test_compact_workspace_sizes_host_only(A):
+    w = C.c_uint64()
+    for n, need in ((0, 256), (1, 256), (256 * 64, 256), (256 * 64 + 1, 512), (131072, 2048), (21385216, 334336)):
+        assert A.lib.lidar_compact_bytes(n, C.byref(w)) == A.OK
+        assert w.value == need and w.value >= 4 * ((n + 255) // 256), n
+    assert A.lib.lidar_compact_bytes((1 << 31) + 1, C.byref(w)) == A.ERR_INVALID_ARG
+    assert A.lib.lidar_compact_bytes(10, None) == A.ERR_INVALID_ARG
 
 
 def test_create_without_gpu_reports_error(A):
