@@ -347,7 +347,7 @@ __device__ inline RayBox prep_box_test(const Ray &r) {
 template <int K>
 __device__ inline uint32_t quad_bcast(uint32_t v) {
     constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, true);
 }
 template <int K>
 __device__ inline float quad_bcast(float v) {
@@ -355,13 +355,13 @@ __device__ inline float quad_bcast(float v) {
 }
 // value of lane (lane ^ 1) / (lane ^ 2) within the quad
 __device__ inline uint32_t quad_xor1(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
 }
 __device__ inline uint32_t quad_xor2(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true);
 }
 __device__ inline uint32_t quad_xor3(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x1B, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x1B, 0xF, 0xF, true);
 }
 
 // ---------------------------------------------------------------------------

@@ -230,10 +230,35 @@ __device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__
 // multi-lane traversal: LANES (2 or 4) adjacent lanes of one DPP quad share a
 // beam; lane s = lane % LANES tests child boxes s * 4 / LANES .. (one 32-byte
 // slot each, so the lanes of a beam read one 128-byte node line together) and
-// the triangles s, s + LANES, ... of a leaf.  The lanes exchange their keys
-// through quad_perm DPP moves, put the four children in node order and run the
-// same sorting network, so they agree on the order without further exchanges.
+// the triangles s, s + LANES, ... of a leaf.
+//
+// Quad (LANES = 4) node step: lane s holds the entry distance of child s.  The
+// distance bits (positive floats and +inf order like unsigned integers), with
+// the two low mantissa bits replaced by s, form a key unique within the quad;
+// each lane counts the smaller keys of its three partners (quad_perm xor 1, 2,
+// 3) to get its child's rank in near-to-far order.  The rank-0 child is
+// descended into (its reference is OR-reduced over the quad), and the lane of
+// the child of rank r >= 1 that was hit pushes its own reference to stack entry
+// sp + h - r (h further children hit), so the nearest of them is popped first.
+// Pair (LANES = 2): each lane tests two children, the pair swaps keys through
+// quad_perm and both run the same sorting network.
+//
+// Leaves: each lane keeps the lexicographic (t, original index) minimum of the
+// triangles it tested; after a leaf the lanes only agree on the smallest t (the
+// culling bound), and the full minimum is reduced over the lanes once, at the
+// end.  Culling uses the same bound as a per-leaf reduction would, so the same
+// nodes are visited and the result is the same.
 // ---------------------------------------------------------------------------
+// Smallest t over the beam's lanes.  Distances are positive, so their bit
+// patterns order like unsigned integers (no float canonicalisation needed).
+template <int LANES>
+__device__ inline float group_min_t(float t) {
+    uint32_t u = __float_as_uint(t);
+    u = min(u, quad_xor1(u));
+    if (LANES == 4) u = min(u, quad_xor2(u));
+    return __uint_as_float(u);
+}
+
 template <int LANES, int STACK, int NSLOT, bool COUNT>
 __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
                                      uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
@@ -243,7 +268,8 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
     const float inf = __builtin_inff();
-    Hit h{kNone, kNone, t_hi, kNone};
+    Hit h{kNone, kNone, t_hi, kNone};   // this lane's best
+    float best_t = t_hi;                // the beam's best distance (minimum over its lanes)
     uint32_t ref = root;
     int sp = 0;
     uint32_t steps = 0;
@@ -252,45 +278,49 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
         if (ref & kLeafBit) {
             uint32_t first = leaf_first(ref), n = leaf_count(ref);
             if (COUNT) cnt.tris += n;
-            float bt = inf;
-            uint32_t bo = kNone, bs = kNone;
             for (uint32_t k = s; k < n; k += LANES) {
                 const TriRec *r = tris + first + k;
                 float4 a = r->a, b = r->b, c = r->c;
                 float t;
                 if (tri_hit(T, a, b, c, t_lo, t)) {
                     uint32_t orig = __float_as_uint(a.w);
-                    if (better(t, orig, bt, bo)) { bt = t; bo = orig; bs = first + k; }
+                    if (better(t, orig, h.t, h.orig)) { h.t = t; h.orig = orig; h.slot = first + k; }
                 }
             }
-            // lexicographic (t, orig) minimum over the beam's lanes
-            {
-                float ot = __uint_as_float(quad_xor1(__float_as_uint(bt)));
-                uint32_t oo = quad_xor1(bo), os = quad_xor1(bs);
-                if (better(ot, oo, bt, bo)) { bt = ot; bo = oo; bs = os; }
-                if (LANES == 4) {
-                    ot = __uint_as_float(quad_xor2(__float_as_uint(bt)));
-                    oo = quad_xor2(bo);
-                    os = quad_xor2(bs);
-                    if (better(ot, oo, bt, bo)) { bt = ot; bo = oo; bs = os; }
-                }
-            }
-            if (better(bt, bo, h.t, h.orig)) { h.t = bt; h.orig = bo; h.slot = bs; }
+            best_t = group_min_t<LANES>(h.t);
         } else {
             if (COUNT) cnt.nodes += 1;
-            float k0, k1, k2, k3;
-            uint32_t c0, c1, c2, c3;
             if (LANES == 4) {
                 const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 2 * s;
                 float4 a = np[0], b = np[1];
-                float key = slab(B, a, b, t_lo, box_limit(h.t));
-                uint32_t cref = __float_as_uint(a.w);
-                k0 = quad_bcast<0>(key); k1 = quad_bcast<1>(key); k2 = quad_bcast<2>(key); k3 = quad_bcast<3>(key);
-                c0 = quad_bcast<0>(cref); c1 = quad_bcast<1>(cref); c2 = quad_bcast<2>(cref); c3 = quad_bcast<3>(cref);
+                const float key = slab(B, a, b, t_lo, box_limit(best_t));
+                const uint32_t cref = __float_as_uint(a.w);
+                const uint32_t kk = (__float_as_uint(key) & ~3u) | s;
+                const uint32_t rank = (uint32_t)(quad_xor1(kk) < kk) + (uint32_t)(quad_xor2(kk) < kk) +
+                                      (uint32_t)(quad_xor3(kk) < kk);
+                // children hit by the beam: the finite keys of its quad
+                const uint64_t fin = __ballot(kk < 0x7F800000u);
+                const uint32_t nfin = (uint32_t)__popc((uint32_t)(fin >> (threadIdx.x & 60u)) & 0xFu);
+                if (nfin != 0) {
+                    uint32_t nxt = rank == 0 ? cref : 0u;
+                    nxt |= quad_xor1(nxt);
+                    nxt |= quad_xor2(nxt);
+                    const int nh = (int)nfin - 1;
+                    if (sp + nh <= cap) {
+                        if (rank >= 1 && (int)rank <= nh) stk[(sp + nh - (int)rank) * NSLOT] = cref;
+                        sp += nh;
+                    } else {
+                        overflow = true;
+                    }
+                    ref = nxt;
+                    continue;
+                }
             } else {
+                float k0, k1, k2, k3;
+                uint32_t c0, c1, c2, c3;
                 const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 4 * s;
                 float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3];
-                float lim = box_limit(h.t);
+                float lim = box_limit(best_t);
                 float ka = slab(B, a0, b0, t_lo, lim), kb = slab(B, a1, b1, t_lo, lim);
                 uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
                 float oa = __uint_as_float(quad_xor1(__float_as_uint(ka)));
@@ -301,21 +331,9 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                 k1 = lo ? kb : ob; c1 = lo ? cb : ocb;
                 k2 = lo ? oa : ka; c2 = lo ? oca : ca;
                 k3 = lo ? ob : kb; c3 = lo ? ocb : cb;
-            }
-            sort4(k0, c0, k1, c1, k2, c2, k3, c3);
-            if (k0 != inf) {
-                if (LANES == 4) {
-                    // the h further children hit go on the stack farthest first: lane s = 1..3 of the
-                    // quad writes c_s to entry sp + h - s, one store per lane
-                    const int nh = (k1 != inf) + (k2 != inf) + (k3 != inf);
-                    if (sp + nh <= cap) {
-                        if (s >= 1 && (int)s <= nh) stk[(sp + nh - (int)s) * NSLOT] = (s == 1) ? c1 : (s == 2) ? c2 : c3;
-                        sp += nh;
-                    } else {
-                        overflow = true;
-                    }
-                } else {
-                    // pair: lane s writes c_(s+1) to entry sp + h - (s + 1); lane 1 also writes c3 when h = 3
+                sort4(k0, c0, k1, c1, k2, c2, k3, c3);
+                if (k0 != inf) {
+                    // lane s writes c_(s+1) to entry sp + h - (s + 1); lane 1 also writes c3 when h = 3
                     const int nh = (k1 != inf) + (k2 != inf) + (k3 != inf);
                     if (sp + nh <= cap) {
                         if ((int)s + 1 <= nh) stk[(sp + nh - 1 - (int)s) * NSLOT] = (s == 0) ? c1 : c2;
@@ -324,13 +342,25 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                     } else {
                         overflow = true;
                     }
+                    ref = c0;
+                    continue;
                 }
-                ref = c0;
-                continue;
             }
         }
         if (sp == 0) break;
         ref = stk[(--sp) * NSLOT];
+    }
+    // lexicographic (t, original index) minimum over the beam's lanes
+    {
+        float ot = __uint_as_float(quad_xor1(__float_as_uint(h.t)));
+        uint32_t oo = quad_xor1(h.orig), os = quad_xor1(h.slot);
+        if (better(ot, oo, h.t, h.orig)) { h.t = ot; h.orig = oo; h.slot = os; }
+        if (LANES == 4) {
+            ot = __uint_as_float(quad_xor2(__float_as_uint(h.t)));
+            oo = quad_xor2(h.orig);
+            os = quad_xor2(h.slot);
+            if (better(ot, oo, h.t, h.orig)) { h.t = ot; h.orig = oo; h.slot = os; }
+        }
     }
     return h;
 }
