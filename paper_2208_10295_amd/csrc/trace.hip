@@ -559,21 +559,6 @@ __device__ inline uint32_t logical_block(int xcd_remap) {
 // ---------------------------------------------------------------------------
 // Kernel 1: one scan, lane per ray
 // ---------------------------------------------------------------------------
-// The beam of padded ray r: channel j, azimuth i, scan counter and pose.  A
-// scan uses the instance pose (with the calibration delta); a sweep maps the
-// launch column to (azimuth, scan) and reads the column's pose.
-template <bool SWEEP>
-__device__ inline Ray beam_ray(const InstanceDev &in, const Overrides &ov, uint32_t j, uint32_t k, uint32_t &i,
-                               uint32_t &scan) {
-    if (SWEEP) {
-        i = column_azimuth(in, k, scan);
-        return make_ray(in, column_pose(in, nullptr, k), j, i);
-    }
-    i = k;
-    scan = in.scan;
-    return make_ray(in, make_pose(in, ov.pose_delta), j, i);
-}
-
 // The pose of a scan is the same for every beam: thread 0 of the block builds
 // it (make_pose, FP64) into LDS once, instead of every lane.  Must be reached
 // by all threads of the block (it holds a barrier).
@@ -951,9 +936,13 @@ __global__ __launch_bounds__(BLOCK) void bruteforce_kernel(SceneDev S, InstanceD
 
 // ---------------------------------------------------------------------------
 // Kernel 3: batched persistent form.  Every wavefront pops packets of
-// `packet` padded rays from a device counter until the queue is empty; a
-// packet may span instances, each lane finds its instance by binary search
-// over the instances' first padded ray.
+// `packet` padded rays from a device counter until the queue is empty.  A
+// packet is walked in groups of 64 padded rays; an instance's padded rays are
+// a whole number of 64-ray tiles, so a group lies in one instance: the
+// instance (binary search over the instances' first padded ray) and its pose
+// are found once per group.  The group's rays are traversed 64 / LANES at a
+// time; the hits go through LDS to an epilogue in which every lane of the
+// wavefront shades and writes one beam.
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t find_instance(const InstanceDev *__restrict__ insts, uint32_t n_inst, uint64_t r) {
     uint32_t lo = 0, hi = n_inst;
@@ -964,6 +953,14 @@ __device__ inline uint32_t find_instance(const InstanceDev *__restrict__ insts, 
     return lo;
 }
 
+// LDS exchange between the lanes of one wavefront (waves of a block run
+// different numbers of packets, so no block barrier can be used here)
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int STACK, int BLOCK, int LANES>
 __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts,
                                                             uint32_t n_inst, MaterialsDev M, Outputs out,
@@ -972,7 +969,9 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
     constexpr int NSLOT = BLOCK / LANES;
     constexpr uint32_t RAYS_PER_WAVE = 64u / LANES;
     __shared__ uint32_t stk[STACK * NSLOT];
-    const uint32_t lane = threadIdx.x & 63u;
+    // per wavefront, per ray of the current 64-ray group: record slot, triangle index, t bits
+    __shared__ uint32_t hand[BLOCK / 64][3][64];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t slot = threadIdx.x / LANES;
     const uint32_t sub_lane = lane / LANES;
     const uint32_t s = threadIdx.x % LANES;
@@ -985,23 +984,41 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
         if (lane == 0) pk = atomicAdd(queue, 1u);
         pk = __shfl(pk, 0, 64);
         if ((uint64_t)pk >= n_packets) break;
-        for (uint32_t sub = 0; sub < packet; sub += RAYS_PER_WAVE) {
-            uint64_t r = (uint64_t)pk * packet + sub + sub_lane;
-            if ((uint64_t)pk * packet + sub >= n_padded_total) break;   // uniform over the wave
-            const InstanceDev &in = insts[find_instance(insts, n_inst, r)];
-            uint32_t j, k, i, scan;
-            if (!ray_coords(r - in.ray_base, in, tile_az_log2, j, k)) continue;
-            Ray ray = beam_ray<false>(in, ov, j, k, i, scan);   // batch instances are whole scans
-            Hit h;
-            if constexpr (LANES == 1)
-                h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace,
-                                                  stk + slot, overflow, cnt);
-            else
-                h = traverse_multi<LANES, STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
-                                                               in.t_trace, stk + slot, s, overflow, cnt);
-            if (s != 0) continue;
-            uint32_t beam = j * in.n_az + i;
-            shade_and_write(in, M, ov, out, in.out_base + beam, beam, scan, ray, S.tris, h);
+        for (uint32_t g = 0; g < packet; g += 64u) {
+            const uint64_t base = (uint64_t)pk * packet + g;      // uniform over the wave
+            if (base >= n_padded_total) break;
+            const uint32_t ii = __builtin_amdgcn_readfirstlane(find_instance(insts, n_inst, base));
+            const InstanceDev &in = insts[ii];
+            const Pose64 P = make_pose(in, nullptr);
+            const uint64_t r0 = base - in.ray_base;
+            for (uint32_t sub = 0; sub < 64u; sub += RAYS_PER_WAVE) {
+                uint32_t j, k;
+                Hit h{kNone, kNone, 0.0f, kNone};
+                if (ray_coords(r0 + sub + sub_lane, in, tile_az_log2, j, k)) {
+                    const Ray ray = make_ray(in, P, j, k);
+                    if constexpr (LANES == 1)
+                        h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
+                                                          in.t_trace, stk + slot, overflow, cnt);
+                    else
+                        h = traverse_multi<LANES, STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray,
+                                                                       in.t_min, in.t_trace, stk + slot, s, overflow,
+                                                                       cnt);
+                }
+                if (s == 0) {
+                    hand[wave][0][sub + sub_lane] = h.slot;
+                    hand[wave][1][sub + sub_lane] = h.orig;
+                    hand[wave][2][sub + sub_lane] = __float_as_uint(h.t);
+                }
+            }
+            wave_lds_sync();
+            uint32_t j, k;
+            if (ray_coords(r0 + lane, in, tile_az_log2, j, k)) {
+                const Ray ray = make_ray(in, P, j, k);
+                const Hit h{hand[wave][0][lane], hand[wave][1][lane], __uint_as_float(hand[wave][2][lane]), kNone};
+                const uint32_t beam = j * in.n_az + k;
+                shade_and_write(in, M, ov, out, in.out_base + beam, beam, in.scan, ray, S.tris, h);
+            }
+            wave_lds_sync();     // the hand-off slots are rewritten by the next group
         }
     }
     if (overflow) atomicOr(err, 1u);
@@ -1149,7 +1166,7 @@ int batch_blocks_per_cu(const TraceOpts &t) {
     int block = lanes == 4 ? kQuadBlock : lanes == 2 ? kPairBlock : kBlock;
     int slots = block / lanes;
     int waves = block / 64;
-    int by_lds = (160 * 1024) / (st * slots * 4);
+    int by_lds = (160 * 1024) / (st * slots * 4 + waves * 3 * 64 * 4);   // stacks + epilogue hand-off
     int by_waves = 32 / waves;          // at most 8 waves per SIMD
     int b = by_lds < by_waves ? by_lds : by_waves;
     return b < 1 ? 1 : b;
