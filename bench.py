@@ -67,6 +67,27 @@ def read_traffic():
         return None
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "trace_scan_config2_counters.txt")
+# wavefront VALU instructions per second one MI355X can issue: 256 CUs x 4 SIMDs x 2.4 GHz, one 64-lane
+# FP32 instruction per SIMD every 4 cycles (16 lanes per cycle)
+VALU_PEAK_GINST_S = 256 * 4 * 2.4 / 4
+
+
+def read_counters():
+    """Per-launch instruction and L2 counters from the committed PMC summary, if taken on the current source."""
+    try:
+        kv = {}
+        for line in open(COUNTERS_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return {k: float(v) for k, v in kv.items() if k.startswith(("SQ_", "TCC_"))}
+    except (OSError, ValueError):
+        return None
+
+
 def timed_launches(fn, n, torch):
     """Run fn() n times with HIP events around each call on the current stream; returns (wall_s, [ms])."""
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
@@ -206,6 +227,13 @@ def main():
         traffic = read_traffic()
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+        cnt = read_counters()
+        if cnt:
+            # the second bound: vector-instruction issue (the traversal's data stays in L2 and MALL)
+            ginst = cnt["SQ_INSTS_VALU"] / (kernel_ms * 1e-3) / 1e9
+            result["valu"] = {"insts_per_launch": cnt["SQ_INSTS_VALU"], "achieved_ginst_s": ginst,
+                              "peak_ginst_s": VALU_PEAK_GINST_S, "frac": ginst / VALU_PEAK_GINST_S,
+                              "l2_hit_rate": cnt["TCC_HIT_sum"] / cnt["TCC_REQ_sum"]}
         result["traversal"] = {"node_visits_per_ray": n_nodes / n, "tri_tests_per_ray": n_tris / n,
                                "alg_bytes_per_ray": alg_bytes / n, "alg_bytes_per_launch": alg_bytes,
                                "kernel_source_sha256_16": kernel_source_hash()}

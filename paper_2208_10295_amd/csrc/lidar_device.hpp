@@ -344,16 +344,7 @@ __device__ inline RayBox prep_box_test(const Ray &r) {
 // ---------------------------------------------------------------------------
 // Quad (4-lane) exchanges through DPP quad_perm
 // ---------------------------------------------------------------------------
-template <int K>
-__device__ inline uint32_t quad_bcast(uint32_t v) {
-    constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, true);
-}
-template <int K>
-__device__ inline float quad_bcast(float v) {
-    return __uint_as_float(quad_bcast<K>(__float_as_uint(v)));
-}
-// value of lane (lane ^ 1) / (lane ^ 2) within the quad
+// value of lane (lane ^ 1) / (lane ^ 2) / (lane ^ 3) within the quad
 __device__ inline uint32_t quad_xor1(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
 }

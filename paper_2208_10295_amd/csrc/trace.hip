@@ -259,6 +259,38 @@ __device__ inline float group_min_t(float t) {
     return __uint_as_float(u);
 }
 
+// One quad node step (see above): returns false if the beam hits none of the
+// node's children; otherwise pushes the further children hit, sets `next` to
+// the nearest one and returns true.
+template <int NSLOT>
+__device__ inline bool quad_node_step(const Node4 *__restrict__ node, const RayBox &B, float t_lo, float lim,
+                                      uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap, bool &overflow,
+                                      uint32_t &next) {
+    const float4 *np = reinterpret_cast<const float4 *>(node) + 2 * s;
+    float4 a = np[0], b = np[1];
+    const float key = slab(B, a, b, t_lo, lim);
+    const uint32_t cref = __float_as_uint(a.w);
+    const uint32_t kk = (__float_as_uint(key) & ~3u) | s;
+    const uint32_t rank = (uint32_t)(quad_xor1(kk) < kk) + (uint32_t)(quad_xor2(kk) < kk) +
+                          (uint32_t)(quad_xor3(kk) < kk);
+    // children hit by the beam: the finite keys of its quad
+    const uint64_t fin = __ballot(kk < 0x7F800000u);
+    const uint32_t nfin = (uint32_t)__popc((uint32_t)(fin >> (threadIdx.x & 60u)) & 0xFu);
+    if (nfin == 0) return false;
+    uint32_t nxt = rank == 0 ? cref : 0u;
+    nxt |= quad_xor1(nxt);
+    nxt |= quad_xor2(nxt);
+    const int nh = (int)nfin - 1;
+    if (sp + nh <= cap) {
+        if (rank >= 1 && (int)rank <= nh) stk[(sp + nh - (int)rank) * NSLOT] = cref;
+        sp += nh;
+    } else {
+        overflow = true;
+    }
+    next = nxt;
+    return true;
+}
+
 template <int LANES, int STACK, int NSLOT, bool COUNT>
 __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
                                      uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
@@ -291,27 +323,8 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
         } else {
             if (COUNT) cnt.nodes += 1;
             if (LANES == 4) {
-                const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 2 * s;
-                float4 a = np[0], b = np[1];
-                const float key = slab(B, a, b, t_lo, box_limit(best_t));
-                const uint32_t cref = __float_as_uint(a.w);
-                const uint32_t kk = (__float_as_uint(key) & ~3u) | s;
-                const uint32_t rank = (uint32_t)(quad_xor1(kk) < kk) + (uint32_t)(quad_xor2(kk) < kk) +
-                                      (uint32_t)(quad_xor3(kk) < kk);
-                // children hit by the beam: the finite keys of its quad
-                const uint64_t fin = __ballot(kk < 0x7F800000u);
-                const uint32_t nfin = (uint32_t)__popc((uint32_t)(fin >> (threadIdx.x & 60u)) & 0xFu);
-                if (nfin != 0) {
-                    uint32_t nxt = rank == 0 ? cref : 0u;
-                    nxt |= quad_xor1(nxt);
-                    nxt |= quad_xor2(nxt);
-                    const int nh = (int)nfin - 1;
-                    if (sp + nh <= cap) {
-                        if (rank >= 1 && (int)rank <= nh) stk[(sp + nh - (int)rank) * NSLOT] = cref;
-                        sp += nh;
-                    } else {
-                        overflow = true;
-                    }
+                uint32_t nxt;
+                if (quad_node_step<NSLOT>(nodes + ref, B, t_lo, box_limit(best_t), s, stk, sp, cap, overflow, nxt)) {
                     ref = nxt;
                     continue;
                 }
@@ -403,6 +416,12 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
                     if (better(hb.t, g, h.t, h.orig)) { h.t = hb.t; h.orig = g; h.slot = hb.slot; h.actor = a; }
                 }
             }
+        } else if constexpr (LANES == 4) {
+            uint32_t nxt;
+            if (quad_node_step<NSLOT>(A.nodes + ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, overflow, nxt)) {
+                ref = nxt;
+                continue;
+            }
         } else {
             const float lim = box_limit(h.t);
             float k0, k1, k2, k3;
@@ -413,12 +432,6 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
                 k0 = slab(B, a0, b0, t_lo, lim); k1 = slab(B, a1, b1, t_lo, lim);
                 k2 = slab(B, a2, b2, t_lo, lim); k3 = slab(B, a3, b3, t_lo, lim);
                 c0 = __float_as_uint(a0.w); c1 = __float_as_uint(a1.w); c2 = __float_as_uint(a2.w); c3 = __float_as_uint(a3.w);
-            } else if constexpr (LANES == 4) {
-                float4 a = np[2 * s], b = np[2 * s + 1];
-                float key = slab(B, a, b, t_lo, lim);
-                uint32_t cref = __float_as_uint(a.w);
-                k0 = quad_bcast<0>(key); k1 = quad_bcast<1>(key); k2 = quad_bcast<2>(key); k3 = quad_bcast<3>(key);
-                c0 = quad_bcast<0>(cref); c1 = quad_bcast<1>(cref); c2 = quad_bcast<2>(cref); c3 = quad_bcast<3>(cref);
             } else {
                 float4 a0 = np[4 * s], b0 = np[4 * s + 1], a1 = np[4 * s + 2], b1 = np[4 * s + 3];
                 float ka = slab(B, a0, b0, t_lo, lim), kb = slab(B, a1, b1, t_lo, lim);
