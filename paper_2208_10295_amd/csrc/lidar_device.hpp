@@ -342,6 +342,27 @@ __device__ inline RayBox prep_box_test(const Ray &r) {
 }
 
 // ---------------------------------------------------------------------------
+// Buffer fetches of nodes and triangle records: a buffer resource (base in
+// SGPRs) plus a 32-bit byte offset per lane, instead of a 64-bit address per
+// lane.  Raw buffer, 32-bit data format; the range is not used for clamping
+// (every offset the traversal forms is inside the array).
+// ---------------------------------------------------------------------------
+typedef int lidar_v4i __attribute__((ext_vector_type(4)));
+typedef int lidar_v3i __attribute__((ext_vector_type(3)));
+
+__device__ inline __amdgpu_buffer_rsrc_t raw_buffer(const void *base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ inline float4 buf_load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const lidar_v4i v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), __int_as_float(v.w));
+}
+__device__ inline float4 buf_load3(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const lidar_v3i v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0);
+    return make_float4(__int_as_float(v.x), __int_as_float(v.y), __int_as_float(v.z), 0.0f);
+}
+
+// ---------------------------------------------------------------------------
 // Quad (4-lane) exchanges through DPP quad_perm
 // ---------------------------------------------------------------------------
 // value of lane (lane ^ 1) / (lane ^ 2) / (lane ^ 3) within the quad

@@ -263,11 +263,11 @@ __device__ inline float group_min_t(float t) {
 // node's children; otherwise pushes the further children hit, sets `next` to
 // the nearest one and returns true.
 template <int NSLOT>
-__device__ inline bool quad_node_step(const Node4 *__restrict__ node, const RayBox &B, float t_lo, float lim,
-                                      uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap, bool &overflow,
-                                      uint32_t &next) {
-    const float4 *np = reinterpret_cast<const float4 *>(node) + 2 * s;
-    float4 a = np[0], b = np[1];
+__device__ inline bool quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
+                                      float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
+                                      bool &overflow, uint32_t &next) {
+    const uint32_t off = ref * (uint32_t)sizeof(Node4) + s * 32u;   // child slot s of node ref
+    const float4 a = buf_load4(nodes, off), b = buf_load4(nodes, off + 16u);
     const float key = slab(B, a, b, t_lo, lim);
     const uint32_t cref = __float_as_uint(a.w);
     const uint32_t kk = (__float_as_uint(key) & ~3u) | s;
@@ -297,6 +297,7 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                                      uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt,
                                      int cap = STACK) {
     static_assert(LANES == 2 || LANES == 4, "2 or 4 lanes per beam");
+    const __amdgpu_buffer_rsrc_t nbuf = raw_buffer(nodes), tbuf = raw_buffer(tris);
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
     const float inf = __builtin_inff();
@@ -311,8 +312,8 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
             uint32_t first = leaf_first(ref), n = leaf_count(ref);
             if (COUNT) cnt.tris += n;
             for (uint32_t k = s; k < n; k += LANES) {
-                const TriRec *r = tris + first + k;
-                float4 a = r->a, b = r->b, c = r->c;
+                const uint32_t off = (first + k) * (uint32_t)sizeof(TriRec);
+                const float4 a = buf_load4(tbuf, off), b = buf_load3(tbuf, off + 16u), c = buf_load3(tbuf, off + 32u);
                 float t;
                 if (tri_hit(T, a, b, c, t_lo, t)) {
                     uint32_t orig = __float_as_uint(a.w);
@@ -324,15 +325,16 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
             if (COUNT) cnt.nodes += 1;
             if (LANES == 4) {
                 uint32_t nxt;
-                if (quad_node_step<NSLOT>(nodes + ref, B, t_lo, box_limit(best_t), s, stk, sp, cap, overflow, nxt)) {
+                if (quad_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap, overflow, nxt)) {
                     ref = nxt;
                     continue;
                 }
             } else {
                 float k0, k1, k2, k3;
                 uint32_t c0, c1, c2, c3;
-                const float4 *np = reinterpret_cast<const float4 *>(nodes + ref) + 4 * s;
-                float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3];
+                const uint32_t off = ref * (uint32_t)sizeof(Node4) + s * 64u;   // child slots 2s, 2s + 1
+                const float4 a0 = buf_load4(nbuf, off), b0 = buf_load4(nbuf, off + 16u);
+                const float4 a1 = buf_load4(nbuf, off + 32u), b1 = buf_load4(nbuf, off + 48u);
                 float lim = box_limit(best_t);
                 float ka = slab(B, a0, b0, t_lo, lim), kb = slab(B, a1, b1, t_lo, lim);
                 uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
@@ -418,7 +420,8 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
             }
         } else if constexpr (LANES == 4) {
             uint32_t nxt;
-            if (quad_node_step<NSLOT>(A.nodes + ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, overflow, nxt)) {
+            if (quad_node_step<NSLOT>(raw_buffer(A.nodes), ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, overflow,
+                                      nxt)) {
                 ref = nxt;
                 continue;
             }

@@ -208,3 +208,57 @@ def test_wavelength_clamp_warning_and_values(L):
     o = O.simulate(scene, s2, pose, seed=5)
     assert o["wavelength_clamped"]
     compare(g, o)
+
+
+def test_degenerate_triangles_and_axis_aligned_beams(L):
+    """Zero-area triangles (a repeated vertex, collinear vertices, all three equal) are never hit and do not
+    change any other beam; beams exactly along the axes (elevation 0, azimuths 0/90/180/270 deg: two zero
+    direction components) hit axis-aligned walls, including a wall edge, as the oracle and the brute force
+    say."""
+    def box(x0, y0, z0, x1, y1, z1):
+        v = [[x0, y0, z0], [x1, y0, z0], [x1, y1, z0], [x0, y1, z0], [x0, y0, z1], [x1, y0, z1], [x1, y1, z1],
+             [x0, y1, z1]]
+        t = [[0, 1, 2], [0, 2, 3], [4, 6, 5], [4, 7, 6], [0, 4, 5], [0, 5, 1], [1, 5, 6], [1, 6, 2], [2, 6, 7],
+             [2, 7, 3], [3, 7, 4], [3, 4, 0]]
+        return np.array(v, np.float64), np.array(t)
+    parts = [box(-60, -60, -3, 60, 60, -2), box(8, -2, -1, 9, 2, 1), box(-2, 12, -1, 2, 13, 1),
+             box(-15, 0, -1, -14, 2, 1), box(-1, -21, -1, 1, -20, 1)]   # the -x wall's edge is at y = 0
+    good_v, good_t, nv = [], [], 0
+    for v, t in parts:
+        good_v.append(v)
+        good_t.append(t + nv)
+        nv += len(v)
+    gv = np.concatenate(good_v)
+    gt = np.concatenate(good_t)
+    # degenerate triangles, placed where the axis beams pass
+    dv = np.array([[5, -1, 0], [5, 1, 0], [5, 1, 0],            # repeated vertex
+                   [0, 6, -1], [0, 6, 0], [0, 6, 1],            # collinear along z, on the +y beam
+                   [-7, 0, 0], [-7, 0, 0], [-7, 0, 0]], np.float64)   # a point on the -x beam
+    dt = np.arange(9).reshape(3, 3) + len(gv)
+    def scene_of(v, t):
+        nt = len(t)
+        return S.Scene(v.astype(np.float32), t.astype(np.uint32), np.zeros(nt, np.uint16),
+                       np.arange(1, nt + 1, dtype=np.uint32), np.full((1, 61), 0.7, np.float32),
+                       np.array([0.0], np.float32), np.array([1.0], np.float32))
+    with_deg = scene_of(np.concatenate([gv, dv]), np.concatenate([gt, dt]))
+    without = scene_of(gv, gt)
+    sensor = S.Sensor(np.array([-30.0, -5.0, 0.0, 5.0]), 8, d_max=50.0, noise_on=False)
+    pose = S.Pose(np.zeros(3, np.float32), np.array([1, 0, 0, 0], np.float32))
+    ca = _ctx(L, with_deg, sensor, pose)
+    a = to_np(ca.simulate(0, 0, debug=True))
+    b = to_np(ca.simulate(0, 0, debug=True, bruteforce=True))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    cw = _ctx(L, without, sensor, pose)
+    w = to_np(cw.simulate(0, 0, debug=True))
+    for k in a:
+        assert np.array_equal(a[k], w[k]), k            # the degenerate triangles change nothing
+    assert not np.isin(a["tri"], np.arange(len(gt), len(gt) + 3)).any()     # no degenerate triangle is hit
+    o = O.simulate(with_deg, sensor, pose)
+    _report("degenerate + axis beams", compare(a, o))
+    # elevation-0 beams at azimuths 0, 90, 180, 270 deg (every second of 8 steps): walls at x = 8 (through
+    # the diagonal shared by the face's two triangles: a tie, the smaller index wins), y = 12, x = -14 (on
+    # the wall's lower edge, y = 0) and y = -20
+    j0 = 2 * 8
+    for i, t in ((0, 8.0), (2, 12.0), (4, 14.0), (6, 20.0)):
+        assert a["valid"][j0 + i] == 1 and abs(a["range"][j0 + i] - t) < 1e-5 * t, (i, a["range"][j0 + i])
