@@ -240,8 +240,8 @@ __device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__
 // descended into (its reference is OR-reduced over the quad), and the lane of
 // the child of rank r >= 1 that was hit pushes its own reference to stack entry
 // sp + h - r (h further children hit), so the nearest of them is popped first.
-// Pair (LANES = 2): each lane tests two children, the pair swaps keys through
-// quad_perm and both run the same sorting network.
+// Pair (LANES = 2): each lane tests two children and ranks its two keys the
+// same way against the other three (pair_node_step).
 //
 // Leaves: each lane keeps the lexicographic (t, original index) minimum of the
 // triangles it tested; after a leaf the lanes only agree on the smallest t (the
@@ -291,6 +291,41 @@ __device__ inline bool quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref
     return true;
 }
 
+// One pair node step: lane s (0 or 1) of the beam's pair tests children 2s and
+// 2s + 1 and ranks its two keys against the other three (its own other key
+// and the partner's two, through one quad_perm swap each); otherwise as the
+// quad step.
+template <int NSLOT>
+__device__ inline bool pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
+                                      float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
+                                      bool &overflow, uint32_t &next) {
+    const uint32_t off = ref * (uint32_t)sizeof(Node4) + s * 64u;   // child slots 2s, 2s + 1
+    const float4 a0 = buf_load4(nodes, off), b0 = buf_load4(nodes, off + 16u);
+    const float4 a1 = buf_load4(nodes, off + 32u), b1 = buf_load4(nodes, off + 48u);
+    const uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
+    const uint32_t ka = (__float_as_uint(slab(B, a0, b0, t_lo, lim)) & ~3u) | (2u * s);
+    const uint32_t kb = (__float_as_uint(slab(B, a1, b1, t_lo, lim)) & ~3u) | (2u * s + 1u);
+    const uint32_t pa = quad_xor1(ka), pb = quad_xor1(kb);
+    const uint32_t ra = (uint32_t)(kb < ka) + (uint32_t)(pa < ka) + (uint32_t)(pb < ka);
+    const uint32_t rb = (uint32_t)(ka < kb) + (uint32_t)(pa < kb) + (uint32_t)(pb < kb);
+    constexpr uint32_t kInfKey = 0x7F800000u;
+    const uint32_t nfin = (uint32_t)(ka < kInfKey) + (uint32_t)(kb < kInfKey) + (uint32_t)(pa < kInfKey) +
+                          (uint32_t)(pb < kInfKey);
+    if (nfin == 0) return false;
+    uint32_t nxt = (ra == 0 ? ca : 0u) | (rb == 0 ? cb : 0u);
+    nxt |= quad_xor1(nxt);
+    const int nh = (int)nfin - 1;
+    if (sp + nh <= cap) {
+        if (ra >= 1 && (int)ra <= nh) stk[(sp + nh - (int)ra) * NSLOT] = ca;
+        if (rb >= 1 && (int)rb <= nh) stk[(sp + nh - (int)rb) * NSLOT] = cb;
+        sp += nh;
+    } else {
+        overflow = true;
+    }
+    next = nxt;
+    return true;
+}
+
 template <int LANES, int STACK, int NSLOT, bool COUNT>
 __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
                                      uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
@@ -300,7 +335,6 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
     const __amdgpu_buffer_rsrc_t nbuf = raw_buffer(nodes), tbuf = raw_buffer(tris);
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
-    const float inf = __builtin_inff();
     Hit h{kNone, kNone, t_hi, kNone};   // this lane's best
     float best_t = t_hi;                // the beam's best distance (minimum over its lanes)
     uint32_t ref = root;
@@ -330,34 +364,9 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                     continue;
                 }
             } else {
-                float k0, k1, k2, k3;
-                uint32_t c0, c1, c2, c3;
-                const uint32_t off = ref * (uint32_t)sizeof(Node4) + s * 64u;   // child slots 2s, 2s + 1
-                const float4 a0 = buf_load4(nbuf, off), b0 = buf_load4(nbuf, off + 16u);
-                const float4 a1 = buf_load4(nbuf, off + 32u), b1 = buf_load4(nbuf, off + 48u);
-                float lim = box_limit(best_t);
-                float ka = slab(B, a0, b0, t_lo, lim), kb = slab(B, a1, b1, t_lo, lim);
-                uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
-                float oa = __uint_as_float(quad_xor1(__float_as_uint(ka)));
-                float ob = __uint_as_float(quad_xor1(__float_as_uint(kb)));
-                uint32_t oca = quad_xor1(ca), ocb = quad_xor1(cb);
-                const bool lo = (s == 0);   // lane 0 holds children 0, 1; lane 1 children 2, 3
-                k0 = lo ? ka : oa; c0 = lo ? ca : oca;
-                k1 = lo ? kb : ob; c1 = lo ? cb : ocb;
-                k2 = lo ? oa : ka; c2 = lo ? oca : ca;
-                k3 = lo ? ob : kb; c3 = lo ? ocb : cb;
-                sort4(k0, c0, k1, c1, k2, c2, k3, c3);
-                if (k0 != inf) {
-                    // lane s writes c_(s+1) to entry sp + h - (s + 1); lane 1 also writes c3 when h = 3
-                    const int nh = (k1 != inf) + (k2 != inf) + (k3 != inf);
-                    if (sp + nh <= cap) {
-                        if ((int)s + 1 <= nh) stk[(sp + nh - 1 - (int)s) * NSLOT] = (s == 0) ? c1 : c2;
-                        if (nh == 3 && s == 1) stk[sp * NSLOT] = c3;
-                        sp += nh;
-                    } else {
-                        overflow = true;
-                    }
-                    ref = c0;
+                uint32_t nxt;
+                if (pair_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap, overflow, nxt)) {
+                    ref = nxt;
                     continue;
                 }
             }
@@ -425,35 +434,26 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
                 ref = nxt;
                 continue;
             }
+        } else if constexpr (LANES == 2) {
+            uint32_t nxt;
+            if (pair_node_step<NSLOT>(raw_buffer(A.nodes), ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, overflow,
+                                      nxt)) {
+                ref = nxt;
+                continue;
+            }
         } else {
             const float lim = box_limit(h.t);
-            float k0, k1, k2, k3;
-            uint32_t c0, c1, c2, c3;
             const float4 *np = reinterpret_cast<const float4 *>(A.nodes + ref);
-            if constexpr (LANES == 1) {
-                float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3], a2 = np[4], b2 = np[5], a3 = np[6], b3 = np[7];
-                k0 = slab(B, a0, b0, t_lo, lim); k1 = slab(B, a1, b1, t_lo, lim);
-                k2 = slab(B, a2, b2, t_lo, lim); k3 = slab(B, a3, b3, t_lo, lim);
-                c0 = __float_as_uint(a0.w); c1 = __float_as_uint(a1.w); c2 = __float_as_uint(a2.w); c3 = __float_as_uint(a3.w);
-            } else {
-                float4 a0 = np[4 * s], b0 = np[4 * s + 1], a1 = np[4 * s + 2], b1 = np[4 * s + 3];
-                float ka = slab(B, a0, b0, t_lo, lim), kb = slab(B, a1, b1, t_lo, lim);
-                uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
-                float oa = __uint_as_float(quad_xor1(__float_as_uint(ka)));
-                float ob = __uint_as_float(quad_xor1(__float_as_uint(kb)));
-                uint32_t oca = quad_xor1(ca), ocb = quad_xor1(cb);
-                const bool lo = (s == 0);
-                k0 = lo ? ka : oa; c0 = lo ? ca : oca;
-                k1 = lo ? kb : ob; c1 = lo ? cb : ocb;
-                k2 = lo ? oa : ka; c2 = lo ? oca : ca;
-                k3 = lo ? ob : kb; c3 = lo ? ocb : cb;
-            }
+            float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3], a2 = np[4], b2 = np[5], a3 = np[6], b3 = np[7];
+            float k0 = slab(B, a0, b0, t_lo, lim), k1 = slab(B, a1, b1, t_lo, lim);
+            float k2 = slab(B, a2, b2, t_lo, lim), k3 = slab(B, a3, b3, t_lo, lim);
+            uint32_t c0 = __float_as_uint(a0.w), c1 = __float_as_uint(a1.w), c2 = __float_as_uint(a2.w),
+                     c3 = __float_as_uint(a3.w);
             sort4(k0, c0, k1, c1, k2, c2, k3, c3);
             if (k0 != inf) {
-                const bool w = (LANES == 1) || s == 0;
-                if (k3 != inf) { if (sp < STACK) { if (w) stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
-                if (k2 != inf) { if (sp < STACK) { if (w) stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
-                if (k1 != inf) { if (sp < STACK) { if (w) stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
+                if (k3 != inf) { if (sp < STACK) { stk[sp * NSLOT] = c3; ++sp; } else overflow = true; }
+                if (k2 != inf) { if (sp < STACK) { stk[sp * NSLOT] = c2; ++sp; } else overflow = true; }
+                if (k1 != inf) { if (sp < STACK) { stk[sp * NSLOT] = c1; ++sp; } else overflow = true; }
                 ref = c0;
                 continue;
             }
