@@ -275,6 +275,7 @@ lidar_status no_actors(lidar_ctx *ctx, const char *what) {
 int stack_for_depth(uint32_t depth) {
     int need = 3 * (int)(depth > 0 ? depth - 1 : 0) + 1;
     if (need <= 32) return 32;
+    if (need <= 48) return 48;
     if (need <= 64) return 64;
     if (need <= 96) return 96;
     return -1;
@@ -794,6 +795,7 @@ static void host_rotation(const float q[4], double R[9]) {
 
 static int stack_for_need(int need) {
     if (need <= 32) return 32;
+    if (need <= 48) return 48;
     if (need <= 64) return 64;
     if (need <= 96) return 96;
     return -1;

@@ -1090,6 +1090,7 @@ void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev 
                        const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err, uint32_t *n_nodes,
                        uint32_t *n_tris, const ActorsDev *actors, hipStream_t s) {
     if (t.stack <= 32) launch_scan_s<32>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
+    else if (t.stack <= 48) launch_scan_s<48>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
     else if (t.stack <= 64) launch_scan_s<64>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
     else launch_scan_s<96>(t, S, in, M, ov, out, n_padded, err, n_nodes, n_tris, actors, s);
 }
@@ -1120,10 +1121,12 @@ void launch_trace_subrays(const TraceOpts &t, const SceneDev &S, const InstanceD
     const ActorsDev none{};
     if (actors) {
         if (t.stack <= 32) launch_subrays_t<32, true>(t, S, in, M, pat, sub, n_padded, err, *actors, s);
+        else if (t.stack <= 48) launch_subrays_t<48, true>(t, S, in, M, pat, sub, n_padded, err, *actors, s);
         else if (t.stack <= 64) launch_subrays_t<64, true>(t, S, in, M, pat, sub, n_padded, err, *actors, s);
         else launch_subrays_t<96, true>(t, S, in, M, pat, sub, n_padded, err, *actors, s);
     } else {
         if (t.stack <= 32) launch_subrays_t<32, false>(t, S, in, M, pat, sub, n_padded, err, none, s);
+        else if (t.stack <= 48) launch_subrays_t<48, false>(t, S, in, M, pat, sub, n_padded, err, none, s);
         else if (t.stack <= 64) launch_subrays_t<64, false>(t, S, in, M, pat, sub, n_padded, err, none, s);
         else launch_subrays_t<96, false>(t, S, in, M, pat, sub, n_padded, err, none, s);
     }
@@ -1171,13 +1174,14 @@ void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev
                         const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
                         uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
     if (t.stack <= 32) launch_batch_s<32>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
+    else if (t.stack <= 48) launch_batch_s<48>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
     else if (t.stack <= 64) launch_batch_s<64>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
     else launch_batch_s<96>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
 }
 
 int batch_blocks_per_cu(const TraceOpts &t) {
     // LDS per block = stack entries x stack slots x 4 bytes; 160 KB per CU on gfx950
-    int st = t.stack <= 32 ? 32 : t.stack <= 64 ? 64 : 96;
+    int st = t.stack <= 32 ? 32 : t.stack <= 48 ? 48 : t.stack <= 64 ? 64 : 96;
     int lanes = t.lanes_per_ray;
     int block = lanes == 4 ? kQuadBlock : lanes == 2 ? kPairBlock : kBlock;
     int slots = block / lanes;
