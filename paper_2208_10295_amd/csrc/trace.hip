@@ -960,6 +960,15 @@ __global__ __launch_bounds__(BLOCK) void bruteforce_kernel(SceneDev S, InstanceD
 // time; the hits go through LDS to an epilogue in which every lane of the
 // wavefront shades and writes one beam.
 // ---------------------------------------------------------------------------
+__device__ inline Pose64 lds_pose(const double *q) {
+    Pose64 P;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) P.R[e] = q[e];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) P.p[e] = q[9 + e];
+    return P;
+}
+
 __device__ inline uint32_t find_instance(const InstanceDev *__restrict__ insts, uint32_t n_inst, uint64_t r) {
     uint32_t lo = 0, hi = n_inst;
     while (hi - lo > 1) {
@@ -978,7 +987,7 @@ __device__ inline void wave_lds_sync() {
 }
 
 template <int STACK, int BLOCK, int LANES>
-__global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts,
+__global__ __launch_bounds__(BLOCK, LANES == 4 ? 8 : LANES == 2 ? 6 : 1) void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts,
                                                             uint32_t n_inst, MaterialsDev M, Outputs out,
                                                             int tile_az_log2, uint64_t n_padded_total,
                                                             uint32_t packet, uint32_t *queue, uint32_t *err) {
@@ -987,6 +996,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
     __shared__ uint32_t stk[STACK * NSLOT];
     // per wavefront, per ray of the current 64-ray group: record slot, triangle index, t bits
     __shared__ uint32_t hand[BLOCK / 64][3][64];
+    __shared__ double gpose[BLOCK / 64][12];    // per wavefront: the group's FP64 pose (R row-major, p)
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t slot = threadIdx.x / LANES;
     const uint32_t sub_lane = lane / LANES;
@@ -1005,13 +1015,22 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
             if (base >= n_padded_total) break;
             const uint32_t ii = __builtin_amdgcn_readfirstlane(find_instance(insts, n_inst, base));
             const InstanceDev &in = insts[ii];
-            const Pose64 P = make_pose(in, nullptr);
+            {
+                const Pose64 P = make_pose(in, nullptr);
+                if (lane == 0) {
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) gpose[wave][e] = P.R[e];
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) gpose[wave][9 + e] = P.p[e];
+                }
+            }
+            wave_lds_sync();
             const uint64_t r0 = base - in.ray_base;
             for (uint32_t sub = 0; sub < 64u; sub += RAYS_PER_WAVE) {
                 uint32_t j, k;
                 Hit h{kNone, kNone, 0.0f, kNone};
                 if (ray_coords(r0 + sub + sub_lane, in, tile_az_log2, j, k)) {
-                    const Ray ray = make_ray(in, P, j, k);
+                    const Ray ray = make_ray(in, lds_pose(gpose[wave]), j, k);
                     if constexpr (LANES == 1)
                         h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
                                                           in.t_trace, stk + slot, overflow, cnt);
@@ -1029,7 +1048,7 @@ __global__ __launch_bounds__(BLOCK) void trace_batch_kernel(SceneDev S, const In
             wave_lds_sync();
             uint32_t j, k;
             if (ray_coords(r0 + lane, in, tile_az_log2, j, k)) {
-                const Ray ray = make_ray(in, P, j, k);
+                const Ray ray = make_ray(in, lds_pose(gpose[wave]), j, k);
                 const Hit h{hand[wave][0][lane], hand[wave][1][lane], __uint_as_float(hand[wave][2][lane]), kNone};
                 const uint32_t beam = j * in.n_az + k;
                 shade_and_write(in, M, ov, out, in.out_base + beam, beam, in.scan, ray, S.tris, h);
@@ -1186,7 +1205,7 @@ int batch_blocks_per_cu(const TraceOpts &t) {
     int block = lanes == 4 ? kQuadBlock : lanes == 2 ? kPairBlock : kBlock;
     int slots = block / lanes;
     int waves = block / 64;
-    int by_lds = (160 * 1024) / (st * slots * 4 + waves * 3 * 64 * 4);   // stacks + epilogue hand-off
+    int by_lds = (160 * 1024) / (st * slots * 4 + waves * (3 * 64 * 4 + 96));   // stacks, hand-off, poses
     int by_waves = 32 / waves;          // at most 8 waves per SIMD
     int b = by_lds < by_waves ? by_lds : by_waves;
     return b < 1 ? 1 : b;
