@@ -65,14 +65,12 @@ __device__ inline float round_up(double x) {
     return ((double)f < x) ? nextafterf(f, kInf) : f;
 }
 
-// world box of each actor: the mesh root box (union of the root's slots) with
-// its 8 corners transformed; also max |coordinate| of all boxes into word[0]
-__global__ __launch_bounds__(256) void actor_boxes_kernel(const ActorDev *__restrict__ actors, uint32_t n,
-                                                          const MeshDev *__restrict__ meshes, float *__restrict__ lohi,
-                                                          uint32_t *word) {
-    uint32_t a = blockIdx.x * 256 + threadIdx.x;
+// world box of actor a: the mesh root box (union of the root's slots) with its
+// 8 corners transformed in FP64, rounded outward; returns max |coordinate|
+__device__ inline float actor_box(const ActorDev *__restrict__ actors, uint32_t a,
+                                  const MeshDev *__restrict__ meshes, float *__restrict__ lohi) {
     float m = 0.0f;
-    if (a < n) {
+    {
         const ActorDev A = actors[a];
         const Node4 root = meshes[A.mesh].nodes[0];
         float lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
@@ -99,6 +97,16 @@ __global__ __launch_bounds__(256) void actor_boxes_kernel(const ActorDev *__rest
             m = fmaxf(m, fmaxf(fabsf(l), fabsf(h)));
         }
     }
+    return m;
+}
+
+// world box of each actor; also max |coordinate| of all boxes into word[0]
+__global__ __launch_bounds__(256) void actor_boxes_kernel(const ActorDev *__restrict__ actors, uint32_t n,
+                                                          const MeshDev *__restrict__ meshes, float *__restrict__ lohi,
+                                                          uint32_t *word) {
+    uint32_t a = blockIdx.x * 256 + threadIdx.x;
+    float m = 0.0f;
+    if (a < n) m = actor_box(actors, a, meshes, lohi);
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(word, __float_as_uint(m));
 }
@@ -129,13 +137,8 @@ __global__ __launch_bounds__(256) void tlas_records_kernel(TriRec *__restrict__ 
     recs[s] = r;
 }
 
-__global__ __launch_bounds__(256) void refit_level_kernel(Node4 *__restrict__ nodes, const TriRec *__restrict__ recs,
-                                                          uint32_t first, uint32_t count,
-                                                          const uint32_t *__restrict__ word) {
-    uint32_t n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= count) return;
-    n += first;
-    const float pad = __uint_as_float(word[1]);
+// the child boxes of node n from its children (records or child nodes, already refit)
+__device__ inline void refit_node(Node4 *__restrict__ nodes, const TriRec *__restrict__ recs, uint32_t n, float pad) {
     Node4 nd = nodes[n];
     for (int k = 0; k < 4; ++k) {
         const uint32_t ref = nd.c[k].ref;
@@ -174,6 +177,98 @@ __global__ __launch_bounds__(256) void refit_level_kernel(Node4 *__restrict__ no
     nodes[n] = nd;
 }
 
+__global__ __launch_bounds__(256) void refit_level_kernel(Node4 *__restrict__ nodes, const TriRec *__restrict__ recs,
+                                                          uint32_t first, uint32_t count,
+                                                          const uint32_t *__restrict__ word) {
+    const uint32_t n = blockIdx.x * 256 + threadIdx.x;
+    if (n < count) refit_node(nodes, recs, first + n, __uint_as_float(word[1]));
+}
+
+// Small trees (a few thousand nodes) refit in one workgroup: the phases and the
+// levels are separated by workgroup barriers instead of kernel launches, which
+// would cost more than the work.  Same operations, same results.
+constexpr uint32_t kSmallRefitThreads = 1024;
+constexpr uint32_t kSmallRefitNodes = 4096;
+
+struct Levels {
+    uint32_t depth;
+    uint32_t base[kMaxLevels + 1];
+};
+
+__device__ inline void refit_levels_block(Node4 *__restrict__ nodes, const TriRec *__restrict__ recs,
+                                          const Levels &L, float pad) {
+    for (int l = (int)L.depth - 1; l >= 0; --l) {
+        for (uint32_t n = L.base[l] + threadIdx.x; n < L.base[l + 1]; n += kSmallRefitThreads)
+            refit_node(nodes, recs, n, pad);
+        __syncthreads();
+    }
+}
+
+// max |x| over a block's values into LDS, then the builder's pad formula
+__device__ inline float block_pad(float m, uint32_t *lds_max) {
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(lds_max, __float_as_uint(m));
+    __syncthreads();
+    return __uint_as_float(*lds_max) * 9.5367431640625e-07f + 1e-20f;
+}
+
+__global__ __launch_bounds__(kSmallRefitThreads) void refit_mesh_small_kernel(Node4 *__restrict__ nodes,
+                                                                              TriRec *__restrict__ recs, Levels L,
+                                                                              uint32_t nt,
+                                                                              const uint32_t *__restrict__ idx,
+                                                                              const float *__restrict__ v,
+                                                                              uint64_t nv) {
+    __shared__ uint32_t lds_max;
+    if (threadIdx.x == 0) lds_max = 0u;
+    __syncthreads();
+    float m = 0.0f;
+    for (uint64_t k = threadIdx.x; k < 3 * nv; k += kSmallRefitThreads) m = fmaxf(m, fabsf(v[k]));
+    const float pad = block_pad(m, &lds_max);
+    for (uint32_t s = threadIdx.x; s < nt; s += kSmallRefitThreads) {
+        TriRec r = recs[s];
+        const uint32_t k = __float_as_uint(r.a.w);
+        const uint32_t i0 = idx[3 * (size_t)k], i1 = idx[3 * (size_t)k + 1], i2 = idx[3 * (size_t)k + 2];
+        r.a.x = v[3 * (size_t)i0]; r.a.y = v[3 * (size_t)i0 + 1]; r.a.z = v[3 * (size_t)i0 + 2];
+        r.b.x = v[3 * (size_t)i1]; r.b.y = v[3 * (size_t)i1 + 1]; r.b.z = v[3 * (size_t)i1 + 2];
+        r.c.x = v[3 * (size_t)i2]; r.c.y = v[3 * (size_t)i2 + 1]; r.c.z = v[3 * (size_t)i2 + 2];
+        recs[s] = r;
+    }
+    __syncthreads();
+    refit_levels_block(nodes, recs, L, pad);
+}
+
+// per-frame update of a small top-level BVH: actor boxes, pad, leaf records, levels
+__global__ __launch_bounds__(kSmallRefitThreads) void update_tlas_small_kernel(const ActorDev *__restrict__ actors,
+                                                                               uint32_t n,
+                                                                               const MeshDev *__restrict__ meshes,
+                                                                               float *__restrict__ lohi,
+                                                                               Node4 *__restrict__ nodes,
+                                                                               TriRec *__restrict__ recs, Levels L) {
+    __shared__ uint32_t lds_max;
+    if (threadIdx.x == 0) lds_max = 0u;
+    __syncthreads();
+    float m = 0.0f;
+    for (uint32_t a = threadIdx.x; a < n; a += kSmallRefitThreads) m = fmaxf(m, actor_box(actors, a, meshes, lohi));
+    const float pad = block_pad(m, &lds_max);     // its barrier also publishes the boxes
+    for (uint32_t s = threadIdx.x; s < n; s += kSmallRefitThreads) {
+        TriRec r = recs[s];
+        const float *b = lohi + 6 * (size_t)__float_as_uint(r.a.w);
+        r.a.x = b[0]; r.a.y = b[1]; r.a.z = b[2];
+        r.b.x = b[3]; r.b.y = b[4]; r.b.z = b[5];
+        r.c.x = b[0]; r.c.y = b[1]; r.c.z = b[2];
+        recs[s] = r;
+    }
+    __syncthreads();
+    refit_levels_block(nodes, recs, L, pad);
+}
+
+Levels levels_of(const BuildResult &br) {
+    Levels L{};
+    L.depth = br.depth;
+    for (uint32_t l = 0; l <= br.depth && l <= (uint32_t)kMaxLevels; ++l) L.base[l] = br.level_base[l];
+    return L;
+}
+
 inline uint32_t grid_of(uint64_t n) { return (uint32_t)((n + 255) / 256); }
 
 // child boxes of every node, deepest level first
@@ -190,6 +285,10 @@ bool refit_supported(const BuildResult &br) { return br.depth >= 1 && br.depth <
 
 void refit_mesh(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t nt, const uint32_t *idx,
                 const float *vertices, uint64_t nv, uint32_t *word, hipStream_t s) {
+    if (br.n_nodes <= kSmallRefitNodes) {
+        refit_mesh_small_kernel<<<1, kSmallRefitThreads, 0, s>>>(nodes, recs, levels_of(br), nt, idx, vertices, nv);
+        return;
+    }
     zero_words_kernel<<<1, 1, 0, s>>>(word);
     uint32_t g = grid_of(3 * nv);
     maxabs_kernel<<<g < 1024 ? g : 1024, 256, 0, s>>>(vertices, 3 * nv, word);
@@ -206,6 +305,16 @@ void actor_boxes(const ActorDev *actors, uint32_t n, const MeshDev *meshes, floa
 
 void actor_prims(const float *lohi, uint32_t n, float *vtx, uint32_t *idx, uint16_t *mat, hipStream_t s) {
     actor_prims_kernel<<<grid_of(n), 256, 0, s>>>(lohi, n, vtx, idx, mat);
+}
+
+void update_tlas(const ActorDev *actors, uint32_t n, const MeshDev *meshes, float *lohi, Node4 *nodes,
+                 TriRec *recs, const BuildResult &br, uint32_t *word, hipStream_t s) {
+    if (br.n_nodes <= kSmallRefitNodes && n <= 4 * kSmallRefitNodes) {
+        update_tlas_small_kernel<<<1, kSmallRefitThreads, 0, s>>>(actors, n, meshes, lohi, nodes, recs, levels_of(br));
+        return;
+    }
+    actor_boxes(actors, n, meshes, lohi, word, s);
+    refit_tlas(nodes, recs, br, n, lohi, word, s);
 }
 
 void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,

@@ -1031,8 +1031,8 @@ lidar_status lidar_actors_update(lidar_ctx *ctx, const lidar_actor *actors, uint
             hipSuccess ||
         (e = hipEventRecord(ctx->staging_ev, s)) != hipSuccess)
         return ctx->hip_fail(e, "actor upload");
-    actor_boxes(ctx->actors_dev, n_actors, (const MeshDev *)ctx->mesh_table.p, ctx->actor_lohi, ctx->refit_word(), s);
-    refit_tlas((Node4 *)ctx->A.nodes, ctx->tlas_recs, ctx->tlas_br, n_actors, ctx->actor_lohi, ctx->refit_word(), s);
+    update_tlas(ctx->actors_dev, n_actors, (const MeshDev *)ctx->mesh_table.p, ctx->actor_lohi, (Node4 *)ctx->A.nodes,
+                ctx->tlas_recs, ctx->tlas_br, ctx->refit_word(), s);
     if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "actor update");
     ctx->tlas_stale = false;
     return LIDAR_OK;

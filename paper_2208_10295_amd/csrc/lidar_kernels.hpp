@@ -120,6 +120,9 @@ void refit_mesh(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t nt, 
 void actor_boxes(const ActorDev *actors, uint32_t n, const MeshDev *meshes, float *lohi, uint32_t *word,
                  hipStream_t s);
 void actor_prims(const float *lohi, uint32_t n, float *vtx, uint32_t *idx, uint16_t *mat, hipStream_t s);
+// actor boxes + top-level refit of a per-frame update (one workgroup for small trees)
+void update_tlas(const ActorDev *actors, uint32_t n, const MeshDev *meshes, float *lohi, Node4 *nodes,
+                 TriRec *recs, const BuildResult &br, uint32_t *word, hipStream_t s);
 void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,
                 hipStream_t s);
 
