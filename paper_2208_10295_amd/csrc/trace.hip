@@ -647,9 +647,10 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
 // ---------------------------------------------------------------------------
 // Without actors the kernel is held to 64 VGPRs (8 waves per SIMD: 65.6 vs
 // 67.4 us on the 64 x 2048 scan, three spilled dwords outside the hot loop);
-// the actor variant needs ~100 VGPRs and is left unconstrained.
+// the actor variant is held to 5 waves per SIMD (96 VGPRs, no spills; 117 vs
+// 123 us unconstrained at 4 waves, 121 us at 6 with spills).
 template <int STACK, int BLOCK, int LANES, bool COUNT, bool SWEEP, bool ACTORS>
-__global__ __launch_bounds__(BLOCK, ACTORS ? 1 : 8) void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
+__global__ __launch_bounds__(BLOCK, ACTORS ? 5 : 8) void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
                                                                  Overrides ov, Outputs out, int tile_az_log2,
                                                                  uint64_t n_padded, int xcd_remap, uint32_t *err,
                                                                  uint32_t *__restrict__ n_nodes,
