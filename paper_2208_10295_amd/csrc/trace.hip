@@ -30,6 +30,16 @@
 
 namespace lidar {
 
+// Waves per SIMD to ask of the register allocator: `want`, or fewer when the
+// block's LDS (160 KB per CU, four SIMDs) cannot hold that many blocks.  Asking
+// for more than LDS allows would cap the VGPRs for occupancy never reached.
+// Rounded up: 11 blocks of two waves put 6 waves on two SIMDs and 5 on two.
+constexpr int lds_waves(int want, int lds_bytes, int block) {
+    int w = ((160 * 1024 / lds_bytes) * (block / 64) + 3) / 4;
+    w = w < 1 ? 1 : w;
+    return want < w ? want : w;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 direction tables from data-sheet angles (degrees)
 // ---------------------------------------------------------------------------
@@ -650,11 +660,10 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
 // the actor variant is held to 5 waves per SIMD (96 VGPRs, no spills; 117 vs
 // 123 us unconstrained at 4 waves, 121 us at 6 with spills).
 template <int STACK, int BLOCK, int LANES, bool COUNT, bool SWEEP, bool ACTORS>
-__global__ __launch_bounds__(BLOCK, ACTORS ? 5 : 8) void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M,
-                                                                 Overrides ov, Outputs out, int tile_az_log2,
-                                                                 uint64_t n_padded, int xcd_remap, uint32_t *err,
-                                                                 uint32_t *__restrict__ n_nodes,
-                                                                 uint32_t *__restrict__ n_tris, ActorsDev A) {
+__global__ __launch_bounds__(BLOCK, lds_waves(ACTORS ? 5 : 8, 4 * (STACK + 6) * (BLOCK / LANES) + 96, BLOCK))
+void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrides ov, Outputs out,
+                             int tile_az_log2, uint64_t n_padded, int xcd_remap, uint32_t *err,
+                             uint32_t *__restrict__ n_nodes, uint32_t *__restrict__ n_tris, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
     static_assert(NR == 64, "one 64-beam tile per block; its epilogue runs in the first wavefront");
     __shared__ uint32_t stk[STACK * NR];
@@ -988,10 +997,11 @@ __device__ inline void wave_lds_sync() {
 }
 
 template <int STACK, int BLOCK, int LANES>
-__global__ __launch_bounds__(BLOCK, LANES == 4 ? 8 : LANES == 2 ? 6 : 1) void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts,
-                                                            uint32_t n_inst, MaterialsDev M, Outputs out,
-                                                            int tile_az_log2, uint64_t n_padded_total,
-                                                            uint32_t packet, uint32_t *queue, uint32_t *err) {
+__global__ __launch_bounds__(BLOCK, lds_waves(LANES == 4 ? 8 : LANES == 2 ? 6 : 1,
+                                           4 * STACK * (BLOCK / LANES) + (BLOCK / 64) * (3 * 64 * 4 + 96), BLOCK))
+void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts, uint32_t n_inst, MaterialsDev M,
+                        Outputs out, int tile_az_log2, uint64_t n_padded_total, uint32_t packet,
+                        uint32_t *queue, uint32_t *err) {
     constexpr int NSLOT = BLOCK / LANES;
     constexpr uint32_t RAYS_PER_WAVE = 64u / LANES;
     __shared__ uint32_t stk[STACK * NSLOT];
