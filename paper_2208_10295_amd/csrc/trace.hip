@@ -34,6 +34,10 @@ namespace lidar {
 // block's LDS (160 KB per CU, four SIMDs) cannot hold that many blocks.  Asking
 // for more than LDS allows would cap the VGPRs for occupancy never reached.
 // Rounded up: 11 blocks of two waves put 6 waves on two SIMDs and 5 on two.
+// Stack entries per beam beyond the capacity of the multi-lane walk (its
+// bottom entry and the scratch stores of the node steps, see quad_node_step).
+constexpr int kStackPad = 5;
+
 constexpr int lds_waves(int want, int lds_bytes, int block) {
     int w = ((160 * 1024 / lds_bytes) * (block / 64) + 3) / 4;
     w = w < 1 ? 1 : w;
@@ -269,36 +273,45 @@ __device__ inline float group_min_t(float t) {
     return __uint_as_float(u);
 }
 
-// One quad node step (see above): returns false if the beam hits none of the
-// node's children; otherwise pushes the further children hit, sets `next` to
-// the nearest one and returns true.
+// One quad node step (see above): returns the nearest child hit by the beam,
+// or kEmptyRef if it hits none, and pushes the further children hit.  Every
+// lane stores its child without a branch, at entry sp + ((h - rank) mod 4):
+// the ranks of a quad are a permutation of 0..3, and so are these offsets, so
+// children of rank 1..h land in entries sp + h - 1 .. sp, and the nearest child
+// and the missed ones land in entries sp + h .. sp + 3, above the new top,
+// where they are never read.  The step leaves sp + h entries (h = -1 when the
+// beam misses every child: the entry to pop next is then the top one).  A node
+// that would push the stack past `lim` entries clamps it there (children are
+// lost); `peak` records sp + h, and peak > lim after the walk marks the beam as
+// overflowed.
+__device__ inline int push_level(int sp, int nh, int rank) { return sp + ((nh - rank) & 3); }
+
+__device__ inline int push_clamp(int sp, int nh, int lim, int &peak) {
+    const int top = sp + nh;
+    peak = top > peak ? top : peak;
+    return min(top, lim);
+}
+
 template <int NSLOT>
-__device__ inline bool quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
-                                      float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
-                                      bool &overflow, uint32_t &next) {
+__device__ inline uint32_t quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
+                                          float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
+                                          int &peak) {
     const uint32_t off = ref * (uint32_t)sizeof(Node4) + s * 32u;   // child slot s of node ref
     const float4 a = buf_load4(nodes, off), b = buf_load4(nodes, off + 16u);
     const float key = slab(B, a, b, t_lo, lim);
     const uint32_t cref = __float_as_uint(a.w);
     const uint32_t kk = (__float_as_uint(key) & ~3u) | s;
-    const uint32_t rank = (uint32_t)(quad_xor1(kk) < kk) + (uint32_t)(quad_xor2(kk) < kk) +
-                          (uint32_t)(quad_xor3(kk) < kk);
+    const int rank = (int)(quad_xor1(kk) < kk) + (int)(quad_xor2(kk) < kk) + (int)(quad_xor3(kk) < kk);
     // children hit by the beam: the finite keys of its quad
     const uint64_t fin = __ballot(kk < 0x7F800000u);
-    const uint32_t nfin = (uint32_t)__popc((uint32_t)(fin >> (threadIdx.x & 60u)) & 0xFu);
-    if (nfin == 0) return false;
-    uint32_t nxt = rank == 0 ? cref : 0u;
+    const int nh = __popc((uint32_t)(fin >> (threadIdx.x & 60u)) & 0xFu) - 1;
+    // the rank-0 child, or kEmptyRef if even that one was missed
+    uint32_t nxt = rank == 0 ? (kk < 0x7F800000u ? cref : kEmptyRef) : 0u;
     nxt |= quad_xor1(nxt);
     nxt |= quad_xor2(nxt);
-    const int nh = (int)nfin - 1;
-    if (sp + nh <= cap) {
-        if (rank >= 1 && (int)rank <= nh) stk[(sp + nh - (int)rank) * NSLOT] = cref;
-        sp += nh;
-    } else {
-        overflow = true;
-    }
-    next = nxt;
-    return true;
+    stk[push_level(sp, nh, rank) * NSLOT] = cref;
+    sp = push_clamp(sp, nh, cap, peak);
+    return nxt;
 }
 
 // One pair node step: lane s (0 or 1) of the beam's pair tests children 2s and
@@ -306,9 +319,9 @@ __device__ inline bool quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref
 // and the partner's two, through one quad_perm swap each); otherwise as the
 // quad step.
 template <int NSLOT>
-__device__ inline bool pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
-                                      float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
-                                      bool &overflow, uint32_t &next) {
+__device__ inline uint32_t pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
+                                          float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
+                                          int &peak) {
     const uint32_t off = ref * (uint32_t)sizeof(Node4) + s * 64u;   // child slots 2s, 2s + 1
     const float4 a0 = buf_load4(nodes, off), b0 = buf_load4(nodes, off + 16u);
     const float4 a1 = buf_load4(nodes, off + 32u), b1 = buf_load4(nodes, off + 48u);
@@ -316,24 +329,16 @@ __device__ inline bool pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref
     const uint32_t ka = (__float_as_uint(slab(B, a0, b0, t_lo, lim)) & ~3u) | (2u * s);
     const uint32_t kb = (__float_as_uint(slab(B, a1, b1, t_lo, lim)) & ~3u) | (2u * s + 1u);
     const uint32_t pa = quad_xor1(ka), pb = quad_xor1(kb);
-    const uint32_t ra = (uint32_t)(kb < ka) + (uint32_t)(pa < ka) + (uint32_t)(pb < ka);
-    const uint32_t rb = (uint32_t)(ka < kb) + (uint32_t)(pa < kb) + (uint32_t)(pb < kb);
+    const int ra = (int)(kb < ka) + (int)(pa < ka) + (int)(pb < ka);
+    const int rb = (int)(ka < kb) + (int)(pa < kb) + (int)(pb < kb);
     constexpr uint32_t kInfKey = 0x7F800000u;
-    const uint32_t nfin = (uint32_t)(ka < kInfKey) + (uint32_t)(kb < kInfKey) + (uint32_t)(pa < kInfKey) +
-                          (uint32_t)(pb < kInfKey);
-    if (nfin == 0) return false;
-    uint32_t nxt = (ra == 0 ? ca : 0u) | (rb == 0 ? cb : 0u);
+    const int nh = (int)(ka < kInfKey) + (int)(kb < kInfKey) + (int)(pa < kInfKey) + (int)(pb < kInfKey) - 1;
+    uint32_t nxt = (ra == 0 ? (ka < kInfKey ? ca : kEmptyRef) : 0u) | (rb == 0 ? (kb < kInfKey ? cb : kEmptyRef) : 0u);
     nxt |= quad_xor1(nxt);
-    const int nh = (int)nfin - 1;
-    if (sp + nh <= cap) {
-        if (ra >= 1 && (int)ra <= nh) stk[(sp + nh - (int)ra) * NSLOT] = ca;
-        if (rb >= 1 && (int)rb <= nh) stk[(sp + nh - (int)rb) * NSLOT] = cb;
-        sp += nh;
-    } else {
-        overflow = true;
-    }
-    next = nxt;
-    return true;
+    stk[push_level(sp, nh, ra) * NSLOT] = ca;
+    stk[push_level(sp, nh, rb) * NSLOT] = cb;
+    sp = push_clamp(sp, nh, cap, peak);
+    return nxt;
 }
 
 template <int LANES, int STACK, int NSLOT, bool COUNT>
@@ -347,11 +352,18 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
     const RayTri T = prep_tri_test(ray);
     Hit h{kNone, kNone, t_hi, kNone};   // this lane's best
     float best_t = t_hi;                // the beam's best distance (minimum over its lanes)
+    // Entry 0 holds kEmptyRef: popping it ends the walk, so the loop has one
+    // exit, also taken when the step budget runs out.  The step count is the
+    // wavefront's, so running out marks every beam of the wavefront as
+    // overflowed.  Entries 1 .. cap hold pushed children, and the scratch
+    // stores of the node steps reach entry cap + 4: the stack has
+    // cap + kStackPad entries.
     uint32_t ref = root;
-    int sp = 0;
+    stk[0] = kEmptyRef;
+    int sp = 1, peak = 0;
     uint32_t steps = 0;
-    while (true) {
-        if (++steps > max_steps) { overflow = true; break; }
+    for (; ref != kEmptyRef && steps <= max_steps; ++steps) {
+        uint32_t nxt = kEmptyRef;
         if (ref & kLeafBit) {
             uint32_t first = leaf_first(ref), n = leaf_count(ref);
             if (COUNT) cnt.tris += n;
@@ -365,25 +377,16 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                 }
             }
             best_t = group_min_t<LANES>(h.t);
+            --sp;
         } else {
             if (COUNT) cnt.nodes += 1;
-            if (LANES == 4) {
-                uint32_t nxt;
-                if (quad_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap, overflow, nxt)) {
-                    ref = nxt;
-                    continue;
-                }
-            } else {
-                uint32_t nxt;
-                if (pair_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap, overflow, nxt)) {
-                    ref = nxt;
-                    continue;
-                }
-            }
+            nxt = LANES == 4 ? quad_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap + 1, peak)
+                             : pair_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap + 1, peak);
         }
-        if (sp == 0) break;
-        ref = stk[(--sp) * NSLOT];
+        if (nxt == kEmptyRef) nxt = stk[sp * NSLOT];
+        ref = nxt;
     }
+    if (steps > max_steps || peak > cap + 1) overflow = true;
     // lexicographic (t, original index) minimum over the beam's lanes
     {
         float ot = __uint_as_float(quad_xor1(__float_as_uint(h.t)));
@@ -414,7 +417,7 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
     const float inf = __builtin_inff();
     Counts cnt{0u, 0u};
     uint32_t ref = 0;
-    int sp = 0;
+    int sp = 0, peak = 0;
     uint32_t steps = 0;
     while (true) {
         if (++steps > A.max_steps) { overflow = true; break; }
@@ -437,17 +440,18 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
                     if (better(hb.t, g, h.t, h.orig)) { h.t = hb.t; h.orig = g; h.slot = hb.slot; h.actor = a; }
                 }
             }
-        } else if constexpr (LANES == 4) {
-            uint32_t nxt;
-            if (quad_node_step<NSLOT>(raw_buffer(A.nodes), ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, overflow,
-                                      nxt)) {
+            --sp;
+        } else if constexpr (LANES == 4) {    // a miss leaves sp one lower (see quad_node_step)
+            const uint32_t nxt =
+                quad_node_step<NSLOT>(raw_buffer(A.nodes), ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, peak);
+            if (nxt != kEmptyRef) {
                 ref = nxt;
                 continue;
             }
         } else if constexpr (LANES == 2) {
-            uint32_t nxt;
-            if (pair_node_step<NSLOT>(raw_buffer(A.nodes), ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, overflow,
-                                      nxt)) {
+            const uint32_t nxt =
+                pair_node_step<NSLOT>(raw_buffer(A.nodes), ref, B, t_lo, box_limit(h.t), s, stk, sp, STACK, peak);
+            if (nxt != kEmptyRef) {
                 ref = nxt;
                 continue;
             }
@@ -467,10 +471,12 @@ __device__ inline void traverse_actors(const ActorsDev &A, const Ray &ray, float
                 ref = c0;
                 continue;
             }
+            --sp;
         }
-        if (sp == 0) break;
-        ref = stk[(--sp) * NSLOT];
+        if (sp < 0) break;
+        ref = stk[sp * NSLOT];
     }
+    if (peak > STACK) overflow = true;
 }
 
 // ---------------------------------------------------------------------------
@@ -660,13 +666,13 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
 // the actor variant is held to 5 waves per SIMD (96 VGPRs, no spills; 117 vs
 // 123 us unconstrained at 4 waves, 121 us at 6 with spills).
 template <int STACK, int BLOCK, int LANES, bool COUNT, bool SWEEP, bool ACTORS>
-__global__ __launch_bounds__(BLOCK, lds_waves(ACTORS ? 5 : 8, 4 * (STACK + 6) * (BLOCK / LANES) + 96, BLOCK))
+__global__ __launch_bounds__(BLOCK, lds_waves(ACTORS ? 5 : 8, 4 * (STACK + kStackPad + 6) * (BLOCK / LANES) + 96, BLOCK))
 void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrides ov, Outputs out,
                              int tile_az_log2, uint64_t n_padded, int xcd_remap, uint32_t *err,
                              uint32_t *__restrict__ n_nodes, uint32_t *__restrict__ n_tris, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
     static_assert(NR == 64, "one 64-beam tile per block; its epilogue runs in the first wavefront");
-    __shared__ uint32_t stk[STACK * NR];
+    __shared__ uint32_t stk[(STACK + kStackPad) * NR];
     __shared__ double pose[12];
     // hits of the block's beams, handed from the walking lanes to the epilogue wavefront:
     // (j << 20 | launch column), record slot, triangle index, t bits, actor, beam active
@@ -753,7 +759,7 @@ __global__ __launch_bounds__(BLOCK) void trace_subrays_kernel(SceneDev S, Instan
                                                               int tile_az_log2, uint64_t n_padded, int xcd_remap,
                                                               uint32_t *err, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
-    __shared__ uint32_t stk[STACK * NR];
+    __shared__ uint32_t stk[(STACK + kStackPad) * NR];
     __shared__ double pose[12];
     const Overrides ov{nullptr, nullptr, nullptr, nullptr};
     block_pose(in, ov, pose);
@@ -998,13 +1004,13 @@ __device__ inline void wave_lds_sync() {
 
 template <int STACK, int BLOCK, int LANES>
 __global__ __launch_bounds__(BLOCK, lds_waves(LANES == 4 ? 8 : LANES == 2 ? 6 : 1,
-                                           4 * STACK * (BLOCK / LANES) + (BLOCK / 64) * (3 * 64 * 4 + 96), BLOCK))
+                                           4 * (STACK + kStackPad) * (BLOCK / LANES) + (BLOCK / 64) * (3 * 64 * 4 + 96), BLOCK))
 void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts, uint32_t n_inst, MaterialsDev M,
                         Outputs out, int tile_az_log2, uint64_t n_padded_total, uint32_t packet,
                         uint32_t *queue, uint32_t *err) {
     constexpr int NSLOT = BLOCK / LANES;
     constexpr uint32_t RAYS_PER_WAVE = 64u / LANES;
-    __shared__ uint32_t stk[STACK * NSLOT];
+    __shared__ uint32_t stk[(STACK + kStackPad) * NSLOT];
     // per wavefront, per ray of the current 64-ray group: record slot, triangle index, t bits
     __shared__ uint32_t hand[BLOCK / 64][3][64];
     __shared__ double gpose[BLOCK / 64][12];    // per wavefront: the group's FP64 pose (R row-major, p)
@@ -1216,7 +1222,7 @@ int batch_blocks_per_cu(const TraceOpts &t) {
     int block = lanes == 4 ? kQuadBlock : lanes == 2 ? kPairBlock : kBlock;
     int slots = block / lanes;
     int waves = block / 64;
-    int by_lds = (160 * 1024) / (st * slots * 4 + waves * (3 * 64 * 4 + 96));   // stacks, hand-off, poses
+    int by_lds = (160 * 1024) / ((st + kStackPad) * slots * 4 + waves * (3 * 64 * 4 + 96));   // stacks, hand-off, poses
     int by_waves = 32 / waves;          // at most 8 waves per SIMD
     int b = by_lds < by_waves ? by_lds : by_waves;
     return b < 1 ? 1 : b;
