@@ -291,7 +291,10 @@ __device__ inline RayTri prep_tri_test(const Ray &r) {
 }
 
 // Returns true and the distance t if the ray hits the triangle with
-// t_lo < t; the caller compares t with its current best.
+// t_lo < t; the caller compares t with its current best.  Apart from the rare
+// FP64 recomputation of an edge function that rounds to zero, the test runs
+// without branches (a wavefront tests its lanes' triangles together, so early
+// exits would only add exec-mask work).
 __device__ inline bool tri_hit(const RayTri &R, float4 a, float4 b, float4 c, float t_lo, float &t_out) {
     float Ax0 = a.x - R.ox, Ay0 = a.y - R.oy, Az0 = a.z - R.oz;
     float Bx0 = b.x - R.ox, By0 = b.y - R.oy, Bz0 = b.z - R.oz;
@@ -310,15 +313,13 @@ __device__ inline bool tri_hit(const RayTri &R, float4 a, float4 b, float4 c, fl
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
         W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
     }
-    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
-    float det = U + V + W;
-    if (det == 0.0f) return false;
-    float Az = R.Sz * Akz, Bz = R.Sz * Bkz, Cz = R.Sz * Ckz;
-    float T = U * Az + V * Bz + W * Cz;
-    float t = __fdiv_rn(T, det);
-    if (!(t > t_lo)) return false;
+    const bool outside = (U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f);
+    const float det = U + V + W;
+    const float Az = R.Sz * Akz, Bz = R.Sz * Bkz, Cz = R.Sz * Ckz;
+    const float T = U * Az + V * Bz + W * Cz;
+    const float t = __fdiv_rn(T, det);
     t_out = t;
-    return true;
+    return !outside && det != 0.0f && t > t_lo;
 }
 
 // ---------------------------------------------------------------------------

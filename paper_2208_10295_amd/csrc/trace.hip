@@ -150,8 +150,10 @@ struct Counts {
     uint32_t nodes, tris;
 };
 
+// (t, orig) < (bt, bo) lexicographically; non-short-circuit, so it compiles
+// to compares and selects rather than branches
 __device__ inline bool better(float t, uint32_t orig, float bt, uint32_t bo) {
-    return t < bt || (t == bt && orig < bo);
+    return (t < bt) | ((t == bt) & (orig < bo));
 }
 
 __device__ inline void csort(float &ka, uint32_t &va, float &kb, uint32_t &vb) {
@@ -363,6 +365,9 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
     int sp = 1, peak = 0;
     uint32_t steps = 0;
     for (; ref != kEmptyRef && steps <= max_steps; ++steps) {
+        // the entry a pop would return, read before the node fetch so that
+        // its latency is hidden (a step that pops has pushed nothing)
+        const uint32_t top = stk[(sp - 1) * NSLOT];
         uint32_t nxt = kEmptyRef;
         if (ref & kLeafBit) {
             uint32_t first = leaf_first(ref), n = leaf_count(ref);
@@ -371,10 +376,12 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                 const uint32_t off = (first + k) * (uint32_t)sizeof(TriRec);
                 const float4 a = buf_load4(tbuf, off), b = buf_load3(tbuf, off + 16u), c = buf_load3(tbuf, off + 32u);
                 float t;
-                if (tri_hit(T, a, b, c, t_lo, t)) {
-                    uint32_t orig = __float_as_uint(a.w);
-                    if (better(t, orig, h.t, h.orig)) { h.t = t; h.orig = orig; h.slot = first + k; }
-                }
+                const uint32_t orig = __float_as_uint(a.w);
+                const bool hit = tri_hit(T, a, b, c, t_lo, t);
+                const bool take = hit && better(t, orig, h.t, h.orig);
+                h.t = take ? t : h.t;
+                h.orig = take ? orig : h.orig;
+                h.slot = take ? first + k : h.slot;
             }
             best_t = group_min_t<LANES>(h.t);
             --sp;
@@ -383,8 +390,7 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
             nxt = LANES == 4 ? quad_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap + 1, peak)
                              : pair_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap + 1, peak);
         }
-        if (nxt == kEmptyRef) nxt = stk[sp * NSLOT];
-        ref = nxt;
+        ref = nxt == kEmptyRef ? top : nxt;
     }
     if (steps > max_steps || peak > cap + 1) overflow = true;
     // lexicographic (t, original index) minimum over the beam's lanes
