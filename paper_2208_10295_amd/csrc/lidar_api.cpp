@@ -224,7 +224,7 @@ InstanceDev make_instance(const lidar_ctx *ctx, int tile_az_log2, const lidar_se
     in.wavelength_nm = d.wavelength_nm;
     in.d_max = d.d_max;
     in.r_l_max = d.r_l_max;
-    in.t_min = d.t_min;
+    in.t_min = d.t_min + 0.0f;   // -0 becomes +0 (the box test compares bit patterns)
     in.sigma_i = d.sigma_intensity;
     in.t_trace = trace_limit(ctx, d);
     in.noise_on = d.noise_on ? 1u : 0u;

@@ -162,14 +162,20 @@ __device__ inline void csort(float &ka, uint32_t &va, float &kb, uint32_t &vb) {
     uint32_t tv = sw ? vb : va; vb = sw ? va : vb; va = tv;
 }
 
-// entry distance of the ray into a child box, +inf if missed
+// Entry distance of the ray into a child box, +inf if missed.  The clamps to
+// [t_lo, tmax_lim] are integer max / min of the bit patterns: with t_lo >= +0
+// and tmax_lim > 0 these order like the float values (a negative distance is
+// a negative integer), and unlike float min / max they need no
+// canonicalisation of the two loop-carried bounds on every step.
 __device__ inline float slab(const RayBox &B, float4 lo, float4 hi, float t_lo, float tmax_lim) {
     float x0 = fmaf(lo.x, B.ix, B.nox), x1 = fmaf(hi.x, B.ix, B.nox);
     float y0 = fmaf(lo.y, B.iy, B.noy), y1 = fmaf(hi.y, B.iy, B.noy);
     float z0 = fmaf(lo.z, B.iz, B.noz), z1 = fmaf(hi.z, B.iz, B.noz);
-    float tn = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), t_lo));
-    float tf = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tmax_lim));
-    return (tn <= tf) ? tn : __builtin_inff();
+    const float n3 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fminf(z0, z1));
+    const float f3 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1));
+    const int tn = max(__float_as_int(n3), __float_as_int(t_lo));
+    const int tf = min(__float_as_int(f3), __float_as_int(tmax_lim));
+    return tn <= tf ? __int_as_float(tn) : __builtin_inff();
 }
 
 // Orders the four children nearest first; returns whether any was hit.  The
@@ -303,7 +309,8 @@ __device__ inline uint32_t quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t
     const float key = slab(B, a, b, t_lo, lim);
     const uint32_t cref = __float_as_uint(a.w);
     const uint32_t kk = (__float_as_uint(key) & ~3u) | s;
-    const int rank = (int)(quad_xor1(kk) < kk) + (int)(quad_xor2(kk) < kk) + (int)(quad_xor3(kk) < kk);
+    // keys are below 2^31 (non-negative floats), so partner < kk is the sign of partner - kk
+    const int rank = (int)(((quad_xor1(kk) - kk) >> 31) + ((quad_xor2(kk) - kk) >> 31) + ((quad_xor3(kk) - kk) >> 31));
     // children hit by the beam: the finite keys of its quad
     const uint64_t fin = __ballot(kk < 0x7F800000u);
     const int nh = __popc((uint32_t)(fin >> (threadIdx.x & 60u)) & 0xFu) - 1;
@@ -331,8 +338,8 @@ __device__ inline uint32_t pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t
     const uint32_t ka = (__float_as_uint(slab(B, a0, b0, t_lo, lim)) & ~3u) | (2u * s);
     const uint32_t kb = (__float_as_uint(slab(B, a1, b1, t_lo, lim)) & ~3u) | (2u * s + 1u);
     const uint32_t pa = quad_xor1(ka), pb = quad_xor1(kb);
-    const int ra = (int)(kb < ka) + (int)(pa < ka) + (int)(pb < ka);
-    const int rb = (int)(ka < kb) + (int)(pa < kb) + (int)(pb < kb);
+    const int ra = (int)(((kb - ka) >> 31) + ((pa - ka) >> 31) + ((pb - ka) >> 31));   // as in the quad step
+    const int rb = (int)(((ka - kb) >> 31) + ((pa - kb) >> 31) + ((pb - kb) >> 31));
     constexpr uint32_t kInfKey = 0x7F800000u;
     const int nh = (int)(ka < kInfKey) + (int)(kb < kInfKey) + (int)(pa < kInfKey) + (int)(pb < kInfKey) - 1;
     uint32_t nxt = (ra == 0 ? (ka < kInfKey ? ca : kEmptyRef) : 0u) | (rb == 0 ? (kb < kInfKey ? cb : kEmptyRef) : 0u);
@@ -354,6 +361,7 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
     const RayTri T = prep_tri_test(ray);
     Hit h{kNone, kNone, t_hi, kNone};   // this lane's best
     float best_t = t_hi;                // the beam's best distance (minimum over its lanes)
+    float lim = box_limit(best_t);      // its box-culling bound, updated after each leaf
     // Entry 0 holds kEmptyRef: popping it ends the walk, so the loop has one
     // exit, also taken when the step budget runs out.  The step count is the
     // wavefront's, so running out marks every beam of the wavefront as
@@ -384,11 +392,12 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
                 h.slot = take ? first + k : h.slot;
             }
             best_t = group_min_t<LANES>(h.t);
+            lim = box_limit(best_t);
             --sp;
         } else {
             if (COUNT) cnt.nodes += 1;
-            nxt = LANES == 4 ? quad_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap + 1, peak)
-                             : pair_node_step<NSLOT>(nbuf, ref, B, t_lo, box_limit(best_t), s, stk, sp, cap + 1, peak);
+            nxt = LANES == 4 ? quad_node_step<NSLOT>(nbuf, ref, B, t_lo, lim, s, stk, sp, cap + 1, peak)
+                             : pair_node_step<NSLOT>(nbuf, ref, B, t_lo, lim, s, stk, sp, cap + 1, peak);
         }
         ref = nxt == kEmptyRef ? top : nxt;
     }
