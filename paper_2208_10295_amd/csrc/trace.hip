@@ -194,6 +194,24 @@ __device__ inline void sort4(float &k0, uint32_t &c0, float &k1, uint32_t &c1, f
 // with a smaller original index may be inside).
 __device__ inline float box_limit(float best_t) { return best_t * 1.0000005f; }
 
+// Traversal stack without branches.  A node step ranks the node's four
+// children near to far (rank 0..3, a permutation) and finds h + 1 of them hit.
+// The child of rank r is stored at entry sp + ((h - r) mod 4): ranks 1..h land
+// in entries sp + h - 1 .. sp (nearest on top), the nearest child and the
+// missed ones in entries sp + h .. sp + 3, above the new top, where they are
+// never read.  The step leaves sp + h entries (h = -1 when every child was
+// missed: the entry to pop next is then the top one).  A node that would push
+// the stack past `lim` entries clamps it there (children are lost); `peak`
+// records sp + h, and peak > lim after the walk marks the beam as overflowed.
+// Stores reach entry lim + 3, hence kStackPad.
+__device__ inline int push_level(int sp, int nh, int rank) { return sp + ((nh - rank) & 3); }
+
+__device__ inline int push_clamp(int sp, int nh, int lim, int &peak) {
+    const int top = sp + nh;
+    peak = top > peak ? top : peak;
+    return min(top, lim);
+}
+
 // ---------------------------------------------------------------------------
 // lane-per-ray traversal
 // ---------------------------------------------------------------------------
@@ -203,48 +221,60 @@ template <int STACK, int NSLOT, bool COUNT>
 __device__ inline Hit traverse(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris, uint32_t root,
                                uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
                                uint32_t *__restrict__ stk, bool &overflow, Counts &cnt, int cap = STACK) {
+    const __amdgpu_buffer_rsrc_t nbuf = raw_buffer(nodes), tbuf = raw_buffer(tris);
     const RayBox B = prep_box_test(ray);
     const RayTri T = prep_tri_test(ray);
     const float inf = __builtin_inff();
     Hit h{kNone, kNone, t_hi, kNone};
+    float lim = box_limit(h.t);
+    // Same stack discipline as the multi-lane walk below: entry 0 holds
+    // kEmptyRef, the sorted children of rank 1..3 are stored without branches
+    // at push_level, and the entry a pop returns is read ahead.
     uint32_t ref = root;
-    int sp = 0;
+    stk[0] = kEmptyRef;
+    int sp = 1, peak = 0;
     uint32_t steps = 0;
-    while (true) {
-        if (++steps > max_steps) { overflow = true; break; }
+    for (; ref != kEmptyRef && steps <= max_steps; ++steps) {
+        const uint32_t top = stk[(sp - 1) * NSLOT];
+        uint32_t nxt = kEmptyRef;
         if (ref & kLeafBit) {
             uint32_t first = leaf_first(ref), n = leaf_count(ref);
             if (COUNT) cnt.tris += n;
             for (uint32_t k = 0; k < n; ++k) {
-                const TriRec *r = tris + first + k;
-                float4 a = r->a, b = r->b, c = r->c;
+                const uint32_t off = (first + k) * (uint32_t)sizeof(TriRec);
+                const float4 a = buf_load4(tbuf, off), b = buf_load3(tbuf, off + 16u), c = buf_load3(tbuf, off + 32u);
                 float t;
-                if (tri_hit(T, a, b, c, t_lo, t)) {
-                    uint32_t orig = __float_as_uint(a.w);
-                    if (better(t, orig, h.t, h.orig)) { h.t = t; h.orig = orig; h.slot = first + k; }
-                }
+                const uint32_t orig = __float_as_uint(a.w);
+                const bool hit = tri_hit(T, a, b, c, t_lo, t);
+                const bool take = hit && better(t, orig, h.t, h.orig);
+                h.t = take ? t : h.t;
+                h.orig = take ? orig : h.orig;
+                h.slot = take ? first + k : h.slot;
             }
+            lim = box_limit(h.t);
+            --sp;
         } else {
             if (COUNT) cnt.nodes += 1;
-            const float4 *np = reinterpret_cast<const float4 *>(nodes + ref);
-            float4 a0 = np[0], b0 = np[1], a1 = np[2], b1 = np[3], a2 = np[4], b2 = np[5], a3 = np[6], b3 = np[7];
-            float lim = box_limit(h.t);
+            const uint32_t off = ref * (uint32_t)sizeof(Node4);
+            const float4 a0 = buf_load4(nbuf, off), b0 = buf_load4(nbuf, off + 16u);
+            const float4 a1 = buf_load4(nbuf, off + 32u), b1 = buf_load4(nbuf, off + 48u);
+            const float4 a2 = buf_load4(nbuf, off + 64u), b2 = buf_load4(nbuf, off + 80u);
+            const float4 a3 = buf_load4(nbuf, off + 96u), b3 = buf_load4(nbuf, off + 112u);
             float k0 = slab(B, a0, b0, t_lo, lim), k1 = slab(B, a1, b1, t_lo, lim);
             float k2 = slab(B, a2, b2, t_lo, lim), k3 = slab(B, a3, b3, t_lo, lim);
             uint32_t c0 = __float_as_uint(a0.w), c1 = __float_as_uint(a1.w), c2 = __float_as_uint(a2.w),
                      c3 = __float_as_uint(a3.w);
             sort4(k0, c0, k1, c1, k2, c2, k3, c3);
-            if (k0 != inf) {
-                if (k3 != inf) { if (sp < cap) stk[(sp++) * NSLOT] = c3; else overflow = true; }
-                if (k2 != inf) { if (sp < cap) stk[(sp++) * NSLOT] = c2; else overflow = true; }
-                if (k1 != inf) { if (sp < cap) stk[(sp++) * NSLOT] = c1; else overflow = true; }
-                ref = c0;
-                continue;
-            }
+            const int nh = (int)(k0 != inf) + (int)(k1 != inf) + (int)(k2 != inf) + (int)(k3 != inf) - 1;
+            stk[push_level(sp, nh, 1) * NSLOT] = c1;
+            stk[push_level(sp, nh, 2) * NSLOT] = c2;
+            stk[push_level(sp, nh, 3) * NSLOT] = c3;
+            sp = push_clamp(sp, nh, cap + 1, peak);
+            nxt = nh >= 0 ? c0 : kEmptyRef;
         }
-        if (sp == 0) break;
-        ref = stk[(--sp) * NSLOT];
+        ref = nxt == kEmptyRef ? top : nxt;
     }
+    if (steps > max_steps || peak > cap + 1) overflow = true;
     return h;
 }
 
@@ -282,24 +312,8 @@ __device__ inline float group_min_t(float t) {
 }
 
 // One quad node step (see above): returns the nearest child hit by the beam,
-// or kEmptyRef if it hits none, and pushes the further children hit.  Every
-// lane stores its child without a branch, at entry sp + ((h - rank) mod 4):
-// the ranks of a quad are a permutation of 0..3, and so are these offsets, so
-// children of rank 1..h land in entries sp + h - 1 .. sp, and the nearest child
-// and the missed ones land in entries sp + h .. sp + 3, above the new top,
-// where they are never read.  The step leaves sp + h entries (h = -1 when the
-// beam misses every child: the entry to pop next is then the top one).  A node
-// that would push the stack past `lim` entries clamps it there (children are
-// lost); `peak` records sp + h, and peak > lim after the walk marks the beam as
-// overflowed.
-__device__ inline int push_level(int sp, int nh, int rank) { return sp + ((nh - rank) & 3); }
-
-__device__ inline int push_clamp(int sp, int nh, int lim, int &peak) {
-    const int top = sp + nh;
-    peak = top > peak ? top : peak;
-    return min(top, lim);
-}
-
+// or kEmptyRef if it hits none, and pushes the further children hit; each
+// lane stores its own child (push_level).
 template <int NSLOT>
 __device__ inline uint32_t quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
                                           float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
@@ -643,7 +657,7 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
                                                            uint64_t n_padded, int xcd_remap, uint32_t *err,
                                                            uint32_t *__restrict__ n_nodes,
                                                            uint32_t *__restrict__ n_tris, ActorsDev A) {
-    __shared__ uint32_t stk[STACK * BLOCK];
+    __shared__ uint32_t stk[(STACK + kStackPad) * BLOCK];
     __shared__ double pose[12];
     if (!SWEEP) block_pose(in, ov, pose);
     uint64_t r = (uint64_t)logical_block(xcd_remap) * BLOCK + threadIdx.x;
