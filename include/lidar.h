@@ -437,10 +437,18 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep,
  *     lanes share a beam, two child boxes each; 4 = the four lanes of a quad
  *     share a beam, one child box each (default 4).
  *   LIDAR_OPT_XCD_REMAP: 1 = the thread blocks that run on one XCD take one
- *     contiguous azimuth sector (default 1); 0 = blocks in launch order. */
+ *     contiguous azimuth sector (default 1); 0 = blocks in launch order.
+ * One option exists to test error handling and does change results:
+ *   LIDAR_OPT_STACK_CAP: 0 = a walk of the static scene may use the whole
+ *     traversal stack sized for the tree's depth (default); n > 0 = at most n
+ *     entries.  A walk that needs more loses the children it cannot push,
+ *     stays within its stack memory and ends normally, and the next
+ *     lidar_sync_check returns LIDAR_ERR_STACK_OVERFLOW.  Kept across scene
+ *     loads. */
 #define LIDAR_OPT_TILE_AZ        1u
 #define LIDAR_OPT_LANES_PER_RAY  2u
 #define LIDAR_OPT_XCD_REMAP      3u
+#define LIDAR_OPT_STACK_CAP      4u
 lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value);
 
 /* ------------------------------------------------------------------------ */

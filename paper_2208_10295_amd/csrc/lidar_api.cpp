@@ -70,6 +70,7 @@ struct lidar_ctx {
     const uint32_t *slot_of = nullptr;
     BuildResult br{};
     int stack = 32;
+    int stack_cap_opt = 0;   // LIDAR_OPT_STACK_CAP (0: the whole stack)
     uint32_t leaf_width = 4;
     float build_ms = 0.f;
     // materials
@@ -440,6 +441,7 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     ctx->S.root = br.root;
     ctx->S.n_tri = nt;
     ctx->S.max_steps = br.n_nodes + br.n_leaves + 1;
+    ctx->S.stack_cap = ctx->stack_cap_opt > 0 && ctx->stack_cap_opt < stack ? ctx->stack_cap_opt : stack;
     ctx->has_scene = true;
     return LIDAR_OK;
 }
@@ -1376,6 +1378,11 @@ lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
     case LIDAR_OPT_XCD_REMAP:
         if (value != 0 && value != 1) return ctx->fail(LIDAR_ERR_INVALID_ARG, "xcd remap must be 0 or 1");
         ctx->xcd_remap = value;
+        return LIDAR_OK;
+    case LIDAR_OPT_STACK_CAP:
+        if (value < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "stack cap must be >= 0");
+        ctx->stack_cap_opt = value;
+        if (ctx->has_scene) ctx->S.stack_cap = value > 0 && value < ctx->stack ? value : ctx->stack;
         return LIDAR_OK;
     default:
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "unknown option");

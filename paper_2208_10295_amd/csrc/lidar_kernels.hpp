@@ -13,6 +13,7 @@ struct SceneDev {
     uint32_t root;
     uint32_t n_tri;
     uint32_t max_steps;    // bound on traversal loop iterations (nodes + leaves)
+    int32_t stack_cap;     // stack entries a walk of this tree may use (fewer than needed only to test overflow)
 };
 
 // --- scan / sort utilities (bvh_build.hip) ---

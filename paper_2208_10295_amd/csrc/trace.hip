@@ -668,7 +668,7 @@ __global__ __launch_bounds__(BLOCK) void trace_scan_kernel(SceneDev S, InstanceD
     bool overflow = false;
     Counts c{0u, 0u};
     Hit h = traverse<STACK, BLOCK, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + threadIdx.x,
-                                          overflow, c);
+                                          overflow, c, min(S.stack_cap, STACK));
     const ActorDev *act = nullptr;
     const TriRec *tris = S.tris;
     if constexpr (ACTORS) {
@@ -717,7 +717,7 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
         bool overflow = false;
         Counts c{0u, 0u};
         Hit h = traverse_multi<LANES, STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
-                                                        in.t_trace, stk + q, s, overflow, c);
+                                                        in.t_trace, stk + q, s, overflow, c, min(S.stack_cap, STACK));
         if constexpr (ACTORS) traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
         if (overflow) atomicOr(err, 1u);
         if (s == 0) {
@@ -809,10 +809,10 @@ __global__ __launch_bounds__(BLOCK) void trace_subrays_kernel(SceneDev S, Instan
     Hit h;
     if constexpr (LANES == 1)
         h = traverse<STACK, NR, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q,
-                                       overflow, c);
+                                       overflow, c, min(S.stack_cap, STACK));
     else
         h = traverse_multi<LANES, STACK, NR, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
-                                                    in.t_trace, stk + q, s, overflow, c);
+                                                    in.t_trace, stk + q, s, overflow, c, min(S.stack_cap, STACK));
     const ActorDev *act = nullptr;
     const TriRec *tris = S.tris;
     if constexpr (ACTORS) {
@@ -1079,11 +1079,12 @@ void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts, uint3
                     const Ray ray = make_ray(in, lds_pose(gpose[wave]), j, k);
                     if constexpr (LANES == 1)
                         h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
-                                                          in.t_trace, stk + slot, overflow, cnt);
+                                                          in.t_trace, stk + slot, overflow, cnt,
+                                                          min(S.stack_cap, STACK));
                     else
                         h = traverse_multi<LANES, STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray,
                                                                        in.t_min, in.t_trace, stk + slot, s, overflow,
-                                                                       cnt);
+                                                                       cnt, min(S.stack_cap, STACK));
                 }
                 if (s == 0) {
                     hand[wave][0][sub + sub_lane] = h.slot;

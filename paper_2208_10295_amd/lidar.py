@@ -256,6 +256,11 @@ class Context:
     def set_xcd_remap(self, on: bool):
         check(lib.lidar_set_option(self.h, A.OPT_XCD_REMAP, 1 if on else 0), self.h)
 
+    def set_stack_cap(self, entries: int):
+        """Limit the traversal stack of static-scene walks to `entries` (0 = no limit).  Only for testing
+        the overflow path: results of walks that overflow are wrong and sync_check() raises."""
+        check(lib.lidar_set_option(self.h, A.OPT_STACK_CAP, int(entries)), self.h)
+
     # -- simulation ---------------------------------------------------------
     def simulate(self, seed: int = 0, scan: int = 0, debug: bool = False, out: dict | None = None,
                  params: dict | None = None, stream=None, bruteforce: bool = False) -> dict:

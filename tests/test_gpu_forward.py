@@ -262,3 +262,35 @@ def test_degenerate_triangles_and_axis_aligned_beams(L):
     j0 = 2 * 8
     for i, t in ((0, 8.0), (2, 12.0), (4, 14.0), (6, 20.0)):
         assert a["valid"][j0 + i] == 1 and abs(a["range"][j0 + i] - t) < 1e-5 * t, (i, a["range"][j0 + i])
+
+
+def test_stack_overflow_is_reported_and_recovered(L):
+    """The overflow path, forced from the host: with the stack capped at one entry every walk that needs a
+    second one loses children, stays within its stack memory and ends; sync_check reports the overflow,
+    and with the cap lifted the same scan is bit-identical to the uncapped one."""
+    from paper_2208_10295_amd import _abi as A
+    scene, sensor, pose = S.config1()
+    c = _ctx(L, scene, sensor, pose)
+    ref = to_np(c.simulate(SEED, 0, debug=True))
+    c.sync_check()
+    for lanes in (1, 2, 4):
+        c.set_lanes_per_ray(lanes)
+        c.set_stack_cap(1)
+        print(f"[overflow] lanes={lanes} cap=1", flush=True)
+        c.simulate(SEED, 0, debug=True)
+        with pytest.raises(L.LidarError) as e:
+            c.sync_check()
+        assert e.value.status == A.ERR_STACK_OVERFLOW
+        c.set_stack_cap(0)
+        g = to_np(c.simulate(SEED, 0, debug=True))
+        c.sync_check()
+        for k in ref:
+            assert np.array_equal(ref[k], g[k]), (lanes, k)
+    # a cap the walks never reach changes nothing
+    c.set_stack_cap(30)
+    g = to_np(c.simulate(SEED, 0, debug=True))
+    c.sync_check()
+    for k in ref:
+        assert np.array_equal(ref[k], g[k]), k
+    with pytest.raises(L.LidarError):
+        c.set_stack_cap(-1)
