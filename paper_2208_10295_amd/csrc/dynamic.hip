@@ -204,6 +204,73 @@ __device__ inline void refit_levels_block(Node4 *__restrict__ nodes, const TriRe
     }
 }
 
+// Trees of up to kLdsRefitNodes nodes keep each node's box (the union of its
+// child slots) in LDS.  Every thread owns nodes t and t + 1024: it first reads
+// their child references and computes their leaf slots from the records (all
+// nodes at once), then, level by level, deepest first, fills their inner slots
+// from the children's boxes in LDS.  Only the leaf slots read global memory,
+// so the refit costs a few memory round trips instead of two per level.  The
+// slot boxes are the same unions as refit_node's.
+constexpr uint32_t kLdsRefitNodes = 2 * kSmallRefitThreads;
+
+__device__ inline void refit_levels_lds(Node4 *__restrict__ nodes, const TriRec *__restrict__ recs,
+                                        const Levels &L, float pad, float (*box)[6]) {
+    const uint32_t n_nodes = L.base[L.depth];
+    uint32_t refs[2][4];
+    for (int o = 0; o < 2; ++o) {
+        const uint32_t n = threadIdx.x + o * kSmallRefitThreads;
+        if (n >= n_nodes) continue;
+        float u[6] = {kInf, kInf, kInf, -kInf, -kInf, -kInf};
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t ref = nodes[n].c[k].ref;
+            refs[o][k] = ref;
+            if (ref == kEmptyRef || !(ref & kLeafBit)) continue;
+            float lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+            const uint32_t f = leaf_first(ref), c = leaf_count(ref);
+            for (uint32_t r = 0; r < c; ++r) {
+                const TriRec t = recs[f + r];
+                lo[0] = fminf(lo[0], fminf(t.a.x, fminf(t.b.x, t.c.x)));
+                lo[1] = fminf(lo[1], fminf(t.a.y, fminf(t.b.y, t.c.y)));
+                lo[2] = fminf(lo[2], fminf(t.a.z, fminf(t.b.z, t.c.z)));
+                hi[0] = fmaxf(hi[0], fmaxf(t.a.x, fmaxf(t.b.x, t.c.x)));
+                hi[1] = fmaxf(hi[1], fmaxf(t.a.y, fmaxf(t.b.y, t.c.y)));
+                hi[2] = fmaxf(hi[2], fmaxf(t.a.z, fmaxf(t.b.z, t.c.z)));
+            }
+            for (int e = 0; e < 3; ++e) {
+                lo[e] = lo[e] - pad;
+                hi[e] = hi[e] + pad;
+                nodes[n].c[k].lo[e] = lo[e];
+                nodes[n].c[k].hi[e] = hi[e];
+                u[e] = fminf(u[e], lo[e]);
+                u[3 + e] = fmaxf(u[3 + e], hi[e]);
+            }
+        }
+        for (int e = 0; e < 6; ++e) box[n][e] = u[e];
+    }
+    __syncthreads();
+    for (int l = (int)L.depth - 1; l >= 0; --l) {
+        for (int o = 0; o < 2; ++o) {
+            const uint32_t n = threadIdx.x + o * kSmallRefitThreads;
+            if (n < L.base[l] || n >= L.base[l + 1]) continue;
+            float u[6];
+            for (int e = 0; e < 6; ++e) u[e] = box[n][e];
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t ref = refs[o][k];
+                if (ref == kEmptyRef || (ref & kLeafBit)) continue;
+                for (int e = 0; e < 3; ++e) {
+                    const float lo = box[ref][e], hi = box[ref][3 + e];
+                    nodes[n].c[k].lo[e] = lo;
+                    nodes[n].c[k].hi[e] = hi;
+                    u[e] = fminf(u[e], lo);
+                    u[3 + e] = fmaxf(u[3 + e], hi);
+                }
+            }
+            for (int e = 0; e < 6; ++e) box[n][e] = u[e];
+        }
+        __syncthreads();
+    }
+}
+
 // max |x| over a block's values into LDS, then the builder's pad formula
 __device__ inline float block_pad(float m, uint32_t *lds_max) {
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
@@ -219,6 +286,7 @@ __global__ __launch_bounds__(kSmallRefitThreads) void refit_mesh_small_kernel(No
                                                                               const float *__restrict__ v,
                                                                               uint64_t nv) {
     __shared__ uint32_t lds_max;
+    __shared__ float box[kLdsRefitNodes][6];
     if (threadIdx.x == 0) lds_max = 0u;
     __syncthreads();
     float m = 0.0f;
@@ -234,7 +302,8 @@ __global__ __launch_bounds__(kSmallRefitThreads) void refit_mesh_small_kernel(No
         recs[s] = r;
     }
     __syncthreads();
-    refit_levels_block(nodes, recs, L, pad);
+    if (L.base[L.depth] <= kLdsRefitNodes) refit_levels_lds(nodes, recs, L, pad, box);
+    else refit_levels_block(nodes, recs, L, pad);
 }
 
 // per-frame update of a small top-level BVH: actor boxes, pad, leaf records, levels
@@ -245,6 +314,7 @@ __global__ __launch_bounds__(kSmallRefitThreads) void update_tlas_small_kernel(c
                                                                                Node4 *__restrict__ nodes,
                                                                                TriRec *__restrict__ recs, Levels L) {
     __shared__ uint32_t lds_max;
+    __shared__ float box[kLdsRefitNodes][6];
     if (threadIdx.x == 0) lds_max = 0u;
     __syncthreads();
     float m = 0.0f;
@@ -259,7 +329,8 @@ __global__ __launch_bounds__(kSmallRefitThreads) void update_tlas_small_kernel(c
         recs[s] = r;
     }
     __syncthreads();
-    refit_levels_block(nodes, recs, L, pad);
+    if (L.base[L.depth] <= kLdsRefitNodes) refit_levels_lds(nodes, recs, L, pad, box);
+    else refit_levels_block(nodes, recs, L, pad);
 }
 
 Levels levels_of(const BuildResult &br) {

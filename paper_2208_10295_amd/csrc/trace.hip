@@ -34,8 +34,8 @@ namespace lidar {
 // block's LDS (160 KB per CU, four SIMDs) cannot hold that many blocks.  Asking
 // for more than LDS allows would cap the VGPRs for occupancy never reached.
 // Rounded up: 11 blocks of two waves put 6 waves on two SIMDs and 5 on two.
-// Stack entries per beam beyond the capacity of the multi-lane walk (its
-// bottom entry and the scratch stores of the node steps, see quad_node_step).
+// Stack entries per beam beyond the capacity of a walk: its bottom entry and
+// the scratch stores of the node steps (see push_level).
 constexpr int kStackPad = 5;
 
 constexpr int lds_waves(int want, int lds_bytes, int block) {
