@@ -154,7 +154,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--legs", default="all", help="comma list of plain,cpu,batch,adjoint,sweep,echo,dynamic,sequence or 'all'")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of plain,roofs,cpu,batch,adjoint,sweep,echo,dynamic,sequence or 'all'")
     ap.add_argument("--leaf-width", type=int, default=4)
     ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
     ap.add_argument("--ploc-radius", type=int, default=32)
@@ -167,8 +168,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": args.gpus}))
         sys.exit(2)
-    legs = ({"plain", "cpu", "batch", "adjoint", "sweep", "echo", "dynamic", "sequence"} if args.legs == "all"
-            else set(args.legs.split(",")))
+    legs = ({"plain", "roofs", "cpu", "batch", "adjoint", "sweep", "echo", "dynamic", "sequence"}
+            if args.legs == "all" else set(args.legs.split(",")))
 
     import numpy as np
     import torch
@@ -249,6 +250,38 @@ def main():
                                          "+ beam index, in beam order",
                              "us_per_scan": c_ms * 1e3, "points": n_pts, "beams": n}
         log(f"compact: {n_pts} points of {n} beams in {c_ms * 1e3:.1f} us")
+
+    if "roofs" in legs:
+        # measured memory roofs beside the published HBM peak: a 2 GiB streaming read, and 128-byte line
+        # fetches by quads over a table of the scene's BVH size, launched like the scan (one quad per beam)
+        sink = torch.zeros(1, dtype=torch.float32, device=ctx.device)
+        big = torch.randint(-2**31, 2**31 - 1, (512 << 20,), dtype=torch.int32, device=ctx.device)
+        stream_run = L.probe_stream_launcher(big, sink)
+        _, s_ms = timed_region(stream_run, 10, torch)
+        stream_gbs = big.numel() * 4 / (s_ms * 1e-3) / 1e9
+        del big
+        sts = ctx.stats()
+        ws = int(sts["node_bytes"] + sts["tri_bytes"])
+        table = torch.randint(-2**31, 2**31 - 1, ((ws + 127) // 128 * 32,), dtype=torch.int32, device=ctx.device)
+        blocks, steps = 2048, 32
+        fetched = blocks * 64 * steps * 128
+        roofs = {"hbm_stream_read_gbs": stream_gbs, "stream_bytes": 2 << 30, "gather_working_set_bytes": ws,
+                 "gather_launch": f"{blocks} blocks x 256 threads (one quad per beam of the scan), {steps} lines of "
+                                  "128 B per quad, 32 B per lane"}
+        for name, chase in (("gather_independent_gbs", False), ("gather_chase_gbs", True)):
+            run = L.probe_gather_launcher(table, blocks, steps, chase, sink)
+            _, g_ms = timed_region(run, 20, torch)
+            roofs[name] = fetched / (g_ms * 1e-3) / 1e9
+        del table
+        if "roofline" in result:
+            a = result["roofline"]["achieved"]
+            roofs["scan_alg_gbs"] = a
+            roofs["scan_over_stream"] = a / stream_gbs
+            roofs["scan_over_gather_chase"] = a / roofs["gather_chase_gbs"]
+        result["roofs"] = roofs
+        log(f"roofs: HBM stream read {stream_gbs:.0f} GB/s; 128-B line gathers over {ws / 1e6:.1f} MB: "
+            f"independent {roofs['gather_independent_gbs']:.0f} GB/s, dependent chains "
+            f"{roofs['gather_chase_gbs']:.0f} GB/s")
 
     if "cpu" in legs:
         log("cpu baseline (FP64 oracle) ...")

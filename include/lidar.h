@@ -591,6 +591,35 @@ lidar_status lidar_sync_check(lidar_ctx *ctx, void *stream);
 lidar_status lidar_debug_copy_bvh(lidar_ctx *ctx, void *host_nodes, uint64_t node_bytes,
                                   void *host_tris, uint64_t tri_bytes);
 
+/* ------------------------------------------------------------------------ */
+/* Memory-roof probes (not part of the simulation)                          */
+/* ------------------------------------------------------------------------ */
+
+/* The trace kernels' traffic is reported as algorithmic bytes per second;
+ * these probes measure the roofs to compare it with, on the caller's device
+ * and stream.  Both are asynchronous single launches that read device memory
+ * only (the caller times them, e.g. with events around repeated launches);
+ * `sink` is one device float that is written only if the data sums to an
+ * improbable value, so the loads stay and add no write traffic.
+ *
+ * lidar_probe_stream reads every 16-byte word of `buf` (device, 16-byte
+ * aligned, `bytes` rounded down to a multiple of 16) once: the HBM read roof
+ * when `bytes` is far larger than the caches.
+ *
+ * lidar_probe_gather runs `blocks` blocks of 256 threads; each quad of lanes
+ * fetches `steps` 128-byte lines of `table` (device, 16-byte aligned, bytes in
+ * [128, 2^31], rounded down to a multiple of 128), 32 bytes per lane, the way
+ * a quad fetches a 4-wide BVH node.  Line indices are uniform over the table.
+ * chase != 0: each index is a hash of the data of the quad's previous line
+ * (a dependent chain per quad, like a BVH walk); chase == 0: a hash of a
+ * counter (independent fetches).  Bytes fetched = blocks * 64 * steps * 128.
+ *
+ * Errors: INVALID_ARG (NULL pointers, misalignment, sizes out of range),
+ * HIP (launch failure). */
+lidar_status lidar_probe_stream(const void *buf, uint64_t bytes, float *sink, void *stream);
+lidar_status lidar_probe_gather(const void *table, uint64_t bytes, uint32_t blocks, uint32_t steps,
+                                int32_t chase, float *sink, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -134,6 +134,8 @@ SIGNATURES = {
     "lidar_compact_points": (C.c_int32, [P, C.POINTER(Outputs), C.c_uint64, C.POINTER(Outputs), P, P, P, C.c_uint64,
                                          P]),
     "lidar_simulate_sweep": (C.c_int32, [P, C.POINTER(SweepDesc), C.POINTER(Outputs), C.POINTER(SweepInfo), P]),
+    "lidar_probe_stream": (C.c_int32, [P, C.c_uint64, P, P]),
+    "lidar_probe_gather": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, P, P]),
     "lidar_echo_bytes": (C.c_int32, [P, C.POINTER(EchoDesc), C.POINTER(C.c_uint64)]),
     "lidar_simulate_echoes": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(EchoDesc), P, C.c_uint64,
                                           C.POINTER(Outputs), P]),

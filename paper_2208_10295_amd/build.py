@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblidar.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["bvh_build.hip", "trace.hip", "adjoint.hip", "dynamic.hip", "compact.hip", "lidar_api.cpp"]
+SOURCES = ["bvh_build.hip", "trace.hip", "adjoint.hip", "dynamic.hip", "compact.hip", "probe.hip", "lidar_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument", "-Wno-unused-value",

@@ -1389,4 +1389,19 @@ lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
     }
 }
 
+lidar_status lidar_probe_stream(const void *buf, uint64_t bytes, float *sink, void *stream) {
+    if (!buf || !sink || bytes < 16 || ((uintptr_t)buf & 15u)) return LIDAR_ERR_INVALID_ARG;
+    launch_probe_stream(buf, bytes, sink, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? LIDAR_OK : LIDAR_ERR_HIP;
+}
+
+lidar_status lidar_probe_gather(const void *table, uint64_t bytes, uint32_t blocks, uint32_t steps, int32_t chase,
+                                float *sink, void *stream) {
+    if (!table || !sink || bytes < 128 || bytes > (1ull << 31) || ((uintptr_t)table & 15u) || blocks == 0 ||
+        blocks > (1u << 20) || steps == 0)
+        return LIDAR_ERR_INVALID_ARG;
+    launch_probe_gather(table, (uint32_t)(bytes / 128), blocks, steps, chase ? 1 : 0, sink, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? LIDAR_OK : LIDAR_ERR_HIP;
+}
+
 }  // extern "C"

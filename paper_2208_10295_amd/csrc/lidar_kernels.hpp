@@ -127,6 +127,11 @@ void update_tlas(const ActorDev *actors, uint32_t n, const MeshDev *meshes, floa
 void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,
                 hipStream_t s);
 
+// --- bandwidth probes (probe.hip) ---
+void launch_probe_stream(const void *buf, uint64_t bytes, float *sink, hipStream_t s);
+void launch_probe_gather(const void *table, uint32_t n_lines, uint32_t blocks, uint32_t steps, int chase,
+                         float *sink, hipStream_t s);
+
 // --- point-cloud compaction (compact.hip) ---
 // counts: compact_blocks(n) device words of scratch; count: one device word
 uint64_t compact_blocks(uint64_t n);

@@ -63,6 +63,27 @@ def outputs_struct(out: dict) -> A.Outputs:
     return s
 
 
+def probe_stream_launcher(buf: torch.Tensor, sink: torch.Tensor, stream=None):
+    """Callable that launches the HBM read probe over `buf` (lidar_probe_stream); one ctypes call each."""
+    assert buf.is_cuda and buf.is_contiguous() and sink.is_cuda
+    args = (C.c_void_p(buf.data_ptr()), C.c_uint64(buf.numel() * buf.element_size()), C.c_void_p(sink.data_ptr()),
+            _stream(stream))
+    fn = lib.lidar_probe_stream
+    check(fn(*args))
+    return lambda *_: fn(*args)
+
+
+def probe_gather_launcher(table: torch.Tensor, blocks: int, steps: int, chase: bool, sink: torch.Tensor,
+                          stream=None):
+    """Callable that launches the 128-byte line gather probe over `table` (lidar_probe_gather)."""
+    assert table.is_cuda and table.is_contiguous() and sink.is_cuda
+    args = (C.c_void_p(table.data_ptr()), C.c_uint64(table.numel() * table.element_size()), C.c_uint32(blocks),
+            C.c_uint32(steps), C.c_int32(1 if chase else 0), C.c_void_p(sink.data_ptr()), _stream(stream))
+    fn = lib.lidar_probe_gather
+    check(fn(*args))
+    return lambda *_: fn(*args)
+
+
 def sensor_struct(sensor):
     """lidar_sensor_desc from an object with the sensor attributes (keeps the elevation array alive)."""
     elev = np.ascontiguousarray(np.asarray(sensor.elev_deg, dtype=np.float64))

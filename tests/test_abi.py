@@ -137,3 +137,21 @@ def test_actor_workspace_sizes_host_only(A):
     d.n_vertices, d.n_triangles, d.flags = 100, 50, A.SCENE_DEVICE_PTRS
     assert A.lib.lidar_mesh_bytes(C.byref(d), C.byref(p), C.byref(s)) == A.OK
     assert p.value >= 50 * (128 + 48 + 4 + 12)
+
+
+def test_probe_arguments_checked_on_the_host(A):
+    """The bandwidth probes reject bad arguments before any launch (no GPU needed)."""
+    P = C.c_void_p
+    aligned, misaligned, sink = P(1 << 20), P((1 << 20) + 4), P(1 << 21)
+    assert A.lib.lidar_probe_stream(None, 1 << 20, sink, None) == A.ERR_INVALID_ARG
+    assert A.lib.lidar_probe_stream(aligned, 1 << 20, None, None) == A.ERR_INVALID_ARG
+    assert A.lib.lidar_probe_stream(misaligned, 1 << 20, sink, None) == A.ERR_INVALID_ARG
+    assert A.lib.lidar_probe_stream(aligned, 8, sink, None) == A.ERR_INVALID_ARG
+    g = A.lib.lidar_probe_gather
+    assert g(None, 1 << 20, 8, 4, 0, sink, None) == A.ERR_INVALID_ARG
+    assert g(misaligned, 1 << 20, 8, 4, 1, sink, None) == A.ERR_INVALID_ARG
+    assert g(aligned, 64, 8, 4, 0, sink, None) == A.ERR_INVALID_ARG             # less than one line
+    assert g(aligned, (1 << 31) + 128, 8, 4, 0, sink, None) == A.ERR_INVALID_ARG  # beyond 32-bit offsets
+    assert g(aligned, 1 << 20, 0, 4, 0, sink, None) == A.ERR_INVALID_ARG
+    assert g(aligned, 1 << 20, 8, 0, 0, sink, None) == A.ERR_INVALID_ARG
+    assert g(aligned, 1 << 20, 8, 4, 0, None, None) == A.ERR_INVALID_ARG
