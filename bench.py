@@ -165,8 +165,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
-                                   "DESIGN.md but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "runs on one GPU only: sharding across GPUs is designed but not implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     legs = ({"plain", "roofs", "cpu", "batch", "adjoint", "sweep", "echo", "dynamic", "sequence"}
             if args.legs == "all" else set(args.legs.split(",")))
