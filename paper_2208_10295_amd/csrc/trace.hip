@@ -178,6 +178,36 @@ __device__ inline float slab(const RayBox &B, float4 lo, float4 hi, float t_lo, 
     return tn <= tf ? __int_as_float(tn) : __builtin_inff();
 }
 
+// The same test for a wavefront whose beams all have the direction signs
+// MODE (bit a set: component a of 1/d negative).  The near plane of each slab
+// is then lo or hi by the sign alone, and since fma is monotonic in its first
+// argument the near and far distances are the values the min / max above
+// select: the keys are bit-identical, at 5 fewer instructions per box.
+// MODE 8: signs differ within the wavefront, the general test.
+template <int MODE>
+__device__ inline float slab_t(const RayBox &B, float4 lo, float4 hi, float t_lo, float tmax_lim) {
+    if constexpr (MODE == 8) {
+        return slab(B, lo, hi, t_lo, tmax_lim);
+    } else {
+        const float nx = fmaf((MODE & 1) ? hi.x : lo.x, B.ix, B.nox), fx = fmaf((MODE & 1) ? lo.x : hi.x, B.ix, B.nox);
+        const float ny = fmaf((MODE & 2) ? hi.y : lo.y, B.iy, B.noy), fy = fmaf((MODE & 2) ? lo.y : hi.y, B.iy, B.noy);
+        const float nz = fmaf((MODE & 4) ? hi.z : lo.z, B.iz, B.noz), fz = fmaf((MODE & 4) ? lo.z : hi.z, B.iz, B.noz);
+        const int tn = max(__float_as_int(fmaxf(fmaxf(nx, ny), nz)), __float_as_int(t_lo));
+        const int tf = min(__float_as_int(fminf(fminf(fx, fy), fz)), __float_as_int(tmax_lim));
+        return tn <= tf ? __int_as_float(tn) : __builtin_inff();
+    }
+}
+
+// Direction-sign mode of a wavefront's walk: 0..7 if all its active lanes
+// share the signs of 1/d (then the specialised test applies), 8 otherwise.
+// Wavefront-uniform.
+__device__ inline int sign_mode(const RayBox &B) {
+    const int sg = (int)((__float_as_uint(B.ix) >> 31) | ((__float_as_uint(B.iy) >> 31) << 1) |
+                         ((__float_as_uint(B.iz) >> 31) << 2));
+    const int s0 = __builtin_amdgcn_readfirstlane(sg);
+    return __ballot(sg != s0) == 0 ? s0 : 8;
+}
+
 // Orders the four children nearest first; returns whether any was hit.  The
 // caller pushes c3, c2, c1 (those hit) and descends into c0.
 __device__ inline void sort4(float &k0, uint32_t &c0, float &k1, uint32_t &c1, float &k2, uint32_t &c2, float &k3,
@@ -314,13 +344,13 @@ __device__ inline float group_min_t(float t) {
 // One quad node step (see above): returns the nearest child hit by the beam,
 // or kEmptyRef if it hits none, and pushes the further children hit; each
 // lane stores its own child (push_level).
-template <int NSLOT>
+template <int NSLOT, int MODE = 8>
 __device__ inline uint32_t quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
                                           float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
                                           int &peak) {
     const uint32_t off = ref * (uint32_t)sizeof(Node4) + s * 32u;   // child slot s of node ref
     const float4 a = buf_load4(nodes, off), b = buf_load4(nodes, off + 16u);
-    const float key = slab(B, a, b, t_lo, lim);
+    const float key = slab_t<MODE>(B, a, b, t_lo, lim);
     const uint32_t cref = __float_as_uint(a.w);
     const uint32_t kk = (__float_as_uint(key) & ~3u) | s;
     // keys are below 2^31 (non-negative floats), so partner < kk is the sign of partner - kk
@@ -341,7 +371,7 @@ __device__ inline uint32_t quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t
 // 2s + 1 and ranks its two keys against the other three (its own other key
 // and the partner's two, through one quad_perm swap each); otherwise as the
 // quad step.
-template <int NSLOT>
+template <int NSLOT, int MODE = 8>
 __device__ inline uint32_t pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
                                           float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
                                           int &peak) {
@@ -349,8 +379,8 @@ __device__ inline uint32_t pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t
     const float4 a0 = buf_load4(nodes, off), b0 = buf_load4(nodes, off + 16u);
     const float4 a1 = buf_load4(nodes, off + 32u), b1 = buf_load4(nodes, off + 48u);
     const uint32_t ca = __float_as_uint(a0.w), cb = __float_as_uint(a1.w);
-    const uint32_t ka = (__float_as_uint(slab(B, a0, b0, t_lo, lim)) & ~3u) | (2u * s);
-    const uint32_t kb = (__float_as_uint(slab(B, a1, b1, t_lo, lim)) & ~3u) | (2u * s + 1u);
+    const uint32_t ka = (__float_as_uint(slab_t<MODE>(B, a0, b0, t_lo, lim)) & ~3u) | (2u * s);
+    const uint32_t kb = (__float_as_uint(slab_t<MODE>(B, a1, b1, t_lo, lim)) & ~3u) | (2u * s + 1u);
     const uint32_t pa = quad_xor1(ka), pb = quad_xor1(kb);
     const int ra = (int)(((kb - ka) >> 31) + ((pa - ka) >> 31) + ((pb - ka) >> 31));   // as in the quad step
     const int rb = (int)(((ka - kb) >> 31) + ((pa - kb) >> 31) + ((pb - kb) >> 31));
@@ -364,11 +394,11 @@ __device__ inline uint32_t pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t
     return nxt;
 }
 
-template <int LANES, int STACK, int NSLOT, bool COUNT>
-__device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
-                                     uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
-                                     uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt,
-                                     int cap = STACK) {
+template <int LANES, int STACK, int NSLOT, bool COUNT, int MODE>
+__device__ inline Hit traverse_multi_mode(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
+                                          uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
+                                          uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt,
+                                          int cap) {
     static_assert(LANES == 2 || LANES == 4, "2 or 4 lanes per beam");
     const __amdgpu_buffer_rsrc_t nbuf = raw_buffer(nodes), tbuf = raw_buffer(tris);
     const RayBox B = prep_box_test(ray);
@@ -410,8 +440,8 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
             --sp;
         } else {
             if (COUNT) cnt.nodes += 1;
-            nxt = LANES == 4 ? quad_node_step<NSLOT>(nbuf, ref, B, t_lo, lim, s, stk, sp, cap + 1, peak)
-                             : pair_node_step<NSLOT>(nbuf, ref, B, t_lo, lim, s, stk, sp, cap + 1, peak);
+            nxt = LANES == 4 ? quad_node_step<NSLOT, MODE>(nbuf, ref, B, t_lo, lim, s, stk, sp, cap + 1, peak)
+                             : pair_node_step<NSLOT, MODE>(nbuf, ref, B, t_lo, lim, s, stk, sp, cap + 1, peak);
         }
         ref = nxt == kEmptyRef ? top : nxt;
     }
@@ -429,6 +459,33 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
         }
     }
     return h;
+}
+
+// The walk with its box test specialised for the wavefront's direction signs
+// when SPECIALISE (one copy of the loop per sign pattern, chosen once per
+// walk), else with the general test.
+template <int LANES, int STACK, int NSLOT, bool COUNT, bool SPECIALISE = false>
+__device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
+                                     uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
+                                     uint32_t *__restrict__ stk, uint32_t s, bool &overflow, Counts &cnt,
+                                     int cap = STACK) {
+#define LIDAR_WALK(M) traverse_multi_mode<LANES, STACK, NSLOT, COUNT, M>(nodes, tris, root, max_steps, ray, t_lo, \
+                                                                        t_hi, stk, s, overflow, cnt, cap)
+    if constexpr (SPECIALISE) {
+        switch (sign_mode(prep_box_test(ray))) {
+        case 0: return LIDAR_WALK(0);
+        case 1: return LIDAR_WALK(1);
+        case 2: return LIDAR_WALK(2);
+        case 3: return LIDAR_WALK(3);
+        case 4: return LIDAR_WALK(4);
+        case 5: return LIDAR_WALK(5);
+        case 6: return LIDAR_WALK(6);
+        case 7: return LIDAR_WALK(7);
+        default: break;
+        }
+    }
+    return LIDAR_WALK(8);
+#undef LIDAR_WALK
 }
 
 // ---------------------------------------------------------------------------
@@ -716,8 +773,11 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
         const Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
         bool overflow = false;
         Counts c{0u, 0u};
-        Hit h = traverse_multi<LANES, STACK, NR, COUNT>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
-                                                        in.t_trace, stk + q, s, overflow, c, min(S.stack_cap, STACK));
+        // the static walk, specialised for the wavefront's direction signs (not in the counting and actor
+        // variants, which keep one copy of the loop)
+        Hit h = traverse_multi<LANES, STACK, NR, COUNT, !COUNT && !ACTORS>(
+            S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q, s, overflow, c,
+            min(S.stack_cap, STACK));
         if constexpr (ACTORS) traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
         if (overflow) atomicOr(err, 1u);
         if (s == 0) {
@@ -811,7 +871,7 @@ __global__ __launch_bounds__(BLOCK) void trace_subrays_kernel(SceneDev S, Instan
         h = traverse<STACK, NR, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q,
                                        overflow, c, min(S.stack_cap, STACK));
     else
-        h = traverse_multi<LANES, STACK, NR, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
+        h = traverse_multi<LANES, STACK, NR, false, !ACTORS>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
                                                     in.t_trace, stk + q, s, overflow, c, min(S.stack_cap, STACK));
     const ActorDev *act = nullptr;
     const TriRec *tris = S.tris;
@@ -1082,7 +1142,7 @@ void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts, uint3
                                                           in.t_trace, stk + slot, overflow, cnt,
                                                           min(S.stack_cap, STACK));
                     else
-                        h = traverse_multi<LANES, STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray,
+                        h = traverse_multi<LANES, STACK, NSLOT, false, true>(S.nodes, S.tris, S.root, S.max_steps, ray,
                                                                        in.t_min, in.t_trace, stk + slot, s, overflow,
                                                                        cnt, min(S.stack_cap, STACK));
                 }
