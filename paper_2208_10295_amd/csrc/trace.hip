@@ -894,7 +894,7 @@ __global__ __launch_bounds__(BLOCK) void trace_subrays_kernel(SceneDev S, Instan
 
 // ---------------------------------------------------------------------------
 // Kernel 1f: echoes of one beam from its sub-ray hits.  The hits, ordered by
-// (t, k) with an odd-even transposition network over KMAX registers, form
+// (t, k) with a sorting network over KMAX registers, form
 // echoes split where consecutive ranges differ by more than echo_sep.  Echo e:
 // strength P = (1/K) sum R_k, range t_first + sum R_k (t_k - t_first) / sum R_k
 // (plain mean if every R is 0), label/material/index of its strongest sub-ray
@@ -921,20 +921,34 @@ __global__ __launch_bounds__(128) void echo_kernel(InstanceDev in, MaterialsDev 
             t[q] = __builtin_inff(); rl[q] = 0.0f; orig[q] = kNone; lab[q] = kNone; mat[q] = 0xFFFFu;
         }
     }
-#pragma unroll
-    for (int round = 0; round < KMAX; ++round) {
-#pragma unroll
-        for (int q = round & 1; q + 1 < KMAX; q += 2) {
-            const bool sw = t[q + 1] < t[q] || (t[q + 1] == t[q] && kk[q + 1] < kk[q]);
-#define LIDAR_CSWAP(A)                                  \
-            {                                           \
-                auto lo_ = sw ? A[q + 1] : A[q];        \
-                auto hi_ = sw ? A[q] : A[q + 1];        \
-                A[q] = lo_;                             \
-                A[q + 1] = hi_;                         \
-            }
-            LIDAR_CSWAP(t) LIDAR_CSWAP(rl) LIDAR_CSWAP(kk) LIDAR_CSWAP(orig) LIDAR_CSWAP(lab) LIDAR_CSWAP(mat)
+    // compare-exchange of entries q < r by (t, k); (t, k) pairs are distinct, so any sorting network gives
+    // the same order
+    auto cx = [&](int q, int r) {
+        const bool sw = t[r] < t[q] || (t[r] == t[q] && kk[r] < kk[q]);
+#define LIDAR_CSWAP(A)                          \
+        {                                       \
+            auto lo_ = sw ? A[r] : A[q];        \
+            auto hi_ = sw ? A[q] : A[r];        \
+            A[q] = lo_;                         \
+            A[r] = hi_;                         \
+        }
+        LIDAR_CSWAP(t) LIDAR_CSWAP(rl) LIDAR_CSWAP(kk) LIDAR_CSWAP(orig) LIDAR_CSWAP(lab) LIDAR_CSWAP(mat)
 #undef LIDAR_CSWAP
+    };
+    if constexpr (KMAX == 4) {          // 5 comparators, depth 3
+        cx(0, 1); cx(2, 3); cx(0, 2); cx(1, 3); cx(1, 2);
+    } else if constexpr (KMAX == 8) {   // 19 comparators, depth 6 (checked by the 0-1 principle)
+        cx(0, 2); cx(1, 3); cx(4, 6); cx(5, 7);
+        cx(0, 4); cx(1, 5); cx(2, 6); cx(3, 7);
+        cx(0, 1); cx(2, 3); cx(4, 5); cx(6, 7);
+        cx(2, 4); cx(3, 5);
+        cx(1, 4); cx(3, 6);
+        cx(1, 2); cx(3, 4); cx(5, 6);
+    } else {                            // odd-even transposition, KMAX rounds
+#pragma unroll
+        for (int round = 0; round < KMAX; ++round) {
+#pragma unroll
+            for (int q = round & 1; q + 1 < KMAX; q += 2) cx(q, q + 1);
         }
     }
     const uint32_t j = beam / in.n_az, i = beam - j * in.n_az;
