@@ -45,10 +45,17 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources' code: comments and blank lines are dropped, so that editing a comment does
+    not orphan the profiles taken on unchanged kernels."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

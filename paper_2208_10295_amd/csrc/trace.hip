@@ -1,6 +1,6 @@
 // trace.hip -- first-hit query and return model for every beam (gfx950).
 //
-// Two traversal shapes share one intersection test and one epilogue:
+// Three traversal shapes share one intersection test and one epilogue:
 //   * lane-per-ray: one lane walks the 4-wide BVH for its beam and tests the
 //     four child boxes itself;
 //   * quad-per-ray: the four lanes of a DPP quad share a beam; lane s tests
@@ -8,8 +8,13 @@
 //     leaf, and the quad agrees on the traversal order through quad_perm
 //     exchanges.  This gives 4x the wavefronts for the same beams, which a
 //     single 131k-beam scan needs to hide the latency of dependent node
-//     fetches.
-// Both visit the same nodes in the same order and return bit-identical hits.
+//     fetches;
+//   * pair-per-ray: two lanes, two child boxes each (the batched form, which
+//     has parallelism to spare, prefers its fewer instructions per beam).
+// All return bit-identical hits.  The walks keep their stack in LDS without
+// branches (push_level) and, where a wavefront's beams share the signs of
+// their direction components, run a copy of the loop whose box test takes
+// the near planes by sign (slab_t).
 //
 // Beams are grouped in 64-beam tiles of tile_ch channels x tile_az azimuth
 // steps, numbered column-major (all channel rows of an azimuth column, then
