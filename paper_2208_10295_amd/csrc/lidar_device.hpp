@@ -274,6 +274,13 @@ __device__ inline float pick(float x, float y, float z, int k) {
     return k == 0 ? x : (k == 1 ? y : z);
 }
 
+// component K (0, 1, 2) if known at compile time, else component k
+template <int K>
+__device__ inline float pick_c(float x, float y, float z, int k) {
+    if constexpr (K < 0) return pick(x, y, z, k);
+    else return K == 0 ? x : (K == 1 ? y : z);
+}
+
 __device__ inline RayTri prep_tri_test(const Ray &r) {
     RayTri R;
     R.ox = r.ox; R.oy = r.oy; R.oz = r.oz;
@@ -295,13 +302,19 @@ __device__ inline RayTri prep_tri_test(const Ray &r) {
 // FP64 recomputation of an edge function that rounds to zero, the test runs
 // without branches (a wavefront tests its lanes' triangles together, so early
 // exits would only add exec-mask work).
+// KX, KY, KZ >= 0: the caller guarantees R.kx == KX etc. (a wavefront whose
+// beams share the axis permutation), and the component selections are fixed.
+template <int KX = -1, int KY = -1, int KZ = -1>
 __device__ inline bool tri_hit(const RayTri &R, float4 a, float4 b, float4 c, float t_lo, float &t_out) {
     float Ax0 = a.x - R.ox, Ay0 = a.y - R.oy, Az0 = a.z - R.oz;
     float Bx0 = b.x - R.ox, By0 = b.y - R.oy, Bz0 = b.z - R.oz;
     float Cx0 = c.x - R.ox, Cy0 = c.y - R.oy, Cz0 = c.z - R.oz;
-    float Akx = pick(Ax0, Ay0, Az0, R.kx), Aky = pick(Ax0, Ay0, Az0, R.ky), Akz = pick(Ax0, Ay0, Az0, R.kz);
-    float Bkx = pick(Bx0, By0, Bz0, R.kx), Bky = pick(Bx0, By0, Bz0, R.ky), Bkz = pick(Bx0, By0, Bz0, R.kz);
-    float Ckx = pick(Cx0, Cy0, Cz0, R.kx), Cky = pick(Cx0, Cy0, Cz0, R.ky), Ckz = pick(Cx0, Cy0, Cz0, R.kz);
+    float Akx = pick_c<KX>(Ax0, Ay0, Az0, R.kx), Aky = pick_c<KY>(Ax0, Ay0, Az0, R.ky);
+    float Akz = pick_c<KZ>(Ax0, Ay0, Az0, R.kz);
+    float Bkx = pick_c<KX>(Bx0, By0, Bz0, R.kx), Bky = pick_c<KY>(Bx0, By0, Bz0, R.ky);
+    float Bkz = pick_c<KZ>(Bx0, By0, Bz0, R.kz);
+    float Ckx = pick_c<KX>(Cx0, Cy0, Cz0, R.kx), Cky = pick_c<KY>(Cx0, Cy0, Cz0, R.ky);
+    float Ckz = pick_c<KZ>(Cx0, Cy0, Cz0, R.kz);
     float Ax = fmaf(-R.Sx, Akz, Akx), Ay = fmaf(-R.Sy, Akz, Aky);
     float Bx = fmaf(-R.Sx, Bkz, Bkx), By = fmaf(-R.Sy, Bkz, Bky);
     float Cx = fmaf(-R.Sx, Ckz, Ckx), Cy = fmaf(-R.Sy, Ckz, Cky);

@@ -183,15 +183,26 @@ __device__ inline float slab(const RayBox &B, float4 lo, float4 hi, float t_lo, 
     return tn <= tf ? __int_as_float(tn) : __builtin_inff();
 }
 
-// The same test for a wavefront whose beams all have the direction signs
-// MODE (bit a set: component a of 1/d negative).  The near plane of each slab
-// is then lo or hi by the sign alone, and since fma is monotonic in its first
-// argument the near and far distances are the values the min / max above
-// select: the keys are bit-identical, at 5 fewer instructions per box.
-// MODE 8: signs differ within the wavefront, the general test.
+// Walk modes.  A wavefront whose beams share the signs of their direction
+// components (bits 0..2: component a of 1/d negative) and the dominant axis kz
+// of the triangle test (bit 3: 0 = x, 1 = y) runs mode 0..15; a wavefront with
+// kz = z (beams steeper than 45 degrees) or with mixed signs or axes runs
+// kGeneralMode.
+constexpr int kGeneralMode = 16;
+constexpr int mode_kz(int m) { return m >> 3; }
+constexpr bool mode_neg(int m, int axis) { return ((m >> axis) & 1) != 0; }
+// the triangle test's axis permutation in mode m (as prep_tri_test: kx, ky
+// follow kz cyclically and swap when the dominant component is negative)
+constexpr int mode_kx(int m) { return mode_neg(m, mode_kz(m)) ? (mode_kz(m) + 2) % 3 : (mode_kz(m) + 1) % 3; }
+constexpr int mode_ky(int m) { return mode_neg(m, mode_kz(m)) ? (mode_kz(m) + 1) % 3 : (mode_kz(m) + 2) % 3; }
+
+// The box test in mode MODE.  The near plane of each slab is lo or hi by the
+// sign alone, and since fma is monotonic in its first argument the near and
+// far distances are the values the min / max above select: the keys are
+// bit-identical, at 5 fewer instructions per box.
 template <int MODE>
 __device__ inline float slab_t(const RayBox &B, float4 lo, float4 hi, float t_lo, float tmax_lim) {
-    if constexpr (MODE == 8) {
+    if constexpr (MODE == kGeneralMode) {
         return slab(B, lo, hi, t_lo, tmax_lim);
     } else {
         const float nx = fmaf((MODE & 1) ? hi.x : lo.x, B.ix, B.nox), fx = fmaf((MODE & 1) ? lo.x : hi.x, B.ix, B.nox);
@@ -203,14 +214,13 @@ __device__ inline float slab_t(const RayBox &B, float4 lo, float4 hi, float t_lo
     }
 }
 
-// Direction-sign mode of a wavefront's walk: 0..7 if all its active lanes
-// share the signs of 1/d (then the specialised test applies), 8 otherwise.
-// Wavefront-uniform.
-__device__ inline int sign_mode(const RayBox &B) {
-    const int sg = (int)((__float_as_uint(B.ix) >> 31) | ((__float_as_uint(B.iy) >> 31) << 1) |
-                         ((__float_as_uint(B.iz) >> 31) << 2));
-    const int s0 = __builtin_amdgcn_readfirstlane(sg);
-    return __ballot(sg != s0) == 0 ? s0 : 8;
+// The mode of a wavefront's walk (wavefront-uniform).
+__device__ inline int walk_mode(const RayBox &B, const RayTri &T) {
+    int m = (int)((__float_as_uint(B.ix) >> 31) | ((__float_as_uint(B.iy) >> 31) << 1) |
+                  ((__float_as_uint(B.iz) >> 31) << 2));
+    m = T.kz < 2 ? m | (T.kz << 3) : kGeneralMode;
+    const int m0 = __builtin_amdgcn_readfirstlane(m);
+    return (__ballot(m != m0) == 0 && m0 != kGeneralMode) ? m0 : kGeneralMode;
 }
 
 // Orders the four children nearest first; returns whether any was hit.  The
@@ -349,7 +359,7 @@ __device__ inline float group_min_t(float t) {
 // One quad node step (see above): returns the nearest child hit by the beam,
 // or kEmptyRef if it hits none, and pushes the further children hit; each
 // lane stores its own child (push_level).
-template <int NSLOT, int MODE = 8>
+template <int NSLOT, int MODE = kGeneralMode>
 __device__ inline uint32_t quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
                                           float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
                                           int &peak) {
@@ -376,7 +386,7 @@ __device__ inline uint32_t quad_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t
 // 2s + 1 and ranks its two keys against the other three (its own other key
 // and the partner's two, through one quad_perm swap each); otherwise as the
 // quad step.
-template <int NSLOT, int MODE = 8>
+template <int NSLOT, int MODE = kGeneralMode>
 __device__ inline uint32_t pair_node_step(__amdgpu_buffer_rsrc_t nodes, uint32_t ref, const RayBox &B, float t_lo,
                                           float lim, uint32_t s, uint32_t *__restrict__ stk, int &sp, int cap,
                                           int &peak) {
@@ -434,7 +444,9 @@ __device__ inline Hit traverse_multi_mode(const Node4 *__restrict__ nodes, const
                 const float4 a = buf_load4(tbuf, off), b = buf_load3(tbuf, off + 16u), c = buf_load3(tbuf, off + 32u);
                 float t;
                 const uint32_t orig = __float_as_uint(a.w);
-                const bool hit = tri_hit(T, a, b, c, t_lo, t);
+                bool hit;
+                if constexpr (MODE == kGeneralMode) hit = tri_hit(T, a, b, c, t_lo, t);
+                else hit = tri_hit<mode_kx(MODE), mode_ky(MODE), mode_kz(MODE)>(T, a, b, c, t_lo, t);
                 const bool take = hit && better(t, orig, h.t, h.orig);
                 h.t = take ? t : h.t;
                 h.orig = take ? orig : h.orig;
@@ -466,9 +478,9 @@ __device__ inline Hit traverse_multi_mode(const Node4 *__restrict__ nodes, const
     return h;
 }
 
-// The walk with its box test specialised for the wavefront's direction signs
-// when SPECIALISE (one copy of the loop per sign pattern, chosen once per
-// walk), else with the general test.
+// The walk specialised for the wavefront's mode when SPECIALISE (one copy of
+// the loop per mode: box test by direction signs, triangle test with a fixed
+// axis permutation; chosen once per walk), else the general loop.
 template <int LANES, int STACK, int NSLOT, bool COUNT, bool SPECIALISE = false>
 __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriRec *__restrict__ tris,
                                      uint32_t root, uint32_t max_steps, const Ray &ray, float t_lo, float t_hi,
@@ -477,7 +489,7 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
 #define LIDAR_WALK(M) traverse_multi_mode<LANES, STACK, NSLOT, COUNT, M>(nodes, tris, root, max_steps, ray, t_lo, \
                                                                         t_hi, stk, s, overflow, cnt, cap)
     if constexpr (SPECIALISE) {
-        switch (sign_mode(prep_box_test(ray))) {
+        switch (walk_mode(prep_box_test(ray), prep_tri_test(ray))) {
         case 0: return LIDAR_WALK(0);
         case 1: return LIDAR_WALK(1);
         case 2: return LIDAR_WALK(2);
@@ -486,10 +498,18 @@ __device__ inline Hit traverse_multi(const Node4 *__restrict__ nodes, const TriR
         case 5: return LIDAR_WALK(5);
         case 6: return LIDAR_WALK(6);
         case 7: return LIDAR_WALK(7);
+        case 8: return LIDAR_WALK(8);
+        case 9: return LIDAR_WALK(9);
+        case 10: return LIDAR_WALK(10);
+        case 11: return LIDAR_WALK(11);
+        case 12: return LIDAR_WALK(12);
+        case 13: return LIDAR_WALK(13);
+        case 14: return LIDAR_WALK(14);
+        case 15: return LIDAR_WALK(15);
         default: break;
         }
     }
-    return LIDAR_WALK(8);
+    return LIDAR_WALK(kGeneralMode);
 #undef LIDAR_WALK
 }
 
@@ -778,8 +798,8 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
         const Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
         bool overflow = false;
         Counts c{0u, 0u};
-        // the static walk, specialised for the wavefront's direction signs (not in the counting and actor
-        // variants, which keep one copy of the loop)
+        // the static walk, specialised for the wavefront's mode (not in the counting and actor variants,
+        // which keep one copy of the loop)
         Hit h = traverse_multi<LANES, STACK, NR, COUNT, !COUNT && !ACTORS>(
             S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q, s, overflow, c,
             min(S.stack_cap, STACK));
