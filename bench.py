@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--leaf-width", type=int, default=4)
     ap.add_argument("--builder", default="ploc", choices=("ploc", "lbvh"))
     ap.add_argument("--ploc-radius", type=int, default=32)
+    ap.add_argument("--collapse", default="sah", choices=("sah", "greedy"))
+    ap.add_argument("--leaf-cost", type=float, default=0.0, help="leaf-step weight of the SAH collapse (0 = default)")
     ap.add_argument("--tile-az", type=int, default=0, help="64-beam tile width in azimuth steps; 0 = automatic")
     ap.add_argument("--lanes", type=int, default=4, help="lanes per ray (1, 2 or 4)")
     ap.add_argument("--xcd", type=int, default=1, help="XCD-aware block remap (0 or 1)")
@@ -188,7 +190,8 @@ def main():
     scene, sensor, pose = S.config2()
     log(f"config2: {scene.n_tri} triangles, {sensor.n_beams} beams")
     ctx = L.Context(0)
-    st = ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius)
+    st = ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius, collapse=args.collapse,
+                  leaf_cost=args.leaf_cost)
     ctx.set_sensor(sensor)
     ctx.set_pose(pose.p, pose.q)
     ctx.set_tile_shape(args.tile_az)
@@ -203,7 +206,7 @@ def main():
                                     "(256x256 terrain cells, 400 buildings, 2,000 poles, 200 cars), 32 materials, "
                                     "905 nm, d_max 100 m, range noise 0.02 m",
                         "beams": n, "triangles": scene.n_tri, "leaf_width": st["leaf_width"], "bvh_builder": args.builder,
-                        "ploc_radius": args.ploc_radius,
+                        "ploc_radius": args.ploc_radius, "collapse": args.collapse,
                         "tile_az": args.tile_az or "auto (2; 16 for the batch, 8 with actors)",
                         "lanes_per_ray": args.lanes, "xcd_remap": args.xcd,
                         "bvh_nodes": st["n_nodes"], "bvh_depth": st["depth"]}
@@ -547,7 +550,7 @@ def main():
     if "sequence" in legs:
         sc3, s3, poses = S.config3()
         cs = L.Context(0)
-        st3 = cs.load(sc3)
+        st3 = cs.load(sc3, collapse=args.collapse, leaf_cost=args.leaf_cost)
         cs.set_sensor(s3)
         out3 = alloc_outputs(s3.n_beams, POINT_OUTPUTS, cs.device)
         cs.set_pose(poses[0].p, poses[0].q)

@@ -88,7 +88,11 @@ const char *lidar_last_error(const lidar_ctx *ctx);
 
 #define LIDAR_SCENE_DEVICE_PTRS 1u   /* the four arrays below are device pointers */
 #define LIDAR_SCENE_BUILD_LBVH  2u   /* build the binary tree as an LBVH instead of by PLOC clustering */
-/* flags bits 8-15: PLOC search radius in Morton order, 1..128 (0 = 32) */
+#define LIDAR_SCENE_COLLAPSE_GREEDY 4u /* collapse to 4-wide nodes greedily (largest child first) instead
+                                        of by the surface-area cost */
+/* flags bits 8-15: PLOC search radius in Morton order, 1..128 (0 = 32)
+ * flags bits 16-23: weight of a leaf step against a node step in the
+ *   surface-area cost of the collapse, in sixteenths (0 = 24, i.e. 1.5) */
 
 typedef struct {
     uint64_t n_vertices;
@@ -112,8 +116,9 @@ lidar_status lidar_scene_bytes(const lidar_scene_desc *desc, uint64_t *persisten
 /* Builds the BVH on the GPU into `persistent`, replacing any previous scene:
  * Morton codes and a radix sort, then a binary tree by PLOC clustering
  * (default) or as an LBVH, then a collapse to a 4-wide BVH with leaves of at
- * most leaf_width triangles.  Every build option gives the same simulation
- * results (only the speed differs).
+ * most leaf_width triangles, shaped by a surface-area cost (default) or
+ * greedily.  Every build option gives the same simulation results (only the
+ * speed differs).
  * Validates every triangle index on the device.  Synchronises `stream` (it
  * reads back the tree size and depth).  Errors: INVALID_ARG (bad sizes,
  * index out of range), WORKSPACE_TOO_SMALL, STACK_OVERFLOW (tree deeper than

@@ -31,6 +31,7 @@ NO_TRIANGLE = 0xFFFFFFFF
 NO_MATERIAL = 0xFFFF
 SCENE_DEVICE_PTRS = 1
 SCENE_BUILD_LBVH = 2
+SCENE_COLLAPSE_GREEDY = 4
 OPT_TILE_AZ = 1
 OPT_LANES_PER_RAY = 2
 OPT_XCD_REMAP = 3

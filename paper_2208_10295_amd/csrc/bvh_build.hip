@@ -18,12 +18,22 @@
 //        identical codes split by position, then a bottom-up bounding-box
 //        refit where the second child to arrive at a node computes its box
 // 5. (nothing: both trees have their boxes)
-// 6. level-synchronous collapse to 4 children: starting from the node's two
-//    children, the child with the largest surface area that holds more than
-//    leaf_width triangles is replaced by its two children until there are 4;
-//    children with <= leaf_width triangles become leaves.  New nodes of a level
-//    are numbered by an exclusive scan, so the layout is deterministic and
-//    breadth-first.
+// 6. level-synchronous collapse to 4 children.  By default the shape comes
+//    from a surface-area cost minimised over the binary tree (the dynamic
+//    programme of Ylitie, Karras and Laine, "Efficient incoherent ray
+//    traversal on GPUs through compressed wide BVHs", HPG 2017, for 4 slots):
+//    bottom-up, every binary node n gets the least cost C(n, i) of covering its
+//    subtree with at most i children of a 4-wide node, where a child is either
+//    a leaf of <= leaf_width triangles (cost: leaf weight x area) or a 4-wide
+//    node (node weight x area + the best split of its binary children over 4
+//    slots); the walk fetches a node's 4 boxes, or a leaf's triangles, in one
+//    step, hence one weight per step kind.  The collapse then follows the
+//    recorded choices top-down.  The greedy alternative replaces, starting
+//    from the node's two children, the child with the largest surface area
+//    that holds more than leaf_width triangles by its two children until there
+//    are 4; children with <= leaf_width triangles become leaves.  New nodes of
+//    a level are numbered by an exclusive scan, so the layout is deterministic
+//    and breadth-first.
 // Child boxes are padded outward by 2^-20 of the largest vertex coordinate,
 // which exceeds the rounding error of the FP32 box and triangle tests for rays
 // starting inside the scene's extent.
@@ -685,6 +695,162 @@ __global__ __launch_bounds__(256) void ploc_bintree_kernel(uint32_t n, const uin
     T.last[k] = first[id] + ncount[id] - 1;
     const float *b = nbox + 6 * (size_t)id;
     for (int a = 0; a < 6; ++a) T.box[6 * (size_t)k + a] = b[a];
+    // parent links for the bottom-up cost pass
+    if (l < n) T.parent_leaf[first[l]] = k; else T.parent_int[l - n] = k;
+    if (r < n) T.parent_leaf[first[r]] = k; else T.parent_int[r - n] = k;
+}
+
+// ---------------------------------------------------------------------------
+// Surface-area-cost collapse
+// ---------------------------------------------------------------------------
+// Per binary internal node k: cost[4k + i - 1] = C(k, i), i = 1..4, and a
+// packed choice word:
+//   bit 0        C(k, 1) is a leaf (else a 4-wide node)
+//   bits 1+3(i-2)..  (i = 2..4, 3 bits) the number of children e <= i that
+//                C(k, i) uses: 1 = k itself as one child, e >= 2 = k's two
+//                binary children spread over e slots
+//   bits 10+2(e-2).. (e = 2..4, 2 bits) how many of those e slots go to the
+//                left child in the best spread
+struct SahTables {
+    float *cost;
+    uint32_t *choice;
+};
+
+__device__ inline uint32_t sah_uses(uint32_t w, int i) { return i == 1 ? 1u : (w >> (1 + 3 * (i - 2))) & 7u; }
+__device__ inline uint32_t sah_left(uint32_t w, int e) { return (w >> (10 + 2 * (e - 2))) & 3u; }
+
+__device__ inline float box_half_area(const float lo[3], const float hi[3]) {
+    const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    return ex * ey + ey * ez + ez * ex;
+}
+
+// C(c, 1..4) of a child code: a single triangle is a leaf whatever the slots
+__device__ inline void sah_child_costs(const BinTree &T, const TriRec *__restrict__ recs, const float *cost,
+                                       uint32_t code, float leaf_w, float C[4]) {
+    if (code & kLeafBit) {
+        float lo[3], hi[3];
+        rec_box(recs, code & ~kLeafBit, lo, hi);
+        const float c = leaf_w * box_half_area(lo, hi);
+        for (int i = 0; i < 4; ++i) C[i] = c;
+    } else {
+        // written by another thread of this pass: read past the vector L1
+        for (int i = 0; i < 4; ++i)
+            C[i] = __hip_atomic_load(cost + 4 * (size_t)code + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Bottom-up over the binary tree, one thread per triangle climbing from its
+// leaf; the second thread to reach a node evaluates it (both children done).
+__global__ __launch_bounds__(256) void sah_cost_kernel(BinTree T, const TriRec *__restrict__ recs, int n,
+                                                       uint32_t root, uint32_t W, float leaf_w, SahTables S) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    uint32_t p = T.parent_leaf[s];
+    while (true) {
+        __threadfence();
+        if (atomicAdd(&T.visit[p], 1u) == 0) return;
+        __threadfence();
+        float L[4], R[4];
+        sah_child_costs(T, recs, S.cost, T.left[p], leaf_w, L);
+        sah_child_costs(T, recs, S.cost, T.right[p], leaf_w, R);
+        const float *b = T.box + 6 * (size_t)p;
+        const float area = box_half_area(b, b + 3);
+        // best spread of the two children over e = 2..4 slots (smallest left share on ties)
+        float spread[5];
+        uint32_t w = 0;
+        for (int e = 2; e <= 4; ++e) {
+            int best_k = 1;
+            float best = L[0] + R[e - 2];
+            for (int k = 2; k < e; ++k) {
+                const float c = L[k - 1] + R[e - k - 1];
+                if (c < best) { best = c; best_k = k; }
+            }
+            spread[e] = best;
+            w |= (uint32_t)best_k << (10 + 2 * (e - 2));
+        }
+        const uint32_t count = T.last[p] - T.first[p] + 1u;
+        // a leaf is one walk step for up to 4 triangles (the lanes of a ray test them side by side)
+        const float as_leaf = count <= W ? leaf_w * area * (float)((count + 3u) / 4u) : __builtin_inff();
+        const float as_node = area + spread[4];
+        float C[4];
+        C[0] = fminf(as_leaf, as_node);
+        if (as_leaf <= as_node) w |= 1u;
+        uint32_t uses = 1;
+        for (int i = 2; i <= 4; ++i) {
+            if (spread[i] < C[i - 2]) { C[i - 1] = spread[i]; uses = (uint32_t)i; }
+            else C[i - 1] = C[i - 2];
+            w |= uses << (1 + 3 * (i - 2));
+        }
+        for (int i = 0; i < 4; ++i)
+            __hip_atomic_store(S.cost + 4 * (size_t)p + i, C[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        S.choice[p] = w;
+        if (p == root) return;
+        p = T.parent_int[p];
+    }
+}
+
+// One 4-wide node per frontier entry, shaped by the recorded choices: the
+// node's binary children spread over 4 slots, each part expanded until it is
+// one child.  Output as collapse_kernel.
+__global__ __launch_bounds__(256) void collapse_sah_kernel(BinTree T, const TriRec *__restrict__ recs,
+                                                           const uint32_t *__restrict__ frontier, uint32_t n_front,
+                                                           uint32_t node_base, const uint32_t *__restrict__ choice,
+                                                           const Bounds *__restrict__ bnd, Node4 *__restrict__ nodes,
+                                                           uint32_t *__restrict__ pending,
+                                                           uint32_t *__restrict__ counts, uint32_t *stat) {
+    const uint32_t f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= n_front) return;
+    const float pad = bnd[0].pad_;
+    const uint32_t b = frontier[f];
+    // work list of (code, slots); the slots of all entries plus the children found sum to 4
+    uint32_t wc[4], wi[4];
+    int nw = 0;
+    const uint32_t k4 = sah_left(choice[b], 4);
+    wc[nw] = T.right[b]; wi[nw++] = 4u - k4;
+    wc[nw] = T.left[b]; wi[nw++] = k4;
+    uint32_t C[4];
+    uint32_t nc = 0;
+    while (nw > 0) {
+        --nw;
+        const uint32_t c = wc[nw], i = wi[nw];
+        const uint32_t e = (c & kLeafBit) ? 1u : sah_uses(choice[c], (int)i);
+        const uint32_t k = e >= 2u ? sah_left(choice[c], (int)e) : 0u;
+        // (the guards never fail for choices written by sah_cost_kernel: the slots still open
+        // always cover the list, so it holds at most 4 entries)
+        if (e >= 2u && e <= i && k >= 1u && k < e && nw <= 2) {
+            wc[nw] = T.right[c]; wi[nw++] = e - k;
+            wc[nw] = T.left[c]; wi[nw++] = k;
+        } else if (nc < 4) {
+            C[nc++] = c;
+        }
+    }
+    Node4 nd;
+    uint32_t n_int = 0, n_leaf = 0;
+    for (uint32_t k = 0; k < 4; ++k) {
+        if (k < nc) {
+            float lo[3], hi[3];
+            child_box(T, recs, C[k], lo, hi);
+            for (int a = 0; a < 3; ++a) {
+                nd.c[k].lo[a] = lo[a] - pad;
+                nd.c[k].hi[a] = hi[a] + pad;
+            }
+            if ((C[k] & kLeafBit) || (choice[C[k]] & 1u)) {
+                nd.c[k].ref = leaf_ref(code_first(T, C[k]), code_count(T, C[k]));
+                ++n_leaf;
+            } else {
+                nd.c[k].ref = 0u;   // set by assign_kernel
+                pending[4 * (size_t)f + n_int] = C[k] | ((uint32_t)k << 29);
+                ++n_int;
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) nd.c[k].lo[a] = nd.c[k].hi[a] = 1e30f;
+            nd.c[k].ref = kEmptyRef;
+        }
+        nd.c[k].pad = 0u;
+    }
+    nodes[node_base + f] = nd;
+    counts[f] = n_int;
+    atomicAdd(&stat[2], n_leaf);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,7 +860,7 @@ namespace {
 struct ScratchLayout {
     size_t cent, partials, keys, vals, keys2, vals2, sort_tmp, left, right, first, last, pint, pleaf, box,
         visit, front_a, front_b, pending, counts, offsets, scan_tmp, stat, recs_m, nbox, ncount, nleft, nright,
-        nfirst, ca, cb, nn, leader, keep, loff, koff, total;
+        nfirst, ca, cb, nn, leader, keep, loff, koff, sah_cost, sah_choice, total;
 };
 
 ScratchLayout scratch_layout(uint32_t nt) {
@@ -738,6 +904,8 @@ ScratchLayout scratch_layout(uint32_t nt) {
     L.keep = take(4 * n);
     L.loff = take(4 * n);
     L.koff = take(4 * n);
+    L.sah_cost = take(16 * n);
+    L.sah_choice = take(4 * n);
     L.total = o;
     return L;
 }
@@ -850,6 +1018,13 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
             karras_kernel<<<nb, 256, 0, s>>>(keys, (int)nt, T);
             refit_kernel<<<nb, 256, 0, s>>>(T, recs, (int)nt);
         }
+        const bool sah = in.collapse == 0;
+        SahTables sah_t{(float *)(sc + L.sah_cost), (uint32_t *)(sc + L.sah_choice)};
+        if (sah) {
+            HIP_TRY(hipMemsetAsync(T.visit, 0, 4 * (size_t)nt, s));
+            sah_cost_kernel<<<nb, 256, 0, s>>>(T, recs, (int)nt, root_code, in.leaf_width, in.leaf_cost, sah_t);
+            HIP_TRY(hipGetLastError());
+        }
         uint32_t *fa = (uint32_t *)(sc + L.front_a), *fb = (uint32_t *)(sc + L.front_b);
         uint32_t *pending = (uint32_t *)(sc + L.pending);
         uint32_t *counts = (uint32_t *)(sc + L.counts), *offsets = (uint32_t *)(sc + L.offsets);
@@ -861,8 +1036,12 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
             if (depth >= 1024 || n_nodes + n_front > (nt > 1 ? nt : 1)) return hipErrorIllegalState;
             if (depth <= (uint32_t)kMaxLevels) res.level_base[depth] = base;
             uint32_t g = (n_front + 255) / 256;
-            collapse_kernel<<<g, 256, 0, s>>>(T, recs, fa, n_front, base, in.leaf_width, partials, nodes,
-                                              pending, counts, stat);
+            if (sah)
+                collapse_sah_kernel<<<g, 256, 0, s>>>(T, recs, fa, n_front, base, sah_t.choice, partials, nodes,
+                                                      pending, counts, stat);
+            else
+                collapse_kernel<<<g, 256, 0, s>>>(T, recs, fa, n_front, base, in.leaf_width, partials, nodes,
+                                                  pending, counts, stat);
             scan_exclusive_u32(counts, offsets, n_front, stmp, s);
             uint32_t last_cnt = 0, last_off = 0;
             HIP_TRY(hipMemcpyAsync(&last_cnt, counts + n_front - 1, 4, hipMemcpyDeviceToHost, s));

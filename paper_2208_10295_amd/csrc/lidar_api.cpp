@@ -153,6 +153,14 @@ struct lidar_batch {
 
 namespace {
 
+// collapse options of a scene or mesh build from the descriptor flags
+constexpr float kDefaultLeafCost = 1.5f;   // a leaf step costs about 1.5 node steps of the walk
+void set_collapse(BuildInputs &in, uint32_t flags) {
+    in.collapse = (flags & LIDAR_SCENE_COLLAPSE_GREEDY) ? 1u : 0u;
+    const uint32_t sixteenths = (flags >> 16) & 0xFFu;
+    in.leaf_cost = sixteenths ? (float)sixteenths / 16.0f : kDefaultLeafCost;
+}
+
 bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
 lidar_status check_sensor(lidar_ctx *ctx, const lidar_sensor_desc *d) {
@@ -387,6 +395,7 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     in.ploc_radius = (desc->flags >> 8) & 0xFFu;
     if (in.ploc_radius == 0) in.ploc_radius = 32;
     if (in.ploc_radius > 128) return ctx->fail(LIDAR_ERR_INVALID_ARG, "PLOC radius (flags bits 8-15) must be <= 128");
+    set_collapse(in, desc->flags);
     if (desc->flags & LIDAR_SCENE_DEVICE_PTRS) {
         in.vtx = desc->vertices;
         in.idx = desc->indices;
@@ -847,6 +856,7 @@ lidar_status lidar_mesh_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void 
     in.ploc_radius = (desc->flags >> 8) & 0xFFu;
     if (in.ploc_radius == 0) in.ploc_radius = 32;
     if (in.ploc_radius > 128) return ctx->fail(LIDAR_ERR_INVALID_ARG, "PLOC radius (flags bits 8-15) must be <= 128");
+    set_collapse(in, desc->flags);
     if (desc->flags & LIDAR_SCENE_DEVICE_PTRS) {
         in.vtx = desc->vertices;
         in.idx = desc->indices;
@@ -978,6 +988,7 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
     in.leaf_width = 4;
     in.builder = 0;
     in.ploc_radius = 32;
+    set_collapse(in, 0u);
     BuildResult br{};
     if ((e = build_bvh(in, persistent, scratch, br, s)) != hipSuccess) return ctx->hip_fail(e, "actor BVH build");
     if (!refit_supported(br)) return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "actor BVH too deep");

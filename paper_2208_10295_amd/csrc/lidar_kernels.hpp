@@ -34,7 +34,9 @@ struct BuildInputs {
     uint32_t nt;
     uint32_t leaf_width;
     uint32_t builder;          // 0 = PLOC, 1 = LBVH (binary radix tree)
-    uint32_t ploc_radius;      // PLOC search radius, 1..32
+    uint32_t ploc_radius;      // PLOC search radius, 1..128
+    uint32_t collapse;         // 0 = surface-area cost (default), 1 = greedy (largest child first)
+    float leaf_cost;           // leaf step weight of the cost model, a node step weighing 1
 };
 
 // Persistent layout: [nodes: Node4 x max(nt,1)] [records: TriRec x nt] [slot_of: u32 x nt]

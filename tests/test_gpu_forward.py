@@ -94,56 +94,61 @@ def test_config2_full_scan_sampled_oracle(L):
 
 
 def test_config2_bvh_equals_bruteforce_full(L):
-    """Both tree builders and both traversal shapes reproduce the brute-force scan bit for bit."""
+    """Both tree builders, both collapses and every traversal shape reproduce the brute-force scan bit for bit."""
     scene, sensor, pose = S.config2()
     c = _ctx(L, scene, sensor, pose)
     b = to_np(c.simulate(SEED, 0, debug=True, bruteforce=True))
-    for builder in ("ploc", "lbvh"):
-        st = c.load(scene, builder=builder)
-        print(f"[bvh] config2 {builder}: nodes {st['n_nodes']} leaves {st['n_leaves']} depth {st['depth']} "
-              f"build {st['build_ms']:.2f} ms", flush=True)
+    for builder, collapse in (("ploc", "sah"), ("lbvh", "sah"), ("ploc", "greedy"), ("lbvh", "greedy")):
+        st = c.load(scene, builder=builder, collapse=collapse)
+        print(f"[bvh] config2 {builder} {collapse}: nodes {st['n_nodes']} leaves {st['n_leaves']} "
+              f"depth {st['depth']} build {st['build_ms']:.2f} ms", flush=True)
         for lanes in (1, 2, 4):
             c.set_lanes_per_ray(lanes)
             a = to_np(c.simulate(SEED, 0, debug=True))
             for k in a:
-                assert np.array_equal(a[k], b[k]), (builder, lanes, k)
+                assert np.array_equal(a[k], b[k]), (builder, collapse, lanes, k)
 
 
-def test_bvh_structure_invariants(L):
-    """Every triangle lies in exactly one leaf and every child box contains its triangles."""
+@pytest.mark.parametrize("builder,collapse,leaf_width,leaf_cost", [
+    ("ploc", "sah", 4, 0.0), ("lbvh", "sah", 4, 0.0), ("ploc", "greedy", 4, 0.0), ("lbvh", "greedy", 4, 0.0),
+    ("ploc", "sah", 1, 0.0), ("ploc", "sah", 8, 0.0), ("lbvh", "sah", 2, 0.0), ("ploc", "sah", 4, 0.25),
+    ("ploc", "sah", 4, 8.0)])
+def test_bvh_structure_invariants(L, builder, collapse, leaf_width, leaf_cost):
+    """Every triangle lies in exactly one leaf of at most leaf_width triangles, and every child box contains
+    its triangles, for each builder and collapse (a very cheap and a very dear leaf step included)."""
     scene, sensor, pose = S.config1()
-    for builder in ("ploc", "lbvh"):
-        c = _ctx(L, scene, sensor, pose)
-        c.load(scene, builder=builder)
-        st = c.stats()
-        nodes_b, tris_b = c.debug_bvh()
-        nodes = nodes_b.view(np.float32).reshape(-1, 4, 8)
-        refs = nodes_b.view(np.uint32).reshape(-1, 4, 8)[:, :, 3]
-        recs = tris_b.view(np.float32).reshape(-1, 12)
-        orig = tris_b.view(np.uint32).reshape(-1, 12)[:, 3]
-        assert sorted(orig.tolist()) == list(range(scene.n_tri))
-        seen = np.zeros(scene.n_tri, np.int64)
-        reached = np.zeros(st["n_nodes"], np.int64)
-        stack = [0]
-        reached[0] = 1
-        while stack:
-            nd = stack.pop()
-            for k in range(4):
-                ref = int(refs[nd, k])
-                if ref == 0xFFFFFFFF:
-                    continue
-                lo, hi = nodes[nd, k, 0:3], nodes[nd, k, 4:7]
-                if ref & 0x80000000:
-                    first, cnt = (ref >> 3) & 0x0FFFFFFF, (ref & 7) + 1
-                    assert cnt <= st["leaf_width"]
-                    seen[first:first + cnt] += 1
-                    v = recs[first:first + cnt][:, [0, 1, 2, 4, 5, 6, 8, 9, 10]].reshape(-1, 3)
-                    assert np.all(v >= lo) and np.all(v <= hi)
-                else:
-                    assert 0 < ref < st["n_nodes"] and reached[ref] == 0
-                    reached[ref] = 1
-                    stack.append(ref)
-        assert np.all(seen == 1) and np.all(reached == 1)
+    c = _ctx(L, scene, sensor, pose)
+    c.load(scene, leaf_width, builder=builder, collapse=collapse, leaf_cost=leaf_cost)
+    st = c.stats()
+    assert st["leaf_width"] == leaf_width
+    nodes_b, tris_b = c.debug_bvh()
+    nodes = nodes_b.view(np.float32).reshape(-1, 4, 8)
+    refs = nodes_b.view(np.uint32).reshape(-1, 4, 8)[:, :, 3]
+    recs = tris_b.view(np.float32).reshape(-1, 12)
+    orig = tris_b.view(np.uint32).reshape(-1, 12)[:, 3]
+    assert sorted(orig.tolist()) == list(range(scene.n_tri))
+    seen = np.zeros(scene.n_tri, np.int64)
+    reached = np.zeros(st["n_nodes"], np.int64)
+    stack = [0]
+    reached[0] = 1
+    while stack:
+        nd = stack.pop()
+        for k in range(4):
+            ref = int(refs[nd, k])
+            if ref == 0xFFFFFFFF:
+                continue
+            lo, hi = nodes[nd, k, 0:3], nodes[nd, k, 4:7]
+            if ref & 0x80000000:
+                first, cnt = (ref >> 3) & 0x0FFFFFFF, (ref & 7) + 1
+                assert cnt <= st["leaf_width"]
+                seen[first:first + cnt] += 1
+                v = recs[first:first + cnt][:, [0, 1, 2, 4, 5, 6, 8, 9, 10]].reshape(-1, 3)
+                assert np.all(v >= lo) and np.all(v <= hi)
+            else:
+                assert 0 < ref < st["n_nodes"] and reached[ref] == 0
+                reached[ref] = 1
+                stack.append(ref)
+    assert np.all(seen == 1) and np.all(reached == 1)
 
 
 def test_ragged_sensor_and_offsets(L):
