@@ -151,6 +151,36 @@ def test_bvh_structure_invariants(L, builder, collapse, leaf_width, leaf_cost):
     assert np.all(seen == 1) and np.all(reached == 1)
 
 
+
+def _collapse_cost(nodes_b, pad, leaf_cost):
+    """Surface-area cost of a 4-wide tree with the collapse's weights: 1 x area per node below the root,
+    leaf_cost x area x ceil(count / 4) per leaf, in FP64 on the stored child boxes with their pad removed."""
+    f = nodes_b.view(np.float32).reshape(-1, 4, 8).astype(np.float64)
+    refs = nodes_b.view(np.uint32).reshape(-1, 4, 8)[:, :, 3]
+    e = np.maximum((f[:, :, 4:7] - pad) - (f[:, :, 0:3] + pad), 0.0)
+    area = e[..., 0] * e[..., 1] + e[..., 1] * e[..., 2] + e[..., 2] * e[..., 0]
+    used = refs != 0xFFFFFFFF
+    leaf = used & ((refs & 0x80000000) != 0)
+    inner = used & ~leaf
+    steps = ((refs & 7) + 1 + 3) // 4
+    return float((area * inner).sum() + leaf_cost * (area * steps * leaf).sum())
+
+
+@pytest.mark.parametrize("builder,leaf_width", [("ploc", 4), ("lbvh", 4), ("ploc", 8), ("lbvh", 1)])
+def test_cost_shaped_collapse_is_no_worse_than_greedy(L, builder, leaf_width):
+    """The bottom-up programme minimises the surface-area cost over every 4-wide collapse of the binary
+    tree, and the greedy collapse is one of them: the cost of the default tree cannot exceed the greedy
+    tree's (same builder, same binary tree; the two share only the binary tree)."""
+    scene, sensor, pose = S.config1()
+    c = _ctx(L, scene, sensor, pose)
+    cost = {}
+    for collapse in ("sah", "greedy"):
+        st = c.load(scene, leaf_width, builder=builder, collapse=collapse)
+        cost[collapse] = _collapse_cost(c.debug_bvh()[0], float(st["box_pad"]), 1.5)
+    print(f"[collapse] {builder} W={leaf_width}: cost sah {cost['sah']:.6g} greedy {cost['greedy']:.6g}", flush=True)
+    # the programme sums in FP32 and the unpadded boxes are rounded: a relative 1e-4 covers both
+    assert cost["sah"] <= cost["greedy"] * (1 + 1e-4)
+
 def test_ragged_sensor_and_offsets(L):
     """Odd channel/azimuth counts, a partial FOV and a scene far from the origin."""
     scene, _, _ = S.config1()
