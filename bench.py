@@ -550,8 +550,12 @@ def main():
     if "sequence" in legs:
         sc3, s3, poses = S.config3()
         cs = L.Context(0)
-        st3 = cs.load(sc3, collapse=args.collapse, leaf_cost=args.leaf_cost)
+        st3 = cs.load(sc3, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius,
+                      collapse=args.collapse, leaf_cost=args.leaf_cost)
         cs.set_sensor(s3)
+        cs.set_tile_shape(args.tile_az)
+        cs.set_lanes_per_ray(args.lanes)
+        cs.set_xcd_remap(args.xcd)
         out3 = alloc_outputs(s3.n_beams, POINT_OUTPUTS, cs.device)
         cs.set_pose(poses[0].p, poses[0].q)
         cs.simulate(seed, 0, out=out3)
@@ -566,7 +570,21 @@ def main():
                               "bvh_build_ms": st3["build_ms"], "bvh_nodes": st3["n_nodes"],
                               "bvh_depth": st3["depth"]}
         log(f"sequence: {result['sequence']['rays_per_s']:.4g} rays/s")
-        del cs
+        # the same 100 scans (same Philox counters) as one batched launch: a recorded trajectory replayed
+        # offline, where every pose is known before the first scan
+        sb = cs.batch([S.Instance(s3, poses[k], seed=seed, scan=k) for k in range(len(poses))], 0)
+        sbo = alloc_outputs(sb.n_rays, POINT_OUTPUTS, cs.device)
+        stune = sb.tune(packet_rays=(256,), leaf_widths=(2, 4), lanes_per_ray=(2, 4), reps=3, out=sbo)
+        sb.simulate(sbo)
+        cs.sync_check()
+        wall_b, ms_b = timed_launches(lambda k: sb.simulate(sbo), 5, torch)
+        cs.sync_check()
+        result["sequence"]["batched"] = {
+            "rays_per_s": 5 * sb.n_rays / wall_b, "ms_per_trajectory": float(np.mean(ms_b)),
+            "tuned_leaf_width": stune["best_leaf_width"], "tuned_lanes_per_ray": stune["best_lanes_per_ray"]}
+        log(f"sequence batched: {result['sequence']['batched']['rays_per_s']:.4g} rays/s "
+            f"({result['sequence']['batched']['ms_per_trajectory']:.2f} ms per 100-scan trajectory)")
+        del sb, sbo, cs
 
     if "value" not in result:
         result["value"] = None
