@@ -37,6 +37,7 @@
 // Child boxes are padded outward by 2^-20 of the largest vertex coordinate,
 // which exceeds the rounding error of the FP32 box and triangle tests for rays
 // starting inside the scene's extent.
+#include <utility>
 #include <vector>
 
 #include "lidar_kernels.hpp"
@@ -695,9 +696,6 @@ __global__ __launch_bounds__(256) void ploc_bintree_kernel(uint32_t n, const uin
     T.last[k] = first[id] + ncount[id] - 1;
     const float *b = nbox + 6 * (size_t)id;
     for (int a = 0; a < 6; ++a) T.box[6 * (size_t)k + a] = b[a];
-    // parent links for the bottom-up cost pass
-    if (l < n) T.parent_leaf[first[l]] = k; else T.parent_int[l - n] = k;
-    if (r < n) T.parent_leaf[first[r]] = k; else T.parent_int[r - n] = k;
 }
 
 // ---------------------------------------------------------------------------
@@ -739,8 +737,48 @@ __device__ inline void sah_child_costs(const BinTree &T, const TriRec *__restric
     }
 }
 
+// C(p, 1..4) and the choice word of binary node p from its children's costs
+__device__ inline void sah_eval(const BinTree &T, const TriRec *__restrict__ recs, uint32_t p, uint32_t W,
+                                float leaf_w, const SahTables &S) {
+    float L[4], R[4];
+    sah_child_costs(T, recs, S.cost, T.left[p], leaf_w, L);
+    sah_child_costs(T, recs, S.cost, T.right[p], leaf_w, R);
+    const float *b = T.box + 6 * (size_t)p;
+    const float area = box_half_area(b, b + 3);
+    // best spread of the two children over e = 2..4 slots (smallest left share on ties)
+    float spread[5];
+    uint32_t w = 0;
+    for (int e = 2; e <= 4; ++e) {
+        int best_k = 1;
+        float best = L[0] + R[e - 2];
+        for (int k = 2; k < e; ++k) {
+            const float c = L[k - 1] + R[e - k - 1];
+            if (c < best) { best = c; best_k = k; }
+        }
+        spread[e] = best;
+        w |= (uint32_t)best_k << (10 + 2 * (e - 2));
+    }
+    const uint32_t count = T.last[p] - T.first[p] + 1u;
+    // a leaf is one walk step for up to 4 triangles (the lanes of a ray test them side by side)
+    const float as_leaf = count <= W ? leaf_w * area * (float)((count + 3u) / 4u) : __builtin_inff();
+    const float as_node = area + spread[4];
+    float C[4];
+    C[0] = fminf(as_leaf, as_node);
+    if (as_leaf <= as_node) w |= 1u;
+    uint32_t uses = 1;
+    for (int i = 2; i <= 4; ++i) {
+        if (spread[i] < C[i - 2]) { C[i - 1] = spread[i]; uses = (uint32_t)i; }
+        else C[i - 1] = C[i - 2];
+        w |= uses << (1 + 3 * (i - 2));
+    }
+    for (int i = 0; i < 4; ++i)
+        __hip_atomic_store(S.cost + 4 * (size_t)p + i, C[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    S.choice[p] = w;
+}
+
 // Bottom-up over the binary tree, one thread per triangle climbing from its
 // leaf; the second thread to reach a node evaluates it (both children done).
+// For the LBVH, whose nodes carry no creation order.
 __global__ __launch_bounds__(256) void sah_cost_kernel(BinTree T, const TriRec *__restrict__ recs, int n,
                                                        uint32_t root, uint32_t W, float leaf_w, SahTables S) {
     const int s = blockIdx.x * 256 + threadIdx.x;
@@ -750,43 +788,18 @@ __global__ __launch_bounds__(256) void sah_cost_kernel(BinTree T, const TriRec *
         __threadfence();
         if (atomicAdd(&T.visit[p], 1u) == 0) return;
         __threadfence();
-        float L[4], R[4];
-        sah_child_costs(T, recs, S.cost, T.left[p], leaf_w, L);
-        sah_child_costs(T, recs, S.cost, T.right[p], leaf_w, R);
-        const float *b = T.box + 6 * (size_t)p;
-        const float area = box_half_area(b, b + 3);
-        // best spread of the two children over e = 2..4 slots (smallest left share on ties)
-        float spread[5];
-        uint32_t w = 0;
-        for (int e = 2; e <= 4; ++e) {
-            int best_k = 1;
-            float best = L[0] + R[e - 2];
-            for (int k = 2; k < e; ++k) {
-                const float c = L[k - 1] + R[e - k - 1];
-                if (c < best) { best = c; best_k = k; }
-            }
-            spread[e] = best;
-            w |= (uint32_t)best_k << (10 + 2 * (e - 2));
-        }
-        const uint32_t count = T.last[p] - T.first[p] + 1u;
-        // a leaf is one walk step for up to 4 triangles (the lanes of a ray test them side by side)
-        const float as_leaf = count <= W ? leaf_w * area * (float)((count + 3u) / 4u) : __builtin_inff();
-        const float as_node = area + spread[4];
-        float C[4];
-        C[0] = fminf(as_leaf, as_node);
-        if (as_leaf <= as_node) w |= 1u;
-        uint32_t uses = 1;
-        for (int i = 2; i <= 4; ++i) {
-            if (spread[i] < C[i - 2]) { C[i - 1] = spread[i]; uses = (uint32_t)i; }
-            else C[i - 1] = C[i - 2];
-            w |= uses << (1 + 3 * (i - 2));
-        }
-        for (int i = 0; i < 4; ++i)
-            __hip_atomic_store(S.cost + 4 * (size_t)p + i, C[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        S.choice[p] = w;
+        sah_eval(T, recs, p, W, leaf_w, S);
         if (p == root) return;
         p = T.parent_int[p];
     }
+}
+
+// The nodes one clustering round created, [k0, k0 + cnt): their children come from earlier rounds, so
+// running the rounds in creation order evaluates every node after its children, without atomics.
+__global__ __launch_bounds__(256) void sah_round_kernel(BinTree T, const TriRec *__restrict__ recs, uint32_t k0,
+                                                        uint32_t cnt, uint32_t W, float leaf_w, SahTables S) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k < cnt) sah_eval(T, recs, k0 + k, W, leaf_w, S);
 }
 
 // One 4-wide node per frontier entry, shaped by the recorded choices: the
@@ -968,6 +981,7 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
         T.visit = (uint32_t *)(sc + L.visit);
         uint32_t *stmp = (uint32_t *)(sc + L.scan_tmp);
         uint32_t root_code = 0;
+        std::vector<std::pair<uint32_t, uint32_t>> ploc_rounds;   // (first node id, count) per round
         if (ploc) {
             float *nbox = (float *)(sc + L.nbox);
             uint32_t *ncount = (uint32_t *)(sc + L.ncount), *nleft = (uint32_t *)(sc + L.nleft),
@@ -1013,6 +1027,7 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
             ploc_bintree_kernel<<<nb, 256, 0, s>>>(nt, nleft, nright, ncount, nfirst, nbox, T);
             HIP_TRY(hipGetLastError());
             root_code = root - nt;
+            for (size_t r = 0; r < round_start.size(); ++r) ploc_rounds.emplace_back(round_start[r], round_count[r]);
         } else {
             HIP_TRY(hipMemsetAsync(T.visit, 0, 4 * (size_t)nt, s));
             karras_kernel<<<nb, 256, 0, s>>>(keys, (int)nt, T);
@@ -1020,7 +1035,12 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
         }
         const bool sah = in.collapse == 0;
         SahTables sah_t{(float *)(sc + L.sah_cost), (uint32_t *)(sc + L.sah_choice)};
-        if (sah) {
+        if (sah && ploc) {
+            for (size_t r = 0; r < ploc_rounds.size(); ++r)
+                sah_round_kernel<<<(ploc_rounds[r].second + 255) / 256, 256, 0, s>>>(
+                    T, recs, ploc_rounds[r].first - nt, ploc_rounds[r].second, in.leaf_width, in.leaf_cost, sah_t);
+            HIP_TRY(hipGetLastError());
+        } else if (sah) {
             HIP_TRY(hipMemsetAsync(T.visit, 0, 4 * (size_t)nt, s));
             sah_cost_kernel<<<nb, 256, 0, s>>>(T, recs, (int)nt, root_code, in.leaf_width, in.leaf_cost, sah_t);
             HIP_TRY(hipGetLastError());
