@@ -40,6 +40,17 @@ STRUCTS = {"SceneDesc": "lidar_scene_desc", "MaterialDesc": "lidar_material_desc
            "EchoDesc": "lidar_echo_desc"}
 
 
+def test_every_header_constant_is_mirrored(A):
+    """Each numeric #define of the header (status codes, sentinels, scene flags, options) has the same value
+    under the same name, without the LIDAR_ prefix, in the ctypes mirror."""
+    txt = open(HEADER).read()
+    found = re.findall(r"^#define LIDAR_([A-Z0-9_]+)\s+(-?(?:0x[0-9A-Fa-f]+|\d+))u?\b", txt, flags=re.M)
+    assert len(found) >= 20
+    for name, value in found:
+        assert hasattr(A, name), name
+        assert getattr(A, name) == int(value, 0), (name, value)
+
+
 def test_struct_layouts_match_header(A, tmp_path):
     """Size and every field offset of the ctypes mirror equal what a C compiler sees in include/lidar.h."""
     import subprocess
