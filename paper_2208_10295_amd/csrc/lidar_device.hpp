@@ -408,17 +408,17 @@ __device__ inline uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 }
 
 // Standard normal from two words: u1 = (xa + 1) 2^-32, u2 = xb 2^-32,
-// z = sqrt(-2 ln u1) cos(2 pi u2).  ln u1 is taken as log1p(-(1 - u1)) when
-// u1 > 1/2 so that it keeps its relative accuracy near u1 = 1.
+// z = sqrt(-2 ln u1) cos(2 pi u2).  Evaluated with the hardware base-2
+// logarithm and the hardware cosine, whose argument is in revolutions, so
+// cos(2 pi u2) needs no range reduction; no branch, so a wavefront does not
+// run two logarithms.  Near u1 = 1 the logarithm loses relative accuracy, but
+// there z itself is near 0: the absolute error of z stays far below what a
+// range noise of centimetres can show.
 __device__ inline float box_muller(uint32_t xa, uint32_t xb) {
-    float lnu;
-    if (xa < 0x80000000u) {
-        lnu = logf((float)(xa + 1u) * 2.3283064365386963e-10f);
-    } else {
-        lnu = log1pf(-(float)(~xa) * 2.3283064365386963e-10f);
-    }
-    float u2 = (float)xb * 2.3283064365386963e-10f;
-    return sqrtf(-2.0f * lnu) * cospif(2.0f * u2);
+    const float u1 = (float)xa * 2.3283064365386963e-10f + 2.3283064365386963e-10f;   // in (0, 1]
+    const float lnu = __builtin_amdgcn_logf(u1) * 0.69314718055994531f;
+    const float u2 = (float)xb * 2.3283064365386963e-10f;
+    return __builtin_sqrtf(-2.0f * lnu) * __builtin_amdgcn_cosf(u2);
 }
 
 }  // namespace lidar

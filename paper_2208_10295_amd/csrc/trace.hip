@@ -615,7 +615,8 @@ __device__ inline Shade shade_hit(const MaterialsDev &M, const Overrides &ov, fl
     float cy = fmaf(e1z, e2x, -e1x * e2z);
     float cz = fmaf(e1x, e2y, -e1y * e2x);
     float len = __fsqrt_rn(fmaf(cx, cx, fmaf(cy, cy, cz * cz)));
-    S.nx = cx / len; S.ny = cy / len; S.nz = cz / len;
+    const float inv = 1.0f / len;
+    S.nx = cx * inv; S.ny = cy * inv; S.nz = cz * inv;
     if (act) {
         const double X = S.nx, Y = S.ny, Z = S.nz;
         S.nx = (float)(act->R[0] * X + act->R[1] * Y + act->R[2] * Z);
