@@ -329,3 +329,30 @@ def test_stack_overflow_is_reported_and_recovered(L):
         assert np.array_equal(ref[k], g[k]), k
     with pytest.raises(L.LidarError):
         c.set_stack_cap(-1)
+
+
+def test_range_and_intensity_noise_are_independent_standard_normals(L):
+    """The noise the kernel adds (Philox4x32-10 words through Box-Muller, Section II-A range noise and the
+    intensity noise) is standard normal and independent between range and intensity: z_d = (d - t) / sigma_m
+    and z_I = (I - R_lambda) / sigma_I over the beams whose detection and clamp the noise cannot change."""
+    import dataclasses
+    from scipy import stats
+    scene, sensor, pose = S.config2()
+    sensor = dataclasses.replace(sensor, sigma_intensity=0.01)
+    c = _ctx(L, scene, sensor, pose)
+    g = to_np(c.simulate(SEED, 3, debug=True))
+    mat = g["material"].astype(np.int64)
+    sig = np.asarray(scene.sigma_range, np.float64)[np.minimum(mat, len(scene.sigma_range) - 1)]
+    t, d, rl, inten = (g[k].astype(np.float64) for k in ("t_hit", "range", "r_lambda", "intensity"))
+    # far from the eq.5 limit, the range cutoff and the intensity clamp at 0 (more than 8 sigma)
+    safe = ((g["valid"] == 1) & (sig > 0) & (t < 0.8 * sensor.d_max) &
+            (rl > (sensor.r_l_max / sensor.d_max) * (t + 8 * sig) * 1.01) & (rl > 8 * sensor.sigma_intensity))
+    assert safe.sum() > 20000
+    zd = (d[safe] - t[safe]) / sig[safe]
+    zi = (inten[safe] - rl[safe]) / sensor.sigma_intensity
+    print(f"[noise] n={safe.sum()} z_d mean {zd.mean():.4f} std {zd.std():.4f}; "
+          f"z_I mean {zi.mean():.4f} std {zi.std():.4f}; corr {np.corrcoef(zd, zi)[0, 1]:.4f}", flush=True)
+    for z in (zd, zi):
+        assert abs(z.mean()) < 0.03 and abs(z.std() - 1.0) < 0.03
+        assert stats.kstest(z, "norm").pvalue > 1e-4
+    assert abs(np.corrcoef(zd, zi)[0, 1]) < 0.03
