@@ -6,7 +6,7 @@
 // only the detected points.  Compaction copies the beams with valid != 0 to
 // the front of the output arrays, in beam order, plus each point's beam index.
 //
-// Three launches, all stream-ordered, no atomics (the result is deterministic):
+// Stream-ordered launches, no atomics (the result is deterministic):
 //   1. per 256-beam block: the wavefront's detected beams as a 64-bit ballot,
 //      their popcounts summed in LDS -> counts[block];
 //   2. one 1024-thread block: exclusive prefix sum of counts, in chunks of
@@ -14,6 +14,9 @@
 //   3. per 256-beam block: the beam's rank = the block's offset + the counts
 //      of the block's earlier wavefronts + popcount(ballot & lanes below), then
 //      every requested field is copied to that rank.
+// Up to kFusedBlocks blocks (a scan of up to 524,288 beams) steps 2 and 3 are
+// one launch: each block sums the counts before it itself (at most 8 loads per
+// thread), which costs less than a launch of its own.
 #include "lidar_device.hpp"
 #include "lidar_kernels.hpp"
 
@@ -77,19 +80,45 @@ __global__ __launch_bounds__(kScanBlock) void compact_scan_kernel(uint32_t *__re
     if (threadIdx.x == 0) *total = carry_s;
 }
 
+constexpr uint32_t kFusedBlocks = 2048;
+
+// FUSED: `offsets` holds the per-block counts of step 1; the block's offset is
+// their sum over the blocks before it, and the last block writes the total.
+template <bool FUSED>
 __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(Outputs dense, Outputs comp,
                                                                         uint32_t *__restrict__ beam_index,
                                                                         const uint32_t *__restrict__ offsets,
-                                                                        uint64_t n) {
+                                                                        uint64_t n, uint32_t *__restrict__ total) {
     __shared__ uint32_t wsum[kCompactBlock / 64];
+    __shared__ uint32_t wpre[kCompactBlock / 64];
     const uint64_t g = (uint64_t)blockIdx.x * kCompactBlock + threadIdx.x;
     const bool v = g < n && dense.valid[g] != 0;
     const uint64_t m = __ballot(v);
     const uint32_t wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63u) == 0) wsum[wave] = (uint32_t)__popcll(m);
+    uint32_t base = 0;
+    if constexpr (FUSED) {
+        uint32_t part = 0;
+        for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kCompactBlock) part += offsets[b];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+        if ((threadIdx.x & 63u) == 0) wpre[wave] = part;
+    }
     __syncthreads();
+    if constexpr (FUSED) {
+#pragma unroll
+        for (int w = 0; w < kCompactBlock / 64; ++w) base += wpre[w];
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+            uint32_t c = base;
+#pragma unroll
+            for (int w = 0; w < kCompactBlock / 64; ++w) c += wsum[w];
+            *total = c;
+        }
+    } else {
+        base = offsets[blockIdx.x];
+    }
     if (!v) return;
-    uint32_t pos = offsets[blockIdx.x];
+    uint32_t pos = base;
     for (uint32_t w = 0; w < wave; ++w) pos += wsum[w];
     pos += (uint32_t)__popcll(m & lanes_below());
     if (comp.valid) comp.valid[pos] = dense.valid[g];
@@ -117,8 +146,14 @@ void launch_compact(const Outputs &dense, const Outputs &comp, uint32_t *beam_in
                     uint32_t *counts, hipStream_t s) {
     const uint64_t nb = compact_blocks(n);
     if (nb > 0) compact_count_kernel<<<(uint32_t)nb, kCompactBlock, 0, s>>>(dense.valid, n, counts);
+    if (nb > 0 && nb <= kFusedBlocks) {
+        compact_scatter_kernel<true><<<(uint32_t)nb, kCompactBlock, 0, s>>>(dense, comp, beam_index, counts, n, count);
+        return;
+    }
     compact_scan_kernel<<<1, kScanBlock, 0, s>>>(counts, (uint32_t)nb, count);
-    if (nb > 0) compact_scatter_kernel<<<(uint32_t)nb, kCompactBlock, 0, s>>>(dense, comp, beam_index, counts, n);
+    if (nb > 0)
+        compact_scatter_kernel<false><<<(uint32_t)nb, kCompactBlock, 0, s>>>(dense, comp, beam_index, counts, n,
+                                                                            count);
 }
 
 }  // namespace lidar

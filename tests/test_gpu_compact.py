@@ -77,11 +77,12 @@ def test_config1_point_cloud_matches_dense_and_oracle(L):
     assert np.all(np.abs(rg - pc["range"][oi][ok]) <= 1e-5 * pc["range"][oi][ok])
 
 
-@pytest.mark.parametrize("n", [0, 1, 63, 64, 257, 1000, 262144, 300001])
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 257, 1000, 262144, 300001, 524288, 600001])
 @pytest.mark.parametrize("density", [0.0, 0.37, 1.0])
 def test_synthetic_dense_arrays_ragged_sizes(c1, n, density):
-    """Any dense arrays (not only simulated ones): empty, single, ragged tails, and more than one
-    1024-block chunk of the prefix sum (300,001 beams = 1,172 blocks)."""
+    """Any dense arrays (not only simulated ones): empty, single, ragged tails; up to 2,048 blocks of 256
+    beams (524,288) each block sums the counts before it, above that (600,001 beams = 2,344 blocks, three
+    1024-block chunks) a separate prefix-sum launch runs."""
     c = c1
     g = torch.Generator().manual_seed(n * 7 + int(density * 100))
     dev = c.device
