@@ -557,12 +557,8 @@ def main():
         cs.set_lanes_per_ray(args.lanes)
         cs.set_xcd_remap(args.xcd)
         out3 = alloc_outputs(s3.n_beams, POINT_OUTPUTS, cs.device)
-        cs.set_pose(poses[0].p, poses[0].q)
-        cs.simulate(seed, 0, out=out3)
-
-        def one(k):
-            cs.set_pose(poses[k].p, poses[k].q)
-            cs.simulate(seed, k, out=out3)
+        one = cs.trajectory_launcher(seed, out3, poses)
+        one(0)
         wall3, ms3 = timed_launches(one, len(poses), torch)
         cs.sync_check()
         result["sequence"] = {"workload": "128ch x 1024 x 100 poses at 10 Hz, 5,224,200-triangle scene, 64 materials",

@@ -346,6 +346,29 @@ class Context:
         run._keep = (o, out)
         return run
 
+    def trajectory_launcher(self, seed: int, out: dict, poses, stream=None):
+        """A callable f(k) that sets pose k of `poses` (objects with p and q) and runs scan k on fixed
+        outputs and stream: a trajectory replayed one scan per tick.  The pose arrays and argument structs
+        are built once, so f(k) costs two ctypes calls on the host."""
+        o = outputs_struct(out)
+        ob = C.byref(o)
+        sp = _stream(stream)
+        h = self.h
+        seed = int(seed)
+        pa = [(C.c_float * 3)(*[float(x) for x in ps.p]) for ps in poses]
+        qa = [(C.c_float * 4)(*[float(x) for x in ps.q]) for ps in poses]
+        set_pose, sim = lib.lidar_pose_set, lib.lidar_simulate
+
+        def run(k: int):
+            st = set_pose(h, pa[k], qa[k])
+            if st < 0:
+                check(st, h)
+            st = sim(h, seed, k, ob, sp)
+            if st < 0:
+                check(st, h)
+        run._keep = (o, out, pa, qa)
+        return run
+
     def backward_launcher(self, tri, valid, dL_dI, dL_drange, params: dict | None = None, spectra: bool = False,
                           stream=None):
         """A callable f() that runs lidar_backward (lidar_backward_spectra if `spectra`) with fixed
