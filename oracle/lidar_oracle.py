@@ -742,11 +742,15 @@ def simulate_actors(scene, meshes, actors, sensor, pose, seed: int = 0, scan: in
 # ----------------------------------------------------------------------------
 # adjoint: gradients of an intensity/depth loss with the hit triangles fixed
 # ----------------------------------------------------------------------------
-def _fixed_triangle_forward(scene, s, tri, R, p, rho, kexp):
-    """Noise-free I and t for beams whose hit triangle is held fixed.
+def _fixed_triangle_forward(scene, s, tri, R, p, rho, kexp, sig_i=0.0, z_i=None):
+    """I and t for beams whose hit triangle is held fixed.
 
     c = n . d with d = R s; t = n . (v0 - p) / c (ray/plane distance of the
-    fixed triangle); I = rho_m |c|^k_m (eq.4 with the cos^k reading).
+    fixed triangle); R_lambda = rho_m |c|^k_m (eq.4 with the cos^k reading).
+    The intensity is R_lambda itself, or, with intensity noise (sig_i > 0 and
+    the per-beam standard normals z_i of the forward scan), the forward's
+    max(0, R_lambda + sig_i z_i).  Also returns the mask of beams whose
+    intensity is not clamped at 0 (the ones through which R_lambda reaches I).
     """
     v = scene.vertices.astype(np.float64)[scene.indices[tri].astype(np.int64)]
     n = np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0])
@@ -755,28 +759,36 @@ def _fixed_triangle_forward(scene, s, tri, R, p, rho, kexp):
     c = np.einsum("ij,ij->i", n, d)
     t = np.einsum("ij,ij->i", n, v[:, 0] - p) / c
     m = scene.material[tri].astype(np.int64)
-    I = rho[m] * np.abs(c) ** kexp[m]
-    return I, t, n, d, c, m
+    r_lam = rho[m] * np.abs(c) ** kexp[m]
+    if z_i is None or sig_i == 0.0:
+        return r_lam, t, n, d, c, m, np.ones(len(t), dtype=bool)
+    pre = r_lam + sig_i * np.asarray(z_i, dtype=np.float64)
+    return np.maximum(0.0, pre), t, n, d, c, m, pre > 0.0
 
 
-def calib_loss(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0):
+def calib_loss(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0, sig_i=0.0,
+               z_i=None):
     """L = mean((I - I*)^2) + lam_d * mean((t - t*)^2) over the given beams.
 
-    Pose: p = p_ref + dp, R = Exp(dw) R_ref.  FP64.
+    Pose: p = p_ref + dp, R = Exp(dw) R_ref.  I as in ``_fixed_triangle_forward``
+    (with intensity noise when sig_i and z_i are given).  FP64.
     """
     s = beam_directions(sensor).reshape(-1, 3)[np.asarray(beams)]
     R = so3_exp(dw) @ rotation_from_quat(pose_ref.q)
     p = np.asarray(pose_ref.p, dtype=np.float64) + np.asarray(dp, dtype=np.float64)
     I, t, *_ = _fixed_triangle_forward(scene, s, np.asarray(tri), R, p,
-                                       np.asarray(rho, np.float64), np.asarray(kexp, np.float64))
+                                       np.asarray(rho, np.float64), np.asarray(kexp, np.float64), sig_i, z_i)
     N = len(beams)
     return float(np.sum((I - I_tgt) ** 2) / N + lam_d * np.sum((t - t_tgt) ** 2) / N)
 
 
-def calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0):
+def calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0, sig_i=0.0,
+               z_i=None):
     """Analytic gradient of ``calib_loss``: returns (d_rho[nmat], d_k[nmat], d_pose6[6]).
 
-    With g_I = dL/dI and g_t = dL/dt per beam:
+    With g_I = dL/dI and g_t = dL/dt per beam, and g_I taken as 0 where the
+    intensity is clamped at 0 (I = max(0, R_lambda + sig_i z_i) does not move
+    with R_lambda there):
       dL/drho_m = sum g_I |c|^k;  dL/dk_m = sum g_I rho |c|^k ln|c|;
       dL/dp = sum -g_t n / c;
       dL/d(left rotation perturbation) = sum gamma (d x n),
@@ -788,9 +800,9 @@ def calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_
     s = beam_directions(sensor).reshape(-1, 3)[np.asarray(beams)]
     R = so3_exp(dw) @ rotation_from_quat(pose_ref.q)
     p = np.asarray(pose_ref.p, dtype=np.float64) + np.asarray(dp, dtype=np.float64)
-    I, t, n, d, c, m = _fixed_triangle_forward(scene, s, np.asarray(tri), R, p, rho, kexp)
+    I, t, n, d, c, m, live = _fixed_triangle_forward(scene, s, np.asarray(tri), R, p, rho, kexp, sig_i, z_i)
     N = len(beams)
-    gI = 2.0 * (I - I_tgt) / N
+    gI = np.where(live, 2.0 * (I - I_tgt) / N, 0.0)
     gt = 2.0 * lam_d * (t - t_tgt) / N
     ac = np.abs(c)
     k_b = kexp[m]
@@ -804,7 +816,8 @@ def calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_
     return d_rho, d_k, np.concatenate([d_p, d_w])
 
 
-def calib_grad_spectral(scene, sensor, pose_ref, tri, beams, spectra, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0):
+def calib_grad_spectral(scene, sensor, pose_ref, tri, beams, spectra, kexp, dp, dw, I_tgt, t_tgt, lam_d=1.0,
+                        sig_i=0.0, z_i=None):
     """Gradient of ``calib_loss`` with R_lambda(0) taken from the spectral table
     at the sensor wavelength: returns (d_spectra[nmat, nbins], d_k, d_pose6).
 
@@ -814,6 +827,7 @@ def calib_grad_spectral(scene, sensor, pose_ref, tri, beams, spectra, kexp, dp, 
     """
     T = np.asarray(spectra, np.float64)
     rho = reflectance_at_wavelength(T, sensor.wavelength_nm)[0]
-    d_rho, d_k, d_pose = calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d)
+    d_rho, d_k, d_pose = calib_grad(scene, sensor, pose_ref, tri, beams, rho, kexp, dp, dw, I_tgt, t_tgt, lam_d,
+                                    sig_i, z_i)
     w = spectral_weights(T.shape[1], sensor.wavelength_nm)
     return np.outer(d_rho, w), d_k, d_pose

@@ -297,6 +297,78 @@ def test_noise_added_before_capability_test():
     assert seen_in > 5 and seen_out > 5
 
 
+def _kat_zero_words():
+    """Philox4x32-10 of counter (0, 0, 0, 0) under key (0, 0): the first published known-answer vector."""
+    kat = json.load(open(os.path.join(GOLDEN, "philox4x32_10_kat.json")))
+    vec = kat["vectors"][0]
+    assert vec["counter"] == ["00000000"] * 4 and vec["key"] == ["00000000"] * 2
+    return [int(x, 16) for x in vec["out"]]
+
+
+def _bm_by_hand(xa, xb):
+    """Box-Muller of two 32-bit words written out with math: u1 = (xa + 1) 2^-32, u2 = xb 2^-32."""
+    u1 = (xa + 1) / 4294967296.0
+    u2 = xb / 4294967296.0
+    return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+
+
+def _yawed_wall_case(sigma_i, sigma_r=0.02):
+    """Beam 0 (elevation 0, azimuth 0) of a sensor yawed by 30 degrees hits the wall x = 10 (rho 0.5)
+    at t = 10 / cos 30 with cos(theta) = cos 30; seed 0, scan 0, instance 0 make its Philox block the
+    all-zero known-answer vector."""
+    sensor = S.Sensor(np.array([0.0]), 4, d_max=50.0, noise_on=True, sigma_intensity=sigma_i)
+    q = S.quat_from_ypr(math.radians(30.0))
+    pose = S.Pose(np.zeros(3, np.float32), np.asarray(q, np.float32))
+    return _wall(10.0, 0.5, sigma=sigma_r), sensor, pose
+
+
+def test_intensity_noise_uses_words_2_3_and_clamps_at_zero():
+    """Intensity noise (a reading: the paper has range noise only): I = max(0, R_lambda + sigma_I z_I)
+    with z_I from Philox words 2-3 of counter (beam, scan, instance, 0); range noise from words 0-1."""
+    w = _kat_zero_words()
+    z_d, z_i = _bm_by_hand(w[0], w[1]), _bm_by_hand(w[2], w[3])
+    assert abs(z_d - z_i) > 0.5 and z_i < -0.5          # a swap of the word pairs, or a sign, shows
+    for sigma_i in (0.0, 0.05, 0.3):
+        scene, sensor, pose = _yawed_wall_case(sigma_i)
+        r = O.simulate(scene, sensor, pose, seed=0, scan=0, inst=0, beams=[0])
+        # the pose rounds to FP32, so cos(theta) and t are those of the FP32 quaternion's yaw
+        d = O.rotation_from_quat(pose.q) @ np.array([1.0, 0.0, 0.0])
+        cos_t, t = d[0], 10.0 / d[0]
+        assert abs(cos_t - math.cos(math.radians(30.0))) < 1e-7
+        r_lam = 0.5 * cos_t
+        assert r["valid"][0] == 1
+        assert abs(r["r_lambda"][0] - r_lam) < 1e-12
+        assert abs(r["range"][0] - (t + 0.02 * z_d)) < 1e-9
+        assert abs(r["intensity"][0] - max(0.0, r_lam + float(np.float32(sigma_i)) * z_i)) < 1e-12
+    # sigma_I large enough that R_lambda + sigma_I z_I < 0: the clamp gives exactly 0, and the
+    # point is still detected (the eq.5 test uses the noise-free R_lambda)
+    scene, sensor, pose = _yawed_wall_case(1.0)
+    r = O.simulate(scene, sensor, pose, seed=0, scan=0, inst=0, beams=[0])
+    assert 0.5 * math.cos(math.radians(30.0)) + 1.0 * z_i < 0.0
+    assert r["valid"][0] == 1 and r["intensity"][0] == 0.0 and r["range"][0] > 0.0
+    # no noise at all: the intensity is R_lambda whatever sigma_I says
+    sensor.noise_on = False
+    r = O.simulate(scene, sensor, pose, seed=0, scan=0, inst=0, beams=[0])
+    assert abs(r["intensity"][0] - 0.5 * math.cos(math.radians(30.0))) < 1e-7
+
+
+def test_echo_intensity_noise_uses_words_2_3_and_clamps_at_zero():
+    """The multi-echo path draws echo e's noise from counter (beam, scan, instance, e): with one
+    sub-ray and no divergence, echo 0 of beam 0 at seed 0 uses the all-zero known-answer block."""
+    w = _kat_zero_words()
+    z_d, z_i = _bm_by_hand(w[0], w[1]), _bm_by_hand(w[2], w[3])
+    for sigma_i in (0.05, 1.0):
+        scene, sensor, pose = _yawed_wall_case(sigma_i)
+        e = O.simulate_echoes(scene, sensor, pose, n_sub=1, max_echoes=1, divergence_rad=0.0, echo_sep_m=0.5,
+                              seed=0, scan=0, beams=[0])
+        d = O.rotation_from_quat(pose.q) @ np.array([1.0, 0.0, 0.0])
+        r_lam = 0.5 * d[0]
+        assert e["valid"][0, 0] == 1
+        assert abs(e["range"][0, 0] - (10.0 / d[0] + 0.02 * z_d)) < 1e-9
+        assert abs(e["intensity"][0, 0] - max(0.0, r_lam + float(np.float32(sigma_i)) * z_i)) < 1e-12
+    assert e["intensity"][0, 0] == 0.0
+
+
 # ----------------------------------------------------------------------------
 # P4: invariance under a rigid transform of scene + sensor
 # ----------------------------------------------------------------------------
@@ -475,6 +547,67 @@ def test_adjoint_matches_central_differences():
     for sl in (slice(0, 20), slice(20, 40), slice(40, 43), slice(43, 46)):
         err = np.linalg.norm(g[sl] - fd[sl]) / np.linalg.norm(fd[sl])
         assert err < 1e-4, (sl, err)
+
+
+def test_calibration_forward_is_the_scan_with_the_triangle_fixed():
+    """With the hit triangles held fixed, the calibration forward at the hidden parameters reproduces
+    the scan the targets came from: I = the scan's R_lambda (cos^k with k != 1), t = its hit
+    distance, at a rotated and displaced pose; so the loss there is 0."""
+    c5, beams, tri, I_t, t_t = _calib_problem(n_beams=2000, seed=3)
+    scene, sensor, pose = c5["scene"], c5["sensor"], c5["pose_true"]
+    rho, kexp = c5["rho_true"].astype(np.float64), c5["k_true"].astype(np.float64)
+    assert np.all(np.abs(kexp - 1.0) > 1e-3)           # exponents away from the Lambertian value
+    fwd = O.simulate(scene, sensor, pose, beams=beams, rho=rho, angle_exp=kexp)
+    s = O.beam_directions(sensor).reshape(-1, 3)[beams]
+    I, t, n, d, c, m, live = O._fixed_triangle_forward(scene, s, tri, O.rotation_from_quat(pose.q),
+                                                       np.asarray(pose.p, np.float64), rho, kexp)
+    assert np.all(live) and np.all(fwd["tri"] == tri)
+    assert np.all(np.abs(np.abs(c) - 1.0) > 1e-3)      # oblique incidence, where the exponent matters
+    assert np.allclose(I, fwd["r_lambda"], rtol=1e-12, atol=0)
+    assert np.allclose(t, fwd["t_hit"], rtol=1e-12, atol=0)
+    zero = np.zeros(3)
+    assert O.calib_loss(scene, sensor, pose, tri, beams, rho, kexp, zero, zero, I_t, t_t) < 1e-20
+    # and not 0 one step away from it, in every group
+    for bump in ((0.01, 0, 0, 0), (0, 0.01, 0, 0), (0, 0, 0.01, 0), (0, 0, 0, 0.001)):
+        L = O.calib_loss(scene, sensor, pose, tri, beams, rho + bump[0], kexp + bump[1], zero + bump[2],
+                         zero + bump[3], I_t, t_t)
+        assert L > 1e-9, bump
+
+
+def test_adjoint_with_intensity_noise_clamp_matches_central_differences():
+    """I = max(0, R_lambda + sigma_I z_I): where the clamp holds, I does not move with rho, k or the
+    pose.  The analytic gradient (g_I zeroed there) against central differences of the clamped loss,
+    with a sigma_I that clamps a good share of the beams."""
+    c5, beams, tri, I_t, t_t = _calib_problem(n_beams=1500, seed=4)
+    scene, sensor, pose = c5["scene"], c5["sensor"], c5["pose_true"]
+    _, z_i = O.beam_normals(77, 0, 0, beams)
+    sig_i = 0.25
+    rho = c5["rho0"].astype(np.float64) + 0.05 * np.arange(20) / 20
+    kexp = c5["k0"].astype(np.float64) + 0.3 * np.sin(np.arange(20))
+    dp, dw = np.array(c5["dp0"]) * 0.05, np.array(c5["dw0"]) * 0.05
+    s = O.beam_directions(sensor).reshape(-1, 3)[beams]
+    R = O.so3_exp(dw) @ O.rotation_from_quat(pose.q)
+    I, *_, live = O._fixed_triangle_forward(scene, s, tri, R, np.asarray(pose.p, np.float64) + dp, rho, kexp,
+                                            sig_i, z_i)
+    assert 0.1 < np.mean(~live) < 0.9 and np.all(I[~live] == 0.0)
+    args = (scene, sensor, pose, tri, beams)
+    g = np.concatenate(O.calib_grad(*args, rho, kexp, dp, dw, I_t, t_t, sig_i=sig_i, z_i=z_i))
+    g_free = np.concatenate(O.calib_grad(*args, rho, kexp, dp, dw, I_t, t_t))
+    h = 1e-6
+    fd = np.zeros(46)
+    for i in range(46):
+        x = np.concatenate([rho, kexp, dp, dw])
+        x[i] += h
+        lp = O.calib_loss(*args, x[:20], x[20:40], x[40:43], x[43:46], I_t, t_t, sig_i=sig_i, z_i=z_i)
+        x[i] -= 2 * h
+        lm = O.calib_loss(*args, x[:20], x[20:40], x[40:43], x[43:46], I_t, t_t, sig_i=sig_i, z_i=z_i)
+        fd[i] = (lp - lm) / (2 * h)
+    for sl in (slice(0, 20), slice(20, 40), slice(40, 43), slice(43, 46)):
+        err = np.linalg.norm(g[sl] - fd[sl]) / np.linalg.norm(fd[sl])
+        assert err < 1e-4, (sl, err)
+        # ignoring the clamp is wrong by far more than the tolerance (the translation has no
+        # intensity term)
+        assert np.linalg.norm(g_free[sl] - fd[sl]) / np.linalg.norm(fd[sl]) > 1e-3 or sl == slice(40, 43), sl
 
 
 def test_adjoint_special_cases():
