@@ -14,8 +14,9 @@
  * Conventions shared by every call
  * --------------------------------
  * - Status: 0 = success, < 0 = error (nothing was enqueued), > 0 = warning
- *   (the call succeeded; see each call).  No C++ exception crosses the ABI.
- *   lidar_last_error() returns a message for the last failing call.
+ *   (the call succeeded; see each call): a bit set of LIDAR_WARN_* flags.  No
+ *   C++ exception crosses the ABI.  lidar_last_error() returns a message for
+ *   the last failing call.
  * - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  *   stream).  Device work is enqueued on it and the call returns without
  *   waiting, unless the call says it synchronises.
@@ -56,6 +57,19 @@ typedef int32_t lidar_status;
 #define LIDAR_ERR_NO_FORWARD_STATE     -7  /* backward called without the forward's saved triangle ids */
 #define LIDAR_ERR_OUT_OF_MEMORY        -8  /* a set-up allocation failed */
 #define LIDAR_WARN_WAVELENGTH_CLAMPED   1  /* wavelength outside the spectral table: end bin used */
+#define LIDAR_WARN_ORIGIN_OUTSIDE_SCENE 2  /* a ray origin lies outside the region the BVH's box padding
+                                              covers (see lidar_origin_check): results are computed, but
+                                              the walk may rarely miss a hit the brute force finds */
+
+/* Size limits of a scene or mesh.  The walk addresses triangle records and
+ * nodes with 32-bit byte offsets into buffers of at most 2^31 - 1 bytes:
+ * records are 48 bytes, so at most LIDAR_MAX_TRIANGLES triangles
+ * (lidar_scene_bytes and lidar_mesh_bytes refuse more), and nodes are 128
+ * bytes, so a built tree may have at most LIDAR_MAX_NODES 4-wide nodes
+ * (lidar_scene_load and lidar_mesh_load refuse a larger tree; only leaf
+ * width 1 on scenes near the triangle limit comes close). */
+#define LIDAR_MAX_TRIANGLES 44739242u   /* floor((2^31 - 1) / 48) */
+#define LIDAR_MAX_NODES     16777216u   /* 2^24 */
 
 /* Miss / drop encodings in the outputs. */
 #define LIDAR_NO_LABEL     0xFFFFFFFFu
@@ -96,7 +110,7 @@ const char *lidar_last_error(const lidar_ctx *ctx);
 
 typedef struct {
     uint64_t n_vertices;
-    uint64_t n_triangles;      /* >= 1 and < 2^28 */
+    uint64_t n_triangles;      /* 1 .. LIDAR_MAX_TRIANGLES */
     const float *vertices;     /* [n_vertices][3] world coordinates, metres */
     const uint32_t *indices;   /* [n_triangles][3] vertex indices (< n_vertices) */
     const uint16_t *material;  /* [n_triangles] material id (< nmat of lidar_materials_set) */
@@ -121,8 +135,10 @@ lidar_status lidar_scene_bytes(const lidar_scene_desc *desc, uint64_t *persisten
  * speed differs).
  * Validates every triangle index on the device.  Synchronises `stream` (it
  * reads back the tree size and depth).  Errors: INVALID_ARG (bad sizes,
- * index out of range), WORKSPACE_TOO_SMALL, STACK_OVERFLOW (tree deeper than
- * the traversal stack supports), HIP. */
+ * index out of range, more than LIDAR_MAX_NODES nodes), WORKSPACE_TOO_SMALL,
+ * STACK_OVERFLOW (tree deeper than the traversal stack supports), HIP.
+ * Warning: LIDAR_WARN_ORIGIN_OUTSIDE_SCENE if the current pose's origin lies
+ * outside the new scene's cube (lidar_origin_check). */
 lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc,
                               void *persistent, uint64_t persistent_bytes,
                               void *scratch, uint64_t scratch_bytes, void *stream);
@@ -173,8 +189,23 @@ lidar_status lidar_sensor_set(lidar_ctx *ctx, const lidar_sensor_desc *desc);
 
 /* Sets the sensor pose used by lidar_simulate: origin p (world, metres) and
  * orientation quaternion q = (w, x, y, z), which must have unit norm to 1e-4
- * (it is renormalised).  World beam direction d = R(q) s. */
+ * (it is renormalised).  World beam direction d = R(q) s.  Returns
+ * LIDAR_WARN_ORIGIN_OUTSIDE_SCENE (the pose is still set) when a scene is
+ * loaded and p lies outside its cube (lidar_origin_check). */
 lidar_status lidar_pose_set(lidar_ctx *ctx, const float p[3], const float q_wxyz[4]);
+
+/* The BVH's child boxes are padded outward by 2^-20 M, M the scene's largest
+ * |vertex coordinate| (lidar_stats.max_abs_coord).  The FP32 slab test
+ * fma(b, 1/d, -o/d) errs by at most 2^-24 (2|b_i| + 3|o_i|) along axis i and
+ * the watertight triangle test by a few units of 2^-24 (|v| + |o|), both
+ * below the pad when every |o_i| <= M: for ray origins in the cube
+ * |x|, |y|, |z| <= M the BVH walk finds exactly the brute force's hits.  This
+ * host-only check returns LIDAR_OK for an origin p in that cube (M =
+ * max_abs_coord) and LIDAR_WARN_ORIGIN_OUTSIDE_SCENE otherwise, or
+ * LIDAR_ERR_INVALID_ARG for a NULL or non-finite p.  lidar_pose_set,
+ * lidar_scene_load, lidar_batch_create and lidar_simulate_sweep apply it to
+ * their origins. */
+lidar_status lidar_origin_check(float max_abs_coord, const float p[3]);
 
 /* ------------------------------------------------------------------------ */
 /* Simulation                                                                */
@@ -328,7 +359,16 @@ lidar_status lidar_simulate_echoes(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
  * lidar_simulate, lidar_simulate_ex and lidar_simulate_sweep see the actors;
  * the brute-force reference, traversal counting, the batched form and the
  * adjoint cover the static scene only and return LIDAR_ERR_INVALID_ARG while
- * actors are set. */
+ * actors are set.
+ * A mesh is walked with the ray taken to object space, whose origin lies at
+ * the sensor's distance from the actor.  Mesh boxes are therefore padded as
+ * for a scene whose largest coordinate is at least LIDAR_MESH_REACH metres
+ * (see lidar_origin_check), and the top-level tree as for the static scene's
+ * cube.  lidar_simulate, lidar_simulate_ex and lidar_simulate_sweep return
+ * LIDAR_WARN_ORIGIN_OUTSIDE_SCENE while actors are set if the traceable range
+ * (d_max plus the largest noise excursion) plus twice a placed mesh's largest
+ * coordinate exceeds LIDAR_MESH_REACH. */
+#define LIDAR_MESH_REACH 1024.0f
 
 /* Workspace sizes of a mesh (lidar_scene_desc with label ignored, may be NULL;
  * the workspaces hold the mesh BVH and a copy of the indices). */
@@ -428,7 +468,8 @@ typedef struct {
  * ordered on one stream.  Errors: LIDAR_ERR_INVALID_ARG for a window longer
  * than 360 degrees, non-finite values, non-unit quaternions (1e-4) or a
  * revolution index >= 2^32 - 1; nothing is launched when no column fires.
- * Asynchronous. */
+ * Warning: LIDAR_WARN_ORIGIN_OUTSIDE_SCENE if p_begin or p_end lies outside
+ * the scene's cube (lidar_origin_check).  Asynchronous. */
 lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep, const lidar_outputs *out,
                                   lidar_sweep_info *info, void *stream);
 
@@ -474,7 +515,9 @@ typedef struct {
  * same [n_ch][n_az] order as a single scan; its Philox counter is
  * (beam, scan, k, 0).  `packet_rays` (multiple of 64, 0 = tuned/default)
  * is the number of rays a wavefront claims per queue pop.  Returns
- * LIDAR_WARN_WAVELENGTH_CLAMPED if any instance clamps. */
+ * LIDAR_WARN_WAVELENGTH_CLAMPED if any instance clamps and
+ * LIDAR_WARN_ORIGIN_OUTSIDE_SCENE if a scene is loaded and an instance's
+ * origin lies outside its cube. */
 lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint32_t n_inst,
                                 uint32_t packet_rays, lidar_batch **out);
 
@@ -484,7 +527,10 @@ lidar_status lidar_batch_rays(const lidar_batch *batch, uint64_t *n_rays);
 /* Runs every instance of the batch in one persistent kernel: wavefronts pop
  * ray packets from a device queue until it is empty.  The queue reset and
  * the kernel are captured once into a hipGraph per (stream-independent)
- * output binding and replayed on `stream`.  Outputs as in lidar_simulate,
+ * output binding and replayed on `stream`; a new scene, new materials or a
+ * new stack cap since the capture make the next call capture again (and
+ * re-derive each instance's traceable range from the material noise).
+ * Outputs as in lidar_simulate,
  * indexed by out_offset[k] + beam.  Results are bit-identical to
  * lidar_simulate_batch_sequential, and instance k equals a plain scan of the
  * same sensor and pose whose Philox counter word 2 is k.  Asynchronous. */
@@ -538,17 +584,24 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
  * rho (R_lambda(0)), the per-material exponent k (I = rho |n.d|^k) and the
  * pose delta (dp, dw) of lidar_params, given dL/dI and dL/drange per beam of
  * the current sensor.  The forward state is the per-beam original triangle
- * id from the forward call (outputs.tri) and the per-beam valid mask;
- * beams with valid == 0 or tri == LIDAR_NO_TRIANGLE contribute nothing.  With
- * the triangle fixed, range t = n.(v0 - p) / (n.d).  Per-block partial sums
+ * id from the forward call (outputs.tri), the per-beam valid mask and the
+ * forward's intensity output; beams with valid == 0 or
+ * tri == LIDAR_NO_TRIANGLE contribute nothing.  With the triangle fixed,
+ * range t = n.(v0 - p) / (n.d) (range noise is additive, so dL/drange flows
+ * to t unchanged).  With intensity noise (noise_on and sigma_intensity > 0)
+ * the forward's intensity is max(0, R_lambda + sigma_I z): where it is 0 the
+ * clamp holds and the intensity terms of that beam are 0; `intensity` (device
+ * [n], the forward's output) is then required (NO_FORWARD_STATE if NULL) and
+ * is otherwise ignored (may be NULL).  Per-block partial sums
  * are reduced in a fixed order (deterministic); results are FP32 written to
  * d_rho[nmat], d_k[nmat], d_pose6[6] (device).  `params` must be the same as
  * in the forward call (without rho, R_lambda(0) is the spectral table at the
  * sensor wavelength).  Materials are limited to nmat <= 256.  Asynchronous.
- * Errors: NO_FORWARD_STATE if tri is NULL. */
+ * Errors: NO_FORWARD_STATE if tri or valid is NULL, or intensity is NULL while
+ * the sensor has intensity noise. */
 lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
-                            const uint8_t *valid, const float *dL_dI, const float *dL_drange,
-                            float *d_rho, float *d_k, float *d_pose6, void *stream);
+                            const uint8_t *valid, const float *intensity, const float *dL_dI,
+                            const float *dL_drange, float *d_rho, float *d_k, float *d_pose6, void *stream);
 
 /* Full-spectrum adjoint: as lidar_backward, with R_lambda(0) read from the
  * spectral table (params->spectra, else the table of lidar_materials_set) at
@@ -562,8 +615,9 @@ lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const ui
  * params->rho is set or d_spectra is NULL; otherwise as lidar_backward.
  * Asynchronous. */
 lidar_status lidar_backward_spectra(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
-                                    const uint8_t *valid, const float *dL_dI, const float *dL_drange,
-                                    float *d_spectra, float *d_k, float *d_pose6, void *stream);
+                                    const uint8_t *valid, const float *intensity, const float *dL_dI,
+                                    const float *dL_drange, float *d_spectra, float *d_k, float *d_pose6,
+                                    void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Introspection                                                             */
@@ -581,6 +635,8 @@ typedef struct {
     uint64_t tri_bytes;            /* bytes of triangle records */
     float build_ms;                /* last lidar_scene_load, GPU time */
     float box_pad;                 /* conservative bounding-box padding, metres */
+    float max_abs_coord;           /* largest |vertex coordinate| M (lidar_origin_check) */
+    uint32_t pad_;
 } lidar_stats;
 
 lidar_status lidar_get_stats(lidar_ctx *ctx, lidar_stats *out);

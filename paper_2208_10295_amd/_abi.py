@@ -25,6 +25,10 @@ ERR_STACK_OVERFLOW = -6
 ERR_NO_FORWARD_STATE = -7
 ERR_OUT_OF_MEMORY = -8
 WARN_WAVELENGTH_CLAMPED = 1
+WARN_ORIGIN_OUTSIDE_SCENE = 2
+MAX_TRIANGLES = 44739242
+MAX_NODES = 16777216
+MESH_REACH = 1024.0
 
 NO_LABEL = 0xFFFFFFFF
 NO_TRIANGLE = 0xFFFFFFFF
@@ -42,7 +46,7 @@ STATUS_NAMES = {
     ERR_WORKSPACE_TOO_SMALL: "ERR_WORKSPACE_TOO_SMALL", ERR_HIP: "ERR_HIP",
     ERR_UNSUPPORTED_DEVICE: "ERR_UNSUPPORTED_DEVICE", ERR_STACK_OVERFLOW: "ERR_STACK_OVERFLOW",
     ERR_NO_FORWARD_STATE: "ERR_NO_FORWARD_STATE", ERR_OUT_OF_MEMORY: "ERR_OUT_OF_MEMORY",
-    WARN_WAVELENGTH_CLAMPED: "WARN_WAVELENGTH_CLAMPED",
+    WARN_WAVELENGTH_CLAMPED: "WARN_WAVELENGTH_CLAMPED", WARN_ORIGIN_OUTSIDE_SCENE: "WARN_ORIGIN_OUTSIDE_SCENE",
 }
 
 P = C.c_void_p
@@ -93,7 +97,7 @@ class Stats(C.Structure):
     _fields_ = [("n_triangles", C.c_uint64), ("n_nodes", C.c_uint64), ("n_leaves", C.c_uint64),
                 ("depth", C.c_uint32), ("leaf_width", C.c_uint32), ("stack_entries", C.c_uint32),
                 ("root", C.c_uint32), ("node_bytes", C.c_uint64), ("tri_bytes", C.c_uint64),
-                ("build_ms", C.c_float), ("box_pad", C.c_float)]
+                ("build_ms", C.c_float), ("box_pad", C.c_float), ("max_abs_coord", C.c_float), ("pad_", C.c_uint32)]
 
 
 class Actor(C.Structure):
@@ -126,6 +130,7 @@ SIGNATURES = {
     "lidar_materials_set": (C.c_int32, [P, C.POINTER(MaterialDesc)]),
     "lidar_sensor_set": (C.c_int32, [P, C.POINTER(SensorDesc)]),
     "lidar_pose_set": (C.c_int32, [P, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "lidar_origin_check": (C.c_int32, [C.c_float, C.POINTER(C.c_float)]),
     "lidar_set_option": (C.c_int32, [P, C.c_uint32, C.c_int32]),
     "lidar_simulate": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Outputs), P]),
     "lidar_simulate_ex": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.POINTER(Params), C.POINTER(Outputs), P]),
@@ -155,8 +160,8 @@ SIGNATURES = {
     "lidar_batch_destroy": (C.c_int32, [P]),
     "lidar_tune": (C.c_int32, [P, C.POINTER(SceneDesc), P, C.c_uint64, P, C.c_uint64, P, C.POINTER(Outputs),
                                C.POINTER(TuneDesc), C.POINTER(TuneResult), P]),
-    "lidar_backward": (C.c_int32, [P, C.POINTER(Params), P, P, P, P, P, P, P, P]),
-    "lidar_backward_spectra": (C.c_int32, [P, C.POINTER(Params), P, P, P, P, P, P, P, P]),
+    "lidar_backward": (C.c_int32, [P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]),
+    "lidar_backward_spectra": (C.c_int32, [P, C.POINTER(Params), P, P, P, P, P, P, P, P, P]),
     "lidar_get_stats": (C.c_int32, [P, C.POINTER(Stats)]),
     "lidar_sync_check": (C.c_int32, [P, P]),
     "lidar_debug_copy_bvh": (C.c_int32, [P, P, C.c_uint64, P, C.c_uint64]),

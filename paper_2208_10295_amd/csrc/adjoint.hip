@@ -4,7 +4,8 @@
 // Per valid beam with hit triangle (v0, v1, v2), unit normal n, world beam
 // direction d = R s and origin p:
 //   c = n . d,  t = n . (v0 - p) / c,  I = rho_m |c|^k_m   (eq.4 with cos^k)
-// Given g_I = dL/dI and g_t = dL/drange:
+// Given g_I = dL/dI and g_t = dL/drange (g_I taken as 0 on beams whose
+// forward intensity max(0, R_lambda + sigma_I z) was clamped at 0):
 //   dL/drho_m += g_I |c|^k
 //   dL/dk_m   += g_I rho |c|^k ln|c|
 //   dL/dp     += -g_t n / c
@@ -30,6 +31,7 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(SceneDev S, const ui
                                                            InstanceDev in, MaterialsDev M, Overrides ov,
                                                            const uint32_t *__restrict__ tri,
                                                            const uint8_t *__restrict__ valid,
+                                                           const float *__restrict__ clamp_I,
                                                            const float *__restrict__ gI_in,
                                                            const float *__restrict__ gd_in,
                                                            double *__restrict__ partials) {
@@ -67,7 +69,9 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(SceneDev S, const ui
         float lnc = logf(ac);
         float ck = (k == 1.0f) ? ac : expf(k * lnc);              // |c|^k
         float ck1 = (k == 1.0f) ? 1.0f : expf((k - 1.0f) * lnc);  // |c|^(k-1)
-        float gI = gI_in ? gI_in[b] : 0.0f;
+        // the forward's intensity max(0, R_lambda + sigma_I z): 0 where the clamp holds, and
+        // there I does not move with rho, k or the pose
+        float gI = gI_in && !(clamp_I && clamp_I[b] == 0.0f) ? gI_in[b] : 0.0f;
         float gt = gd_in ? gd_in[b] : 0.0f;
         a_rho = gI * ck;
         a_k = gI * rho * ck * lnc;
@@ -186,14 +190,14 @@ size_t adjoint_partial_bytes(uint32_t n_beams, uint32_t nmat) {
 }
 
 void launch_adjoint(const SceneDev &S, const uint32_t *slot_of, const InstanceDev &in, const MaterialsDev &M,
-                    const Overrides &ov, const uint32_t *tri, const uint8_t *valid, const float *gI,
-                    const float *gd, double *partials, float *d_rho, float *d_k, float *d_pose6, float *d_spectra,
+                    const Overrides &ov, const uint32_t *tri, const uint8_t *valid, const float *clamp_I,
+                    const float *gI, const float *gd, double *partials, float *d_rho, float *d_k, float *d_pose6, float *d_spectra,
                     hipStream_t s) {
     uint32_t nb = in.n_ch * in.n_az;
     uint32_t blocks = (nb + kAdjBlock - 1) / kAdjBlock;
     uint32_t n_out = 2 * M.nmat + 6;
     double *tot = partials + (size_t)blocks * n_out;
-    adjoint_kernel<<<blocks, kAdjBlock, 0, s>>>(S, slot_of, in, M, ov, tri, valid, gI, gd, partials);
+    adjoint_kernel<<<blocks, kAdjBlock, 0, s>>>(S, slot_of, in, M, ov, tri, valid, clamp_I, gI, gd, partials);
     adjoint_sum_kernel<<<n_out, 256, 0, s>>>(partials, blocks, n_out, tot);
     adjoint_final_kernel<<<1, 64, 0, s>>>(tot, M.nmat, ov.pose_delta, d_rho, d_k, d_pose6, d_spectra, M,
                                           in.wavelength_nm);

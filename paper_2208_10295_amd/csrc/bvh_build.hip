@@ -34,9 +34,12 @@
 //    are 4; children with <= leaf_width triangles become leaves.  New nodes of
 //    a level are numbered by an exclusive scan, so the layout is deterministic
 //    and breadth-first.
-// Child boxes are padded outward by 2^-20 of the largest vertex coordinate,
-// which exceeds the rounding error of the FP32 box and triangle tests for rays
-// starting inside the scene's extent.
+// Child boxes are padded outward by 2^-20 of M = max(largest |vertex
+// coordinate|, reach).  The FP32 slab distance fma(b, 1/d, -o/d) is off by at
+// most 2^-24 (2|b_i| + 3|o_i|) along axis i, and the watertight test's distance
+// by a few units of 2^-24 (|v| + |o|); with |b_i|, |o_i| <= M both stay below
+// the pad 16 * 2^-24 M, so for every ray origin inside the cube
+// |x|, |y|, |z| <= M the walk never culls a triangle the test accepts.
 #include <utility>
 #include <vector>
 
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(256) void tri_prep_kernel(BuildInputs in, float *__
     }
 }
 
-__global__ __launch_bounds__(256) void bounds_reduce_kernel(Bounds *__restrict__ partials, uint32_t nb) {
+__global__ __launch_bounds__(256) void bounds_reduce_kernel(Bounds *__restrict__ partials, uint32_t nb, float reach) {
     __shared__ float red[7][256];
     float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(256) void bounds_reduce_kernel(Bounds *__restrict__
         Bounds b;
         for (int a = 0; a < 3; ++a) { b.lo[a] = red[a][0]; b.hi[a] = red[3 + a][0]; }
         b.maxabs = red[6][0];
-        b.pad_ = b.maxabs * 9.5367431640625e-07f + 1e-20f;  // 2^-20 * max |coordinate|
+        b.pad_ = fmaxf(b.maxabs, reach) * 9.5367431640625e-07f + 1e-20f;  // 2^-20 * max(max |coordinate|, reach)
         partials[0] = b;
     }
 }
@@ -960,7 +963,7 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
     TriRec *recs_m = ploc ? (TriRec *)(sc + L.recs_m) : recs;   // Morton-order records
     HIP_TRY(hipMemsetAsync(stat, 0, 64, s));
     tri_prep_kernel<<<nb, 256, 0, s>>>(in, cent, partials, stat);
-    bounds_reduce_kernel<<<1, 256, 0, s>>>(partials, nb);
+    bounds_reduce_kernel<<<1, 256, 0, s>>>(partials, nb, in.reach);
     morton_kernel<<<nb, 256, 0, s>>>(cent, nt, partials, keys, vals);
     radix_sort_u64(keys, vals, (uint64_t *)(sc + L.keys2), (uint32_t *)(sc + L.vals2), nt, 63, sc + L.sort_tmp, s);
     write_records_kernel<<<nb, 256, 0, s>>>(in, vals, recs_m, slot_of);
@@ -1093,6 +1096,8 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
     res.max_material = hstat[0];
     res.bad_index = hstat[1];
     res.box_pad = hb.pad_;
+    res.max_abs = hb.maxabs;
+    res.reach = in.reach;
     return hipSuccess;
 }
 

@@ -14,7 +14,7 @@
 // Refit reproduces the builder's boxes exactly for unchanged inputs: a leaf
 // slot is the union of its records' vertices minus/plus the pad, an inner slot
 // the union of its child node's (padded) slots, and the pad is 2^-20 of the
-// largest coordinate as in the build.
+// larger of the largest coordinate and the tree's reach, as in the build.
 #include "lidar_kernels.hpp"
 
 namespace lidar {
@@ -37,9 +37,9 @@ __global__ void zero_words_kernel(uint32_t *word) {
     word[1] = 0u;
 }
 
-// word[1] = bits of the box pad 2^-20 max |x| + 1e-20 (the builder's formula)
-__global__ void pad_kernel(uint32_t *word) {
-    word[1] = __float_as_uint(__uint_as_float(word[0]) * 9.5367431640625e-07f + 1e-20f);
+// word[1] = bits of the box pad 2^-20 max(max |x|, reach) + 1e-20 (the builder's formula)
+__global__ void pad_kernel(uint32_t *word, float reach) {
+    word[1] = __float_as_uint(fmaxf(__uint_as_float(word[0]), reach) * 9.5367431640625e-07f + 1e-20f);
 }
 
 __global__ __launch_bounds__(256) void mesh_records_kernel(TriRec *__restrict__ recs, uint32_t nt,
@@ -272,11 +272,11 @@ __device__ inline void refit_levels_lds(Node4 *__restrict__ nodes, const TriRec 
 }
 
 // max |x| over a block's values into LDS, then the builder's pad formula
-__device__ inline float block_pad(float m, uint32_t *lds_max) {
+__device__ inline float block_pad(float m, uint32_t *lds_max, float reach) {
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(lds_max, __float_as_uint(m));
     __syncthreads();
-    return __uint_as_float(*lds_max) * 9.5367431640625e-07f + 1e-20f;
+    return fmaxf(__uint_as_float(*lds_max), reach) * 9.5367431640625e-07f + 1e-20f;
 }
 
 __global__ __launch_bounds__(kSmallRefitThreads) void refit_mesh_small_kernel(Node4 *__restrict__ nodes,
@@ -284,14 +284,14 @@ __global__ __launch_bounds__(kSmallRefitThreads) void refit_mesh_small_kernel(No
                                                                               uint32_t nt,
                                                                               const uint32_t *__restrict__ idx,
                                                                               const float *__restrict__ v,
-                                                                              uint64_t nv) {
+                                                                              uint64_t nv, float reach) {
     __shared__ uint32_t lds_max;
     __shared__ float box[kLdsRefitNodes][6];
     if (threadIdx.x == 0) lds_max = 0u;
     __syncthreads();
     float m = 0.0f;
     for (uint64_t k = threadIdx.x; k < 3 * nv; k += kSmallRefitThreads) m = fmaxf(m, fabsf(v[k]));
-    const float pad = block_pad(m, &lds_max);
+    const float pad = block_pad(m, &lds_max, reach);
     for (uint32_t s = threadIdx.x; s < nt; s += kSmallRefitThreads) {
         TriRec r = recs[s];
         const uint32_t k = __float_as_uint(r.a.w);
@@ -312,14 +312,15 @@ __global__ __launch_bounds__(kSmallRefitThreads) void update_tlas_small_kernel(c
                                                                                const MeshDev *__restrict__ meshes,
                                                                                float *__restrict__ lohi,
                                                                                Node4 *__restrict__ nodes,
-                                                                               TriRec *__restrict__ recs, Levels L) {
+                                                                               TriRec *__restrict__ recs, Levels L,
+                                                                               float reach) {
     __shared__ uint32_t lds_max;
     __shared__ float box[kLdsRefitNodes][6];
     if (threadIdx.x == 0) lds_max = 0u;
     __syncthreads();
     float m = 0.0f;
     for (uint32_t a = threadIdx.x; a < n; a += kSmallRefitThreads) m = fmaxf(m, actor_box(actors, a, meshes, lohi));
-    const float pad = block_pad(m, &lds_max);     // its barrier also publishes the boxes
+    const float pad = block_pad(m, &lds_max, reach);     // its barrier also publishes the boxes
     for (uint32_t s = threadIdx.x; s < n; s += kSmallRefitThreads) {
         TriRec r = recs[s];
         const float *b = lohi + 6 * (size_t)__float_as_uint(r.a.w);
@@ -357,13 +358,14 @@ bool refit_supported(const BuildResult &br) { return br.depth >= 1 && br.depth <
 void refit_mesh(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t nt, const uint32_t *idx,
                 const float *vertices, uint64_t nv, uint32_t *word, hipStream_t s) {
     if (br.n_nodes <= kSmallRefitNodes) {
-        refit_mesh_small_kernel<<<1, kSmallRefitThreads, 0, s>>>(nodes, recs, levels_of(br), nt, idx, vertices, nv);
+        refit_mesh_small_kernel<<<1, kSmallRefitThreads, 0, s>>>(nodes, recs, levels_of(br), nt, idx, vertices, nv,
+                                                                 br.reach);
         return;
     }
     zero_words_kernel<<<1, 1, 0, s>>>(word);
     uint32_t g = grid_of(3 * nv);
     maxabs_kernel<<<g < 1024 ? g : 1024, 256, 0, s>>>(vertices, 3 * nv, word);
-    pad_kernel<<<1, 1, 0, s>>>(word);
+    pad_kernel<<<1, 1, 0, s>>>(word, br.reach);
     mesh_records_kernel<<<grid_of(nt), 256, 0, s>>>(recs, nt, idx, vertices);
     refit_tree(nodes, recs, br, word, s);
 }
@@ -381,7 +383,8 @@ void actor_prims(const float *lohi, uint32_t n, float *vtx, uint32_t *idx, uint1
 void update_tlas(const ActorDev *actors, uint32_t n, const MeshDev *meshes, float *lohi, Node4 *nodes,
                  TriRec *recs, const BuildResult &br, uint32_t *word, hipStream_t s) {
     if (br.n_nodes <= kSmallRefitNodes && n <= 4 * kSmallRefitNodes) {
-        update_tlas_small_kernel<<<1, kSmallRefitThreads, 0, s>>>(actors, n, meshes, lohi, nodes, recs, levels_of(br));
+        update_tlas_small_kernel<<<1, kSmallRefitThreads, 0, s>>>(actors, n, meshes, lohi, nodes, recs, levels_of(br),
+                                                                  br.reach);
         return;
     }
     actor_boxes(actors, n, meshes, lohi, word, s);
@@ -390,7 +393,7 @@ void update_tlas(const ActorDev *actors, uint32_t n, const MeshDev *meshes, floa
 
 void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,
                 hipStream_t s) {
-    pad_kernel<<<1, 1, 0, s>>>(word);
+    pad_kernel<<<1, 1, 0, s>>>(word, br.reach);
     tlas_records_kernel<<<grid_of(n), 256, 0, s>>>(recs, n, lohi);
     refit_tree(nodes, recs, br, word, s);
 }

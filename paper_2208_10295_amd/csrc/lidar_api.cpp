@@ -108,6 +108,10 @@ struct lidar_ctx {
     size_t staging_n = 0;
     hipEvent_t staging_ev = nullptr;
     int actor_stack = 0;
+    float actor_reach_need = 0.f;   // twice the largest coordinate of any placed mesh
+    // generations: bumped when the scene (or its stack cap) or the materials change, so that a
+    // batch's captured graph, which holds their device pointers by value, is captured again
+    uint64_t scene_gen = 1, mat_gen = 1;
 
     int trace_stack() const { return has_actors && actor_stack > stack ? actor_stack : stack; }
     // automatic tile shape (measured on the 64 x 2048 scan): 2 azimuth steps x 32 channels for the
@@ -137,6 +141,8 @@ struct lidar_batch {
     uint32_t packet = 256;
     int tile_az_log2 = 3;      // tile shape fixed at creation (padded ray layout depends on it)
     TraceOpts graph_opts{-1, -1, -1, -1};
+    uint64_t graph_scene_gen = 0, graph_mat_gen = 0;   // context generations the graph was captured at
+    uint64_t inst_mat_gen = 0;                         // material generation of the instances' t_trace
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Outputs bound{};
@@ -198,11 +204,27 @@ lidar_status check_quat(lidar_ctx *ctx, const float *p, const float *q) {
     return LIDAR_OK;
 }
 
-float trace_limit(const lidar_ctx *ctx, const lidar_sensor_desc &d) {
-    if (!d.noise_on) return d.d_max;
+float trace_limit(const lidar_ctx *ctx, float d_max, bool noise_on) {
+    if (!noise_on) return d_max;
     float smax = 0.f;
     for (float s : ctx->sigma_h) smax = std::max(smax, s);
-    return d.d_max + kBoxMullerBound * smax;
+    return d_max + kBoxMullerBound * smax;
+}
+
+float trace_limit(const lidar_ctx *ctx, const lidar_sensor_desc &d) { return trace_limit(ctx, d.d_max, d.noise_on != 0); }
+
+// LIDAR_WARN_ORIGIN_OUTSIDE_SCENE if a scene is loaded and p lies outside its cube, else 0
+lidar_status origin_warning(const lidar_ctx *ctx, const float *p) {
+    if (!ctx->has_scene) return LIDAR_OK;
+    return lidar_origin_check(ctx->br.max_abs, p) == LIDAR_WARN_ORIGIN_OUTSIDE_SCENE ? LIDAR_WARN_ORIGIN_OUTSIDE_SCENE
+                                                                                       : LIDAR_OK;
+}
+
+// with actors: the object-space origin of a mesh walk is within the traceable range plus the mesh's
+// extent of the mesh origin; warn when that can exceed the reach its boxes were padded for
+lidar_status actor_reach_warning(const lidar_ctx *ctx, const lidar_sensor_desc &d) {
+    if (!ctx->has_actors) return LIDAR_OK;
+    return trace_limit(ctx, d) + ctx->actor_reach_need > LIDAR_MESH_REACH ? LIDAR_WARN_ORIGIN_OUTSIDE_SCENE : LIDAR_OK;
 }
 
 uint32_t tiles_az(int tile_az_log2, uint32_t n_az) {
@@ -354,7 +376,7 @@ const char *lidar_last_error(const lidar_ctx *ctx) {
 
 lidar_status lidar_scene_bytes(const lidar_scene_desc *desc, uint64_t *persistent_bytes, uint64_t *scratch_bytes) {
     if (!desc || !persistent_bytes || !scratch_bytes) return LIDAR_ERR_INVALID_ARG;
-    if (desc->n_triangles < 1 || desc->n_triangles >= (1ull << 28) || desc->n_vertices < 1 ||
+    if (desc->n_triangles < 1 || desc->n_triangles > LIDAR_MAX_TRIANGLES || desc->n_vertices < 1 ||
         desc->n_vertices >= (1ull << 32))
         return LIDAR_ERR_INVALID_ARG;
     uint32_t nt = (uint32_t)desc->n_triangles;
@@ -378,7 +400,7 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     if (W < 1 || W > 8) return ctx->fail(LIDAR_ERR_INVALID_ARG, "leaf_width must be in 1..8");
     uint64_t need_p = 0, need_s = 0;
     if (lidar_scene_bytes(desc, &need_p, &need_s) != LIDAR_OK)
-        return ctx->fail(LIDAR_ERR_INVALID_ARG, "triangle/vertex count out of range");
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "triangle count out of 1..LIDAR_MAX_TRIANGLES or vertex count out of range");
     if (!persistent || !scratch) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace pointer is null");
     if (((uintptr_t)persistent & 255) || ((uintptr_t)scratch & 255))
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspaces must be 256-byte aligned");
@@ -434,6 +456,8 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     hipEventDestroy(e1);
     if (e != hipSuccess) return ctx->hip_fail(e, "BVH build");
     if (br.bad_index) return ctx->fail(LIDAR_ERR_INVALID_ARG, "a triangle index is >= n_vertices");
+    if (br.n_nodes > LIDAR_MAX_NODES)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "the BVH has more than LIDAR_MAX_NODES nodes (2 GiB of nodes)");
     int stack = stack_for_depth(br.depth);
     if (stack < 0) {
         char buf[128];
@@ -452,7 +476,8 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     ctx->S.max_steps = br.n_nodes + br.n_leaves + 1;
     ctx->S.stack_cap = ctx->stack_cap_opt > 0 && ctx->stack_cap_opt < stack ? ctx->stack_cap_opt : stack;
     ctx->has_scene = true;
-    return LIDAR_OK;
+    ++ctx->scene_gen;
+    return origin_warning(ctx, ctx->p);
 }
 
 lidar_status lidar_materials_set(lidar_ctx *ctx, const lidar_material_desc *d) {
@@ -491,6 +516,7 @@ lidar_status lidar_materials_set(lidar_ctx *ctx, const lidar_material_desc *d) {
     ctx->M.dlambda = d->dlambda_nm;
     ctx->sigma_h.assign(d->sigma_range, d->sigma_range + d->nmat);
     ctx->has_mat = true;
+    ++ctx->mat_gen;
     if (ctx->has_sensor && d->nmat <= kMaxAdjMaterials) {
         size_t pb = adjoint_partial_bytes(ctx->sensor.d.n_ch * ctx->sensor.d.n_az, d->nmat);
         if (ctx->adj_partials.ensure(pb) != hipSuccess)
@@ -534,6 +560,13 @@ lidar_status lidar_pose_set(lidar_ctx *ctx, const float p[3], const float q[4]) 
     if (st != LIDAR_OK) return st;
     std::memcpy(ctx->p, p, 12);
     std::memcpy(ctx->q, q, 16);
+    return origin_warning(ctx, p);
+}
+
+lidar_status lidar_origin_check(float max_abs_coord, const float p[3]) {
+    if (!p || !finite3(p) || !std::isfinite(max_abs_coord)) return LIDAR_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!(std::fabs(p[k]) <= max_abs_coord)) return LIDAR_WARN_ORIGIN_OUTSIDE_SCENE;
     return LIDAR_OK;
 }
 
@@ -568,8 +601,9 @@ static lidar_status simulate_common(lidar_ctx *ctx, uint64_t seed, uint32_t scan
                            n_nodes, n_tris, ctx->has_actors ? &ctx->A : nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "trace launch");
-    return wavelength_clamped(ctx, d.wavelength_nm) && !(params && params->rho) ? LIDAR_WARN_WAVELENGTH_CLAMPED
-                                                                                : LIDAR_OK;
+    return (wavelength_clamped(ctx, d.wavelength_nm) && !(params && params->rho) ? LIDAR_WARN_WAVELENGTH_CLAMPED
+                                                                                 : LIDAR_OK) |
+           actor_reach_warning(ctx, d);
 }
 
 lidar_status lidar_simulate(lidar_ctx *ctx, uint64_t seed, uint32_t scan, const lidar_outputs *out, void *stream) {
@@ -681,7 +715,8 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, co
             info->count[r] = run_count[r];
         }
     }
-    lidar_status ok = wavelength_clamped(ctx, d.wavelength_nm) ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK;
+    lidar_status ok = (wavelength_clamped(ctx, d.wavelength_nm) ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK) |
+                      origin_warning(ctx, sw->p_begin) | origin_warning(ctx, sw->p_end) | actor_reach_warning(ctx, d);
     if (n_cols == 0) return ok;
     hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
@@ -875,12 +910,15 @@ lidar_status lidar_mesh_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void 
         in.mat = m;
     }
     in.label = nullptr;
+    in.reach = LIDAR_MESH_REACH;
     uint32_t *idx_copy = (uint32_t *)((char *)persistent + al256(build_persistent_bytes(nt)));
     if ((e = hipMemcpyAsync(idx_copy, in.idx, 12 * (uint64_t)nt, hipMemcpyDeviceToDevice, s)) != hipSuccess)
         return ctx->hip_fail(e, "mesh index copy");
     BuildResult br{};
     if ((e = build_bvh(in, persistent, scratch, br, s)) != hipSuccess) return ctx->hip_fail(e, "mesh BVH build");
     if (br.bad_index) return ctx->fail(LIDAR_ERR_INVALID_ARG, "a triangle index is >= n_vertices");
+    if (br.n_nodes > LIDAR_MAX_NODES)
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "the mesh BVH has more than LIDAR_MAX_NODES nodes");
     if (!refit_supported(br) || stack_for_need(entries_for_depth(br.depth)) < 0)
         return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "mesh BVH too deep");
     MeshHost mh{};
@@ -989,6 +1027,7 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
     in.builder = 0;
     in.ploc_radius = 32;
     set_collapse(in, 0u);
+    in.reach = ctx->br.max_abs;     // rays start in the static scene's cube
     BuildResult br{};
     if ((e = build_bvh(in, persistent, scratch, br, s)) != hipSuccess) return ctx->hip_fail(e, "actor BVH build");
     if (!refit_supported(br)) return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "actor BVH too deep");
@@ -1020,6 +1059,8 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
     ctx->actor_mesh.resize(n_actors);
     for (uint32_t k = 0; k < n_actors; ++k) ctx->actor_mesh[k] = actors[k].mesh;
     ctx->actor_stack = stack;
+    ctx->actor_reach_need = 0.f;
+    for (const ActorDev &d : h) ctx->actor_reach_need = std::max(ctx->actor_reach_need, 2.f * ctx->meshes[d.mesh].br.max_abs);
     ctx->tlas_stale = false;
     ctx->has_actors = true;
     return LIDAR_OK;
@@ -1072,13 +1113,14 @@ lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint
     if (packet_rays % 64 != 0 || packet_rays > 65536)
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "packet_rays must be a multiple of 64 (<= 65536)");
     if (!ctx->has_mat) return ctx->fail(LIDAR_ERR_NOT_READY, "materials must be set before a batch");
-    bool clamped = false;
+    bool clamped = false, origin_out = false;
     size_t table_doubles = 0;
     for (uint32_t k = 0; k < n_inst; ++k) {
         lidar_status st = check_sensor(ctx, &inst[k].sensor);
         if (st != LIDAR_OK) return st;
         st = check_quat(ctx, inst[k].p, inst[k].q_wxyz);
         if (st != LIDAR_OK) return st;
+        origin_out |= origin_warning(ctx, inst[k].p) != LIDAR_OK;
         table_doubles += 2 * ((size_t)inst[k].sensor.n_ch + inst[k].sensor.n_az) + inst[k].sensor.n_ch;
         clamped |= wavelength_clamped(ctx, inst[k].sensor.wavelength_nm);
     }
@@ -1110,6 +1152,7 @@ lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint
     }
     b->n_padded = ray_base;
     b->n_rays = out_base;
+    b->inst_mat_gen = ctx->mat_gen;
     hipError_t e = hipMemcpy(b->d_insts.p, b->h_insts.data(), sizeof(InstanceDev) * n_inst, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
@@ -1120,7 +1163,20 @@ lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint
         return ctx->hip_fail(e, "batch upload");
     }
     *out = b;
-    return clamped ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK;
+    return (clamped ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK) | (origin_out ? LIDAR_WARN_ORIGIN_OUTSIDE_SCENE : LIDAR_OK);
+}
+
+// The instances' traceable range depends on the material noise: after new materials it is derived
+// again and the table re-uploaded (the stream is drained first: a replay may still read it).
+static lidar_status refresh_batch(lidar_ctx *ctx, lidar_batch *b, hipStream_t s) {
+    if (b->inst_mat_gen == ctx->mat_gen) return LIDAR_OK;
+    for (InstanceDev &in : b->h_insts) in.t_trace = trace_limit(ctx, in.d_max, in.noise_on != 0);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_insts.p, b->h_insts.data(), sizeof(InstanceDev) * b->n_inst, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return ctx->hip_fail(e, "batch instance refresh");
+    b->inst_mat_gen = ctx->mat_gen;
+    return LIDAR_OK;
 }
 
 lidar_status lidar_batch_rays(const lidar_batch *b, uint64_t *n) {
@@ -1135,9 +1191,11 @@ lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_ou
     if ((st = no_actors(ctx, "the batched form")) != LIDAR_OK) return st;
     if (!b || b->ctx != ctx || !out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "bad batch or outputs");
     hipSetDevice(ctx->device);
+    if ((st = refresh_batch(ctx, b, (hipStream_t)stream)) != LIDAR_OK) return st;
     Outputs o = to_outputs(out, b->n_rays);
     TraceOpts t = ctx->opts(b->tile_az_log2);
-    if (!b->has_graph || !same_outputs(o, b->bound) || std::memcmp(&t, &b->graph_opts, sizeof t) != 0) {
+    if (!b->has_graph || !same_outputs(o, b->bound) || std::memcmp(&t, &b->graph_opts, sizeof t) != 0 ||
+        b->graph_scene_gen != ctx->scene_gen || b->graph_mat_gen != ctx->mat_gen) {
         b->drop_graph();
         uint32_t grid = (uint32_t)(ctx->n_cu * batch_blocks_per_cu(t));
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -1154,6 +1212,8 @@ lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_ou
         }
         b->bound = o;
         b->graph_opts = t;
+        b->graph_scene_gen = ctx->scene_gen;
+        b->graph_mat_gen = ctx->mat_gen;
         b->has_graph = true;
     }
     hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
@@ -1168,6 +1228,7 @@ lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *b, con
     if ((st = no_actors(ctx, "the batched form")) != LIDAR_OK) return st;
     if (!b || b->ctx != ctx || !out) return ctx->fail(LIDAR_ERR_INVALID_ARG, "bad batch or outputs");
     hipSetDevice(ctx->device);
+    if ((st = refresh_batch(ctx, b, (hipStream_t)stream)) != LIDAR_OK) return st;
     Outputs o = to_outputs(out, b->n_rays);
     Overrides ov{};
     for (uint32_t k = 0; k < b->n_inst; ++k) {
@@ -1225,6 +1286,7 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
     for (uint32_t li = 0; li < desc->n_leaf && st == LIDAR_OK; ++li) {
         sd.leaf_width = desc->leaf_widths[li];
         st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
+        if (st > 0) st = LIDAR_OK;   // a warning (e.g. the pose's origin) does not stop the tuning
         for (uint32_t ni = 0; ni < n_lanes && st == LIDAR_OK; ++ni) {
             ctx->lanes_per_ray = (int)lanes[ni];
             for (uint32_t pi = 0; pi < desc->n_packet && st == LIDAR_OK; ++pi) {
@@ -1258,7 +1320,7 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
     if (st != LIDAR_OK) return st;
     sd.leaf_width = res->best_leaf_width;
     st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
-    if (st != LIDAR_OK) return st;
+    if (st < 0) return st;
     ctx->lanes_per_ray = (int)res->best_lanes_per_ray;
     b->packet = res->best_packet_rays;
     b->drop_graph();
@@ -1269,8 +1331,9 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
 // adjoint
 // ---------------------------------------------------------------------------
 static lidar_status backward_common(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
-                                    const uint8_t *valid, const float *dL_dI, const float *dL_drange, float *d_rho,
-                                    float *d_k, float *d_pose6, float *d_spectra, void *stream) {
+                                    const uint8_t *valid, const float *intensity, const float *dL_dI,
+                                    const float *dL_drange, float *d_rho, float *d_k, float *d_pose6,
+                                    float *d_spectra, void *stream) {
     lidar_status st = ready(ctx, true);
     if (st != LIDAR_OK) return st;
     if (!tri) return ctx->fail(LIDAR_ERR_NO_FORWARD_STATE, "backward needs the forward's triangle ids (tri)");
@@ -1280,6 +1343,11 @@ static lidar_status backward_common(lidar_ctx *ctx, const lidar_params *params, 
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "params: give rho or spectra, not both");
     if ((st = no_actors(ctx, "the adjoint")) != LIDAR_OK) return st;
     const lidar_sensor_desc &d = ctx->sensor.d;
+    // the forward's intensity max(0, R_lambda + sigma_I z) is clamped where it reads 0
+    const bool clamps = d.noise_on && d.sigma_intensity > 0.f;
+    if (clamps && !intensity)
+        return ctx->fail(LIDAR_ERR_NO_FORWARD_STATE,
+                         "with intensity noise the backward needs the forward's intensity (clamped beams)");
     size_t pb = adjoint_partial_bytes(d.n_ch * d.n_az, ctx->M.nmat);
     if (ctx->adj_partials.n < pb) return ctx->fail(LIDAR_ERR_NOT_READY, "adjoint buffer not allocated");
     const double *elev_cs = (const double *)ctx->sensor_tables.p;
@@ -1293,27 +1361,30 @@ static lidar_status backward_common(lidar_ctx *ctx, const lidar_params *params, 
         ov.spectra = params->spectra;
     }
     hipSetDevice(ctx->device);
-    launch_adjoint(ctx->S, ctx->slot_of, in, ctx->M, ov, tri, valid, dL_dI, dL_drange, (double *)ctx->adj_partials.p,
-                   d_rho, d_k, d_pose6, d_spectra, (hipStream_t)stream);
+    launch_adjoint(ctx->S, ctx->slot_of, in, ctx->M, ov, tri, valid, clamps ? intensity : nullptr, dL_dI, dL_drange,
+                   (double *)ctx->adj_partials.p, d_rho, d_k, d_pose6, d_spectra, (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "adjoint launch");
     return LIDAR_OK;
 }
 
 lidar_status lidar_backward(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri, const uint8_t *valid,
-                            const float *dL_dI, const float *dL_drange, float *d_rho, float *d_k, float *d_pose6,
-                            void *stream) {
-    return backward_common(ctx, params, tri, valid, dL_dI, dL_drange, d_rho, d_k, d_pose6, nullptr, stream);
+                            const float *intensity, const float *dL_dI, const float *dL_drange, float *d_rho,
+                            float *d_k, float *d_pose6, void *stream) {
+    return backward_common(ctx, params, tri, valid, intensity, dL_dI, dL_drange, d_rho, d_k, d_pose6, nullptr,
+                           stream);
 }
 
 lidar_status lidar_backward_spectra(lidar_ctx *ctx, const lidar_params *params, const uint32_t *tri,
-                                    const uint8_t *valid, const float *dL_dI, const float *dL_drange,
-                                    float *d_spectra, float *d_k, float *d_pose6, void *stream) {
+                                    const uint8_t *valid, const float *intensity, const float *dL_dI,
+                                    const float *dL_drange, float *d_spectra, float *d_k, float *d_pose6,
+                                    void *stream) {
     if (!ctx) return LIDAR_ERR_INVALID_ARG;
     if (params && params->rho) return ctx->fail(LIDAR_ERR_INVALID_ARG, "the spectral adjoint reads R_lambda(0) "
                                                                        "from the table: params->rho must be NULL");
     if (!d_spectra) return ctx->fail(LIDAR_ERR_INVALID_ARG, "d_spectra is null");
-    return backward_common(ctx, params, tri, valid, dL_dI, dL_drange, nullptr, d_k, d_pose6, d_spectra, stream);
+    return backward_common(ctx, params, tri, valid, intensity, dL_dI, dL_drange, nullptr, d_k, d_pose6, d_spectra,
+                           stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1334,6 +1405,7 @@ lidar_status lidar_get_stats(lidar_ctx *ctx, lidar_stats *o) {
     o->tri_bytes = (uint64_t)ctx->S.n_tri * sizeof(TriRec);
     o->build_ms = ctx->build_ms;
     o->box_pad = ctx->br.box_pad;
+    o->max_abs_coord = ctx->br.max_abs;
     return LIDAR_OK;
 }
 
@@ -1394,6 +1466,7 @@ lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
         if (value < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "stack cap must be >= 0");
         ctx->stack_cap_opt = value;
         if (ctx->has_scene) ctx->S.stack_cap = value > 0 && value < ctx->stack ? value : ctx->stack;
+        ++ctx->scene_gen;
         return LIDAR_OK;
     default:
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "unknown option");

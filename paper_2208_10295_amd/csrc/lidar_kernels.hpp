@@ -37,6 +37,9 @@ struct BuildInputs {
     uint32_t ploc_radius;      // PLOC search radius, 1..128
     uint32_t collapse;         // 0 = surface-area cost (default), 1 = greedy (largest child first)
     float leaf_cost;           // leaf step weight of the cost model, a node step weighing 1
+    float reach;               // child boxes are padded by 2^-20 max(max |vertex coordinate|, reach):
+                               // 0 for a scene, the object-space origin bound for a mesh, the static
+                               // scene's largest coordinate for the actors' top-level tree
 };
 
 // Persistent layout: [nodes: Node4 x max(nt,1)] [records: TriRec x nt] [slot_of: u32 x nt]
@@ -53,6 +56,8 @@ struct BuildResult {
     uint32_t max_material;
     uint32_t bad_index;
     float box_pad;
+    float max_abs;             // largest |vertex coordinate| of the input
+    float reach;               // BuildInputs::reach of the build (refits pad the same way)
     uint32_t level_base[kMaxLevels + 1];   // nodes of level L: [level_base[L], level_base[L + 1])
 };
 
@@ -145,7 +150,8 @@ constexpr int kAdjBlock = 256;
 size_t adjoint_partial_bytes(uint32_t n_beams, uint32_t nmat);
 void launch_adjoint(const SceneDev &S, const uint32_t *slot_of, const InstanceDev &in, const MaterialsDev &M,
                     const Overrides &ov,
-                    const uint32_t *tri, const uint8_t *valid, const float *gI, const float *gd, double *partials,
+                    const uint32_t *tri, const uint8_t *valid, const float *clamp_I, const float *gI, const float *gd,
+                    double *partials,
                     float *d_rho, float *d_k, float *d_pose6, float *d_spectra, hipStream_t s);
 
 }  // namespace lidar

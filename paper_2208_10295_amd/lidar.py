@@ -34,8 +34,12 @@ def _stream(stream):
 
 
 def _warn(status, what):
-    if status == A.WARN_WAVELENGTH_CLAMPED:
+    """Turn the warning bits of a non-negative status into Python warnings; returns the status."""
+    if status > 0 and status & A.WARN_WAVELENGTH_CLAMPED:
         warnings.warn(f"{what}: sensor wavelength outside the spectral table; end bin used", RuntimeWarning)
+    if status > 0 and status & A.WARN_ORIGIN_OUTSIDE_SCENE:
+        warnings.warn(f"{what}: a ray origin lies outside the cube the BVH's box padding covers; the walk may "
+                      "rarely miss a hit the brute force finds", RuntimeWarning)
     return status
 
 
@@ -161,8 +165,8 @@ class Context:
         check(lib.lidar_scene_bytes(C.byref(d), C.byref(pb), C.byref(sb)), self.h)
         persistent = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
         scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
-        check(lib.lidar_scene_load(self.h, C.byref(d), _ptr(persistent), pb.value, _ptr(scratch), sb.value,
-                                   _stream(stream)), self.h)
+        _warn(check(lib.lidar_scene_load(self.h, C.byref(d), _ptr(persistent), pb.value, _ptr(scratch), sb.value,
+                                         _stream(stream)), self.h), "load_scene")
         del scratch
         self.persistent = persistent
         self.scene_desc = d
@@ -277,7 +281,7 @@ class Context:
     def set_pose(self, p, q):
         pa = (C.c_float * 3)(*[float(x) for x in p])
         qa = (C.c_float * 4)(*[float(x) for x in q])
-        check(lib.lidar_pose_set(self.h, pa, qa), self.h)
+        return _warn(check(lib.lidar_pose_set(self.h, pa, qa), self.h), "set_pose")
 
     def set_tile_shape(self, tile_az: int):
         check(lib.lidar_set_option(self.h, A.OPT_TILE_AZ, int(tile_az)), self.h)
@@ -370,7 +374,7 @@ class Context:
         return run
 
     def backward_launcher(self, tri, valid, dL_dI, dL_drange, params: dict | None = None, spectra: bool = False,
-                          stream=None):
+                          stream=None, intensity=None):
         """A callable f() that runs lidar_backward (lidar_backward_spectra if `spectra`) with fixed
         arguments, writing into the returned (d_rho or d_spectra, d_k, d_pose6) tensors."""
         nmat = self.nmat
@@ -379,8 +383,8 @@ class Context:
         d_k = torch.empty(nmat, dtype=torch.float32, device=self.device)
         d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
         p = _params_struct(params)
-        args = (self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(dL_dI), _ptr(dL_drange), _ptr(d_a), _ptr(d_k),
-                _ptr(d_pose), _stream(stream))
+        args = (self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(intensity), _ptr(dL_dI), _ptr(dL_drange), _ptr(d_a),
+                _ptr(d_k), _ptr(d_pose), _stream(stream))
         fn = lib.lidar_backward_spectra if spectra else lib.lidar_backward
         h = self.h
 
@@ -388,7 +392,7 @@ class Context:
             st = fn(*args)
             if st < 0:
                 check(st, h)
-        run._keep = (p, params, tri, valid, dL_dI, dL_drange)
+        run._keep = (p, params, tri, valid, intensity, dL_dI, dL_drange)
         return run, (d_a, d_k, d_pose)
 
     def compact(self, dense: dict, names=None, out: dict | None = None, workspace=None, stream=None,
@@ -463,7 +467,8 @@ class Context:
                 arr[k] = float(x)
         info = A.SweepInfo()
         o = outputs_struct(out)
-        check(lib.lidar_simulate_sweep(self.h, C.byref(d), C.byref(o), C.byref(info), _stream(stream)), self.h)
+        _warn(check(lib.lidar_simulate_sweep(self.h, C.byref(d), C.byref(o), C.byref(info), _stream(stream)), self.h),
+              "simulate_sweep")
         runs = [(int(info.scan[r]), int(info.first[r]), int(info.count[r])) for r in range(info.n_runs)]
         return out, runs
 
@@ -500,24 +505,29 @@ class Context:
     def sync_check(self, stream=None):
         check(lib.lidar_sync_check(self.h, _stream(stream)), self.h)
 
-    def backward(self, tri, valid, dL_dI=None, dL_drange=None, params: dict | None = None, stream=None):
+    def backward(self, tri, valid, dL_dI=None, dL_drange=None, params: dict | None = None, stream=None,
+                 intensity=None):
+        """Adjoint of one scan: (d_rho, d_k, d_pose6).  `intensity` is the forward's intensity output,
+        required when the sensor has intensity noise (its clamp at 0 stops the gradient)."""
         nmat = self.nmat
         d_rho = torch.empty(nmat, dtype=torch.float32, device=self.device)
         d_k = torch.empty(nmat, dtype=torch.float32, device=self.device)
         d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
         p = _params_struct(params)
-        check(lib.lidar_backward(self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(dL_dI), _ptr(dL_drange),
-                                 _ptr(d_rho), _ptr(d_k), _ptr(d_pose), _stream(stream)), self.h)
+        check(lib.lidar_backward(self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(intensity), _ptr(dL_dI),
+                                 _ptr(dL_drange), _ptr(d_rho), _ptr(d_k), _ptr(d_pose), _stream(stream)), self.h)
         return d_rho, d_k, d_pose
 
-    def backward_spectra(self, tri, valid, dL_dI=None, dL_drange=None, params: dict | None = None, stream=None):
+    def backward_spectra(self, tri, valid, dL_dI=None, dL_drange=None, params: dict | None = None, stream=None,
+                         intensity=None):
         """Full-spectrum adjoint: (d_spectra[nmat, nbins], d_k[nmat], d_pose6) at the sensor wavelength."""
         d_T = torch.empty((self.nmat, self.nbins), dtype=torch.float32, device=self.device)
         d_k = torch.empty(self.nmat, dtype=torch.float32, device=self.device)
         d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
         p = _params_struct(params)
-        check(lib.lidar_backward_spectra(self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(dL_dI), _ptr(dL_drange),
-                                         _ptr(d_T), _ptr(d_k), _ptr(d_pose), _stream(stream)), self.h)
+        check(lib.lidar_backward_spectra(self.h, C.byref(p), _ptr(tri), _ptr(valid), _ptr(intensity), _ptr(dL_dI),
+                                         _ptr(dL_drange), _ptr(d_T), _ptr(d_k), _ptr(d_pose), _stream(stream)),
+              self.h)
         return d_T, d_k, d_pose
 
     def batch(self, instances, packet_rays: int = 0) -> "Batch":
@@ -549,7 +559,8 @@ class Batch:
             arr[k].scan = int(inst.scan)
         h = C.c_void_p()
         st = check(lib.lidar_batch_create(ctx.h, arr, len(instances), int(packet_rays), C.byref(h)), ctx.h)
-        self.clamped = st == A.WARN_WAVELENGTH_CLAMPED
+        self.clamped = bool(st & A.WARN_WAVELENGTH_CLAMPED)
+        self.origin_outside = bool(st & A.WARN_ORIGIN_OUTSIDE_SCENE)
         self.h = h
         n = C.c_uint64()
         check(lib.lidar_batch_rays(h, C.byref(n)), ctx.h)
@@ -611,11 +622,14 @@ def _params_struct(params: dict | None) -> A.Params:
 
 
 class LidarReturn(torch.autograd.Function):
-    """(rho[nmat], k[nmat], pose_delta[6]) -> (intensity, range, valid, tri) of one noise-free scan.
+    """(rho[nmat], k[nmat], pose_delta[6]) -> (intensity, range, valid, tri) of one scan.
 
     The backward pass is the library's adjoint kernel with the hit triangles
     of the forward pass held fixed; the pose gradient is with respect to
-    pose_delta = (dp, dw) with p = p0 + dp and R = Exp(dw) R0.
+    pose_delta = (dp, dw) with p = p0 + dp and R = Exp(dw) R0.  With the
+    sensor's noise on, the range noise is additive (its gradient is the
+    range's) and the intensity clamp max(0, R_lambda + sigma_I z) stops the
+    gradient where it holds (the forward's intensity is saved for that).
     """
 
     @staticmethod
@@ -625,23 +639,23 @@ class LidarReturn(torch.autograd.Function):
                                  params=dict(rho=rho.detach().contiguous(), angle_exp=k.detach().contiguous(),
                                              pose_delta=pose_delta.detach().contiguous()))
         ctx_.lidar = lidar_ctx
-        ctx_.save_for_backward(rho, k, pose_delta, out["tri"], out["valid"])
+        ctx_.save_for_backward(rho, k, pose_delta, out["tri"], out["valid"], out["intensity"])
         ctx_.mark_non_differentiable(out["valid"], out["tri"])
         return out["intensity"], out["range"], out["valid"], out["tri"]
 
     @staticmethod
     def backward(ctx_, gI, gR, _gv, _gt):
-        rho, k, pose_delta, tri, valid = ctx_.saved_tensors
+        rho, k, pose_delta, tri, valid, inten = ctx_.saved_tensors
         d_rho, d_k, d_pose = ctx_.lidar.backward(
             tri, valid, None if gI is None else gI.contiguous(), None if gR is None else gR.contiguous(),
             params=dict(rho=rho.detach().contiguous(), angle_exp=k.detach().contiguous(),
-                        pose_delta=pose_delta.detach().contiguous()))
+                        pose_delta=pose_delta.detach().contiguous()), intensity=inten)
         return None, d_rho, d_k, d_pose, None, None
 
 
 class LidarSpectralReturn(torch.autograd.Function):
     """(spectra[nmat, nbins], k[nmat], pose_delta[6]) -> (intensity, range, valid, tri) of one
-    noise-free scan at the context's sensor wavelength.
+    scan at the context's sensor wavelength (noise as in LidarReturn).
 
     R_lambda(0) is read from `spectra` at the wavelength (linear between bins),
     so the backward pass (the library's full-spectrum adjoint, hit triangles
@@ -657,15 +671,15 @@ class LidarSpectralReturn(torch.autograd.Function):
                                                                                   "tri"), lidar_ctx.device),
                                  params=prm)
         ctx_.lidar = lidar_ctx
-        ctx_.save_for_backward(spectra, k, pose_delta, out["tri"], out["valid"])
+        ctx_.save_for_backward(spectra, k, pose_delta, out["tri"], out["valid"], out["intensity"])
         ctx_.mark_non_differentiable(out["valid"], out["tri"])
         return out["intensity"], out["range"], out["valid"], out["tri"]
 
     @staticmethod
     def backward(ctx_, gI, gR, _gv, _gt):
-        spectra, k, pose_delta, tri, valid = ctx_.saved_tensors
+        spectra, k, pose_delta, tri, valid, inten = ctx_.saved_tensors
         d_T, d_k, d_pose = ctx_.lidar.backward_spectra(
             tri, valid, None if gI is None else gI.contiguous(), None if gR is None else gR.contiguous(),
             params=dict(spectra=spectra.detach().contiguous(), angle_exp=k.detach().contiguous(),
-                        pose_delta=pose_delta.detach().contiguous()))
+                        pose_delta=pose_delta.detach().contiguous()), intensity=inten)
         return None, d_T, d_k, d_pose, None, None

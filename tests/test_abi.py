@@ -93,6 +93,38 @@ def test_scene_bytes_host_only(A):
     assert A.lib.lidar_scene_bytes(None, C.byref(p), C.byref(s)) == A.ERR_INVALID_ARG
 
 
+def test_scene_size_limit_keeps_record_offsets_below_2gib(A):
+    """The walk forms 32-bit byte offsets into buffers of at most 2^31 - 1 bytes: 44,739,242 triangles
+    of 48 bytes fit (the last record ends 32 bytes below 2^31), one more is refused by the workspace
+    queries of scenes and meshes (host-only, nothing is allocated)."""
+    assert A.MAX_TRIANGLES == 44_739_242 and 48 * A.MAX_TRIANGLES <= 2 ** 31 - 1 < 48 * (A.MAX_TRIANGLES + 1)
+    assert 128 * A.MAX_NODES <= 2 ** 31
+    d = A.SceneDesc()
+    d.n_vertices, d.flags = 3, A.SCENE_DEVICE_PTRS
+    p, s = C.c_uint64(), C.c_uint64()
+    for fn in (A.lib.lidar_scene_bytes, A.lib.lidar_mesh_bytes):
+        d.n_triangles = 44_739_242
+        assert fn(C.byref(d), C.byref(p), C.byref(s)) == A.OK
+        assert p.value >= 48 * 44_739_242
+        d.n_triangles = 44_739_243
+        assert fn(C.byref(d), C.byref(p), C.byref(s)) == A.ERR_INVALID_ARG
+
+
+def test_origin_check_host_only(A):
+    """The box padding 2^-20 M covers FP32 rounding for ray origins with every |p_i| <= M."""
+    chk = A.lib.lidar_origin_check
+    f3 = C.c_float * 3
+    assert chk(100.0, f3(0.0, 0.0, 0.0)) == A.OK
+    assert chk(100.0, f3(-100.0, 100.0, 99.9)) == A.OK                    # on the cube's faces
+    assert chk(100.0, f3(0.0, 0.0, 100.01)) == A.WARN_ORIGIN_OUTSIDE_SCENE
+    assert chk(100.0, f3(-3000.0, 0.0, 1.5)) == A.WARN_ORIGIN_OUTSIDE_SCENE
+    assert chk(0.0, f3(0.0, 0.0, 0.0)) == A.OK
+    assert chk(100.0, f3(float("nan"), 0.0, 0.0)) == A.ERR_INVALID_ARG
+    assert chk(100.0, f3(float("inf"), 0.0, 0.0)) == A.ERR_INVALID_ARG
+    assert chk(100.0, None) == A.ERR_INVALID_ARG
+    assert A.WARN_ORIGIN_OUTSIDE_SCENE & A.WARN_WAVELENGTH_CLAMPED == 0   # warnings are bits
+
+
 def test_null_context_calls_are_rejected(A):
     lib = A.lib
     assert lib.lidar_destroy(None) == A.OK
@@ -107,7 +139,7 @@ def test_null_context_calls_are_rejected(A):
     assert lib.lidar_echo_bytes(None, None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_sensor_set(None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_materials_set(None, None) == A.ERR_INVALID_ARG
-    assert lib.lidar_backward(None, None, None, None, None, None, None, None, None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_backward(None, None, None, None, None, None, None, None, None, None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_batch_destroy(None) == A.OK
     assert lib.lidar_compact_points(None, None, 0, None, None, None, None, 0, None) == A.ERR_INVALID_ARG
     assert lib.lidar_create(0, None) == A.ERR_INVALID_ARG

@@ -107,6 +107,51 @@ def test_tuner_picks_a_candidate_and_keeps_results(L):
         assert np.array_equal(before[k], after[k]), k
 
 
+def test_batch_recaptures_after_scene_and_material_changes(L):
+    """A batch's captured graph holds the scene and material tables by value: after a new scene (another
+    leaf width, moved and relabelled geometry, a new buffer), new materials (more of them, so the table
+    is reallocated, and a larger range noise, which lengthens the traceable range) or a new stack cap,
+    the next call captures again; the batch equals the plain launches and a batch made afresh."""
+    scene, sensor, pose = S.config1()
+    insts = [S.Instance(S.Sensor(S.elev_table(16), n_az, wavelength_nm=wl, d_max=dm), pose, seed=9, scan=1)
+             for n_az, wl, dm in ((900, 905.0, 100.0), (333, 850.0, 60.0))]
+    ctx = L.Context(0)
+    ctx.load(scene, leaf_width=4)
+    b = ctx.batch(insts, 64)
+
+    def check(tag):
+        got = to_np(b.simulate(debug=True))
+        seq = to_np(b.simulate(debug=True, sequential=True))
+        fresh = to_np(ctx.batch(insts, 64).simulate(debug=True))
+        ctx.sync_check()
+        for k in got:
+            assert np.array_equal(got[k], seq[k]), (tag, k)
+            assert np.array_equal(got[k], fresh[k]), (tag, k)
+        return got
+
+    first = check("initial")
+    moved = S.Scene((scene.vertices.astype(np.float64) + [0.37, -0.21, 0.0]).astype(np.float32), scene.indices,
+                    scene.material, scene.label + 1000, scene.spectra, scene.sigma_range, scene.angle_exp)
+    ctx.load(moved, leaf_width=2)
+    second = check("new scene")
+    assert not np.array_equal(first["label"], second["label"])
+    assert np.all(second["label"][second["valid"] == 1] > 1000)
+    more = np.concatenate([moved.spectra * 0.5, moved.spectra[:3]], axis=0)
+    ctx.set_materials(more, np.full(len(more), 0.3, np.float32))
+    third = check("new materials")
+    assert not np.array_equal(second["intensity"], third["intensity"])
+    # the stack cap changes the scene descriptor the graph holds (a cap of 3 overflows: reported, then
+    # lifting it restores the results)
+    ctx.set_stack_cap(3)
+    b.simulate(debug=True)
+    with pytest.raises(L.LidarError):
+        ctx.sync_check()
+    ctx.set_stack_cap(0)
+    fourth = check("stack cap lifted")
+    for k in third:
+        assert np.array_equal(third[k], fourth[k]), k
+
+
 # ----------------------------------------------------------------------------
 # adjoint
 # ----------------------------------------------------------------------------
@@ -166,6 +211,76 @@ def test_adjoint_matches_oracle_gradient(L, c5):
         err = np.linalg.norm(gg - oo) / np.linalg.norm(oo)
         print(f"[adjoint] {name}: rel err {err:.3g} (|g| {np.linalg.norm(oo):.3g})", flush=True)
         assert err < 1e-4, name
+
+
+def test_adjoint_with_intensity_noise_clamp_matches_oracle(L):
+    """With intensity noise the forward's intensity is max(0, R_lambda + sigma_I z_I): the GPU gradient
+    (clamped beams read from the forward's intensity output) against the oracle's analytic gradient with
+    the same z_I (itself pinned by central differences of the clamped loss), range noise on too."""
+    import dataclasses
+    c = S.config5()
+    scene, pose = c["scene"], c["pose_true"]
+    sig_i, seed = 0.2, 515
+    sensor = dataclasses.replace(c["sensor"], noise_on=True, sigma_intensity=sig_i)
+    ctx = L.Context(0)
+    ctx.load(scene)
+    ctx.set_sensor(sensor)
+    ctx.set_pose(pose.p, pose.q)
+    dev = ctx.device
+    rho0 = c["rho0"] + 0.02 * np.arange(20, dtype=np.float32) / 20
+    k0 = c["k0"] + 0.2 * np.sin(np.arange(20, dtype=np.float32))
+    pose0 = np.r_[c["dp0"], c["dw0"]].astype(np.float32)
+    rng = np.random.default_rng(22)
+    beams = np.sort(rng.choice(sensor.n_beams, 4096, replace=False))
+    tgt = O.simulate(scene, sensor, pose, seed=seed, beams=beams, rho=c["rho_true"], angle_exp=c["k_true"])
+    R0 = O.so3_exp(pose0[3:].astype(np.float64)) @ O.rotation_from_quat(pose.q)
+    p0 = pose.p.astype(np.float64) + pose0[:3].astype(np.float64)
+    cur = O.simulate(scene, sensor, pose, seed=seed, beams=beams, rho=rho0, angle_exp=k0, R=R0, p=p0)
+    _, z_i = O.beam_normals(seed, 0, 0, beams)
+    pre = cur["r_lambda"] + np.float64(np.float32(sig_i)) * z_i
+    keep = ((tgt["valid"] == 1) & (cur["valid"] == 1) & ~tgt["ambiguous"] & ~cur["ambiguous"]
+            & ~cur["grazing"] & ~cur["marginal"] & (np.abs(pre) > 1e-5))
+    B = beams[keep]
+    N = len(B)
+    assert N > 500 and 0.1 < np.mean(pre[keep] <= 0) < 0.9
+    g_rho, g_k, g_pose = O.calib_grad(scene, sensor, pose, cur["tri"][keep].astype(np.int64), B, rho0, k0,
+                                      pose0[:3], pose0[3:], tgt["intensity"][keep], tgt["t_hit"][keep],
+                                      sig_i=float(np.float32(sig_i)), z_i=z_i[keep])
+    f32 = dict(dtype=torch.float32, device=dev)
+    params = dict(rho=torch.tensor(rho0, **f32), angle_exp=torch.tensor(k0, **f32),
+                  pose_delta=torch.tensor(pose0, **f32))
+    out = ctx.simulate(seed, 0, debug=True, params=params)
+    g = to_np(out)
+    assert np.array_equal(g["tri"][B], cur["tri"][keep])
+    assert np.array_equal(g["intensity"][B] == 0, pre[keep] <= 0)
+    I_t = np.zeros(sensor.n_beams, np.float32)
+    R_t = np.zeros(sensor.n_beams, np.float32)
+    I_t[B] = tgt["intensity"][keep]
+    R_t[B] = tgt["range"][keep]          # the same range noise as the forward's: it cancels in R - R*
+    mask = np.zeros(sensor.n_beams, np.uint8)
+    mask[B] = 1
+    mt = torch.tensor(mask, device=dev)
+    gI = ((2.0 / N) * (out["intensity"] - torch.tensor(I_t, device=dev)) * mt).contiguous()
+    gR = ((2.0 / N) * (out["range"] - torch.tensor(R_t, device=dev)) * mt).contiguous()
+    with pytest.raises(L.LidarError) as e:
+        ctx.backward(out["tri"], mt, gI, gR, params=params)       # the clamped beams are needed
+    assert e.value.status == L._abi.ERR_NO_FORWARD_STATE
+    d_rho, d_k, d_pose = ctx.backward(out["tri"], mt, gI, gR, params=params, intensity=out["intensity"])
+    d_rho, d_k, d_pose = (t.cpu().numpy().astype(np.float64) for t in (d_rho, d_k, d_pose))
+    for name, gg, oo in (("rho", d_rho, g_rho), ("k", d_k, g_k), ("p", d_pose[:3], g_pose[:3]),
+                         ("w", d_pose[3:], g_pose[3:])):
+        err = np.linalg.norm(gg - oo) / np.linalg.norm(oo)
+        print(f"[adjoint clamp] {name}: rel err {err:.3g} (|g| {np.linalg.norm(oo):.3g})", flush=True)
+        assert err < 1e-4, name
+    # autograd saves the forward's intensity and gives the same gradient
+    rho = torch.tensor(rho0, **f32).requires_grad_(True)
+    kk = torch.tensor(k0, **f32).requires_grad_(True)
+    p6 = torch.tensor(pose0, **f32).requires_grad_(True)
+    I, R, V, T = L.LidarReturn.apply(ctx, rho, kk, p6, seed, 0)
+    loss = ((I - torch.tensor(I_t, device=dev)) ** 2 * mt).sum() / N + ((R - torch.tensor(R_t, device=dev)) ** 2 * mt).sum() / N
+    loss.backward()
+    assert np.allclose(rho.grad.cpu().numpy(), d_rho, rtol=1e-5, atol=1e-9)
+    assert np.allclose(p6.grad.cpu().numpy(), d_pose, rtol=1e-5, atol=1e-9)
 
 
 def test_autograd_function_and_descent(L, c5):
@@ -267,6 +382,6 @@ def test_error_paths(L):
     with pytest.raises(L.LidarError):
         ctx.set_sensor(S.Sensor(np.array([0.0, np.nan]), 10))
     # backward without forward state
-    assert lib.lidar_backward(h, None, None, None, None, None, None, None, None, None) == A.ERR_NO_FORWARD_STATE
+    assert lib.lidar_backward(h, None, None, None, None, None, None, None, None, None, None) == A.ERR_NO_FORWARD_STATE
     ctx.simulate(0, 0)
     ctx.sync_check()

@@ -375,3 +375,27 @@ def test_trajectory_launcher_equals_pose_then_simulate(L):
         ref = to_np(c.simulate(SEED, k))
         for key in ref:
             assert np.array_equal(got[key], ref[key]), (k, key)
+
+
+def test_origin_outside_the_padded_cube_warns(L):
+    """The box padding covers FP32 rounding for origins inside the cube |x|,|y|,|z| <= M (M the largest
+    |vertex coordinate|): a pose, a sweep end, a batch instance or a scene loaded under a pose outside
+    it gives the warning, and the call still does its work."""
+    from paper_2208_10295_amd import _abi as A
+    scene, sensor, pose = S.config1()
+    c = _ctx(L, scene, sensor, pose)
+    M = float(c.stats()["max_abs_coord"])
+    assert M == float(np.max(np.abs(scene.vertices[scene.indices.astype(np.int64)])))
+    assert c.set_pose(pose.p, pose.q) == A.OK
+    far = np.array([0.0, 0.0, 1.5 * M], np.float32)
+    with pytest.warns(RuntimeWarning, match="outside the cube"):
+        st = c.set_pose(far, pose.q)
+    assert st & A.WARN_ORIGIN_OUTSIDE_SCENE
+    g = to_np(c.simulate(0, 0))              # still simulated (looking down at the scene from above)
+    assert g["valid"].sum() > 0
+    with pytest.warns(RuntimeWarning, match="outside the cube"):
+        c.load(scene)
+    with pytest.warns(RuntimeWarning, match="outside the cube"):
+        c.simulate_sweep(1, 0.0, 10.0, 1 / 60, (pose.p, pose.q), (far, pose.q))
+    b = c.batch([S.Instance(sensor, pose), S.Instance(sensor, S.Pose(far, pose.q))], 64)
+    assert b.origin_outside and not c.batch([S.Instance(sensor, pose)], 64).origin_outside
