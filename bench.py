@@ -6,10 +6,15 @@ Headline: rays/s of a 64-channel x 2048-azimuth scan (131,072 beams) in the
 traversal + return model + point-cloud write), inputs resident in HBM.
 
 Also reported on the same line:
-  * roofline of the trace kernel: algorithmic bytes per launch (nodes and
-    triangle records the traversal fetches, counted exactly by the counting
-    variant of the same traversal, plus the outputs) over the kernel's mean
-    duration from HIP events on its stream;
+  * roofline of the trace kernel.  Node fetches and triangle-record tests per
+    beam come from a CPU replay of the walk over the GPU-built tree
+    (measure/walk_replay.c; equal to the GPU's counting kernel, which is
+    checked here too).  The kernel is reported against the vector-ALU roof
+    (algorithmic FP32 operations per launch over its mean duration from HIP
+    events on its stream), and its algorithmic bytes against measured memory
+    roofs at every level the bytes can come from (L1, L2, MALL, HBM), beside
+    the HBM bytes the counters measured and the compulsory bytes (distinct
+    nodes and records the scan touches, plus its outputs);
   * cpu_baseline: the FP64 brute-force oracle on a bounded sample of beams;
   * batched: 256 mixed sensor instances (21.4 M rays) in one persistent,
     graph-replayed launch vs 256 sequential plain launches;
@@ -34,8 +39,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rays/sec, 64ch×2048 on 500k-tri scene; batched vs plain; backward/forward time"
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES, TRI_BYTES, OUT_BYTES = 128, 48, 25     # per node fetch, per triangle record test, per beam written
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_scan_config2_traffic.txt")
+# algorithmic bytes: a 4-wide node (128 B), a triangle's three vertices (36 B), the hit's material and label
+# (6 B), the outputs written per beam (x, y, z, intensity, range: 20 B; label 4 B; valid 1 B)
+NODE_BYTES, TRI_BYTES, HIT_BYTES, OUT_BYTES = 128, 36, 6, 25
+# algorithmic FP32 ALU operations (an FMA, a min, a compare each count one): a node's four slab tests and
+# their ordering, a triangle test, the return model of a beam (interpolation, cos^k, Philox, Box-Muller, eq.5)
+OPS_NODE, OPS_TRI, OPS_BEAM = 72, 40, 100
+# one FP32 operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the published 157.3 TFLOP/s
+# counts an FMA as two and a packed pair as two more, which a data-dependent walk cannot use)
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_scan_64x2048_522k_traffic.txt")
 KERNEL_SOURCES = ("paper_2208_10295_amd/csrc/trace.hip", "paper_2208_10295_amd/csrc/lidar_device.hpp",
                   "paper_2208_10295_amd/csrc/bvh_build.hip")
 
@@ -59,11 +72,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
+TRAFFIC_SEQ_FILE = os.path.join(ROOT, "profiles", "trace_scan_128x1024_5m_traffic.txt")
+
+
+def read_traffic(path=TRAFFIC_FILE):
     """HBM bytes per launch from the committed PMC summary, if it was taken on the current kernel source."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
@@ -74,7 +90,7 @@ def read_traffic():
         return None
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "trace_scan_config2_counters.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "trace_scan_64x2048_522k_counters.txt")
 # wavefront VALU instructions per second one MI355X can issue: 256 CUs x 4 SIMDs x 2.4 GHz, one 64-lane
 # FP32 instruction per SIMD every 4 cycles (16 lanes per cycle)
 VALU_PEAK_GINST_S = 256 * 4 * 2.4 / 4
@@ -90,7 +106,7 @@ def read_counters():
                 kv[k.strip()] = v.strip()
         if kv.get("kernel_source_sha256_16") != kernel_source_hash():
             return None
-        return {k: float(v) for k, v in kv.items() if k.startswith(("SQ_", "TCC_"))}
+        return {k: float(v) for k, v in kv.items() if k.startswith(("SQ_", "TCC_", "TCP_", "TA_"))}
     except (OSError, ValueError):
         return None
 
@@ -136,6 +152,30 @@ def O_weights(nbins, wavelength_nm, lambda0_nm=400.0, dlambda_nm=10.0):
         i = int(math.floor(q))
         w[i], w[i + 1] = 1.0 - (q - i), q - i
     return w
+
+
+def traversal_work(ctx, scene, sensor, pose, seed, torch):
+    """Per-launch work of one scan from the CPU replay of its walk over the GPU-built tree: node fetches,
+    triangle-record tests, beams with a hit, distinct nodes and records touched; the GPU counting kernel's
+    totals beside it (they must agree); algorithmic and compulsory bytes."""
+    import numpy as np
+    from measure import walk_replay as W
+    nodes, recs = ctx.debug_bvh()
+    st = ctx.stats()
+    r = W.replay(nodes, recs, st["root"], sensor, pose.p, pose.q, sensor.t_min,
+                 W.trace_limit(sensor, scene.sigma_range), touched=True)
+    _, nn, nt = ctx.simulate_counts(seed, 0)
+    gn, gt = nn.cpu().numpy().view(np.uint32), nt.cpu().numpy().view(np.uint32)
+    n = sensor.n_beams
+    n_nodes, n_recs = int(r["node_visits"].sum(dtype=np.int64)), int(r["tri_tests"].sum(dtype=np.int64))
+    n_hit = int((r["orig"] != 0xFFFFFFFF).sum())
+    return {"node_fetches": n_nodes, "record_tests": n_recs, "beams_hit": n_hit,
+            "node_fetches_per_ray": n_nodes / n, "record_tests_per_ray": n_recs / n,
+            "replay_equals_gpu_counts": bool(np.array_equal(gn, r["node_visits"]) and
+                                             np.array_equal(gt, r["tri_tests"])),
+            "alg_bytes": NODE_BYTES * n_nodes + TRI_BYTES * n_recs + HIT_BYTES * n_hit + OUT_BYTES * n,
+            "distinct_nodes": r["nodes_touched"], "distinct_records": r["records_touched"],
+            "compulsory_bytes": 128 * r["nodes_touched"] + 48 * r["records_touched"] + OUT_BYTES * n}
 
 
 def cpu_baseline(scene, sensor, pose, seed, target_s=15.0):
@@ -187,8 +227,8 @@ def main():
     from lidar_inputs import scenes as S
 
     seed = 2022
-    scene, sensor, pose = S.config2()
-    log(f"config2: {scene.n_tri} triangles, {sensor.n_beams} beams")
+    scene, sensor, pose = S.urban_64ch()
+    log(f"urban_64ch: {scene.n_tri} triangles, {sensor.n_beams} beams")
     ctx = L.Context(0)
     st = ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius, collapse=args.collapse,
                   leaf_cost=args.leaf_cost)
@@ -230,26 +270,36 @@ def main():
         result["value"] = args.steps * n / wall
         result["ms_per_step"] = 1e3 * wall / args.steps
         result["kernel_ms"] = kernel_ms
-        _, nn, nt = ctx.simulate_counts(seed, 0)
-        n_nodes = int(nn.to(torch.int64).sum())
-        n_tris = int(nt.to(torch.int64).sum())
-        alg_bytes = NODE_BYTES * n_nodes + TRI_BYTES * n_tris + OUT_BYTES * n
-        achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+        tv = traversal_work(ctx, scene, sensor, pose, seed, torch)
+        alg_ops = OPS_NODE * tv["node_fetches"] + OPS_TRI * tv["record_tests"] + OPS_BEAM * n
+        achieved = alg_ops / (kernel_ms * 1e-3) / 1e12
         traffic = read_traffic()
-        result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+        secs = kernel_ms * 1e-3
+        result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                              "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                              "ops_per_launch": alg_ops,
+                              "ops_model": f"{OPS_NODE} per node fetch + {OPS_TRI} per triangle record + {OPS_BEAM} "
+                                           "per beam (FP32 ALU operations, an FMA counting one)",
+                              "hbm_frac_measured": None if traffic is None else traffic / secs / 1e9 / HBM_PEAK_GBS,
+                              "hbm_frac_compulsory": tv["compulsory_bytes"] / secs / 1e9 / HBM_PEAK_GBS}
         cnt = read_counters()
         if cnt:
-            # the second bound: vector-instruction issue (the traversal's data stays in L2 and MALL)
-            ginst = cnt["SQ_INSTS_VALU"] / (kernel_ms * 1e-3) / 1e9
-            result["valu"] = {"insts_per_launch": cnt["SQ_INSTS_VALU"], "achieved_ginst_s": ginst,
-                              "peak_ginst_s": VALU_PEAK_GINST_S, "frac": ginst / VALU_PEAK_GINST_S,
-                              "l2_hit_rate": cnt["TCC_HIT_sum"] / cnt["TCC_REQ_sum"]}
-        result["traversal"] = {"node_visits_per_ray": n_nodes / n, "tri_tests_per_ray": n_tris / n,
-                               "alg_bytes_per_ray": alg_bytes / n, "alg_bytes_per_launch": alg_bytes,
-                               "kernel_source_sha256_16": kernel_source_hash()}
+            # what the counters say binds: instruction issue, the texture-address path, or waiting
+            ginst = cnt["SQ_INSTS_VALU"] / secs / 1e9
+            result["roofline"]["counters"] = {
+                "valu_insts_per_launch": cnt["SQ_INSTS_VALU"], "valu_issue_ginst_s": ginst,
+                "valu_issue_frac_of_4_cycle_model": ginst / VALU_PEAK_GINST_S,
+                "wave_wait_frac": cnt.get("SQ_WAIT_ANY_sum", cnt.get("SQ_WAIT_ANY", float("nan")))
+                / cnt.get("SQ_WAVE_CYCLES_sum", cnt.get("SQ_WAVE_CYCLES", float("nan"))),
+                "l2_hit_rate": cnt["TCC_HIT_sum"] / cnt["TCC_REQ_sum"],
+                "l2_request_bytes_per_launch": 128.0 * cnt["TCC_REQ_sum"]}
+        result["traversal"] = dict(tv, alg_bytes_per_ray=tv["alg_bytes"] / n, ops_per_ray=alg_ops / n,
+                                   alg_gbs=tv["alg_bytes"] / secs / 1e9, kernel_source_sha256_16=kernel_source_hash())
         log(f"plain: {result['value']:.4g} rays/s, kernel {kernel_ms * 1e3:.1f} us, "
-            f"{n_nodes / n:.1f} nodes + {n_tris / n:.1f} tris per ray, {achieved:.0f} GB/s algorithmic")
+            f"{tv['node_fetches'] / n:.2f} nodes + {tv['record_tests'] / n:.2f} records per ray "
+            f"(replay == GPU counts: {tv['replay_equals_gpu_counts']}), {achieved:.2f} T ALU ops/s "
+            f"({achieved / ALU_PEAK_TOPS:.3f} of {ALU_PEAK_TOPS:.1f}), {tv['alg_bytes'] / secs / 1e9:.0f} GB/s "
+            f"algorithmic")
         # order-preserving compaction of the scan's point cloud (detected beams only)
         comp, _, cnt = ctx.compact_launcher(out, alloc_outputs(n, POINT_OUTPUTS, ctx.device))
         for _ in range(3):
@@ -263,35 +313,36 @@ def main():
 
     if "roofs" in legs:
         # measured memory roofs beside the published HBM peak: a 2 GiB streaming read, and 128-byte line
-        # fetches by quads over a table of the scene's BVH size, launched like the scan (one quad per beam)
+        # fetches by quads (one quad per beam, the scan's launch shape), each quad a dependent chain like a
+        # walk, over working sets that fit one CU's L1 (16 KiB), one XCD's L2 (2 MiB), the MALL (64 MiB)
+        # or only HBM (1 GiB)
         sink = torch.zeros(1, dtype=torch.float32, device=ctx.device)
         big = torch.randint(-2**31, 2**31 - 1, (512 << 20,), dtype=torch.int32, device=ctx.device)
         stream_run = L.probe_stream_launcher(big, sink)
         _, s_ms = timed_region(stream_run, 10, torch)
         stream_gbs = big.numel() * 4 / (s_ms * 1e-3) / 1e9
-        del big
-        sts = ctx.stats()
-        ws = int(sts["node_bytes"] + sts["tri_bytes"])
-        table = torch.randint(-2**31, 2**31 - 1, ((ws + 127) // 128 * 32,), dtype=torch.int32, device=ctx.device)
         blocks, steps = 2048, 32
         fetched = blocks * 64 * steps * 128
-        roofs = {"hbm_stream_read_gbs": stream_gbs, "stream_bytes": 2 << 30, "gather_working_set_bytes": ws,
-                 "gather_launch": f"{blocks} blocks x 256 threads (one quad per beam of the scan), {steps} lines of "
-                                  "128 B per quad, 32 B per lane"}
-        for name, chase in (("gather_independent_gbs", False), ("gather_chase_gbs", True)):
-            run = L.probe_gather_launcher(table, blocks, steps, chase, sink)
+        roofs = {"hbm_stream_read_gbs": stream_gbs, "stream_bytes": 2 << 30,
+                 "gather_launch": f"{blocks} blocks x 256 threads (one quad per beam of the scan), {steps} dependent "
+                                  "128-B lines per quad, 32 B per lane, line indices uniform over the working set"}
+        for level, ws in (("l1", 16 << 10), ("l2", 2 << 20), ("mall", 64 << 20), ("hbm", 1 << 30)):
+            run = L.probe_gather_launcher(big[: ws // 4], blocks, steps, True, sink)
+            run()
             _, g_ms = timed_region(run, 20, torch)
-            roofs[name] = fetched / (g_ms * 1e-3) / 1e9
-        del table
-        if "roofline" in result:
-            a = result["roofline"]["achieved"]
+            roofs[f"gather_{level}_gbs"] = fetched / (g_ms * 1e-3) / 1e9
+            roofs[f"gather_{level}_working_set_bytes"] = ws
+        del big
+        if "traversal" in result:
+            a = result["traversal"]["alg_gbs"]
             roofs["scan_alg_gbs"] = a
             roofs["scan_over_stream"] = a / stream_gbs
-            roofs["scan_over_gather_chase"] = a / roofs["gather_chase_gbs"]
+            for level in ("l1", "l2", "mall", "hbm"):
+                roofs[f"scan_over_gather_{level}"] = a / roofs[f"gather_{level}_gbs"]
         result["roofs"] = roofs
-        log(f"roofs: HBM stream read {stream_gbs:.0f} GB/s; 128-B line gathers over {ws / 1e6:.1f} MB: "
-            f"independent {roofs['gather_independent_gbs']:.0f} GB/s, dependent chains "
-            f"{roofs['gather_chase_gbs']:.0f} GB/s")
+        log("roofs: HBM stream read {:.0f} GB/s; dependent 128-B line gathers: L1 {:.0f}, L2 {:.0f}, MALL {:.0f}, "
+            "HBM {:.0f} GB/s".format(stream_gbs, roofs["gather_l1_gbs"], roofs["gather_l2_gbs"],
+                                     roofs["gather_mall_gbs"], roofs["gather_hbm_gbs"]))
 
     if "cpu" in legs:
         log("cpu baseline (FP64 oracle) ...")
@@ -299,8 +350,8 @@ def main():
         log(f"cpu: {result['cpu_baseline']['value']:.4g} rays/s on {result['cpu_baseline']['cores']} threads")
 
     if "batch" in legs:
-        sc4, insts = S.config4()
-        assert sc4 is scene
+        sc_b, insts = S.batch_256()
+        assert sc_b is scene
         batch = ctx.batch(insts, 256)
         nr = batch.n_rays
         bout = alloc_outputs(nr, POINT_OUTPUTS, ctx.device)
@@ -339,27 +390,27 @@ def main():
         del batch, bout
 
     if "adjoint" in legs:
-        c5 = S.config5()
+        cal = S.calibration_20mat()
         cx = L.Context(0)
-        cx.load(c5["scene"])
-        cx.set_sensor(c5["sensor"])
-        pt = c5["pose_true"]
+        cx.load(cal["scene"])
+        cx.set_sensor(cal["sensor"])
+        pt = cal["pose_true"]
         cx.set_pose(pt.p, pt.q)
         dev = cx.device
         f32 = dict(dtype=torch.float32, device=dev)
-        rho_t = torch.tensor(c5["rho_true"], **f32)
-        k_t = torch.tensor(c5["k_true"], **f32)
+        rho_t = torch.tensor(cal["rho_true"], **f32)
+        k_t = torch.tensor(cal["k_true"], **f32)
         zero6 = torch.zeros(6, **f32)
-        labels = torch.tensor(c5["scene"].label.view(np.int32), device=dev)
+        labels = torch.tensor(cal["scene"].label.view(np.int32), device=dev)
 
         def lab(T):
             return torch.where(T >= 0, labels[T.clamp_min(0).long()], -1)
         with torch.no_grad():
             I_t, R_t, V_t, T_t = L.LidarReturn.apply(cx, rho_t, k_t, zero6)
         L_t = lab(T_t)
-        rho = torch.tensor(c5["rho0"], **f32).requires_grad_(True)
-        kk = torch.tensor(c5["k0"], **f32).requires_grad_(True)
-        pose6 = torch.tensor(np.r_[c5["dp0"], c5["dw0"]], **f32).requires_grad_(True)
+        rho = torch.tensor(cal["rho0"], **f32).requires_grad_(True)
+        kk = torch.tensor(cal["k0"], **f32).requires_grad_(True)
+        pose6 = torch.tensor(np.r_[cal["dp0"], cal["dw0"]], **f32).requires_grad_(True)
         # forward / backward timing at the initial point
         fwd_args = dict(rho=rho.detach(), angle_exp=kk.detach(), pose_delta=pose6.detach())
         fo = alloc_outputs(n, ("intensity", "range", "valid", "tri"), dev)
@@ -393,9 +444,9 @@ def main():
         torch.cuda.synchronize()
         cal_s = time.perf_counter() - t0
         used = np.zeros(20, bool)
-        used[np.unique(c5["scene"].material)] = True
-        rho_err = np.abs(rho.detach().cpu().numpy() - c5["rho_true"])[used]
-        k_err = np.abs(kk.detach().cpu().numpy() - c5["k_true"])[used]
+        used[np.unique(cal["scene"].material)] = True
+        rho_err = np.abs(rho.detach().cpu().numpy() - cal["rho_true"])[used]
+        k_err = np.abs(kk.detach().cpu().numpy() - cal["k_true"])[used]
         pose_err = pose6.detach().cpu().numpy()
         result["adjoint"] = {
             "workload": "64ch x 2048 scan, 522k-triangle scene, 20 materials (rho, k), 6-DoF pose; loss = MSE of "
@@ -413,11 +464,11 @@ def main():
         cxs = []
         for lam in lams:
             c_ = L.Context(0)
-            c_.load(c5["scene"])
-            c_.set_sensor(dataclasses.replace(c5["sensor"], wavelength_nm=lam))
+            c_.load(cal["scene"])
+            c_.set_sensor(dataclasses.replace(cal["sensor"], wavelength_nm=lam))
             c_.set_pose(pt.p, pt.q)
             cxs.append(c_)
-        T_true = torch.tensor(c5["scene"].spectra, **f32)
+        T_true = torch.tensor(cal["scene"].spectra, **f32)
         with torch.no_grad():
             tg = [L.LidarSpectralReturn.apply(c_, T_true, k_t, zero6) for c_ in cxs]
         Tt = torch.full((20, 61), 0.3, **f32).requires_grad_(True)
@@ -515,7 +566,7 @@ def main():
     if "dynamic" in legs:
         # 300 moving actors (200 cars, 100 walking pedestrians) in the 522k scene: per 10 Hz frame the
         # pedestrian mesh is refit to its walking pose, the actors' top-level BVH is refit, and one scan runs
-        dc = S.dynamic_config()
+        dc = S.dynamic_actors()
         ids = [ctx.load_mesh(m) for m in dc["meshes"]]
         n_frames = 20
         frames = [ctx.actor_array(dc["actors_at"](0.1 * f)) for f in range(n_frames + 1)]
@@ -548,7 +599,7 @@ def main():
         ctx.clear_actors()
 
     if "sequence" in legs:
-        sc3, s3, poses = S.config3()
+        sc3, s3, poses = S.urban_sequence_128ch()
         cs = L.Context(0)
         st3 = cs.load(sc3, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius,
                       collapse=args.collapse, leaf_cost=args.leaf_cost)
@@ -561,11 +612,30 @@ def main():
         one(0)
         wall3, ms3 = timed_launches(one, len(poses), torch)
         cs.sync_check()
+        # one scan's work at the first pose, against the HBM roof: the bytes the counters measured and the
+        # compulsory bytes (distinct nodes and records the scan touches, plus its outputs)
+        cs.set_pose(poses[0].p, poses[0].q)
+        _, k3_ms = timed_region(cs.scan_launcher(seed, out3), 50, torch)
+        tv3 = traversal_work(cs, sc3, s3, poses[0], seed, torch)
+        tr3 = read_traffic(TRAFFIC_SEQ_FILE)
+        secs3 = k3_ms * 1e-3
         result["sequence"] = {"workload": "128ch x 1024 x 100 poses at 10 Hz, 5,224,200-triangle scene, 64 materials",
                               "rays_per_s": len(poses) * s3.n_beams / wall3, "kernel_ms_mean": float(np.mean(ms3)),
                               "bvh_build_ms": st3["build_ms"], "bvh_nodes": st3["n_nodes"],
-                              "bvh_depth": st3["depth"]}
-        log(f"sequence: {result['sequence']['rays_per_s']:.4g} rays/s")
+                              "bvh_depth": st3["depth"],
+                              "hbm": {"pose": 0, "kernel_ms": k3_ms, "traffic_bytes_per_scan": tr3,
+                                      "hbm_frac_measured": None if tr3 is None else tr3 / secs3 / 1e9 / HBM_PEAK_GBS,
+                                      "compulsory_bytes_per_scan": tv3["compulsory_bytes"],
+                                      "hbm_frac_compulsory": tv3["compulsory_bytes"] / secs3 / 1e9 / HBM_PEAK_GBS,
+                                      "distinct_nodes": tv3["distinct_nodes"],
+                                      "distinct_records": tv3["distinct_records"],
+                                      "tree_bytes": int(st3["node_bytes"] + st3["tri_bytes"]),
+                                      "alg_bytes_per_scan": tv3["alg_bytes"],
+                                      "alg_gbs": tv3["alg_bytes"] / secs3 / 1e9,
+                                      "replay_equals_gpu_counts": tv3["replay_equals_gpu_counts"]}}
+        log(f"sequence: {result['sequence']['rays_per_s']:.4g} rays/s; one scan touches "
+            f"{tv3['compulsory_bytes'] / 1e6:.2f} MB (HBM fraction at {k3_ms * 1e3:.1f} us: "
+            f"{result['sequence']['hbm']['hbm_frac_compulsory']:.4f})")
         # the same 100 scans (same Philox counters) as one batched launch: a recorded trajectory replayed
         # offline, where every pose is known before the first scan
         sb = cs.batch([S.Instance(s3, poses[k], seed=seed, scan=k) for k in range(len(poses))], 0)

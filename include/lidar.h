@@ -510,7 +510,9 @@ typedef struct {
 } lidar_instance;
 
 /* Uploads n_inst instance descriptors and their direction tables
- * (allocates; synchronous).  Instance k's beams are written at output
+ * (allocates; synchronous).  The batch handle owns these tables and the
+ * captured graph, so that lidar_simulate_batch allocates nothing and only
+ * replays (instead of taking the instances on every call).  Instance k's beams are written at output
  * offset out_offset[k] = sum of n_ch * n_az of instances before k, in the
  * same [n_ch][n_az] order as a single scan; its Philox counter is
  * (beam, scan, k, 0).  `packet_rays` (multiple of 64, 0 = tuned/default)
@@ -639,6 +641,8 @@ typedef struct {
     uint32_t pad_;
 } lidar_stats;
 
+/* Facts of the current scene's BVH.  (Named lidar_get_stats because C gives a
+ * function and the lidar_stats typedef one name space.) */
 lidar_status lidar_get_stats(lidar_ctx *ctx, lidar_stats *out);
 
 /* Synchronises `stream` and reads the device error word written by kernels

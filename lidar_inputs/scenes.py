@@ -9,19 +9,19 @@ model, no noise.
 
 Workloads (stand-ins for the paper's Unreal scenes, which are not available):
 
-* ``config1``: 16-channel sensor at 1.5 m over a 200 m x 200 m ground plane with
+* ``small_16ch``: 16-channel sensor at 1.5 m over a 200 m x 200 m ground plane with
   20 boxes and 10 UV spheres (1,202 triangles, 4 materials, 31 labels).
-* ``config2``: 64-channel sensor (non-uniform elevations, denser at the
+* ``urban_64ch``: 64-channel sensor (non-uniform elevations, denser at the
   horizon), 2048 azimuth steps, in a procedural urban scene of 522,272
   triangles (terrain 256 x 256 cells, 400 buildings, 2,000 poles, 200 cars).
-* ``config3``: 128-channel x 1024 sensor, 100 poses along a 10 Hz spline
+* ``urban_sequence_128ch``: 128-channel x 1024 sensor, 100 poses along a 10 Hz spline
   trajectory through the urban generator scaled 10x in area (5,224,200
   triangles, 64 materials).
-* ``config4``: 256 sensor instances of four beam layouts at random road poses
-  in the config2 scene.
-* ``config5``: config2 geometry with 20 materials and hidden per-material
+* ``batch_256``: 256 sensor instances of four beam layouts at random road poses
+  in the urban_64ch scene.
+* ``calibration_20mat``: urban_64ch geometry with 20 materials and hidden per-material
   reflectance / angle exponent / pose for calibration.
-* ``dynamic_config``: the config2 scene plus 200 moving cars (three car meshes)
+* ``dynamic_actors``: the urban_64ch scene plus 200 moving cars (three car meshes)
   and 100 walking, deforming pedestrians placed by rigid transforms.
 
 The spectral tables stand in for the ECOSTRESS library (paper, Section II-C):
@@ -316,7 +316,7 @@ def _near_origin(box, clear=2.0):
 
 
 @functools.lru_cache(maxsize=4)
-def config1(seed: int = 1001):
+def small_16ch(seed: int = 1001):
     rng = np.random.default_rng(seed)
     mb = _MeshBuilder()
     nmat = 4
@@ -558,7 +558,7 @@ def _sensor_pose_at(scene: Scene, x: float, y: float, yaw: float = 0.0, pitch=0.
     return Pose(np.array([x, y, z], np.float32), quat_from_ypr(yaw, pitch, roll))
 
 
-def config2(seed: int = 2002):
+def urban_64ch(seed: int = 2002):
     scene = urban_small(32, seed)
     sensor = Sensor(elev_table(64), 2048, wavelength_nm=905.0, d_max=100.0)
     return scene, sensor, _sensor_pose_at(scene, 0.0, 0.0)
@@ -598,13 +598,13 @@ def trajectory(scene: Scene, seed: int, n: int = 100, speed: float = 10.0, rate_
     return poses
 
 
-def config3(seed: int = 3003):
+def urban_sequence_128ch(seed: int = 3003):
     scene = urban_large(64, seed)
     sensor = Sensor(elev_table(128), 1024, wavelength_nm=905.0, d_max=100.0, sigma_intensity=0.01)
     return scene, sensor, trajectory(scene, seed + 1)
 
 
-def config4(seed: int = 4004, n_inst: int = 256):
+def batch_256(seed: int = 4004, n_inst: int = 256):
     """256 instances, 1:1:1:1 of 16x900, 32x1800, 64x2048, 128x1024, at random road poses."""
     scene = urban_small(32, 2002)
     rng = np.random.default_rng(seed)
@@ -633,7 +633,7 @@ def config4(seed: int = 4004, n_inst: int = 256):
     return scene, insts
 
 
-def config5(seed: int = 5005):
+def calibration_20mat(seed: int = 5005):
     """Calibration problem: 20 materials, hidden (rho*, k*, pose*), perturbed start."""
     scene = urban_small(20, 2002)
     rng = np.random.default_rng(seed)
@@ -725,7 +725,7 @@ def pedestrian_pose_vertices(mesh: Mesh, phase: float) -> np.ndarray:
     return v.astype(np.float32)
 
 
-def dynamic_config(seed: int = 6006, n_cars: int = 200, n_peds: int = 100):
+def dynamic_actors(seed: int = 6006, n_cars: int = 200, n_peds: int = 100):
     """Moving actors in the 522k-triangle urban scene.
 
     Three car meshes (408 triangles each) and one deformable pedestrian mesh
@@ -735,7 +735,7 @@ def dynamic_config(seed: int = 6006, n_cars: int = 200, n_peds: int = 100):
     actor list at time t (labels 100000 + k).
     """
     scene = urban_small(32, 2002)
-    _, sensor, pose = config2()
+    _, sensor, pose = urban_64ch()
     meshes = [car_mesh(4.5, 1.8, 1.5), car_mesh(4.0, 1.7, 1.45, mats=(4, 7, 11)),
               car_mesh(5.2, 2.0, 1.9, mats=(13, 7, 11)), pedestrian_mesh()]
     rng = np.random.default_rng(seed)

@@ -41,6 +41,11 @@ def compare(g: dict, o: dict, check_debug: bool = True) -> dict:
     n = len(amb)
     rep = {"n": n, "ambiguous": int(amb.sum()), "grazing": int(o["grazing"].sum()),
            "marginal": int((o["marginal"] & ~amb).sum())}
+    # the ambiguous rays by class (a ray can be in several): second hit within 1e-6 m, edge graze, near
+    # miss in front, hit at the trace limit
+    for cls in ("amb_tie", "amb_edge", "amb_near", "amb_limit"):
+        if cls in o:
+            rep[cls] = int(np.asarray(o[cls]).sum())
     ok = ~amb
     if check_debug:
         bad = ok & (g["tri"] != o["tri"])

@@ -26,7 +26,7 @@ def L():
 
 @pytest.fixture(scope="module")
 def c1(L):
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     return _ctx(L, scene, sensor, pose)
 
 
@@ -49,15 +49,15 @@ def _check_against_dense(dense_np, pts, idx, cnt):
         assert np.array_equal(np.ascontiguousarray(g[k]).view(np.uint8), np.ascontiguousarray(want).view(np.uint8)), k
 
 
-def test_config1_point_cloud_matches_dense_and_oracle(L):
-    scene, sensor, pose = S.config1()
+def test_16ch_point_cloud_matches_dense_and_oracle(L):
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     dense = c.simulate(SEED, 2, debug=True)
     pts, idx, cnt = c.compact(dense)
     c.sync_check()
     dn = to_np(dense)
     _check_against_dense(dn, pts, idx, cnt)
-    print(f"[compact] config1: {cnt} of {sensor.n_beams} beams detected", flush=True)
+    print(f"[compact] small_16ch: {cnt} of {sensor.n_beams} beams detected", flush=True)
     # against the oracle's point cloud: same beams except rays it marks ambiguous or marginal
     o = O.simulate(scene, sensor, pose, seed=SEED, scan=2)
     pc = O.point_cloud(o)
@@ -116,7 +116,7 @@ def test_subset_of_fields_and_missing_source(L, c1):
 def test_echo_outputs_compact_per_echo_plane(L):
     """Multi-echo outputs are [echo][beam] planes: compacting all planes at once lists echo 0's
     points, then echo 1's, each in beam order."""
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     r = c.simulate_echoes(SEED, 0, 7, 2, 0.01, 0.5)
     dense = {k: v.reshape(-1) for k, v in r.items()}

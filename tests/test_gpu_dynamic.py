@@ -21,7 +21,7 @@ def L():
 
 @pytest.fixture(scope="module")
 def dyn(L):
-    cfg = S.dynamic_config()
+    cfg = S.dynamic_actors()
     ctx = L.Context(0)
     ctx.load(cfg["scene"])
     ctx.set_sensor(cfg["sensor"])

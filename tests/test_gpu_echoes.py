@@ -33,7 +33,7 @@ def _np(out):
 
 
 def test_one_subray_is_the_single_return_bit_for_bit(L):
-    scene, sensor, pose = S.config2()
+    scene, sensor, pose = S.urban_64ch()
     c = _ctx(L, scene, sensor, pose)
     single = to_np(c.simulate(SEED, 3, debug=True))
     e = _np(c.simulate_echoes(SEED, 3, 1, 2, 0.0, 0.5, debug=True))
@@ -43,7 +43,7 @@ def test_one_subray_is_the_single_return_bit_for_bit(L):
 
 
 def test_echoes_match_oracle_full_16ch(L):
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     pose = S.Pose(pose.p, S.quat_from_ypr(0.3, 0.01, 0.0))
     c = _ctx(L, scene, sensor, pose)
     g = _np(c.simulate_echoes(SEED, 1, 16, 4, 0.01, 0.3, debug=True))
@@ -56,7 +56,7 @@ def test_echoes_match_oracle_full_16ch(L):
 
 
 def test_echoes_match_oracle_sampled_64ch(L):
-    scene, sensor, pose = S.config2()
+    scene, sensor, pose = S.urban_64ch()
     c = _ctx(L, scene, sensor, pose)
     g = _np(c.simulate_echoes(SEED, 0, 7, 3, 0.003, 0.5, debug=True))
     rng = np.random.default_rng(4)
@@ -70,7 +70,7 @@ def test_echoes_match_oracle_sampled_64ch(L):
 
 
 def test_echo_launch_shapes_agree(L):
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     ref = None
     for tile, lanes in ((16, 4), (1, 2), (64, 1), (4, 4)):
@@ -84,7 +84,7 @@ def test_echo_launch_shapes_agree(L):
 
 
 def test_echoes_with_actors_match_oracle(L):
-    cfg = S.dynamic_config()
+    cfg = S.dynamic_actors()
     c = _ctx(L, cfg["scene"], cfg["sensor"], cfg["pose"])
     for m in cfg["meshes"]:
         c.load_mesh(m)
@@ -104,7 +104,7 @@ def test_echoes_with_actors_match_oracle(L):
 
 def test_echo_argument_errors(L):
     from paper_2208_10295_amd import _abi as A
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     for bad in ((0, 1, 0.0, 0.5), (17, 1, 0.0, 0.5), (4, 5, 0.0, 0.5), (4, 2, -1.0, 0.5), (4, 2, 0.01, 0.0)):
         with pytest.raises(L.LidarError):

@@ -35,19 +35,19 @@ def _report(name, rep):
     print(f"[parity] {name}: " + ", ".join(f"{k}={v}" for k, v in rep.items()), flush=True)
 
 
-def test_config1_full_scan_matches_oracle(L):
-    scene, sensor, pose = S.config1()
+def test_16ch_full_scan_matches_oracle(L):
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     g = to_np(c.simulate(SEED, scan=3, debug=True))
     c.sync_check()
     o = O.simulate(scene, sensor, pose, seed=SEED, scan=3)
     rep = compare(g, o)
-    _report("config1 full", rep)
+    _report("small_16ch full", rep)
     assert rep["valid"] > 3000 and rep["ambiguous"] < 0.01 * rep["n"]
 
 
-def test_config1_bvh_equals_bruteforce_and_is_deterministic(L):
-    scene, sensor, pose = S.config1()
+def test_16ch_bvh_equals_bruteforce_and_is_deterministic(L):
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     a = to_np(c.simulate(SEED, 1, debug=True))
     b = to_np(c.simulate(SEED, 1, debug=True, bruteforce=True))
@@ -59,7 +59,7 @@ def test_config1_bvh_equals_bruteforce_and_is_deterministic(L):
 
 def test_launch_shapes_do_not_change_results(L):
     """Leaf width, tile shape, lanes per ray and the XCD remap change speed only."""
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     ref = None
     for W in (1, 2, 3, 4, 8):
         c = _ctx(L, scene, sensor, pose, leaf_width=W)
@@ -76,31 +76,30 @@ def test_launch_shapes_do_not_change_results(L):
                 assert np.array_equal(ref[k], g[k]), (W, tile, lanes, xcd, k)
 
 
-def test_config2_full_scan_sampled_oracle(L):
-    scene, sensor, pose = S.config2()
+def test_64ch_full_scan_matches_oracle_every_beam(L):
+    """The 64 x 2048 scan of the 522,272-triangle scene, every one of its 131,072 beams against the FP64
+    brute-force oracle (6.85e10 ray-triangle tests, about 13 s on 16 host threads)."""
+    scene, sensor, pose = S.urban_64ch()
     c = _ctx(L, scene, sensor, pose)
     st = c.stats()
-    print("[bvh] config2", st, flush=True)
+    print("[bvh] urban_64ch", st, flush=True)
     out = c.simulate(SEED, scan=0, debug=True)
     c.sync_check()
-    rng = np.random.default_rng(7)
-    beams = np.sort(rng.choice(sensor.n_beams, 3072, replace=False))
-    # include whole rows at the ragged start/end of a tile row and the first/last beams
-    beams = np.unique(np.r_[beams, np.arange(0, 70), np.arange(sensor.n_beams - 70, sensor.n_beams)])
-    o = O.simulate(scene, sensor, pose, seed=SEED, scan=0, beams=beams)
-    rep = compare(to_np(out, beams), o)
-    _report("config2 sampled", rep)
-    assert rep["valid"] > 1000
+    o = O.simulate(scene, sensor, pose, seed=SEED, scan=0)
+    rep = compare(to_np(out), o)
+    _report("urban_64ch every beam", rep)
+    assert rep["n"] == 131072 and rep["tri_mismatch"] == 0 and rep["valid_mismatch"] == 0
+    assert rep["valid"] > 50000 and rep["ambiguous"] < 0.01 * rep["n"]
 
 
-def test_config2_bvh_equals_bruteforce_full(L):
+def test_64ch_bvh_equals_bruteforce_full(L):
     """Both tree builders, both collapses and every traversal shape reproduce the brute-force scan bit for bit."""
-    scene, sensor, pose = S.config2()
+    scene, sensor, pose = S.urban_64ch()
     c = _ctx(L, scene, sensor, pose)
     b = to_np(c.simulate(SEED, 0, debug=True, bruteforce=True))
     for builder, collapse in (("ploc", "sah"), ("lbvh", "sah"), ("ploc", "greedy"), ("lbvh", "greedy")):
         st = c.load(scene, builder=builder, collapse=collapse)
-        print(f"[bvh] config2 {builder} {collapse}: nodes {st['n_nodes']} leaves {st['n_leaves']} "
+        print(f"[bvh] urban_64ch {builder} {collapse}: nodes {st['n_nodes']} leaves {st['n_leaves']} "
               f"depth {st['depth']} build {st['build_ms']:.2f} ms", flush=True)
         for lanes in (1, 2, 4):
             c.set_lanes_per_ray(lanes)
@@ -116,7 +115,7 @@ def test_config2_bvh_equals_bruteforce_full(L):
 def test_bvh_structure_invariants(L, builder, collapse, leaf_width, leaf_cost):
     """Every triangle lies in exactly one leaf of at most leaf_width triangles, and every child box contains
     its triangles, for each builder and collapse (a very cheap and a very dear leaf step included)."""
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     c.load(scene, leaf_width, builder=builder, collapse=collapse, leaf_cost=leaf_cost)
     st = c.stats()
@@ -171,7 +170,7 @@ def test_cost_shaped_collapse_is_no_worse_than_greedy(L, builder, leaf_width):
     """The bottom-up programme minimises the surface-area cost over every 4-wide collapse of the binary
     tree, and the greedy collapse is one of them: the cost of the default tree cannot exceed the greedy
     tree's (same builder, same binary tree; the two share only the binary tree)."""
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     cost = {}
     for collapse in ("sah", "greedy"):
@@ -183,7 +182,7 @@ def test_cost_shaped_collapse_is_no_worse_than_greedy(L, builder, leaf_width):
 
 def test_ragged_sensor_and_offsets(L):
     """Odd channel/azimuth counts, a partial FOV and a scene far from the origin."""
-    scene, _, _ = S.config1()
+    scene, _, _ = S.small_16ch()
     off = np.array([3000.0, -1500.0, 40.0])
     sc2 = S.Scene((scene.vertices.astype(np.float64) + off).astype(np.float32), scene.indices, scene.material,
                   scene.label, scene.spectra, scene.sigma_range, scene.angle_exp)
@@ -214,25 +213,32 @@ def test_single_triangle_scene(L):
     assert abs(g["range"][16] - 10.0) < 1e-5 and abs(g["intensity"][16] - 0.6) < 1e-6
 
 
-def test_config3_sequence_sampled(L):
-    scene, sensor, poses = S.config3()
+def test_128ch_5m_sequence_256_beams_of_every_scan(L):
+    """The 100-scan trajectory in the 5,224,200-triangle scene: 256 seeded beams of each of the 100 scans
+    (25,600 beams, 1.3e11 ray-triangle tests) against the oracle, each scan with its own pose and Philox
+    scan counter."""
+    scene, sensor, poses = S.urban_sequence_128ch()
     c = L.Context(0)
     st = c.load(scene)
-    print("[bvh] config3", st, flush=True)
+    print("[bvh] urban_sequence_128ch", st, flush=True)
     c.set_sensor(sensor)
     rng = np.random.default_rng(3)
-    for scan in (0, 57, 99):
-        pose = poses[scan]
+    tot = {}
+    for scan, pose in enumerate(poses):
         c.set_pose(pose.p, pose.q)
         out = c.simulate(SEED, scan, debug=True)
-        c.sync_check()
-        beams = np.sort(rng.choice(sensor.n_beams, 160, replace=False))
+        beams = np.sort(rng.choice(sensor.n_beams, 256, replace=False))
         o = O.simulate(scene, sensor, pose, seed=SEED, scan=scan, beams=beams)
-        _report(f"config3 scan {scan}", compare(to_np(out, beams), o))
+        rep = compare(to_np(out, beams), o)
+        for k, v in rep.items():
+            tot[k] = max(tot.get(k, 0), v) if k.endswith("_max_rel") else tot.get(k, 0) + v
+    c.sync_check()
+    _report("urban_sequence_128ch, 256 beams x 100 scans", tot)
+    assert tot["n"] == 25600 and tot["tri_mismatch"] == 0 and tot["valid_mismatch"] == 0 and tot["valid"] > 5000
 
 
 def test_wavelength_clamp_warning_and_values(L):
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     s2 = S.Sensor(sensor.elev_deg, 64, wavelength_nm=1550.0, d_max=100.0)
     c = L.Context(0)
     c.load(scene)
@@ -304,7 +310,7 @@ def test_stack_overflow_is_reported_and_recovered(L):
     second one loses children, stays within its stack memory and ends; sync_check reports the overflow,
     and with the cap lifted the same scan is bit-identical to the uncapped one."""
     from paper_2208_10295_amd import _abi as A
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     ref = to_np(c.simulate(SEED, 0, debug=True))
     c.sync_check()
@@ -337,7 +343,7 @@ def test_range_and_intensity_noise_are_independent_standard_normals(L):
     and z_I = (I - R_lambda) / sigma_I over the beams whose detection and clamp the noise cannot change."""
     import dataclasses
     from scipy import stats
-    scene, sensor, pose = S.config2()
+    scene, sensor, pose = S.urban_64ch()
     sensor = dataclasses.replace(sensor, sigma_intensity=0.01)
     c = _ctx(L, scene, sensor, pose)
     g = to_np(c.simulate(SEED, 3, debug=True))
@@ -361,7 +367,7 @@ def test_range_and_intensity_noise_are_independent_standard_normals(L):
 def test_trajectory_launcher_equals_pose_then_simulate(L):
     """The per-tick trajectory launcher (pose k, then scan k, argument structs built once) gives the same
     outputs bit for bit as setting each pose and simulating scan k."""
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     poses = [S.Pose((np.asarray(pose.p, np.float64) + [0.7 * k, -0.3 * k, 0.0]).astype(np.float32),
                     S.quat_from_ypr(0.2 * k, 0.01 * k, 0.0)) for k in range(3)]
@@ -382,16 +388,16 @@ def test_origin_outside_the_padded_cube_warns(L):
     |vertex coordinate|): a pose, a sweep end, a batch instance or a scene loaded under a pose outside
     it gives the warning, and the call still does its work."""
     from paper_2208_10295_amd import _abi as A
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
     M = float(c.stats()["max_abs_coord"])
     assert M == float(np.max(np.abs(scene.vertices[scene.indices.astype(np.int64)])))
     assert c.set_pose(pose.p, pose.q) == A.OK
-    far = np.array([0.0, 0.0, 1.5 * M], np.float32)
+    far = np.array([1.2 * M, 0.0, 1.5], np.float32)      # 20 % beyond the ground's edge, 1.5 m up
     with pytest.warns(RuntimeWarning, match="outside the cube"):
         st = c.set_pose(far, pose.q)
     assert st & A.WARN_ORIGIN_OUTSIDE_SCENE
-    g = to_np(c.simulate(0, 0))              # still simulated (looking down at the scene from above)
+    g = to_np(c.simulate(0, 0))              # still simulated: the beams towards the scene see it
     assert g["valid"].sum() > 0
     with pytest.warns(RuntimeWarning, match="outside the cube"):
         c.load(scene)

@@ -26,16 +26,16 @@ def L():
 @pytest.fixture(scope="module")
 def c5w(L):
     """One context per wavelength (a context holds one sensor)."""
-    c5 = S.config5()
+    cal = S.calibration_20mat()
     ctxs = []
     for lam in WAVELENGTHS:
         ctx = L.Context(0)
-        ctx.load(c5["scene"])
-        ctx.set_sensor(dataclasses.replace(c5["sensor"], wavelength_nm=lam))
-        pt = c5["pose_true"]
+        ctx.load(cal["scene"])
+        ctx.set_sensor(dataclasses.replace(cal["sensor"], wavelength_nm=lam))
+        pt = cal["pose_true"]
         ctx.set_pose(pt.p, pt.q)
         ctxs.append(ctx)
-    return ctxs, c5
+    return ctxs, cal
 
 
 def test_spectral_adjoint_matches_oracle(L, c5w):

@@ -63,7 +63,7 @@ def _run_ticks(c, L, sensor, pose, head0, spin, dt, n_ticks, seed):
     return to_np(out), fired
 
 
-@pytest.mark.parametrize("cfg", ["config1", "config2"])
+@pytest.mark.parametrize("cfg", ["small_16ch", "urban_64ch"])
 def test_fixed_pose_ticks_equal_the_full_scan_bit_for_bit(L, cfg):
     """Ticks of one revolution at a fixed pose reproduce lidar_simulate(scan)
     exactly (all outputs), and fire every column once."""
@@ -85,7 +85,7 @@ def test_rolling_shutter_tick_matches_oracle(L):
     """A moving, turning sensor on the 522k-triangle scene; the tick crosses a
     revolution boundary (two runs).  Sampled beams of the fired columns match
     the oracle; columns that did not fire keep their contents."""
-    scene, sensor, pose = S.config2()
+    scene, sensor, pose = S.urban_64ch()
     c = _ctx(L, scene, sensor)
     pa = S.Pose(pose.p, S.quat_from_ypr(0.2, 0.01, -0.02))
     pb = S.Pose((pose.p + np.array([1.5, 0.4, 0.05])).astype(np.float32), S.quat_from_ypr(0.2 + math.radians(6.0),
@@ -109,12 +109,12 @@ def test_rolling_shutter_tick_matches_oracle(L):
                             np.arange(sensor.n_ch) * sensor.n_az + cols[-1]])
     o = O.simulate_sweep(scene, sensor, pa, pb, head, spin, dt, seed=SEED, beams=beams)
     rep = compare({k: v[..., beams] for k, v in g.items()}, o)
-    print("[parity] sweep config2:", rep, flush=True)
+    print("[parity] sweep urban_64ch:", rep, flush=True)
     assert rep["valid"] > 1000 and rep["ambiguous"] < 0.01 * rep["n"]
 
 
 def test_sweep_launch_shapes_and_lbvh_do_not_change_results(L):
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor)
     pa = S.Pose(pose.p, S.quat_from_ypr(0.1))
     pb = S.Pose((pose.p + np.array([0.8, -0.3, 0.0])).astype(np.float32), S.quat_from_ypr(0.4, 0.02))
@@ -135,7 +135,7 @@ def test_sweep_launch_shapes_and_lbvh_do_not_change_results(L):
 
 
 def test_sweep_edge_cases(L):
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor)
     pq = (pose.p, pose.q)
     out = _sentinel_outputs(L, sensor.n_beams)

@@ -11,7 +11,7 @@ from lidar_inputs import scenes as S
 
 
 def test_one_subray_without_divergence_is_the_single_return():
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     pose = S.Pose(pose.p, S.quat_from_ypr(0.4, 0.02, 0.01))
     o = O.simulate(scene, sensor, pose, seed=9, scan=4)
     e = O.simulate_echoes(scene, sensor, pose, 1, 3, 0.0, 0.5, seed=9, scan=4)

@@ -108,7 +108,7 @@ def test_quaternion_rotation_matches_rodrigues():
 # ----------------------------------------------------------------------------
 # P1: ray to a plane at known distance and angle (eq.4, eq.5)
 # ----------------------------------------------------------------------------
-def test_ground_plane_closed_form_config1_numbers():
+def test_ground_plane_closed_form_16ch_numbers():
     """Ground seen from h = 1.5 m: t = h / sin|phi|, cos(theta_inc) = sin|phi|, I = rho cos."""
     h, rho = 1.5, 0.5
     scene = _ground(spectra=np.full((1, 61), rho, np.float32))
@@ -373,7 +373,7 @@ def test_echo_intensity_noise_uses_words_2_3_and_clamps_at_zero():
 # P4: invariance under a rigid transform of scene + sensor
 # ----------------------------------------------------------------------------
 def test_rigid_transform_invariance():
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     rng = np.random.default_rng(11)
     beams = rng.choice(sensor.n_beams, 1500, replace=False)
     r0 = O.simulate(scene, sensor, pose, seed=9, beams=beams)
@@ -501,7 +501,7 @@ def test_spectral_interpolation_and_clamp():
 
 
 def test_label_and_material_of_hit_object():
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     r = O.simulate(scene, sensor, pose, seed=1)
     h = r["hit"]
     assert np.array_equal(r["label"][r["valid"] == 1], scene.label[r["tri"][r["valid"] == 1]])
@@ -516,22 +516,22 @@ def test_label_and_material_of_hit_object():
 # P8: adjoint of the calibration loss (hit triangles fixed)
 # ----------------------------------------------------------------------------
 def _calib_problem(n_beams=3000, seed=0):
-    c5 = S.config5()
-    scene, sensor = c5["scene"], c5["sensor"]
+    cal = S.calibration_20mat()
+    scene, sensor = cal["scene"], cal["sensor"]
     rng = np.random.default_rng(seed)
     beams = np.sort(rng.choice(sensor.n_beams, n_beams, replace=False))
-    fwd = O.simulate(scene, sensor, c5["pose_true"], beams=beams, rho=c5["rho_true"], angle_exp=c5["k_true"])
+    fwd = O.simulate(scene, sensor, cal["pose_true"], beams=beams, rho=cal["rho_true"], angle_exp=cal["k_true"])
     keep = (fwd["valid"] == 1) & ~fwd["ambiguous"] & ~fwd["grazing"]
-    return c5, beams[keep], fwd["tri"][keep], fwd["intensity"][keep], fwd["range"][keep]
+    return cal, beams[keep], fwd["tri"][keep], fwd["intensity"][keep], fwd["range"][keep]
 
 
 def test_adjoint_matches_central_differences():
-    c5, beams, tri, I_t, t_t = _calib_problem()
-    scene, sensor, pose = c5["scene"], c5["sensor"], c5["pose_true"]
-    rho = c5["rho0"].astype(np.float64) + 0.05 * np.arange(20) / 20
-    kexp = c5["k0"].astype(np.float64) + 0.3 * np.sin(np.arange(20))
-    dp = np.array(c5["dp0"]) * 0.05
-    dw = np.array(c5["dw0"]) * 0.05
+    cal, beams, tri, I_t, t_t = _calib_problem()
+    scene, sensor, pose = cal["scene"], cal["sensor"], cal["pose_true"]
+    rho = cal["rho0"].astype(np.float64) + 0.05 * np.arange(20) / 20
+    kexp = cal["k0"].astype(np.float64) + 0.3 * np.sin(np.arange(20))
+    dp = np.array(cal["dp0"]) * 0.05
+    dw = np.array(cal["dw0"]) * 0.05
     args = (scene, sensor, pose, tri, beams)
     g_rho, g_k, g_pose = O.calib_grad(*args, rho, kexp, dp, dw, I_t, t_t)
     g = np.concatenate([g_rho, g_k, g_pose])
@@ -553,9 +553,9 @@ def test_calibration_forward_is_the_scan_with_the_triangle_fixed():
     """With the hit triangles held fixed, the calibration forward at the hidden parameters reproduces
     the scan the targets came from: I = the scan's R_lambda (cos^k with k != 1), t = its hit
     distance, at a rotated and displaced pose; so the loss there is 0."""
-    c5, beams, tri, I_t, t_t = _calib_problem(n_beams=2000, seed=3)
-    scene, sensor, pose = c5["scene"], c5["sensor"], c5["pose_true"]
-    rho, kexp = c5["rho_true"].astype(np.float64), c5["k_true"].astype(np.float64)
+    cal, beams, tri, I_t, t_t = _calib_problem(n_beams=2000, seed=3)
+    scene, sensor, pose = cal["scene"], cal["sensor"], cal["pose_true"]
+    rho, kexp = cal["rho_true"].astype(np.float64), cal["k_true"].astype(np.float64)
     assert np.all(np.abs(kexp - 1.0) > 1e-3)           # exponents away from the Lambertian value
     fwd = O.simulate(scene, sensor, pose, beams=beams, rho=rho, angle_exp=kexp)
     s = O.beam_directions(sensor).reshape(-1, 3)[beams]
@@ -578,13 +578,13 @@ def test_adjoint_with_intensity_noise_clamp_matches_central_differences():
     """I = max(0, R_lambda + sigma_I z_I): where the clamp holds, I does not move with rho, k or the
     pose.  The analytic gradient (g_I zeroed there) against central differences of the clamped loss,
     with a sigma_I that clamps a good share of the beams."""
-    c5, beams, tri, I_t, t_t = _calib_problem(n_beams=1500, seed=4)
-    scene, sensor, pose = c5["scene"], c5["sensor"], c5["pose_true"]
+    cal, beams, tri, I_t, t_t = _calib_problem(n_beams=1500, seed=4)
+    scene, sensor, pose = cal["scene"], cal["sensor"], cal["pose_true"]
     _, z_i = O.beam_normals(77, 0, 0, beams)
     sig_i = 0.25
-    rho = c5["rho0"].astype(np.float64) + 0.05 * np.arange(20) / 20
-    kexp = c5["k0"].astype(np.float64) + 0.3 * np.sin(np.arange(20))
-    dp, dw = np.array(c5["dp0"]) * 0.05, np.array(c5["dw0"]) * 0.05
+    rho = cal["rho0"].astype(np.float64) + 0.05 * np.arange(20) / 20
+    kexp = cal["k0"].astype(np.float64) + 0.3 * np.sin(np.arange(20))
+    dp, dw = np.array(cal["dp0"]) * 0.05, np.array(cal["dw0"]) * 0.05
     s = O.beam_directions(sensor).reshape(-1, 3)[beams]
     R = O.so3_exp(dw) @ O.rotation_from_quat(pose.q)
     I, *_, live = O._fixed_triangle_forward(scene, s, tri, R, np.asarray(pose.p, np.float64) + dp, rho, kexp,
@@ -635,13 +635,13 @@ def test_spectral_adjoint_matches_central_differences_on_the_table():
     central differences of the loss with R_lambda(0) re-read from the perturbed
     table: on a bin centre, between bins, and clamped below and above the table."""
     import dataclasses
-    c5, beams, tri, I_t, t_t = _calib_problem(n_beams=1500, seed=1)
-    scene, pose = c5["scene"], c5["pose_true"]
+    cal, beams, tri, I_t, t_t = _calib_problem(n_beams=1500, seed=1)
+    scene, pose = cal["scene"], cal["pose_true"]
     T = scene.spectra.astype(np.float64)
-    kexp = c5["k0"].astype(np.float64) + 0.2
-    dp, dw = np.array(c5["dp0"]) * 0.05, np.array(c5["dw0"]) * 0.05
+    kexp = cal["k0"].astype(np.float64) + 0.2
+    dp, dw = np.array(cal["dp0"]) * 0.05, np.array(cal["dw0"]) * 0.05
     for lam, hot in ((900.0, (50,)), (905.0, (50, 51)), (931.0, (53, 54)), (380.0, (0,)), (1550.0, (60,))):
-        sensor = dataclasses.replace(c5["sensor"], wavelength_nm=lam)
+        sensor = dataclasses.replace(cal["sensor"], wavelength_nm=lam)
         args = (scene, sensor, pose, tri, beams)
         g_T, g_k, g_pose = O.calib_grad_spectral(*args, T, kexp, dp, dw, I_t, t_t)
         rho_of = lambda TT: O.reflectance_at_wavelength(TT, lam)[0]   # noqa: E731

@@ -144,7 +144,7 @@ def test_rolling_shutter_rotation_closed_form():
 def test_constant_pose_ticks_reproduce_the_full_scan():
     """Ticks with one pose covering revolution 2 give exactly the outputs of
     the full scan with scan counter 2 (same rays, same Philox counters)."""
-    scene, sensor, pose = S.config1()
+    scene, sensor, pose = S.small_16ch()
     pose = S.Pose(pose.p, S.quat_from_ypr(0.7, 0.05, -0.03))
     full = O.simulate(scene, sensor, pose, seed=77, scan=2)
     got = {k: np.zeros_like(full[k]) for k in ("valid", "range", "label", "tri", "intensity", "x", "y", "z")}
