@@ -297,6 +297,23 @@ lidar_status lidar_compact_points(lidar_ctx *ctx, const lidar_outputs *dense, ui
                                   const lidar_outputs *compact, uint32_t *beam_index, uint32_t *count,
                                   void *workspace, uint64_t workspace_bytes, void *stream);
 
+/* lidar_compact_points for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments and results without the workspace: the per-block counts go to a
+ * 512 KiB array of device memory that the library keeps on each GPU (set up
+ * by the first lidar_create on that device, held until the process ends).
+ * Allocates nothing (no hipMalloc, no allocating library call).  n_beams is
+ * at most LIDAR_COMPACT_NOALLOC_MAX_BEAMS; nothing in the array has to start
+ * at zero (every call writes each count before reading it).  All calls on one
+ * GPU share the array: calls ordered on one stream are safe, calls that may
+ * overlap on one GPU (other streams, other threads) race and give wrong
+ * results.  Asynchronous.  Errors: as lidar_compact_points, and INVALID_ARG
+ * for n_beams above the maximum. */
+#define LIDAR_COMPACT_NOALLOC_MAX_BEAMS 33554432u   /* 2^25: 131,072 block counts */
+lidar_status lidar_compact_points_noalloc(lidar_ctx *ctx, const lidar_outputs *dense, uint64_t n_beams,
+                                          const lidar_outputs *compact, uint32_t *beam_index, uint32_t *count,
+                                          void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Divergent beams and multi-echo returns (Section IV: named future work)    */
 /* ------------------------------------------------------------------------ */

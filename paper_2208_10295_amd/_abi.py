@@ -29,6 +29,7 @@ WARN_ORIGIN_OUTSIDE_SCENE = 2
 MAX_TRIANGLES = 44739242
 MAX_NODES = 16777216
 MESH_REACH = 1024.0
+COMPACT_NOALLOC_MAX_BEAMS = 33554432
 
 NO_LABEL = 0xFFFFFFFF
 NO_TRIANGLE = 0xFFFFFFFF
@@ -139,6 +140,7 @@ SIGNATURES = {
     "lidar_compact_bytes": (C.c_int32, [C.c_uint64, C.POINTER(C.c_uint64)]),
     "lidar_compact_points": (C.c_int32, [P, C.POINTER(Outputs), C.c_uint64, C.POINTER(Outputs), P, P, P, C.c_uint64,
                                          P]),
+    "lidar_compact_points_noalloc": (C.c_int32, [P, C.POINTER(Outputs), C.c_uint64, C.POINTER(Outputs), P, P, P]),
     "lidar_simulate_sweep": (C.c_int32, [P, C.POINTER(SweepDesc), C.POINTER(Outputs), C.POINTER(SweepInfo), P]),
     "lidar_probe_stream": (C.c_int32, [P, C.c_uint64, P, P]),
     "lidar_probe_gather": (C.c_int32, [P, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, P, P]),

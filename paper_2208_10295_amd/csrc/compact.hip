@@ -17,8 +17,17 @@
 // Up to kFusedBlocks blocks (a scan of up to 524,288 beams) steps 2 and 3 are
 // one launch: each block sums the counts before it itself (at most 8 loads per
 // thread), which costs less than a launch of its own.
+#include <mutex>
+
 #include "lidar_device.hpp"
 #include "lidar_kernels.hpp"
+
+// Scratch of the allocation-free entry point: the per-block counts of up to
+// kStaticCountWords blocks (2^25 beams), one copy per GPU, held by the library
+// until the process ends.  Host code never uses this name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr uint32_t kStaticCountWords = 131072;   // 512 KiB
+static __device__ __align__(256) uint32_t scratch[kStaticCountWords];
 
 namespace lidar {
 
@@ -141,6 +150,32 @@ __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(Outputs 
 }
 
 uint64_t compact_blocks(uint64_t n) { return (n + kCompactBlock - 1) / kCompactBlock; }
+
+uint64_t compact_static_max_beams() { return (uint64_t)kStaticCountWords * kCompactBlock; }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t compact_static_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    // the caller has made `device` current; each device holds its own copy of the array
+    uint32_t *p = nullptr;
+    hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+    return hipSuccess;
+}
+
+uint32_t *compact_static_counts(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
 
 void launch_compact(const Outputs &dense, const Outputs &comp, uint32_t *beam_index, uint32_t *count, uint64_t n,
                     uint32_t *counts, hipStream_t s) {

@@ -349,6 +349,12 @@ lidar_status lidar_create(int hip_device, lidar_ctx **out) {
         g_create_error = "device allocation failed";
         return LIDAR_ERR_OUT_OF_MEMORY;
     }
+    if ((e = compact_static_init(hip_device)) != hipSuccess) {
+        ctx->words.release();
+        delete ctx;
+        g_create_error = std::string("static scratch lookup failed: ") + hipGetErrorString(e);
+        return LIDAR_ERR_HIP;
+    }
     *out = ctx;
     return LIDAR_OK;
 }
@@ -638,10 +644,8 @@ lidar_status lidar_compact_bytes(uint64_t n_beams, uint64_t *workspace_bytes) {
     return LIDAR_OK;
 }
 
-lidar_status lidar_compact_points(lidar_ctx *ctx, const lidar_outputs *dense, uint64_t n_beams,
-                                  const lidar_outputs *compact, uint32_t *beam_index, uint32_t *count,
-                                  void *workspace, uint64_t workspace_bytes, void *stream) {
-    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+static lidar_status check_compact(lidar_ctx *ctx, const lidar_outputs *dense, uint64_t n_beams,
+                                  const lidar_outputs *compact, const uint32_t *count) {
     if (!dense || !compact) return ctx->fail(LIDAR_ERR_INVALID_ARG, "outputs struct is null");
     if (!dense->valid && n_beams) return ctx->fail(LIDAR_ERR_INVALID_ARG, "dense outputs need the valid array");
     if (!count) return ctx->fail(LIDAR_ERR_INVALID_ARG, "count pointer is null");
@@ -654,6 +658,15 @@ lidar_status lidar_compact_points(lidar_ctx *ctx, const lidar_outputs *dense, ui
                               {compact->r_lambda, dense->r_lambda}};
     for (const auto &pr : pairs)
         if (pr[0] && !pr[1]) return ctx->fail(LIDAR_ERR_INVALID_ARG, "a compact field has no dense source");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_compact_points(lidar_ctx *ctx, const lidar_outputs *dense, uint64_t n_beams,
+                                  const lidar_outputs *compact, uint32_t *beam_index, uint32_t *count,
+                                  void *workspace, uint64_t workspace_bytes, void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    lidar_status st = check_compact(ctx, dense, n_beams, compact, count);
+    if (st != LIDAR_OK) return st;
     uint64_t need = 0;
     lidar_compact_bytes(n_beams, &need);
     if (!workspace || ((uintptr_t)workspace & 255)) return ctx->fail(LIDAR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
@@ -661,6 +674,25 @@ lidar_status lidar_compact_points(lidar_ctx *ctx, const lidar_outputs *dense, ui
     hipSetDevice(ctx->device);
     launch_compact(to_outputs(dense, n_beams), to_outputs(compact, n_beams), beam_index, count, n_beams,
                    (uint32_t *)workspace, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx->hip_fail(e, "compaction launch");
+    return LIDAR_OK;
+}
+
+lidar_status lidar_compact_points_noalloc(lidar_ctx *ctx, const lidar_outputs *dense, uint64_t n_beams,
+                                          const lidar_outputs *compact, uint32_t *beam_index, uint32_t *count,
+                                          void *stream) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    lidar_status st = check_compact(ctx, dense, n_beams, compact, count);
+    if (st != LIDAR_OK) return st;
+    if (n_beams > compact_static_max_beams())
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "n_beams above LIDAR_COMPACT_NOALLOC_MAX_BEAMS (the static scratch "
+                                                "holds the counts of 2^25 beams): use lidar_compact_points");
+    uint32_t *counts = compact_static_counts(ctx->device);   // the device address, never the array's name
+    if (!counts) return ctx->fail(LIDAR_ERR_NOT_READY, "static scratch of this device not set up");
+    hipSetDevice(ctx->device);
+    launch_compact(to_outputs(dense, n_beams), to_outputs(compact, n_beams), beam_index, count, n_beams, counts,
+                   (hipStream_t)stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx->hip_fail(e, "compaction launch");
     return LIDAR_OK;

@@ -142,6 +142,11 @@ void launch_probe_gather(const void *table, uint32_t n_lines, uint32_t blocks, u
 // --- point-cloud compaction (compact.hip) ---
 // counts: compact_blocks(n) device words of scratch; count: one device word
 uint64_t compact_blocks(uint64_t n);
+// the allocation-free variant's counts: a static device array per GPU (compact_static_max_beams() beams);
+// compact_static_init (device current) looks its address up once per device
+uint64_t compact_static_max_beams();
+hipError_t compact_static_init(int device);
+uint32_t *compact_static_counts(int device);
 void launch_compact(const Outputs &dense, const Outputs &comp, uint32_t *beam_index, uint32_t *count, uint64_t n,
                     uint32_t *counts, hipStream_t s);
 

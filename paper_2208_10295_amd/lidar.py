@@ -396,29 +396,34 @@ class Context:
         return run, (d_a, d_k, d_pose)
 
     def compact(self, dense: dict, names=None, out: dict | None = None, workspace=None, stream=None,
-                read_count: bool = True):
+                read_count: bool = True, noalloc: bool = False):
         """Order-preserving compaction of dense outputs (any number of beams) to the detected points.
 
         Returns (points, beam_index, count): `points` maps each requested name (default: every dense
         array) to a tensor of capacity n whose first `count` elements are the detected points in beam
         order, `beam_index` their dense indices, `count` the device count tensor, or its value (a host
-        int, after a synchronisation) if read_count is True; then the tensors are cut to that length."""
+        int, after a synchronisation) if read_count is True; then the tensors are cut to that length.
+        noalloc: use lidar_compact_points_noalloc (the library's static scratch, no workspace)."""
         v = dense.get("valid")
         n = int(v.numel()) if v is not None else int(next(t for t in dense.values() if t is not None).shape[-1])
         dense = {k: t for k, t in dense.items() if t is not None}
         names = tuple(dense.keys()) if names is None else tuple(names)
         if out is None:
             out = alloc_outputs(n, names, self.device)
-        nbytes = C.c_uint64()
-        check(lib.lidar_compact_bytes(n, C.byref(nbytes)), self.h)
-        if workspace is None or workspace.numel() < nbytes.value:
-            workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         beam_index = torch.empty(n, dtype=torch.int32, device=self.device)
         count = torch.zeros(1, dtype=torch.int32, device=self.device)
         di, co = outputs_struct(dense), outputs_struct({k: out[k] for k in names})
-        check(lib.lidar_compact_points(self.h, C.byref(di), n, C.byref(co), _ptr(beam_index), _ptr(count),
-                                       _ptr(workspace), workspace.numel(), _stream(stream)), self.h)
-        self._compact_workspace = workspace
+        if noalloc:
+            check(lib.lidar_compact_points_noalloc(self.h, C.byref(di), n, C.byref(co), _ptr(beam_index),
+                                                   _ptr(count), _stream(stream)), self.h)
+        else:
+            nbytes = C.c_uint64()
+            check(lib.lidar_compact_bytes(n, C.byref(nbytes)), self.h)
+            if workspace is None or workspace.numel() < nbytes.value:
+                workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            check(lib.lidar_compact_points(self.h, C.byref(di), n, C.byref(co), _ptr(beam_index), _ptr(count),
+                                           _ptr(workspace), workspace.numel(), _stream(stream)), self.h)
+            self._compact_workspace = workspace
         if not read_count:
             return out, beam_index, count
         c = int(count.item())
