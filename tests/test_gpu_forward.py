@@ -397,8 +397,8 @@ def test_origin_outside_the_padded_cube_warns(L):
     with pytest.warns(RuntimeWarning, match="outside the cube"):
         st = c.set_pose(far, pose.q)
     assert st & A.WARN_ORIGIN_OUTSIDE_SCENE
-    g = to_np(c.simulate(0, 0))              # still simulated: the beams towards the scene see it
-    assert g["valid"].sum() > 0
+    g = to_np(c.simulate(0, 0, debug=True))  # still simulated: the beams towards the scene hit it
+    assert (g["tri"] != 0xFFFFFFFF).sum() > 100
     with pytest.warns(RuntimeWarning, match="outside the cube"):
         c.load(scene)
     with pytest.warns(RuntimeWarning, match="outside the cube"):
