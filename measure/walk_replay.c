@@ -152,7 +152,7 @@ static void touch(uint8_t *flags, uint64_t k) {
 
 static int walk(const slot_t *nodes, const rec_t *recs, uint32_t root, const ray_t *r, float t_lo, float t_hi,
                 uint32_t *n_nodes, uint32_t *n_tris, uint32_t *n_leaves, float *t_best, uint32_t *orig_best,
-                uint8_t *node_touched, uint8_t *rec_touched) {
+                uint8_t *node_touched, uint8_t *rec_touched, uint64_t *leaf_steps) {
     uint32_t stack[MAX_STACK];
     int sp = 0;
     float best_t = t_hi;
@@ -161,6 +161,7 @@ static int walk(const slot_t *nodes, const rec_t *recs, uint32_t root, const ray
     uint32_t nn = 0, nt = 0, nl = 0;
     uint32_t ref = root;
     for (;;) {
+        if (leaf_steps && (ref & LEAF_BIT) && nn + nl < 128) leaf_steps[(nn + nl) >> 6] |= 1ull << ((nn + nl) & 63);
         if (ref & LEAF_BIT) {
             uint32_t first = (ref >> 3) & 0x0FFFFFFFu, cnt = (ref & 7u) + 1u;
             nt += cnt;
@@ -218,7 +219,9 @@ static int walk(const slot_t *nodes, const rec_t *recs, uint32_t root, const ray
  * over (t_min, t_trace].  Writes per beam the node fetches, the triangle
  * records tested, the leaves visited, the best distance (t_trace if none) and the original index
  * of the best triangle (0xFFFFFFFF if none); node_touched / rec_touched (or
- * NULL) get 1 at every node and record the walks fetch.  Returns the number of beams
+ * NULL) get 1 at every node and record the walks fetch; leaf_steps (or NULL,
+ * two words per beam, zeroed by the caller) gets bit i set when step i of the
+ * beam's walk is a leaf (steps beyond 128 are not marked).  Returns the number of beams
  * that could not be replayed (index beyond the scan, or a stack beyond 256
  * entries); their outputs are zero.
  */
@@ -226,7 +229,7 @@ int64_t walk_replay(const void *nodes, const void *recs, uint32_t root, const do
                     uint32_t n_az, double az0_deg, double fov_h_deg, const float q[4], const float p[3],
                     float t_min, float t_trace, const uint32_t *beams, int64_t n_beams, uint32_t *node_visits,
                     uint32_t *tri_tests, uint32_t *leaf_visits, float *t_hit, uint32_t *tri_orig,
-                    uint8_t *node_touched, uint8_t *rec_touched) {
+                    uint8_t *node_touched, uint8_t *rec_touched, uint64_t *leaf_steps) {
     const double deg = 3.14159265358979323846 / 180.0;
     double w = q[0], x = q[1], y = q[2], z = q[3];
     double n = sqrt(w * w + x * x + y * y + z * z);
@@ -262,7 +265,8 @@ int64_t walk_replay(const void *nodes, const void *recs, uint32_t root, const do
         r.o[2] = p[2];
         ray_setup(&r);
         if (walk((const slot_t *)nodes, (const rec_t *)recs, root, &r, t_lo, t_trace, node_visits + k,
-                 tri_tests + k, leaf_visits + k, t_hit + k, tri_orig + k, node_touched, rec_touched) != 0) {
+                 tri_tests + k, leaf_visits + k, t_hit + k, tri_orig + k, node_touched, rec_touched,
+                 leaf_steps ? leaf_steps + 2 * k : NULL) != 0) {
             node_visits[k] = tri_tests[k] = leaf_visits[k] = 0;
             t_hit[k] = 0.0f;
             tri_orig[k] = NONE;

@@ -36,13 +36,13 @@ def _load():
         P = C.c_void_p
         lib.walk_replay.restype = C.c_int64
         lib.walk_replay.argtypes = [P, P, C.c_uint32, P, C.c_uint32, C.c_uint32, C.c_double, C.c_double, P, P,
-                                    C.c_float, C.c_float, P, C.c_int64, P, P, P, P, P, P, P]
+                                    C.c_float, C.c_float, P, C.c_int64, P, P, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
 
 def replay(nodes: np.ndarray, recs: np.ndarray, root: int, sensor, pose_p, pose_q, t_min: float, t_trace: float,
-           beams=None, touched: bool = False) -> dict:
+           beams=None, touched: bool = False, step_kinds: bool = False) -> dict:
     """Replays the walk for `beams` (default: every beam of the scan) of `sensor` (elev_deg, n_az, az0_deg,
     fov_h_deg) at pose (p, q).  nodes / recs: the device tree's bytes.  Returns dict of per-beam arrays:
     node_visits, tri_tests, leaf_visits (uint32), t (float32), orig (uint32), and the count of beams not
@@ -62,14 +62,18 @@ def replay(nodes: np.ndarray, recs: np.ndarray, root: int, sensor, pose_p, pose_
                leaf_visits=np.zeros(n, np.uint32), t=np.zeros(n, np.float32), orig=np.zeros(n, np.uint32))
     nt_, nr_ = (nodes.size // 128, recs.size // 48) if touched else (0, 0)
     node_t, rec_t = np.zeros(nt_, np.uint8), np.zeros(nr_, np.uint8)
+    kinds = np.zeros((n, 2), np.uint64) if step_kinds else None
     bad = lib.walk_replay(nodes.ctypes.data, recs.ctypes.data, int(root), elev.ctypes.data, n_ch, int(sensor.n_az),
                           float(sensor.az0_deg), float(sensor.fov_h_deg), q.ctypes.data, p.ctypes.data,
                           float(t_min), float(t_trace), beams.ctypes.data, n, out["node_visits"].ctypes.data,
                           out["tri_tests"].ctypes.data, out["leaf_visits"].ctypes.data, out["t"].ctypes.data,
                           out["orig"].ctypes.data,
-                          node_t.ctypes.data if touched else None, rec_t.ctypes.data if touched else None)
+                          node_t.ctypes.data if touched else None, rec_t.ctypes.data if touched else None,
+                          kinds.ctypes.data if step_kinds else None)
     out["beams"] = beams
     out["not_replayed"] = int(bad)
+    if step_kinds:
+        out["leaf_steps"] = kinds          # bit i of word i // 64: step i is a leaf
     if touched:
         out["nodes_touched"] = int(node_t.sum(dtype=np.int64))
         out["records_touched"] = int(rec_t.sum(dtype=np.int64))
