@@ -82,7 +82,6 @@ struct lidar_ctx {
     bool has_sensor = false;
     SensorHost sensor;
     DevBuf sensor_tables;   // elev_cs then az_cs
-    DevBuf sweep_poses;     // [n_az][12] FP64 poses of a tick's fired columns
     DevBuf adj_partials;
     // pose
     float p[3] = {0, 0, 0};
@@ -263,7 +262,8 @@ InstanceDev make_instance(const lidar_ctx *ctx, int tile_az_log2, const lidar_se
     in.seed_hi = (uint32_t)(seed >> 32);
     in.scan = scan;
     in.inst_id = inst_id;
-    in.col_pose = nullptr;
+    in.sweep = 0;
+    in.sw = SweepDev{};
     in.n_cols = d.n_az;
     in.seg_n0 = d.n_az;
     in.seg_i0[0] = in.seg_i0[1] = 0;
@@ -365,7 +365,6 @@ lidar_status lidar_destroy(lidar_ctx *ctx) {
     hipDeviceSynchronize();
     ctx->mat_buf.release();
     ctx->sensor_tables.release();
-    ctx->sweep_poses.release();
     ctx->adj_partials.release();
     ctx->mesh_table.release();
     if (ctx->staging) hipHostFree(ctx->staging);
@@ -544,8 +543,6 @@ lidar_status lidar_sensor_set(lidar_ctx *ctx, const lidar_sensor_desc *d) {
     double *elev_deg = az_cs + 2 * (size_t)d->n_az;
     if ((e = hipMemcpy(elev_deg, d->elev_deg, 8 * (size_t)d->n_ch, hipMemcpyHostToDevice)) != hipSuccess)
         return ctx->hip_fail(e, "sensor upload");
-    if ((e = ctx->sweep_poses.ensure(96 * (size_t)d->n_az)) != hipSuccess)
-        return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "sweep pose table allocation failed");
     launch_dir_tables(elev_deg, d->n_ch, d->az0_deg, d->fov_h_deg, d->n_az, elev_cs, az_cs, 0);
     if ((e = hipDeviceSynchronize()) != hipSuccess) return ctx->hip_fail(e, "direction tables");
     ctx->sensor.d = *d;
@@ -701,6 +698,47 @@ lidar_status lidar_compact_points_noalloc(lidar_ctx *ctx, const lidar_outputs *d
 // ---------------------------------------------------------------------------
 // partial sweep per engine tick
 // ---------------------------------------------------------------------------
+// The parts of a tick's column poses shared by all its columns (see SweepDev):
+// the end quaternions as given and normalised, qb turned to qa's hemisphere,
+// and the arc between them.
+static SweepDev sweep_dev(double a, double b, const lidar_sensor_desc &d, const lidar_sweep_desc *sw) {
+    SweepDev S{};
+    S.a = a;
+    S.b = b;
+    S.az0 = d.az0_deg;
+    S.step = d.fov_h_deg / (double)d.n_az;
+    double na = 0.0, nb = 0.0;
+    for (int e = 0; e < 4; ++e) {
+        S.qa[e] = sw->q_begin[e];
+        S.qb[e] = sw->q_end[e];
+        na += S.qa[e] * S.qa[e];
+        nb += S.qb[e] * S.qb[e];
+    }
+    na = std::sqrt(na);
+    nb = std::sqrt(nb);
+    double dot = 0.0;
+    for (int e = 0; e < 4; ++e) {
+        S.ua[e] = S.qa[e] / na;
+        S.ub[e] = S.qb[e] / nb;
+        dot += S.ua[e] * S.ub[e];
+    }
+    if (dot < 0.0) {
+        for (int e = 0; e < 4; ++e) {
+            S.qb[e] = -S.qb[e];
+            S.ub[e] = -S.ub[e];
+        }
+        dot = -dot;
+    }
+    S.w = std::acos(std::fmin(dot, 1.0));
+    S.chord = S.w < 1e-6 ? 1u : 0u;
+    S.inv_sin_w = S.chord ? 0.0 : 1.0 / std::sin(S.w);
+    for (int e = 0; e < 3; ++e) {
+        S.pa[e] = sw->p_begin[e];
+        S.pb[e] = sw->p_end[e];
+    }
+    return S;
+}
+
 lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, const lidar_outputs *out,
                                   lidar_sweep_info *info, void *stream) {
     lidar_status st = ready(ctx, true);
@@ -752,28 +790,12 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sw, co
     if (n_cols == 0) return ok;
     hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
-    SweepPoseArgs A{};
-    A.a = a;
-    A.b = b;
-    A.az0 = d.az0_deg;
-    A.fov = d.fov_h_deg;
-    A.n_az = d.n_az;
-    A.n_cols = n_cols;
-    A.seg_n0 = run_count[0];
-    A.scan0 = run_scan[0];
-    A.seg_i0[0] = run_first[0];
-    A.seg_i0[1] = run_first[1];
-    std::memcpy(A.pa, sw->p_begin, 12);
-    std::memcpy(A.qa, sw->q_begin, 16);
-    std::memcpy(A.pb, sw->p_end, 12);
-    std::memcpy(A.qb, sw->q_end, 16);
-    double *poses = (double *)ctx->sweep_poses.p;
-    launch_sweep_poses(A, poses, s);
     const double *elev_cs = (const double *)ctx->sensor_tables.p;
     const double *az_cs = elev_cs + 2 * (size_t)d.n_ch;
     InstanceDev in = make_instance(ctx, ctx->tile_log2(), d, elev_cs, az_cs, sw->p_begin, sw->q_begin, sw->seed,
                                    run_scan[0], 0, 0, 0);
-    in.col_pose = poses;
+    in.sweep = 1;
+    in.sw = sweep_dev(a, b, d, sw);
     in.n_cols = n_cols;
     in.seg_n0 = run_count[0];
     in.seg_i0[0] = run_first[0];

@@ -53,6 +53,20 @@ __device__ inline uint32_t leaf_count(uint32_t ref) { return (ref & 7u) + 1u; }
 // Direction tables are FP64: cos/sin of the channel elevations and of the
 // azimuth steps, computed on the device from the data-sheet angles.
 // ---------------------------------------------------------------------------
+// The parts of a partial sweep's column poses that are the same for every
+// column of the tick (computed on the host): the head-angle window [a, b)
+// (degrees), az0 and the azimuth step, the two end quaternions as given (qa,
+// qb: the chord) and normalised with qb turned to the same hemisphere as qa
+// (ua, ub), the arc w between them and 1 / sin(w), and the end positions.
+struct SweepDev {
+    double a, b, az0, step;
+    double qa[4], qb[4], ua[4], ub[4];
+    double w, inv_sin_w;
+    float pa[3], pb[3];
+    uint32_t chord;            // w < 1e-6: interpolate along the chord
+    uint32_t pad_;
+};
+
 struct InstanceDev {
     const double *elev_cs;     // [2*n_ch]: cos phi_j, sin phi_j interleaved
     const double *az_cs;       // [2*n_az]: cos theta_i, sin theta_i interleaved
@@ -69,12 +83,13 @@ struct InstanceDev {
     // Columns traced by the launch.  A scan traces all n_az columns with one
     // pose.  A partial sweep (one engine tick) traces n_cols fired columns in
     // at most two runs: columns k < seg_n0 are azimuth seg_i0[0] + k of scan
-    // `scan`, the rest azimuth seg_i0[1] + (k - seg_n0) of scan + 1; column k
-    // takes the FP64 pose col_pose[12 k ..] (R row-major, then p).
-    const double *col_pose;    // null for a scan
+    // `scan`, the rest azimuth seg_i0[1] + (k - seg_n0) of scan + 1; each
+    // column takes the pose of its own firing time (sweep_pose).
+    uint32_t sweep;            // 0 for a scan
     uint32_t n_cols;
     uint32_t seg_n0;
     uint32_t seg_i0[2];
+    SweepDev sw;
 };
 
 // ---------------------------------------------------------------------------
@@ -208,17 +223,35 @@ __device__ inline uint32_t column_azimuth(const InstanceDev &in, uint32_t k, uin
     return in.seg_i0[1] + (k - in.seg_n0);
 }
 
+// Pose of column (scan s, azimuth i) of a partial sweep.  The column fires
+// when the head reaches A = 360 s + az0 + i step, at the fraction
+// tau = (A - a) / (b - a) of the tick.  The position moves linearly, the
+// orientation along the great arc between the two quaternions (slerp,
+// Shoemake 1985), or along the chord below an arc of 1e-6 rad, so that equal
+// end poses give exactly the scan pose.
+__device__ inline Pose64 sweep_pose(const SweepDev &S, uint32_t s, uint32_t i) {
+    const double ang = 360.0 * (double)s + (S.az0 + (double)i * S.step);
+    const double tau = (ang - S.a) / (S.b - S.a);
+    double q[4];
+    if (S.chord) {
+        for (int e = 0; e < 4; ++e) q[e] = S.qa[e] + tau * (S.qb[e] - S.qa[e]);
+    } else {
+        const double ca = sin((1.0 - tau) * S.w) * S.inv_sin_w, cb = sin(tau * S.w) * S.inv_sin_w;
+        for (int e = 0; e < 4; ++e) q[e] = ca * S.ua[e] + cb * S.ub[e];
+    }
+    Pose64 P;
+    quat_to_rot(q, P.R);
+    for (int e = 0; e < 3; ++e) P.p[e] = (double)S.pa[e] + tau * ((double)S.pb[e] - (double)S.pa[e]);
+    return P;
+}
+
 // Pose of column k: the scan pose (with the calibration delta), or the
 // per-column pose of a partial sweep.
 __device__ inline Pose64 column_pose(const InstanceDev &in, const float *pose_delta, uint32_t k) {
-    if (!in.col_pose) return make_pose(in, pose_delta);
-    const double *c = in.col_pose + 12 * (size_t)k;
-    Pose64 P;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) P.R[e] = c[e];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) P.p[e] = c[9 + e];
-    return P;
+    if (!in.sweep) return make_pose(in, pose_delta);
+    uint32_t s;
+    const uint32_t i = column_azimuth(in, k, s);
+    return sweep_pose(in.sw, s, i);
 }
 
 // Beam (j, i) -> sensor-frame direction s (FP64 then rounded once) and world

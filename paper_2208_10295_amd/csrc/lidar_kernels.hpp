@@ -77,16 +77,6 @@ struct TraceOpts {
 void launch_dir_tables(const double *elev_deg, uint32_t n_ch, double az0_deg, double fov_h_deg,
                        uint32_t n_az, double *elev_cs, double *az_cs, hipStream_t s);
 
-// Partial sweep: the tick's head-angle window [a, b) (degrees), the fired
-// columns (two runs as in InstanceDev) and the poses at the tick's two ends.
-struct SweepPoseArgs {
-    double a, b, az0, fov;
-    uint32_t n_az, n_cols, seg_n0, scan0;
-    uint32_t seg_i0[2];
-    float pa[3], qa[4], pb[3], qb[4];
-};
-// writes 12 doubles (R row-major, p) per fired column to `out`
-void launch_sweep_poses(const SweepPoseArgs &A, double *out, hipStream_t s);
 // n_nodes / n_tris: optional per-beam traversal counts (null = plain kernel);
 // actors: the dynamic part of the scene, or null
 void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,

@@ -76,72 +76,6 @@ void launch_dir_tables(const double *elev_deg, uint32_t n_ch, double az0_deg, do
 }
 
 // ---------------------------------------------------------------------------
-// Partial sweep of one engine tick (Section II-A renders only the part of the
-// horizontal FOV swept since the previous tick): the pose of every fired
-// column at its firing time.  Column (scan s, azimuth i) fires when the head
-// reaches A = 360 s + (az0 + i FOV_h / N_az); over the tick's window [a, b)
-// that is the fraction tau = (A - a) / (b - a).  The position moves linearly,
-// the orientation along the great arc between the two quaternions (slerp,
-// Shoemake 1985), and along the chord below an arc of 1e-6 rad, so that equal
-// end poses give exactly the scan pose.
-// ---------------------------------------------------------------------------
-__global__ void sweep_pose_kernel(SweepPoseArgs A, double *__restrict__ out) {
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.n_cols) return;
-    uint32_t s, i;
-    if (k < A.seg_n0) {
-        s = A.scan0;
-        i = A.seg_i0[0] + k;
-    } else {
-        s = A.scan0 + 1u;
-        i = A.seg_i0[1] + (k - A.seg_n0);
-    }
-    double ang = 360.0 * (double)s + (A.az0 + (double)i * (A.fov / (double)A.n_az));
-    double tau = (ang - A.a) / (A.b - A.a);
-    double qa[4], qb[4], ua[4], ub[4];
-    double na = 0.0, nb = 0.0;
-    for (int e = 0; e < 4; ++e) {
-        qa[e] = A.qa[e];
-        qb[e] = A.qb[e];
-        na += qa[e] * qa[e];
-        nb += qb[e] * qb[e];
-    }
-    na = sqrt(na);
-    nb = sqrt(nb);
-    double dot = 0.0;
-    for (int e = 0; e < 4; ++e) {
-        ua[e] = qa[e] / na;
-        ub[e] = qb[e] / nb;
-        dot += ua[e] * ub[e];
-    }
-    if (dot < 0.0) {
-        for (int e = 0; e < 4; ++e) {
-            qb[e] = -qb[e];
-            ub[e] = -ub[e];
-        }
-        dot = -dot;
-    }
-    double w = acos(fmin(dot, 1.0));
-    double q[4];
-    if (w < 1e-6) {
-        for (int e = 0; e < 4; ++e) q[e] = qa[e] + tau * (qb[e] - qa[e]);
-    } else {
-        double sw = sin(w);
-        double ca = sin((1.0 - tau) * w) / sw, cb = sin(tau * w) / sw;
-        for (int e = 0; e < 4; ++e) q[e] = ca * ua[e] + cb * ub[e];
-    }
-    double R[9];
-    quat_to_rot(q, R);
-    double *o = out + 12 * (size_t)k;
-    for (int e = 0; e < 9; ++e) o[e] = R[e];
-    for (int e = 0; e < 3; ++e) o[9 + e] = (double)A.pa[e] + tau * ((double)A.pb[e] - (double)A.pa[e]);
-}
-
-void launch_sweep_poses(const SweepPoseArgs &A, double *out, hipStream_t s) {
-    sweep_pose_kernel<<<(A.n_cols + 127) / 128, 128, 0, s>>>(A, out);
-}
-
-// ---------------------------------------------------------------------------
 // common pieces
 // ---------------------------------------------------------------------------
 struct Hit {
@@ -784,6 +718,7 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
                              uint32_t *__restrict__ n_nodes, uint32_t *__restrict__ n_tris, ActorsDev A) {
     constexpr int NR = BLOCK / LANES;
     static_assert(NR == 64, "one 64-beam tile per block; its epilogue runs in the first wavefront");
+    static_assert(STACK + kStackPad > 6, "the epilogue's directions are handed over in stack entries 1..6");
     __shared__ uint32_t stk[(STACK + kStackPad) * NR];
     __shared__ double pose[12];
     // hits of the block's beams, handed from the walking lanes to the epilogue wavefront:
@@ -807,6 +742,14 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
         if constexpr (ACTORS) traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
         if (overflow) atomicOr(err, 1u);
         if (s == 0) {
+            // the beam's direction, world and sensor frame, for the epilogue: entries 1..6 of the beam's
+            // stack, free once its walks are done
+            stk[1 * NR + q] = __float_as_uint(ray.dx);
+            stk[2 * NR + q] = __float_as_uint(ray.dy);
+            stk[3 * NR + q] = __float_as_uint(ray.dz);
+            stk[4 * NR + q] = __float_as_uint(ray.sx);
+            stk[5 * NR + q] = __float_as_uint(ray.sy);
+            stk[6 * NR + q] = __float_as_uint(ray.sz);
             if (COUNT) {
                 const uint32_t beam = j * in.n_az + i;
                 n_nodes[beam] = c.nodes;
@@ -828,7 +771,20 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
     j = hand[0][e] >> 20;
     k = hand[0][e] & 0xFFFFFu;
     uint32_t i, scan;
-    const Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
+    if (SWEEP) {
+        i = column_azimuth(in, k, scan);
+    } else {
+        i = k;
+        scan = in.scan;
+    }
+    Ray ray;   // shading uses the beam's directions only
+    ray.ox = ray.oy = ray.oz = 0.0f;
+    ray.dx = __uint_as_float(stk[1 * NR + e]);
+    ray.dy = __uint_as_float(stk[2 * NR + e]);
+    ray.dz = __uint_as_float(stk[3 * NR + e]);
+    ray.sx = __uint_as_float(stk[4 * NR + e]);
+    ray.sy = __uint_as_float(stk[5 * NR + e]);
+    ray.sz = __uint_as_float(stk[6 * NR + e]);
     const Hit h{hand[1][e], hand[2][e], __uint_as_float(hand[3][e]), hand[4][e]};
     const ActorDev *act = nullptr;
     const TriRec *tris = S.tris;
@@ -1238,7 +1194,7 @@ template <int STACK>
 static void launch_scan_s(const TraceOpts &t, const SceneDev &S, const InstanceDev &in, const MaterialsDev &M,
                           const Overrides &ov, const Outputs &out, uint64_t n_padded, uint32_t *err,
                           uint32_t *nn, uint32_t *nt, const ActorsDev *A, hipStream_t s) {
-    const bool sweep = in.col_pose != nullptr;
+    const bool sweep = in.sweep != 0;
     const ActorsDev none{};
     if (A) {   // dynamic scene (never counted)
         if (sweep) launch_scan_t<STACK, false, true, true>(t, S, in, M, ov, out, n_padded, err, nullptr, nullptr, *A, s);
