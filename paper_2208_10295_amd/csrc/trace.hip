@@ -741,7 +741,7 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
             min(S.stack_cap, STACK));
         if constexpr (ACTORS) traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
         if (overflow) atomicOr(err, 1u);
-        if (s == 0) {
+        if (SWEEP && s == 0) {
             // the beam's direction, world and sensor frame, for the epilogue: entries 1..6 of the beam's
             // stack, free once its walks are done
             stk[1 * NR + q] = __float_as_uint(ray.dx);
@@ -750,6 +750,8 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
             stk[4 * NR + q] = __float_as_uint(ray.sx);
             stk[5 * NR + q] = __float_as_uint(ray.sy);
             stk[6 * NR + q] = __float_as_uint(ray.sz);
+        }
+        if (s == 0) {
             if (COUNT) {
                 const uint32_t beam = j * in.n_az + i;
                 n_nodes[beam] = c.nodes;
@@ -771,20 +773,19 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
     j = hand[0][e] >> 20;
     k = hand[0][e] & 0xFFFFFu;
     uint32_t i, scan;
+    Ray ray;
     if (SWEEP) {
         i = column_azimuth(in, k, scan);
+        ray.ox = ray.oy = ray.oz = 0.0f;   // shading uses the beam's directions only
+        ray.dx = __uint_as_float(stk[1 * NR + e]);
+        ray.dy = __uint_as_float(stk[2 * NR + e]);
+        ray.dz = __uint_as_float(stk[3 * NR + e]);
+        ray.sx = __uint_as_float(stk[4 * NR + e]);
+        ray.sy = __uint_as_float(stk[5 * NR + e]);
+        ray.sz = __uint_as_float(stk[6 * NR + e]);
     } else {
-        i = k;
-        scan = in.scan;
+        ray = beam_ray_lds<false>(in, pose, j, k, i, scan);
     }
-    Ray ray;   // shading uses the beam's directions only
-    ray.ox = ray.oy = ray.oz = 0.0f;
-    ray.dx = __uint_as_float(stk[1 * NR + e]);
-    ray.dy = __uint_as_float(stk[2 * NR + e]);
-    ray.dz = __uint_as_float(stk[3 * NR + e]);
-    ray.sx = __uint_as_float(stk[4 * NR + e]);
-    ray.sy = __uint_as_float(stk[5 * NR + e]);
-    ray.sz = __uint_as_float(stk[6 * NR + e]);
     const Hit h{hand[1][e], hand[2][e], __uint_as_float(hand[3][e]), hand[4][e]};
     const ActorDev *act = nullptr;
     const TriRec *tris = S.tris;
