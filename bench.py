@@ -318,7 +318,7 @@ def main():
         # measured memory roofs beside the published HBM peak: a 2 GiB streaming read, and 128-byte line
         # fetches by quads (one quad per beam, the scan's launch shape), each quad a dependent chain like a
         # walk, over working sets that fit one CU's L1 (16 KiB), one XCD's L2 (2 MiB), the MALL (64 MiB)
-        # or only HBM (1 GiB)
+        # or only HBM (1 GiB), and over a working set the size of the scene's tree and records
         sink = torch.zeros(1, dtype=torch.float32, device=ctx.device)
         big = torch.randint(-2**31, 2**31 - 1, (512 << 20,), dtype=torch.int32, device=ctx.device)
         stream_run = L.probe_stream_launcher(big, sink)
@@ -329,7 +329,9 @@ def main():
         roofs = {"hbm_stream_read_gbs": stream_gbs, "stream_bytes": 2 << 30,
                  "gather_launch": f"{blocks} blocks x 256 threads (one quad per beam of the scan), {steps} dependent "
                                   "128-B lines per quad, 32 B per lane, line indices uniform over the working set"}
-        for level, ws in (("l1", 16 << 10), ("l2", 2 << 20), ("mall", 64 << 20), ("hbm", 1 << 30)):
+        scene_ws = (int(st["node_bytes"] + st["tri_bytes"]) + 127) // 128 * 128
+        for level, ws in (("l1", 16 << 10), ("l2", 2 << 20), ("mall", 64 << 20), ("hbm", 1 << 30),
+                          ("scene", scene_ws)):
             run = L.probe_gather_launcher(big[: ws // 4], blocks, steps, True, sink)
             run()
             _, g_ms = timed_region(run, 20, torch)
@@ -340,12 +342,13 @@ def main():
             a = result["traversal"]["alg_gbs"]
             roofs["scan_alg_gbs"] = a
             roofs["scan_over_stream"] = a / stream_gbs
-            for level in ("l1", "l2", "mall", "hbm"):
+            for level in ("l1", "l2", "mall", "hbm", "scene"):
                 roofs[f"scan_over_gather_{level}"] = a / roofs[f"gather_{level}_gbs"]
         result["roofs"] = roofs
         log("roofs: HBM stream read {:.0f} GB/s; dependent 128-B line gathers: L1 {:.0f}, L2 {:.0f}, MALL {:.0f}, "
-            "HBM {:.0f} GB/s".format(stream_gbs, roofs["gather_l1_gbs"], roofs["gather_l2_gbs"],
-                                     roofs["gather_mall_gbs"], roofs["gather_hbm_gbs"]))
+            "HBM {:.0f}, scene-sized ({:.1f} MB) {:.0f} GB/s".format(
+                stream_gbs, roofs["gather_l1_gbs"], roofs["gather_l2_gbs"], roofs["gather_mall_gbs"],
+                roofs["gather_hbm_gbs"], scene_ws / 1e6, roofs["gather_scene_gbs"]))
 
     if "cpu" in legs:
         log("cpu baseline (FP64 oracle) ...")
