@@ -537,18 +537,20 @@ def main():
         for k in range(min(args.warmup, n_ticks)):
             tick(k)
         fired.clear()
-        wall_s, ms_s = timed_launches(tick, n_ticks, torch)
+        wall_s, ms_s = timed_region(tick, n_ticks, torch)
         ctx.sync_check()
         rays = sensor.n_ch * sum(fired)
         assert sum(fired) == n_ticks / tick_hz * spin * sensor.n_az
+        gpu_s = ms_s * 1e-3 * n_ticks
         result["sweep"] = {"workload": "60 engine ticks at 60 Hz of a 10 Hz head (64ch x 2048, ~341 columns per "
                                        "tick) on the 522k-triangle scene, rolling-shutter poses at 10 m/s and "
                                        "10 deg/s yaw, 1 s of simulated time",
-                           "ticks": n_ticks, "rays": rays, "rays_per_s": rays / wall_s,
-                           "tick_us_mean": float(np.mean(ms_s)) * 1e3, "ticks_per_s": n_ticks / wall_s,
-                           "realtime_factor": (n_ticks / tick_hz) / wall_s}
-        log(f"sweep: {n_ticks} ticks in {wall_s * 1e3:.2f} ms ({np.mean(ms_s) * 1e3:.1f} us per tick, "
-            f"{rays / wall_s:.4g} rays/s, {(n_ticks / tick_hz) / wall_s:.0f}x real time)")
+                           "ticks": n_ticks, "rays": rays, "rays_per_s": rays / gpu_s,
+                           "tick_us_mean": ms_s * 1e3, "ticks_per_s": n_ticks / gpu_s,
+                           "realtime_factor": (n_ticks / tick_hz) / gpu_s,
+                           "wall_s": wall_s, "realtime_factor_wall": (n_ticks / tick_hz) / wall_s}
+        log(f"sweep: {n_ticks} ticks, {ms_s * 1e3:.1f} us per tick ({rays / gpu_s:.4g} rays/s, "
+            f"{(n_ticks / tick_hz) / gpu_s:.0f}x real time; host wall {wall_s * 1e3:.2f} ms)")
 
     if "echo" in legs:
         # divergent beams: 7 sub-rays in a 3 mrad cone per beam of the 64 x 2048 scan, up to 3 echoes
@@ -558,15 +560,15 @@ def main():
         for _ in range(3):
             r = ctx.simulate_echoes(seed, 0, K, E, 0.003, 0.5, out=e_out, workspace=ws)
             ws = ctx._echo_workspace
-        wall_e, ms_e = timed_launches(lambda k: ctx.simulate_echoes(seed, k, K, E, 0.003, 0.5, out=e_out,
-                                                                    workspace=ws), 50, torch)
+        wall_e, ms_e = timed_region(lambda k: ctx.simulate_echoes(seed, k, K, E, 0.003, 0.5, out=e_out,
+                                                                  workspace=ws), 50, torch)
         ctx.sync_check()
         det = [int(r["valid"][e].sum()) for e in range(E)]
         result["echo"] = {"workload": "64ch x 2048 scan of the 522k scene, 7 sub-rays per beam in a 3 mrad cone, "
                                       "echo separation 0.5 m, up to 3 echoes per beam",
-                          "ms_per_scan": float(np.mean(ms_e)), "beams_per_s": n / (float(np.mean(ms_e)) * 1e-3),
-                          "subrays_per_s": K * n / (float(np.mean(ms_e)) * 1e-3), "detected_per_echo": det}
-        log(f"echo: {np.mean(ms_e) * 1e3:.1f} us per scan ({K * n / (np.mean(ms_e) * 1e-3):.4g} sub-rays/s), "
+                          "ms_per_scan": ms_e, "beams_per_s": n / (ms_e * 1e-3),
+                          "subrays_per_s": K * n / (ms_e * 1e-3), "detected_per_echo": det}
+        log(f"echo: {ms_e * 1e3:.1f} us per scan ({K * n / (ms_e * 1e-3):.4g} sub-rays/s), "
             f"detected per echo {det}")
 
     if "dynamic" in legs:
@@ -583,24 +585,26 @@ def main():
         torch.cuda.synchronize()
         set_ms = (time.perf_counter() - t0) * 1e3
         outd = alloc_outputs(n, POINT_OUTPUTS, ctx.device)
-        ctx.simulate(seed, 0, out=outd)
+        scan_d = ctx.scan_launcher(seed, outd)
+        scan_d(0)
 
         def frame(f):
             ctx.refit_mesh(ids[3], sways[f + 1])
             ctx.update_actors(frames[f + 1])
-            ctx.simulate(seed, f, out=outd)
-        wall_d, ms_d = timed_launches(frame, n_frames, torch)
+            scan_d(f)
+        wall_d, frame_ms = timed_region(frame, n_frames, torch)
         ctx.sync_check()
-        _, scan_ms = timed_region(ctx.scan_launcher(seed, outd), 50, torch)
+        _, scan_ms = timed_region(scan_d, 50, torch)
         n_act = int((outd["label"].view(torch.int32) >= 100000).sum())
         result["dynamic"] = {
             "workload": "522k-triangle scene + 300 actors (200 cars of 408 triangles, 100 deforming pedestrians of "
                         "304 triangles) moving at 10 Hz; per frame: pedestrian mesh refit, actor BVH refit, "
                         "64ch x 2048 scan",
-            "frames": n_frames, "frame_ms_mean": float(np.mean(ms_d)), "rays_per_s_with_updates": n_frames * n / wall_d,
+            "frames": n_frames, "frame_ms_mean": frame_ms, "rays_per_s_with_updates": n / (frame_ms * 1e-3),
+            "rays_per_s_with_updates_wall": n_frames * n / wall_d,
             "scan_ms_mean": scan_ms, "rays_per_s_scan": n / (scan_ms * 1e-3),
             "actors_set_ms": set_ms, "beams_on_actors_last_frame": n_act}
-        log(f"dynamic: {np.mean(ms_d) * 1e3:.1f} us per frame (refits + scan), scan {scan_ms * 1e3:.1f} us, "
+        log(f"dynamic: {frame_ms * 1e3:.1f} us per frame (refits + scan), scan {scan_ms * 1e3:.1f} us, "
             f"actor BVH build {set_ms:.2f} ms, {n_act} beams on actors")
         ctx.clear_actors()
 
@@ -616,7 +620,7 @@ def main():
         out3 = alloc_outputs(s3.n_beams, POINT_OUTPUTS, cs.device)
         one = cs.trajectory_launcher(seed, out3, poses)
         one(0)
-        wall3, ms3 = timed_launches(one, len(poses), torch)
+        wall3, ms3 = timed_region(one, len(poses), torch)
         cs.sync_check()
         # one scan's work at the first pose, against the HBM roof: the bytes the counters measured and the
         # compulsory bytes (distinct nodes and records the scan touches, plus its outputs)
@@ -627,7 +631,8 @@ def main():
         secs3 = k3_ms * 1e-3
         result["sequence"] = {"workload": "128ch x 1024 x 100 poses at 10 Hz, 5,224,200-triangle scene, 64 materials",
                               "xcd_remap": args.seq_xcd,
-                              "rays_per_s": len(poses) * s3.n_beams / wall3, "kernel_ms_mean": float(np.mean(ms3)),
+                              "rays_per_s": s3.n_beams / (ms3 * 1e-3), "ms_per_scan": ms3,
+                              "rays_per_s_wall": len(poses) * s3.n_beams / wall3,
                               "bvh_build_ms": st3["build_ms"], "bvh_nodes": st3["n_nodes"],
                               "bvh_depth": st3["depth"],
                               "hbm": {"pose": 0, "kernel_ms": k3_ms, "traffic_bytes_per_scan": tr3,

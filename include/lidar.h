@@ -368,8 +368,8 @@ lidar_status lidar_simulate_echoes(lidar_ctx *ctx, uint64_t seed, uint32_t scan,
  * (object-space triangles with per-triangle materials) in the world with a
  * rigid transform x_world = R(q) x_object + p and gives all of the mesh's
  * triangles the actor's label.  Every mesh has its own BVH; a top-level BVH
- * over the actors' world boxes is built by lidar_actors_set and refit by
- * lidar_actors_update each frame.  The first hit is taken over the static
+ * over the actors' world boxes is built by lidar_actors_set and rebuilt or
+ * refit by lidar_actors_update each frame.  The first hit is taken over the static
  * triangles and all placed meshes as one soup, ties broken by the index in
  * the combined ordering: static triangles 0 .. n_static - 1, then the
  * triangles of actor 0, actor 1, ... (outputs.tri reports that index).
@@ -424,9 +424,11 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
                               uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes, void *stream);
 
 /* Per-frame update: the same actors (count and meshes) at new poses.  Uploads
- * the transforms through a pinned buffer, recomputes the world boxes and refits
- * the top-level BVH (no rebuild: call lidar_actors_set again when the tree has
- * degraded).  Asynchronous; waits only for the previous update's upload. */
+ * the transforms through a pinned buffer, recomputes the world boxes and
+ * rebuilds the top-level BVH in one workgroup (up to 4,096 actors, see
+ * LIDAR_OPT_ACTOR_TREE) or refits it (the builder's tree: call
+ * lidar_actors_set again when the refit tree has degraded).  Asynchronous;
+ * waits only for the previous update's upload. */
 lidar_status lidar_actors_update(lidar_ctx *ctx, const lidar_actor *actors, uint32_t n_actors, void *stream);
 
 /* Removes the actors (the workspaces are the caller's). */
@@ -501,6 +503,13 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep,
  *     share a beam, one child box each (default 4).
  *   LIDAR_OPT_XCD_REMAP: 1 = the thread blocks that run on one XCD take one
  *     contiguous azimuth sector (default 1); 0 = blocks in launch order.
+ *   LIDAR_OPT_ACTOR_TREE: 0 = up to 4,096 actors, the top-level tree is
+ *     rebuilt by lidar_actors_set and by every lidar_actors_update in one
+ *     workgroup (Morton order of the actor boxes, one actor per leaf, four
+ *     entries per node), so it stays tight as the actors move; more actors
+ *     as for 1 (default 0).  1 = the scene builder's tree, built by
+ *     lidar_actors_set and refit by lidar_actors_update.  Read by
+ *     lidar_actors_set.
  * One option exists to test error handling and does change results:
  *   LIDAR_OPT_STACK_CAP: 0 = a walk of the static scene may use the whole
  *     traversal stack sized for the tree's depth (default); n > 0 = at most n
@@ -512,6 +521,7 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep,
 #define LIDAR_OPT_LANES_PER_RAY  2u
 #define LIDAR_OPT_XCD_REMAP      3u
 #define LIDAR_OPT_STACK_CAP      4u
+#define LIDAR_OPT_ACTOR_TREE     5u
 lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value);
 
 /* ------------------------------------------------------------------------ */

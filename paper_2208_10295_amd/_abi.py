@@ -41,6 +41,7 @@ OPT_TILE_AZ = 1
 OPT_LANES_PER_RAY = 2
 OPT_XCD_REMAP = 3
 OPT_STACK_CAP = 4
+OPT_ACTOR_TREE = 5
 
 STATUS_NAMES = {
     OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_NOT_READY: "ERR_NOT_READY",

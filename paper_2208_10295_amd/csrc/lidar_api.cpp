@@ -91,11 +91,13 @@ struct lidar_ctx {
     int tile_az_log2 = -1;    // -1: automatic (tile_log2())
     int lanes_per_ray = 4;
     int xcd_remap = 1;
+    int actor_tree_opt = 0;   // LIDAR_OPT_ACTOR_TREE (0: packed rebuild up to kPackedTlasMax actors)
     // dynamic scene: meshes and the actors placing them
     std::vector<MeshHost> meshes;
     DevBuf mesh_table;        // MeshDev[kMaxMeshes]
     bool has_actors = false;
     bool tlas_stale = false;  // a mesh was refit after the actors' boxes were computed
+    bool tlas_packed = false; // the top-level tree is rebuilt by every update (else refit)
     ActorsDev A{};
     BuildResult tlas_br{};
     TriRec *tlas_recs = nullptr;
@@ -103,9 +105,17 @@ struct lidar_ctx {
     float *actor_lohi = nullptr;
     std::vector<uint32_t> actor_mesh;
     std::vector<ActorDev> actor_host;
-    ActorDev *staging = nullptr;   // pinned upload buffer of lidar_actors_update
+    // pinned, device-mapped upload buffers of lidar_actors_update: a ring of staging_slots slots of
+    // staging_n actors in two halves.  An event is recorded after the work that reads the last slot of a
+    // half, and the host waits for it before it writes the first slot of that half again: one event per
+    // half a ring instead of one per update (each event on the stream costs the GPU a few microseconds).
+    ActorDev *staging = nullptr;
+    const ActorDev *staging_dev = nullptr;
     size_t staging_n = 0;
-    hipEvent_t staging_ev = nullptr;
+    uint32_t staging_slots = 0;
+    uint64_t staging_next = 0;
+    hipStream_t staging_stream = nullptr;
+    hipEvent_t staging_ev[2] = {nullptr, nullptr};
     int actor_stack = 0;
     float actor_reach_need = 0.f;   // twice the largest coordinate of any placed mesh
     // generations: bumped when the scene (or its stack cap) or the materials change, so that a
@@ -368,7 +378,8 @@ lidar_status lidar_destroy(lidar_ctx *ctx) {
     ctx->adj_partials.release();
     ctx->mesh_table.release();
     if (ctx->staging) hipHostFree(ctx->staging);
-    if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
+    for (hipEvent_t ev : ctx->staging_ev)
+        if (ev) hipEventDestroy(ev);
     ctx->words.release();
     delete ctx;
     return LIDAR_OK;
@@ -1068,38 +1079,70 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
     hipError_t e;
     if ((e = hipMemcpyAsync(ad, h.data(), sizeof(ActorDev) * n, hipMemcpyHostToDevice, s)) != hipSuccess)
         return ctx->hip_fail(e, "actor upload");
-    actor_boxes(ad, n_actors, (const MeshDev *)ctx->mesh_table.p, lohi, ctx->refit_word(), s);
-    actor_prims(lohi, n_actors, vtx, idx, mat, s);
-    BuildInputs in{};
-    in.vtx = vtx;
-    in.idx = idx;
-    in.mat = mat;
-    in.label = nullptr;
-    in.nv = 2 * n;
-    in.nt = n_actors;
-    in.leaf_width = 4;
-    in.builder = 0;
-    in.ploc_radius = 32;
-    set_collapse(in, 0u);
-    in.reach = ctx->br.max_abs;     // rays start in the static scene's cube
+    const bool packed = ctx->actor_tree_opt == 0 && n_actors <= kPackedTlasMax;
     BuildResult br{};
-    if ((e = build_bvh(in, persistent, scratch, br, s)) != hipSuccess) return ctx->hip_fail(e, "actor BVH build");
+    if (packed) {
+        br = packed_tlas_shape(n_actors, ctx->br.max_abs);    // rays start in the static scene's cube
+        rebuild_tlas(ad, ad, n_actors, (const MeshDev *)ctx->mesh_table.p, (uint32_t)ctx->meshes.size(), lohi,
+                     (Node4 *)P, (TriRec *)(P + persistent_nodes_bytes(n_actors)), br, s);
+        if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+            return ctx->hip_fail(e, "actor BVH build");
+    } else {
+        actor_boxes(ad, n_actors, (const MeshDev *)ctx->mesh_table.p, lohi, ctx->refit_word(), s);
+        actor_prims(lohi, n_actors, vtx, idx, mat, s);
+        BuildInputs in{};
+        in.vtx = vtx;
+        in.idx = idx;
+        in.mat = mat;
+        in.label = nullptr;
+        in.nv = 2 * n;
+        in.nt = n_actors;
+        in.leaf_width = 4;
+        in.builder = 0;
+        in.ploc_radius = 32;
+        set_collapse(in, 0u);
+        in.reach = ctx->br.max_abs;     // rays start in the static scene's cube
+        if ((e = build_bvh(in, persistent, scratch, br, s)) != hipSuccess) return ctx->hip_fail(e, "actor BVH build");
+    }
     if (!refit_supported(br)) return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "actor BVH too deep");
     int mesh_need = 0;
     for (const ActorDev &d : h) mesh_need = std::max(mesh_need, entries_for_depth(ctx->meshes[d.mesh].br.depth));
     const int stack = stack_for_need(entries_for_depth(br.depth) + mesh_need);
     if (stack < 0) return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "actor and mesh BVHs too deep for the traversal stack");
-    if (ctx->staging_n < n_actors) {
+    const uint32_t slots = n_actors <= kPackedTlasMax ? 8u : 2u;
+    if (ctx->staging_stream && ctx->staging_stream != s &&
+        (e = hipStreamSynchronize(ctx->staging_stream)) != hipSuccess)
+        return ctx->hip_fail(e, "staging wait");
+    if (ctx->staging_n < n_actors || ctx->staging_slots != slots) {
+        for (hipEvent_t ev : ctx->staging_ev)
+            if (ev && (e = hipEventSynchronize(ev)) != hipSuccess) return ctx->hip_fail(e, "staging wait");
+        if (ctx->staging_stream && (e = hipStreamSynchronize(ctx->staging_stream)) != hipSuccess)
+            return ctx->hip_fail(e, "staging wait");
         if (ctx->staging) hipHostFree(ctx->staging);
         ctx->staging = nullptr;
+        ctx->staging_dev = nullptr;
         ctx->staging_n = 0;
-        if ((e = hipHostMalloc((void **)&ctx->staging, sizeof(ActorDev) * n)) != hipSuccess)
+        ctx->staging_slots = 0;
+        void *dev = nullptr;
+        if ((e = hipHostMalloc((void **)&ctx->staging, slots * sizeof(ActorDev) * n,
+                               hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
             return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "pinned staging allocation failed");
+        if ((e = hipHostGetDevicePointer(&dev, ctx->staging, 0)) != hipSuccess) {
+            hipHostFree(ctx->staging);
+            ctx->staging = nullptr;
+            return ctx->hip_fail(e, "staging mapping");
+        }
+        ctx->staging_dev = (const ActorDev *)dev;
         ctx->staging_n = n_actors;
+        ctx->staging_slots = slots;
     }
-    if (!ctx->staging_ev && (e = hipEventCreateWithFlags(&ctx->staging_ev, hipEventDisableTiming)) != hipSuccess)
-        return ctx->hip_fail(e, "event");
-    if ((e = hipEventRecord(ctx->staging_ev, s)) != hipSuccess) return ctx->hip_fail(e, "event record");
+    for (hipEvent_t &ev : ctx->staging_ev) {
+        if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+            return ctx->hip_fail(e, "event");
+        if ((e = hipEventRecord(ev, s)) != hipSuccess) return ctx->hip_fail(e, "event record");
+    }
+    ctx->staging_next = 0;
+    ctx->staging_stream = s;
     ctx->tlas_br = br;
     ctx->tlas_recs = (TriRec *)(P + persistent_nodes_bytes(n_actors));
     ctx->actors_dev = ad;
@@ -1116,6 +1159,7 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
     ctx->actor_reach_need = 0.f;
     for (const ActorDev &d : h) ctx->actor_reach_need = std::max(ctx->actor_reach_need, 2.f * ctx->meshes[d.mesh].br.max_abs);
     ctx->tlas_stale = false;
+    ctx->tlas_packed = packed;
     ctx->has_actors = true;
     return LIDAR_OK;
 }
@@ -1133,15 +1177,33 @@ lidar_status lidar_actors_update(lidar_ctx *ctx, const lidar_actor *actors, uint
     hipSetDevice(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
-    if ((e = hipEventSynchronize(ctx->staging_ev)) != hipSuccess) return ctx->hip_fail(e, "staging wait");
-    std::memcpy(ctx->staging, ctx->actor_host.data(), sizeof(ActorDev) * n_actors);
-    if ((e = hipMemcpyAsync(ctx->actors_dev, ctx->staging, sizeof(ActorDev) * n_actors, hipMemcpyHostToDevice, s)) !=
-            hipSuccess ||
-        (e = hipEventRecord(ctx->staging_ev, s)) != hipSuccess)
-        return ctx->hip_fail(e, "actor upload");
-    update_tlas(ctx->actors_dev, n_actors, (const MeshDev *)ctx->mesh_table.p, ctx->actor_lohi, (Node4 *)ctx->A.nodes,
-                ctx->tlas_recs, ctx->tlas_br, ctx->refit_word(), s);
+    const uint32_t per_half = ctx->staging_slots / 2;
+    const uint32_t slot = (uint32_t)(ctx->staging_next % ctx->staging_slots), half = slot / per_half;
+    if (s != ctx->staging_stream) {
+        // the events cover one stream's work: let the previous stream finish before switching
+        if ((e = hipStreamSynchronize(ctx->staging_stream)) != hipSuccess) return ctx->hip_fail(e, "staging wait");
+        ctx->staging_stream = s;
+    }
+    if (slot % per_half == 0 && (e = hipEventSynchronize(ctx->staging_ev[half])) != hipSuccess)
+        return ctx->hip_fail(e, "staging wait");
+    ActorDev *host = ctx->staging + (size_t)slot * ctx->staging_n;
+    std::memcpy(host, ctx->actor_host.data(), sizeof(ActorDev) * n_actors);
+    if (ctx->tlas_packed) {
+        // the rebuild reads the transforms from the mapped buffer itself: no copy on another engine
+        rebuild_tlas(ctx->staging_dev + (size_t)slot * ctx->staging_n, ctx->actors_dev, n_actors,
+                     (const MeshDev *)ctx->mesh_table.p, (uint32_t)ctx->meshes.size(), ctx->actor_lohi,
+                     (Node4 *)ctx->A.nodes, ctx->tlas_recs, ctx->tlas_br, s);
+    } else {
+        if ((e = hipMemcpyAsync(ctx->actors_dev, host, sizeof(ActorDev) * n_actors, hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return ctx->hip_fail(e, "actor upload");
+        update_tlas(ctx->actors_dev, n_actors, (const MeshDev *)ctx->mesh_table.p, ctx->actor_lohi,
+                    (Node4 *)ctx->A.nodes, ctx->tlas_recs, ctx->tlas_br, ctx->refit_word(), s);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return ctx->hip_fail(e, "actor update");
+    if (slot % per_half == per_half - 1 && (e = hipEventRecord(ctx->staging_ev[half], s)) != hipSuccess)
+        return ctx->hip_fail(e, "event record");
+    ++ctx->staging_next;
     ctx->tlas_stale = false;
     return LIDAR_OK;
 }
@@ -1150,6 +1212,7 @@ lidar_status lidar_actors_clear(lidar_ctx *ctx) {
     if (!ctx) return LIDAR_ERR_INVALID_ARG;
     ctx->has_actors = false;
     ctx->tlas_stale = false;
+    ctx->tlas_packed = false;
     ctx->A = ActorsDev{};
     ctx->actor_mesh.clear();
     return LIDAR_OK;
@@ -1515,6 +1578,10 @@ lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
     case LIDAR_OPT_XCD_REMAP:
         if (value != 0 && value != 1) return ctx->fail(LIDAR_ERR_INVALID_ARG, "xcd remap must be 0 or 1");
         ctx->xcd_remap = value;
+        return LIDAR_OK;
+    case LIDAR_OPT_ACTOR_TREE:
+        if (value != 0 && value != 1) return ctx->fail(LIDAR_ERR_INVALID_ARG, "actor tree must be 0 or 1");
+        ctx->actor_tree_opt = value;
         return LIDAR_OK;
     case LIDAR_OPT_STACK_CAP:
         if (value < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "stack cap must be >= 0");

@@ -123,6 +123,14 @@ void update_tlas(const ActorDev *actors, uint32_t n, const MeshDev *meshes, floa
                  TriRec *recs, const BuildResult &br, uint32_t *word, hipStream_t s);
 void refit_tlas(Node4 *nodes, TriRec *recs, const BuildResult &br, uint32_t n, const float *lohi, uint32_t *word,
                 hipStream_t s);
+// Top-level tree of at most kPackedTlasMax actors rebuilt in one workgroup:
+// Morton order of the actor boxes, one actor per leaf, four entries per node.
+// packed_tlas_shape gives its node levels (root 0, breadth-first) for n actors.
+constexpr uint32_t kPackedTlasMax = 4096;
+BuildResult packed_tlas_shape(uint32_t n, float reach);
+// The actors are read from src (device or host-mapped memory) and copied to actors when the two differ.
+void rebuild_tlas(const ActorDev *src, ActorDev *actors, uint32_t n, const MeshDev *meshes, uint32_t n_meshes,
+                  float *lohi, Node4 *nodes, TriRec *recs, const BuildResult &shape, hipStream_t s);
 
 // --- bandwidth probes (probe.hip) ---
 void launch_probe_stream(const void *buf, uint64_t bytes, float *sink, hipStream_t s);

@@ -292,6 +292,11 @@ class Context:
     def set_xcd_remap(self, on: bool):
         check(lib.lidar_set_option(self.h, A.OPT_XCD_REMAP, 1 if on else 0), self.h)
 
+    def set_actor_tree(self, mode: int):
+        """0: top-level tree rebuilt by every update (up to 4,096 actors); 1: builder's tree, refit by updates.
+        Read by the next set_actors."""
+        check(lib.lidar_set_option(self.h, A.OPT_ACTOR_TREE, int(mode)), self.h)
+
     def set_stack_cap(self, entries: int):
         """Limit the traversal stack of static-scene walks to `entries` (0 = no limit).  Only for testing
         the overflow path: results of walks that overflow are wrong and sync_check() raises."""

@@ -55,23 +55,95 @@ def test_dynamic_scene_matches_oracle(L, dyn):
 
 
 def test_update_refit_equals_rebuild_and_oracle(L, dyn):
-    """Moving the actors by lidar_actors_update (refit) gives the outputs of a
-    rebuild with lidar_actors_set, bit for bit, and matches the oracle."""
+    """With the builder's top-level tree, moving the actors by lidar_actors_update
+    (refit) gives the outputs of a rebuild with lidar_actors_set, bit for bit, and
+    matches the oracle."""
     ctx, cfg = dyn
     sensor = cfg["sensor"]
-    ctx.set_actors(cfg["actors_at"](0.0))
-    for t in (0.4, 1.3):
-        acts = cfg["actors_at"](t)
-        ctx.update_actors(acts)
-        a = to_np(ctx.simulate(SEED, 1, debug=True))
-        ctx.set_actors(acts)
-        b = to_np(ctx.simulate(SEED, 1, debug=True))
-        for k in a:
-            assert np.array_equal(a[k], b[k]), (t, k)
+    ctx.set_actor_tree(1)
+    try:
+        ctx.set_actors(cfg["actors_at"](0.0))
+        for t in (0.4, 1.3):
+            acts = cfg["actors_at"](t)
+            ctx.update_actors(acts)
+            a = to_np(ctx.simulate(SEED, 1, debug=True))
+            ctx.set_actors(acts)
+            b = to_np(ctx.simulate(SEED, 1, debug=True))
+            for k in a:
+                assert np.array_equal(a[k], b[k]), (t, k)
+    finally:
+        ctx.set_actor_tree(0)
     beams = _sample(a, sensor, np.random.default_rng(2), n=1500)
     o = O.simulate_actors(cfg["scene"], cfg["meshes"], acts, sensor, cfg["pose"], seed=SEED, scan=1, beams=beams)
     rep = compare({k: v[..., beams] for k, v in a.items()}, o)
     print(f"[parity] dynamic t=1.3 (refit): {rep}", flush=True)
+
+
+def _scan_with_tree(ctx, mode, acts, scan=3):
+    ctx.set_actor_tree(mode)
+    try:
+        ctx.set_actors(acts)
+        return to_np(ctx.simulate(SEED, scan, debug=True))
+    finally:
+        ctx.set_actor_tree(0)
+
+
+def test_packed_tree_equals_builder_tree(L, dyn):
+    """The top-level tree rebuilt by every update (Morton-packed, one workgroup)
+    and the builder's tree give the same outputs bit for bit: on frames reached by
+    updates far from the first frame's positions, and for actor sets of 1 to 17
+    actors (trees of one and two levels, partly empty nodes)."""
+    ctx, cfg = dyn
+    ctx.set_actor_tree(0)
+    ctx.set_actors(cfg["actors_at"](0.0))
+    t = 0.0
+    for t_next in (0.9, 2.5):
+        while t < t_next - 1e-9:
+            t = round(t + 0.1, 6)
+            ctx.update_actors(cfg["actors_at"](t))
+        a = to_np(ctx.simulate(SEED, 3, debug=True))
+        b = _scan_with_tree(ctx, 1, cfg["actors_at"](t))
+        ctx.set_actors(cfg["actors_at"](t))        # the packed tree again, for the next updates
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (t, k)
+        assert (a["label"] >= 100000).sum() > 500
+    every = cfg["actors_at"](0.3)
+    near = np.argsort([float(np.hypot(x.p[0], x.p[1])) for x in every])
+    on_actors = 0
+    for n in (1, 2, 4, 5, 17):
+        acts = [every[k] for k in near[:n]]
+        a = _scan_with_tree(ctx, 0, acts)
+        b = _scan_with_tree(ctx, 1, acts)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (n, k)
+        on_actors += int((a["label"] >= 100000).sum())
+    assert on_actors > 0
+
+
+@pytest.mark.parametrize("n_act", [1024, 1025, 4096])
+def test_packed_tree_large_sets(L, n_act):
+    """The rebuild's two orderings at their limits, against the builder's tree: up to
+    1,024 actors (one per thread, each placed by counting smaller keys) and above
+    (bitonic sort), up to 4,096 actors, the most one workgroup rebuilds (a 6-level
+    tree of 1,365 nodes)."""
+    n_peds = n_act // 4
+    cfg = S.dynamic_actors(seed=77, n_cars=n_act - n_peds, n_peds=n_peds)
+    ctx = L.Context(0)
+    ctx.load(cfg["scene"])
+    ctx.set_sensor(cfg["sensor"])
+    ctx.set_pose(cfg["pose"].p, cfg["pose"].q)
+    for m in cfg["meshes"]:
+        ctx.load_mesh(m)
+    acts = cfg["actors_at"](0.5)
+    assert len(acts) == n_act
+    ctx.set_actors(cfg["actors_at"](0.0))
+    ctx.update_actors(acts)
+    a = to_np(ctx.simulate(SEED, 0, debug=True))
+    ctx.sync_check()
+    b = _scan_with_tree(ctx, 1, acts, scan=0)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert (a["label"] >= 100000).sum() > 1000
 
 
 def test_mesh_refit_equals_fresh_build(L, dyn):
