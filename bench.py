@@ -605,7 +605,7 @@ def main():
             "scan_ms_mean": scan_ms, "rays_per_s_scan": n / (scan_ms * 1e-3),
             "actors_set_ms": set_ms, "beams_on_actors_last_frame": n_act}
         log(f"dynamic: {frame_ms * 1e3:.1f} us per frame (refits + scan), scan {scan_ms * 1e3:.1f} us, "
-            f"actor BVH build {set_ms:.2f} ms, {n_act} beams on actors")
+            f"first set_actors call {set_ms:.2f} ms on the host, {n_act} beams on actors")
         ctx.clear_actors()
 
     if "sequence" in legs:
