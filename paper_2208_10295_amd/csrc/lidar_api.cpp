@@ -114,7 +114,8 @@ struct lidar_ctx {
     size_t staging_n = 0;
     uint32_t staging_slots = 0;
     uint64_t staging_next = 0;
-    hipStream_t staging_stream = nullptr;
+    hipStream_t staging_stream = nullptr;   // the stream of the ring's last use (valid once staging_used)
+    bool staging_used = false;
     hipEvent_t staging_ev[2] = {nullptr, nullptr};
     int actor_stack = 0;
     float actor_reach_need = 0.f;   // twice the largest coordinate of any placed mesh
@@ -1110,14 +1111,13 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
     const int stack = stack_for_need(entries_for_depth(br.depth) + mesh_need);
     if (stack < 0) return ctx->fail(LIDAR_ERR_STACK_OVERFLOW, "actor and mesh BVHs too deep for the traversal stack");
     const uint32_t slots = n_actors <= kPackedTlasMax ? 8u : 2u;
-    if (ctx->staging_stream && ctx->staging_stream != s &&
-        (e = hipStreamSynchronize(ctx->staging_stream)) != hipSuccess)
+    // the ring's events cover one stream: after updates on another stream (which may since have been
+    // destroyed), wait for the device before the ring is reused or freed
+    if (ctx->staging_used && ctx->staging_stream != s && (e = hipDeviceSynchronize()) != hipSuccess)
         return ctx->hip_fail(e, "staging wait");
     if (ctx->staging_n < n_actors || ctx->staging_slots != slots) {
         for (hipEvent_t ev : ctx->staging_ev)
             if (ev && (e = hipEventSynchronize(ev)) != hipSuccess) return ctx->hip_fail(e, "staging wait");
-        if (ctx->staging_stream && (e = hipStreamSynchronize(ctx->staging_stream)) != hipSuccess)
-            return ctx->hip_fail(e, "staging wait");
         if (ctx->staging) hipHostFree(ctx->staging);
         ctx->staging = nullptr;
         ctx->staging_dev = nullptr;
@@ -1143,6 +1143,7 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
     }
     ctx->staging_next = 0;
     ctx->staging_stream = s;
+    ctx->staging_used = true;
     ctx->tlas_br = br;
     ctx->tlas_recs = (TriRec *)(P + persistent_nodes_bytes(n_actors));
     ctx->actors_dev = ad;
@@ -1180,8 +1181,9 @@ lidar_status lidar_actors_update(lidar_ctx *ctx, const lidar_actor *actors, uint
     const uint32_t per_half = ctx->staging_slots / 2;
     const uint32_t slot = (uint32_t)(ctx->staging_next % ctx->staging_slots), half = slot / per_half;
     if (s != ctx->staging_stream) {
-        // the events cover one stream's work: let the previous stream finish before switching
-        if ((e = hipStreamSynchronize(ctx->staging_stream)) != hipSuccess) return ctx->hip_fail(e, "staging wait");
+        // the events cover one stream's work: before switching, wait for the device (the previous
+        // stream may since have been destroyed)
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return ctx->hip_fail(e, "staging wait");
         ctx->staging_stream = s;
     }
     if (slot % per_half == 0 && (e = hipEventSynchronize(ctx->staging_ev[half])) != hipSuccess)

@@ -146,6 +146,23 @@ def test_packed_tree_large_sets(L, n_act):
     assert (a["label"] >= 100000).sum() > 1000
 
 
+def test_updates_on_several_streams(L, dyn):
+    """Updates issued on alternating streams (the upload ring wraps) leave the tree a fresh set at the last
+    poses gives, bit for bit."""
+    ctx, cfg = dyn
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ctx.set_actors(cfg["actors_at"](0.0))
+    for f in range(1, 20):
+        ctx.update_actors(cfg["actors_at"](0.1 * f), stream=s1 if f % 3 else s2)
+    torch.cuda.synchronize()
+    a = to_np(ctx.simulate(SEED, 4, debug=True))
+    ctx.set_actors(cfg["actors_at"](1.9))
+    b = to_np(ctx.simulate(SEED, 4, debug=True))
+    ctx.sync_check()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_mesh_refit_equals_fresh_build(L, dyn):
     """A deformed pedestrian mesh refit in place scans like the deformed mesh built from scratch."""
     ctx, cfg = dyn
