@@ -427,8 +427,11 @@ lidar_status lidar_actors_set(lidar_ctx *ctx, const lidar_actor *actors, uint32_
  * the transforms through a pinned buffer, recomputes the world boxes and
  * rebuilds the top-level BVH in one workgroup (up to 4,096 actors, see
  * LIDAR_OPT_ACTOR_TREE) or refits it (the builder's tree: call
- * lidar_actors_set again when the refit tree has degraded).  Asynchronous;
- * waits only for the previous update's upload. */
+ * lidar_actors_set again when the refit tree has degraded).  Asynchronous:
+ * the transforms go through a pinned ring of eight slots (two for more than
+ * 4,096 actors), and the call waits only when it reuses a slot the GPU may
+ * still read; an update on another stream than the previous one first waits
+ * for the device. */
 lidar_status lidar_actors_update(lidar_ctx *ctx, const lidar_actor *actors, uint32_t n_actors, void *stream);
 
 /* Removes the actors (the workspaces are the caller's). */
