@@ -214,6 +214,11 @@ def main():
     ap.add_argument("--seq-xcd", type=int, default=0,
                     help="XCD-aware block remap of the trajectory scans (0 or 1; off by default: the 128 x 1024 scans "
                          "of the 5.2M-triangle scene run 4-5 %% faster in launch order)")
+    ap.add_argument("--seq-up-weight", type=float, default=0.25,
+                    help="horizontal-face weight of the trajectory scene's tree (1 = surface area; the 100 scans "
+                         "along the trajectory run about 10 %% faster at 0.25, at every PLOC radius tried)")
+    ap.add_argument("--batch-up-weight", type=float, default=0.5,
+                    help="horizontal-face weight of the batch's tree (the tuned batch runs about 6 %% faster at 0.5)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -358,6 +363,9 @@ def main():
     if "batch" in legs:
         sc_b, insts = S.batch_256()
         assert sc_b is scene
+        # the batch's own tree: built for rays near the horizontal (many poses), leaf width tuned below
+        ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius, collapse=args.collapse,
+                 leaf_cost=args.leaf_cost, up_weight=args.batch_up_weight)
         batch = ctx.batch(insts, 256)
         nr = batch.n_rays
         bout = alloc_outputs(nr, POINT_OUTPUTS, ctx.device)
@@ -387,13 +395,18 @@ def main():
             "tune_ms_grid_leaf_lanes_packet": tune["ms"].round(4).tolist(),
             "tune_packets": [int(x) for x in tune["packet_rays"]],
             "tune_leaf_widths": [int(x) for x in tune["leaf_widths"]],
-            "tune_lanes_per_ray": [int(x) for x in tune["lanes_per_ray"]]}
+            "tune_lanes_per_ray": [int(x) for x in tune["lanes_per_ray"]],
+            "bvh_up_weight": args.batch_up_weight}
         result["batched"]["speedup_vs_sequential"] = (result["batched"]["batched_rays_per_s"]
                                                       / result["batched"]["sequential_rays_per_s"])
         log(f"batched {result['batched']['batched_rays_per_s']:.4g} rays/s vs sequential "
             f"{result['batched']['sequential_rays_per_s']:.4g} rays/s (tuned W={tune['best_leaf_width']}, "
             f"P={tune['best_packet_rays']}, lanes={tune['best_lanes_per_ray']})")
         del batch, bout
+        # the legs below run on the plain scan's tree again
+        ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius, collapse=args.collapse,
+                 leaf_cost=args.leaf_cost)
+        ctx.set_lanes_per_ray(args.lanes)
 
     if "adjoint" in legs:
         cal = S.calibration_20mat()
@@ -612,7 +625,7 @@ def main():
         sc3, s3, poses = S.urban_sequence_128ch()
         cs = L.Context(0)
         st3 = cs.load(sc3, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius,
-                      collapse=args.collapse, leaf_cost=args.leaf_cost)
+                      collapse=args.collapse, leaf_cost=args.leaf_cost, up_weight=args.seq_up_weight)
         cs.set_sensor(s3)
         cs.set_tile_shape(args.tile_az)
         cs.set_lanes_per_ray(args.lanes)
@@ -630,7 +643,7 @@ def main():
         tr3 = read_traffic(TRAFFIC_SEQ_FILE)
         secs3 = k3_ms * 1e-3
         result["sequence"] = {"workload": "128ch x 1024 x 100 poses at 10 Hz, 5,224,200-triangle scene, 64 materials",
-                              "xcd_remap": args.seq_xcd,
+                              "xcd_remap": args.seq_xcd, "bvh_up_weight": args.seq_up_weight,
                               "rays_per_s": s3.n_beams / (ms3 * 1e-3), "ms_per_scan": ms3,
                               "rays_per_s_wall": len(poses) * s3.n_beams / wall3,
                               "bvh_build_ms": st3["build_ms"], "bvh_nodes": st3["n_nodes"],

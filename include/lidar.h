@@ -106,7 +106,14 @@ const char *lidar_last_error(const lidar_ctx *ctx);
                                         of by the surface-area cost */
 /* flags bits 8-15: PLOC search radius in Morton order, 1..128 (0 = 32)
  * flags bits 16-23: weight of a leaf step against a node step in the
- *   surface-area cost of the collapse, in sixteenths (0 = 24, i.e. 1.5) */
+ *   surface-area cost of the collapse, in sixteenths (0 = 24, i.e. 1.5)
+ * flags bits 24-31: weight of a box's two horizontal (x-y) faces against its
+ *   vertical ones in the area metric of the clustering and the collapse, in
+ *   128ths (0 = 128, i.e. 1: the surface area).  Below 1 the tree is built for
+ *   rays near the horizontal, as a LiDAR's mostly are: scans from many poses
+ *   (trajectories, batches) run faster with 0.15 to 0.5; a single scan's time
+ *   depends on how the top of the tree splits around its one origin.  Scenes
+ *   only (meshes use the surface area).  Results never depend on the tree. */
 
 typedef struct {
     uint64_t n_vertices;

@@ -8,7 +8,9 @@
 //    (a) PLOC (default; Meister and Bittner, "Parallel Locally-Ordered
 //        Clustering for Bounding Volume Hierarchy Construction", TVCG 2018):
 //        clusters in Morton order repeatedly find their nearest neighbour
-//        (smallest merged surface area) within +-R positions (R = 32 by
+//        (smallest merged surface area, its horizontal faces optionally
+//        weighted below the vertical ones for rays near the horizontal; the
+//        collapse's cost uses the same metric) within +-R positions (R = 32 by
 //        default, at most 128); mutual nearest
 //        pairs merge into a new node; the survivors are compacted in order.
 //        Boxes are formed during the merges.  The leaves are then renumbered
@@ -565,9 +567,11 @@ __global__ void single_leaf_root_kernel(const TriRec *__restrict__ recs, uint32_
 constexpr int kPlocRMax = 128;   // largest search radius in Morton order
 constexpr int kPlocBlock = 256;
 
-__device__ inline float half_area(float lx, float ly, float lz, float hx, float hy, float hz) {
+// Half the surface area of a box, its two horizontal faces weighted by wz (1: the plain surface area).
+// A weight below 1 prices boxes for rays that are mostly horizontal, as a LiDAR's are.
+__device__ inline float half_area(float lx, float ly, float lz, float hx, float hy, float hz, float wz) {
     float ex = hx - lx, ey = hy - ly, ez = hz - lz;
-    return ex * ey + ey * ez + ez * ex;
+    return wz * (ex * ey) + ey * ez + ez * ex;
 }
 
 // node ids: leaves 0..n-1 (Morton positions), internal nodes n..2n-2 in creation order
@@ -586,7 +590,7 @@ __global__ __launch_bounds__(256) void ploc_init_kernel(const TriRec *__restrict
 
 __global__ __launch_bounds__(kPlocBlock) void ploc_nn_kernel(const uint32_t *__restrict__ C, uint32_t m,
                                                              const float *__restrict__ nbox, uint32_t *__restrict__ nn,
-                                                             int R) {
+                                                             int R, float wz) {
     __shared__ float sb[(kPlocBlock + 2 * kPlocRMax) * 6];
     const int base = (int)(blockIdx.x * kPlocBlock);
     const int lo_i = base - R;
@@ -610,7 +614,7 @@ __global__ __launch_bounds__(kPlocBlock) void ploc_nn_kernel(const uint32_t *__r
         if (d == 0 || j < 0 || j >= (int)m) continue;
         const float *o = sb + (li + d) * 6;
         float a = half_area(fminf(lx, o[0]), fminf(ly, o[1]), fminf(lz, o[2]), fmaxf(hx, o[3]), fmaxf(hy, o[4]),
-                            fmaxf(hz, o[5]));
+                            fmaxf(hz, o[5]), wz);
         if (a < best) { best = a; bj = j; }    // ties keep the smaller j (ascending scan)
     }
     nn[i] = (uint32_t)bj;
@@ -720,18 +724,18 @@ struct SahTables {
 __device__ inline uint32_t sah_uses(uint32_t w, int i) { return i == 1 ? 1u : (w >> (1 + 3 * (i - 2))) & 7u; }
 __device__ inline uint32_t sah_left(uint32_t w, int e) { return (w >> (10 + 2 * (e - 2))) & 3u; }
 
-__device__ inline float box_half_area(const float lo[3], const float hi[3]) {
+__device__ inline float box_half_area(const float lo[3], const float hi[3], float wz) {
     const float ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
-    return ex * ey + ey * ez + ez * ex;
+    return wz * (ex * ey) + ey * ez + ez * ex;
 }
 
 // C(c, 1..4) of a child code: a single triangle is a leaf whatever the slots
 __device__ inline void sah_child_costs(const BinTree &T, const TriRec *__restrict__ recs, const float *cost,
-                                       uint32_t code, float leaf_w, float C[4]) {
+                                       uint32_t code, float leaf_w, float wz, float C[4]) {
     if (code & kLeafBit) {
         float lo[3], hi[3];
         rec_box(recs, code & ~kLeafBit, lo, hi);
-        const float c = leaf_w * box_half_area(lo, hi);
+        const float c = leaf_w * box_half_area(lo, hi, wz);
         for (int i = 0; i < 4; ++i) C[i] = c;
     } else {
         // written by another thread of this pass: read past the vector L1
@@ -742,12 +746,12 @@ __device__ inline void sah_child_costs(const BinTree &T, const TriRec *__restric
 
 // C(p, 1..4) and the choice word of binary node p from its children's costs
 __device__ inline void sah_eval(const BinTree &T, const TriRec *__restrict__ recs, uint32_t p, uint32_t W,
-                                float leaf_w, const SahTables &S) {
+                                float leaf_w, float wz, const SahTables &S) {
     float L[4], R[4];
-    sah_child_costs(T, recs, S.cost, T.left[p], leaf_w, L);
-    sah_child_costs(T, recs, S.cost, T.right[p], leaf_w, R);
+    sah_child_costs(T, recs, S.cost, T.left[p], leaf_w, wz, L);
+    sah_child_costs(T, recs, S.cost, T.right[p], leaf_w, wz, R);
     const float *b = T.box + 6 * (size_t)p;
-    const float area = box_half_area(b, b + 3);
+    const float area = box_half_area(b, b + 3, wz);
     // best spread of the two children over e = 2..4 slots (smallest left share on ties)
     float spread[5];
     uint32_t w = 0;
@@ -783,7 +787,8 @@ __device__ inline void sah_eval(const BinTree &T, const TriRec *__restrict__ rec
 // leaf; the second thread to reach a node evaluates it (both children done).
 // For the LBVH, whose nodes carry no creation order.
 __global__ __launch_bounds__(256) void sah_cost_kernel(BinTree T, const TriRec *__restrict__ recs, int n,
-                                                       uint32_t root, uint32_t W, float leaf_w, SahTables S) {
+                                                       uint32_t root, uint32_t W, float leaf_w, float wz,
+                                                       SahTables S) {
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     uint32_t p = T.parent_leaf[s];
@@ -791,7 +796,7 @@ __global__ __launch_bounds__(256) void sah_cost_kernel(BinTree T, const TriRec *
         __threadfence();
         if (atomicAdd(&T.visit[p], 1u) == 0) return;
         __threadfence();
-        sah_eval(T, recs, p, W, leaf_w, S);
+        sah_eval(T, recs, p, W, leaf_w, wz, S);
         if (p == root) return;
         p = T.parent_int[p];
     }
@@ -800,9 +805,10 @@ __global__ __launch_bounds__(256) void sah_cost_kernel(BinTree T, const TriRec *
 // The nodes one clustering round created, [k0, k0 + cnt): their children come from earlier rounds, so
 // running the rounds in creation order evaluates every node after its children, without atomics.
 __global__ __launch_bounds__(256) void sah_round_kernel(BinTree T, const TriRec *__restrict__ recs, uint32_t k0,
-                                                        uint32_t cnt, uint32_t W, float leaf_w, SahTables S) {
+                                                        uint32_t cnt, uint32_t W, float leaf_w, float wz,
+                                                        SahTables S) {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
-    if (k < cnt) sah_eval(T, recs, k0 + k, W, leaf_w, S);
+    if (k < cnt) sah_eval(T, recs, k0 + k, W, leaf_w, wz, S);
 }
 
 // One 4-wide node per frontier entry, shaped by the recorded choices: the
@@ -958,6 +964,7 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
     TriRec *recs = (TriRec *)((char *)persistent + persistent_nodes_bytes(nt));
     uint32_t *slot_of = (uint32_t *)((char *)recs + persistent_recs_bytes(nt));
     const uint32_t nb = (nt + 255) / 256;
+    const float wz = in.up_weight > 0.0f ? in.up_weight : 1.0f;   // horizontal-face weight of the area metric
 
     const bool ploc = in.builder == 0 && nt > in.leaf_width;
     TriRec *recs_m = ploc ? (TriRec *)(sc + L.recs_m) : recs;   // Morton-order records
@@ -999,7 +1006,7 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
                 if (round_start.size() > 100000) return hipErrorIllegalState;
                 uint32_t g = (m + 255) / 256;
                 ploc_nn_kernel<<<(m + kPlocBlock - 1) / kPlocBlock, kPlocBlock, 0, s>>>(ca, m, nbox, nn,
-                                                                                         (int)in.ploc_radius);
+                                                                                         (int)in.ploc_radius, wz);
                 ploc_flags_kernel<<<g, 256, 0, s>>>(nn, m, leader, keep);
                 scan_exclusive_u32(leader, loff, m, stmp, s);
                 scan_exclusive_u32(keep, koff, m, stmp, s);
@@ -1041,11 +1048,11 @@ hipError_t build_bvh(const BuildInputs &in, void *persistent, void *scratch, Bui
         if (sah && ploc) {
             for (size_t r = 0; r < ploc_rounds.size(); ++r)
                 sah_round_kernel<<<(ploc_rounds[r].second + 255) / 256, 256, 0, s>>>(
-                    T, recs, ploc_rounds[r].first - nt, ploc_rounds[r].second, in.leaf_width, in.leaf_cost, sah_t);
+                    T, recs, ploc_rounds[r].first - nt, ploc_rounds[r].second, in.leaf_width, in.leaf_cost, wz, sah_t);
             HIP_TRY(hipGetLastError());
         } else if (sah) {
             HIP_TRY(hipMemsetAsync(T.visit, 0, 4 * (size_t)nt, s));
-            sah_cost_kernel<<<nb, 256, 0, s>>>(T, recs, (int)nt, root_code, in.leaf_width, in.leaf_cost, sah_t);
+            sah_cost_kernel<<<nb, 256, 0, s>>>(T, recs, (int)nt, root_code, in.leaf_width, in.leaf_cost, wz, sah_t);
             HIP_TRY(hipGetLastError());
         }
         uint32_t *fa = (uint32_t *)(sc + L.front_a), *fb = (uint32_t *)(sc + L.front_b);

@@ -435,6 +435,10 @@ lidar_status lidar_scene_load(lidar_ctx *ctx, const lidar_scene_desc *desc, void
     if (in.ploc_radius == 0) in.ploc_radius = 32;
     if (in.ploc_radius > 128) return ctx->fail(LIDAR_ERR_INVALID_ARG, "PLOC radius (flags bits 8-15) must be <= 128");
     set_collapse(in, desc->flags);
+    {
+        const uint32_t w128 = (desc->flags >> 24) & 0xFFu;   // horizontal-face weight of the area metric
+        in.up_weight = w128 ? (float)w128 / 128.0f : 1.0f;
+    }
     if (desc->flags & LIDAR_SCENE_DEVICE_PTRS) {
         in.vtx = desc->vertices;
         in.idx = desc->indices;

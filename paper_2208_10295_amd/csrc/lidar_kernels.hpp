@@ -37,6 +37,9 @@ struct BuildInputs {
     uint32_t ploc_radius;      // PLOC search radius, 1..128
     uint32_t collapse;         // 0 = surface-area cost (default), 1 = greedy (largest child first)
     float leaf_cost;           // leaf step weight of the cost model, a node step weighing 1
+    float up_weight;           // weight of a box's two horizontal faces in the area metric of the clustering
+                               // and the collapse (0 or 1: the surface area; below 1: for rays near the
+                               // horizontal)
     float reach;               // child boxes are padded by 2^-20 max(max |vertex coordinate|, reach):
                                // 0 for a scene, the object-space origin bound for a mesh, the static
                                // scene's largest coordinate for the actors' top-level tree

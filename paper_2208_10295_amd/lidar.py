@@ -133,7 +133,7 @@ class Context:
 
     # -- scene --------------------------------------------------------------
     def _scene_desc(self, vertices, indices, material, label, leaf_width, builder="ploc", ploc_radius=0,
-                    collapse="sah", leaf_cost=0.0):
+                    collapse="sah", leaf_cost=0.0, up_weight=1.0):
         dev = self.device
         v = torch.as_tensor(np.ascontiguousarray(vertices, np.float32)).to(dev) if not torch.is_tensor(vertices) else vertices.to(dev, torch.float32).contiguous()
         i = torch.as_tensor(np.ascontiguousarray(indices, np.uint32).view(np.int32)).to(dev) if not torch.is_tensor(indices) else indices.to(dev, torch.int32).contiguous()
@@ -151,16 +151,21 @@ class Context:
         sixteenths = int(round(16 * leaf_cost))
         if not 0 <= sixteenths <= 255:
             raise ValueError("leaf_cost must be in [0, 255/16] (0 = default)")
+        w128 = int(round(128 * up_weight))
+        if not 1 <= w128 <= 255:
+            raise ValueError("up_weight must be in [1/128, 255/128]")
         d.flags = (A.SCENE_DEVICE_PTRS | (A.SCENE_BUILD_LBVH if builder == "lbvh" else 0) | (int(ploc_radius) << 8) |
-                   (A.SCENE_COLLAPSE_GREEDY if collapse == "greedy" else 0) | (sixteenths << 16))
+                   (A.SCENE_COLLAPSE_GREEDY if collapse == "greedy" else 0) | (sixteenths << 16) |
+                   ((0 if w128 == 128 else w128) << 24))
         return d, (v, i, m, lab)
 
     def load_scene(self, vertices, indices, material, label, leaf_width: int = 4, stream=None, builder="ploc",
-                   ploc_radius: int = 0, collapse: str = "sah", leaf_cost: float = 0.0):
+                   ploc_radius: int = 0, collapse: str = "sah", leaf_cost: float = 0.0, up_weight: float = 1.0):
         """Builds the scene BVH.  collapse: 'sah' (surface-area cost, leaf step weighing leaf_cost node
-        steps, 0 = library default) or 'greedy'."""
+        steps, 0 = library default) or 'greedy'; up_weight: weight of a box's horizontal faces in the build's
+        area metric (1 = surface area; below 1 for rays near the horizontal)."""
         d, keep = self._scene_desc(vertices, indices, material, label, leaf_width, builder, ploc_radius, collapse,
-                                   leaf_cost)
+                                   leaf_cost, up_weight)
         pb, sb = C.c_uint64(), C.c_uint64()
         check(lib.lidar_scene_bytes(C.byref(d), C.byref(pb), C.byref(sb)), self.h)
         persistent = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
@@ -174,10 +179,10 @@ class Context:
         return self.stats()
 
     def load(self, scene, leaf_width: int = 4, builder: str = "ploc", ploc_radius: int = 0, collapse: str = "sah",
-             leaf_cost: float = 0.0):
+             leaf_cost: float = 0.0, up_weight: float = 1.0):
         """Scene + materials from an object with vertices/indices/material/label/spectra/sigma_range/angle_exp."""
         st = self.load_scene(scene.vertices, scene.indices, scene.material, scene.label, leaf_width, builder=builder,
-                             ploc_radius=ploc_radius, collapse=collapse, leaf_cost=leaf_cost)
+                             ploc_radius=ploc_radius, collapse=collapse, leaf_cost=leaf_cost, up_weight=up_weight)
         self.set_materials(scene.spectra, scene.sigma_range, scene.angle_exp)
         return st
 

@@ -93,31 +93,35 @@ def test_64ch_full_scan_matches_oracle_every_beam(L):
 
 
 def test_64ch_bvh_equals_bruteforce_full(L):
-    """Both tree builders, both collapses and every traversal shape reproduce the brute-force scan bit for bit."""
+    """Both tree builders, both collapses, trees built for rays near the horizontal (horizontal faces weighted
+    0.5 and 0.15 in the area metric) and every traversal shape reproduce the brute-force scan bit for bit."""
     scene, sensor, pose = S.urban_64ch()
     c = _ctx(L, scene, sensor, pose)
     b = to_np(c.simulate(SEED, 0, debug=True, bruteforce=True))
-    for builder, collapse in (("ploc", "sah"), ("lbvh", "sah"), ("ploc", "greedy"), ("lbvh", "greedy")):
-        st = c.load(scene, builder=builder, collapse=collapse)
-        print(f"[bvh] urban_64ch {builder} {collapse}: nodes {st['n_nodes']} leaves {st['n_leaves']} "
+    for builder, collapse, upw in (("ploc", "sah", 1.0), ("lbvh", "sah", 1.0), ("ploc", "greedy", 1.0),
+                                   ("lbvh", "greedy", 1.0), ("ploc", "sah", 0.5), ("ploc", "sah", 0.15)):
+        st = c.load(scene, builder=builder, collapse=collapse, up_weight=upw)
+        print(f"[bvh] urban_64ch {builder} {collapse} up {upw}: nodes {st['n_nodes']} leaves {st['n_leaves']} "
               f"depth {st['depth']} build {st['build_ms']:.2f} ms", flush=True)
         for lanes in (1, 2, 4):
             c.set_lanes_per_ray(lanes)
             a = to_np(c.simulate(SEED, 0, debug=True))
             for k in a:
-                assert np.array_equal(a[k], b[k]), (builder, collapse, lanes, k)
+                assert np.array_equal(a[k], b[k]), (builder, collapse, upw, lanes, k)
 
 
-@pytest.mark.parametrize("builder,collapse,leaf_width,leaf_cost", [
-    ("ploc", "sah", 4, 0.0), ("lbvh", "sah", 4, 0.0), ("ploc", "greedy", 4, 0.0), ("lbvh", "greedy", 4, 0.0),
-    ("ploc", "sah", 1, 0.0), ("ploc", "sah", 8, 0.0), ("lbvh", "sah", 2, 0.0), ("ploc", "sah", 4, 0.25),
-    ("ploc", "sah", 4, 8.0)])
-def test_bvh_structure_invariants(L, builder, collapse, leaf_width, leaf_cost):
+@pytest.mark.parametrize("builder,collapse,leaf_width,leaf_cost,up_weight", [
+    ("ploc", "sah", 4, 0.0, 1.0), ("lbvh", "sah", 4, 0.0, 1.0), ("ploc", "greedy", 4, 0.0, 1.0),
+    ("lbvh", "greedy", 4, 0.0, 1.0), ("ploc", "sah", 1, 0.0, 1.0), ("ploc", "sah", 8, 0.0, 1.0),
+    ("lbvh", "sah", 2, 0.0, 1.0), ("ploc", "sah", 4, 0.25, 1.0), ("ploc", "sah", 4, 8.0, 1.0),
+    ("ploc", "sah", 4, 0.0, 0.25), ("lbvh", "sah", 2, 0.0, 1.0 / 128)])
+def test_bvh_structure_invariants(L, builder, collapse, leaf_width, leaf_cost, up_weight):
     """Every triangle lies in exactly one leaf of at most leaf_width triangles, and every child box contains
-    its triangles, for each builder and collapse (a very cheap and a very dear leaf step included)."""
+    its triangles, for each builder and collapse (a very cheap and a very dear leaf step, and area metrics
+    that weight the horizontal faces down to 1/128, included)."""
     scene, sensor, pose = S.small_16ch()
     c = _ctx(L, scene, sensor, pose)
-    c.load(scene, leaf_width, builder=builder, collapse=collapse, leaf_cost=leaf_cost)
+    c.load(scene, leaf_width, builder=builder, collapse=collapse, leaf_cost=leaf_cost, up_weight=up_weight)
     st = c.stats()
     assert st["leaf_width"] == leaf_width
     nodes_b, tris_b = c.debug_bvh()
