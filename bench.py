@@ -219,8 +219,6 @@ def main():
     ap.add_argument("--seq-up-weight", type=float, default=0.25,
                     help="horizontal-face weight of the trajectory scene's tree (1 = surface area; the 100 scans "
                          "along the trajectory run about 10 %% faster at 0.25, at every PLOC radius tried)")
-    ap.add_argument("--batch-up-weight", type=float, default=0.5,
-                    help="horizontal-face weight of the batch's tree (the tuned batch runs about 6 %% faster at 0.5)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 256 MiB device copy (PMC scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -365,15 +363,14 @@ def main():
     if "batch" in legs:
         sc_b, insts = S.batch_256()
         assert sc_b is scene
-        # the batch's own tree: built for rays near the horizontal (many poses), leaf width tuned below
-        ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius, collapse=args.collapse,
-                 leaf_cost=args.leaf_cost, up_weight=args.batch_up_weight)
         batch = ctx.batch(insts, 256)
         nr = batch.n_rays
         bout = alloc_outputs(nr, POINT_OUTPUTS, ctx.device)
         log(f"batch: {len(insts)} instances, {nr} rays; tuning ...")
-        tune = batch.tune(packet_rays=(64, 256, 1024), leaf_widths=(2, 4, 8), lanes_per_ray=(1, 2, 4), reps=5,
-                          out=bout)
+        # the tree (leaf width, and the area weight for rays near the horizontal) and the launch shape are
+        # tuned on the batch itself (one lane per ray, never the best, is left out to keep the grid at 54)
+        tune = batch.tune(packet_rays=(64, 256, 1024), leaf_widths=(2, 4, 8), lanes_per_ray=(2, 4), reps=5,
+                          out=bout, up_weights=(1.0, 0.5, 0.25))
         for _ in range(2):
             batch.simulate(bout)
         ctx.sync_check()
@@ -394,16 +391,17 @@ def main():
             "sequential_lanes_per_ray": args.lanes,
             "tuned_packet_rays": tune["best_packet_rays"], "tuned_leaf_width": tune["best_leaf_width"],
             "tuned_lanes_per_ray": tune["best_lanes_per_ray"],
-            "tune_ms_grid_leaf_lanes_packet": tune["ms"].round(4).tolist(),
+            "tune_ms_grid_up_leaf_lanes_packet": tune["ms"].round(4).tolist(),
+            "tune_up_weights": tune["up_weights"], "tuned_up_weight": tune["best_up_weight"],
             "tune_packets": [int(x) for x in tune["packet_rays"]],
             "tune_leaf_widths": [int(x) for x in tune["leaf_widths"]],
-            "tune_lanes_per_ray": [int(x) for x in tune["lanes_per_ray"]],
-            "bvh_up_weight": args.batch_up_weight}
+            "tune_lanes_per_ray": [int(x) for x in tune["lanes_per_ray"]]}
         result["batched"]["speedup_vs_sequential"] = (result["batched"]["batched_rays_per_s"]
                                                       / result["batched"]["sequential_rays_per_s"])
         log(f"batched {result['batched']['batched_rays_per_s']:.4g} rays/s vs sequential "
             f"{result['batched']['sequential_rays_per_s']:.4g} rays/s (tuned W={tune['best_leaf_width']}, "
-            f"P={tune['best_packet_rays']}, lanes={tune['best_lanes_per_ray']})")
+            f"P={tune['best_packet_rays']}, lanes={tune['best_lanes_per_ray']}, area weight "
+            f"{tune['best_up_weight']:g})")
         del batch, bout
         # the legs below run on the plain scan's tree again
         ctx.load(scene, args.leaf_width, builder=args.builder, ploc_radius=args.ploc_radius, collapse=args.collapse,
@@ -667,14 +665,16 @@ def main():
         # offline, where every pose is known before the first scan
         sb = cs.batch([S.Instance(s3, poses[k], seed=seed, scan=k) for k in range(len(poses))], 0)
         sbo = alloc_outputs(sb.n_rays, POINT_OUTPUTS, cs.device)
-        stune = sb.tune(packet_rays=(256,), leaf_widths=(2, 4), lanes_per_ray=(2, 4), reps=3, out=sbo)
+        stune = sb.tune(packet_rays=(256,), leaf_widths=(2, 4), lanes_per_ray=(2, 4), reps=3, out=sbo,
+                        up_weights=(0.5, 0.25))
         sb.simulate(sbo)
         cs.sync_check()
         wall_b, ms_b = timed_launches(lambda k: sb.simulate(sbo), 5, torch)
         cs.sync_check()
         result["sequence"]["batched"] = {
             "rays_per_s": 5 * sb.n_rays / wall_b, "ms_per_trajectory": float(np.mean(ms_b)),
-            "tuned_leaf_width": stune["best_leaf_width"], "tuned_lanes_per_ray": stune["best_lanes_per_ray"]}
+            "tuned_leaf_width": stune["best_leaf_width"], "tuned_lanes_per_ray": stune["best_lanes_per_ray"],
+            "tuned_up_weight": stune["best_up_weight"]}
         log(f"sequence batched: {result['sequence']['batched']['rays_per_s']:.4g} rays/s "
             f"({result['sequence']['batched']['ms_per_trajectory']:.2f} ms per 100-scan trajectory)")
         del sb, sbo, cs

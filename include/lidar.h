@@ -595,6 +595,10 @@ typedef struct {
     const uint32_t *lanes_per_ray; /* host [n_lanes] candidates (1, 2 or 4); NULL = current only */
     uint32_t n_lanes;
     uint32_t reps;                 /* timed repetitions per candidate (median) */
+    const float *up_weights;       /* host [n_up] candidate weights of the horizontal faces in the tree
+                                      build's area metric (scene flags bits 24-31; 1/128 .. 255/128);
+                                      NULL = the scene descriptor's own */
+    uint32_t n_up;
 } lidar_tune_desc;
 
 typedef struct {
@@ -602,14 +606,16 @@ typedef struct {
     uint32_t best_leaf_width;
     uint32_t best_lanes_per_ray;
     float best_ms;
-    float ms[64];                  /* [n_leaf][n_lanes][n_packet] medians, row-major (<= 64 entries) */
+    float ms[64];                  /* [n_up][n_leaf][n_lanes][n_packet] medians, row-major (<= 64 entries) */
+    float best_up_weight;
 } lidar_tune_result;
 
-/* Times lidar_simulate_batch for every (leaf width, lanes per ray, packet
- * size) candidate on the batch, rebuilding the BVH per leaf width from
- * `scene` into the given buffers, then leaves the scene built with the best
- * leaf width, the context set to the best lanes per ray and the batch to the
- * best packet size.  Results never depend on the choice.  Synchronous. */
+/* Times lidar_simulate_batch for every (area weight, leaf width, lanes per
+ * ray, packet size) candidate on the batch, rebuilding the BVH per area
+ * weight and leaf width from `scene` into the given buffers, then leaves the
+ * scene built with the best weight and leaf width, the context set to the
+ * best lanes per ray and the batch to the best packet size.  Results never
+ * depend on the choice.  Synchronous. */
 lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *persistent,
                         uint64_t persistent_bytes, void *scratch, uint64_t scratch_bytes,
                         lidar_batch *batch, const lidar_outputs *out, const lidar_tune_desc *desc,

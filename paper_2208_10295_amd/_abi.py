@@ -87,12 +87,14 @@ class Instance(C.Structure):
 
 class TuneDesc(C.Structure):
     _fields_ = [("packet_rays", P), ("n_packet", C.c_uint32), ("leaf_widths", P), ("n_leaf", C.c_uint32),
-                ("lanes_per_ray", P), ("n_lanes", C.c_uint32), ("reps", C.c_uint32)]
+                ("lanes_per_ray", P), ("n_lanes", C.c_uint32), ("reps", C.c_uint32), ("up_weights", P),
+                ("n_up", C.c_uint32)]
 
 
 class TuneResult(C.Structure):
     _fields_ = [("best_packet_rays", C.c_uint32), ("best_leaf_width", C.c_uint32),
-                ("best_lanes_per_ray", C.c_uint32), ("best_ms", C.c_float), ("ms", C.c_float * 64)]
+                ("best_lanes_per_ray", C.c_uint32), ("best_ms", C.c_float), ("ms", C.c_float * 64),
+                ("best_up_weight", C.c_float)]
 
 
 class Stats(C.Structure):

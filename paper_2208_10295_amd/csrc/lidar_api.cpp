@@ -1385,8 +1385,24 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
     uint32_t cur_lanes = (uint32_t)ctx->lanes_per_ray;
     const uint32_t *lanes = desc->lanes_per_ray ? desc->lanes_per_ray : &cur_lanes;
     uint32_t n_lanes = desc->lanes_per_ray ? desc->n_lanes : 1;
+    // candidate area weights as flags bits 24-31 (128ths, 0 for 1); none: the descriptor's own
+    std::vector<uint32_t> ups;
+    if (desc->n_packet > 64 || desc->n_leaf > 64 || n_lanes > 64 || (desc->up_weights && desc->n_up > 64))
+        return ctx->fail(LIDAR_ERR_INVALID_ARG, "need 1..64 candidate combinations");
+    if (desc->up_weights) {
+        for (uint32_t i = 0; i < desc->n_up; ++i) {
+            const float w = desc->up_weights[i];
+            const long w128 = std::isfinite(w) && w > 0.0f && w < 2.0f ? std::lround((double)w * 128.0) : 0;
+            if (w128 < 1 || w128 > 255)
+                return ctx->fail(LIDAR_ERR_INVALID_ARG, "area weights must be in [1/128, 255/128]");
+            ups.push_back(w128 == 128 ? 0u : (uint32_t)w128);
+        }
+    } else {
+        ups.push_back((scene->flags >> 24) & 0xFFu);
+    }
+    const uint32_t n_up = (uint32_t)ups.size();
     if (!desc->packet_rays || !desc->leaf_widths || desc->n_packet == 0 || desc->n_leaf == 0 || n_lanes == 0 ||
-        desc->n_packet * desc->n_leaf * n_lanes > 64)
+        n_up == 0 || (uint64_t)desc->n_packet * desc->n_leaf * n_lanes * n_up > 64)
         return ctx->fail(LIDAR_ERR_INVALID_ARG, "need 1..64 candidate combinations");
     for (uint32_t i = 0; i < desc->n_packet; ++i)
         if (desc->packet_rays[i] == 0 || desc->packet_rays[i] % 64 != 0 || desc->packet_rays[i] > 65536)
@@ -1406,8 +1422,11 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
     hipEventCreate(&e1);
     lidar_scene_desc sd = *scene;
     lidar_status st = LIDAR_OK;
+    uint32_t best_up = ups[0];
+    for (uint32_t ui = 0; ui < n_up && st == LIDAR_OK; ++ui)
     for (uint32_t li = 0; li < desc->n_leaf && st == LIDAR_OK; ++li) {
         sd.leaf_width = desc->leaf_widths[li];
+        sd.flags = (scene->flags & 0x00FFFFFFu) | (ups[ui] << 24);
         st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
         if (st > 0) st = LIDAR_OK;   // a warning (e.g. the pose's origin) does not stop the tuning
         for (uint32_t ni = 0; ni < n_lanes && st == LIDAR_OK; ++ni) {
@@ -1428,12 +1447,13 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
                 if (st != LIDAR_OK) break;
                 std::sort(t.begin(), t.end());
                 float med = t[t.size() / 2];
-                res->ms[(li * n_lanes + ni) * desc->n_packet + pi] = med;
+                res->ms[((ui * desc->n_leaf + li) * n_lanes + ni) * desc->n_packet + pi] = med;
                 if (med < res->best_ms) {
                     res->best_ms = med;
                     res->best_packet_rays = desc->packet_rays[pi];
                     res->best_leaf_width = desc->leaf_widths[li];
                     res->best_lanes_per_ray = lanes[ni];
+                    best_up = ups[ui];
                 }
             }
         }
@@ -1442,6 +1462,8 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
     hipEventDestroy(e1);
     if (st != LIDAR_OK) return st;
     sd.leaf_width = res->best_leaf_width;
+    sd.flags = (scene->flags & 0x00FFFFFFu) | (best_up << 24);
+    res->best_up_weight = best_up ? (float)best_up / 128.0f : 1.0f;
     st = lidar_scene_load(ctx, &sd, persistent, persistent_bytes, scratch, scratch_bytes, stream);
     if (st < 0) return st;
     ctx->lanes_per_ray = (int)res->best_lanes_per_ray;

@@ -593,7 +593,9 @@ class Batch:
         return out
 
     def tune(self, packet_rays=(64, 128, 256, 512), leaf_widths=(2, 4, 8), lanes_per_ray=(1, 4), reps=5, out=None,
-             stream=None):
+             stream=None, up_weights=None):
+        """Autotunes the batch (lidar_tune).  up_weights: candidate weights of the horizontal faces in the tree
+        build's area metric (None: the scene's own); with them the timing grid has a leading weight axis."""
         ctx = self.ctx
         if out is None:
             out = alloc_outputs(self.n_rays, POINT_OUTPUTS, ctx.device)
@@ -601,7 +603,9 @@ class Batch:
         pk = np.ascontiguousarray(packet_rays, np.uint32)
         lw = np.ascontiguousarray(leaf_widths, np.uint32)
         ln = np.ascontiguousarray(lanes_per_ray, np.uint32)
-        d = A.TuneDesc(pk.ctypes.data, len(pk), lw.ctypes.data, len(lw), ln.ctypes.data, len(ln), int(reps))
+        uw = None if up_weights is None else np.ascontiguousarray(up_weights, np.float32)
+        d = A.TuneDesc(pk.ctypes.data, len(pk), lw.ctypes.data, len(lw), ln.ctypes.data, len(ln), int(reps),
+                       None if uw is None else uw.ctypes.data, 0 if uw is None else len(uw))
         r = A.TuneResult()
         sd = ctx.scene_desc
         pb, sb = C.c_uint64(), C.c_uint64()
@@ -609,10 +613,14 @@ class Batch:
         scratch = torch.empty(sb.value, dtype=torch.uint8, device=ctx.device)
         check(lib.lidar_tune(ctx.h, C.byref(sd), _ptr(ctx.persistent), ctx.persistent.numel(), _ptr(scratch),
                              sb.value, self.h, C.byref(o), C.byref(d), C.byref(r), _stream(stream)), ctx.h)
-        grid = np.array(r.ms[:len(pk) * len(lw) * len(ln)], np.float64).reshape(len(lw), len(ln), len(pk))
+        nu = 1 if uw is None else len(uw)
+        grid = np.array(r.ms[:nu * len(pk) * len(lw) * len(ln)], np.float64).reshape(nu, len(lw), len(ln), len(pk))
+        if uw is None:
+            grid = grid[0]
         return dict(best_packet_rays=r.best_packet_rays, best_leaf_width=r.best_leaf_width,
-                    best_lanes_per_ray=r.best_lanes_per_ray, best_ms=r.best_ms, ms=grid, packet_rays=list(pk),
-                    leaf_widths=list(lw), lanes_per_ray=list(ln))
+                    best_lanes_per_ray=r.best_lanes_per_ray, best_ms=r.best_ms, best_up_weight=r.best_up_weight,
+                    ms=grid, packet_rays=list(pk), leaf_widths=list(lw), lanes_per_ray=list(ln),
+                    up_weights=None if uw is None else [float(x) for x in uw])
 
     def close(self):
         if getattr(self, "h", None):

@@ -110,6 +110,30 @@ def test_tuner_picks_a_candidate_and_keeps_results(L):
         assert np.array_equal(before[k], after[k]), k
 
 
+def test_tuner_area_weights(L):
+    """With candidate area weights the grid gains a leading weight axis, the chosen weight is a candidate,
+    the outputs are those of the untuned batch (the tree changes, the first hits do not), and a weight
+    outside 1/128..255/128 is refused."""
+    scene, sensor, pose = S.small_16ch()
+    insts = [S.Instance(S.Sensor(S.elev_table(16), 900), pose, seed=5, scan=k) for k in range(3)]
+    ctx = L.Context(0)
+    ctx.load(scene)
+    b = ctx.batch(insts, 64)
+    before = to_np(b.simulate(debug=True))
+    res = b.tune(packet_rays=(64, 256), leaf_widths=(2, 4), lanes_per_ray=(2, 4), reps=2,
+                 up_weights=(1.0, 0.25, 1 / 128))
+    assert res["ms"].shape == (3, 2, 2, 2) and np.all(res["ms"] > 0)
+    assert res["best_up_weight"] in (1.0, 0.25, 1 / 128)
+    assert res["best_ms"] == pytest.approx(float(res["ms"].min()))
+    after = to_np(b.simulate(debug=True))
+    ctx.sync_check()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    for bad in ((0.0,), (2.0,), (float("nan"),), (1.0,) * 65):
+        with pytest.raises(L.LidarError):
+            b.tune(packet_rays=(64,), leaf_widths=(2,), lanes_per_ray=(2,), reps=1, up_weights=bad)
+
+
 def test_batch_recaptures_after_scene_and_material_changes(L):
     """A batch's captured graph holds the scene and material tables by value: after a new scene (another
     leaf width, moved and relabelled geometry, a new buffer), new materials (more of them, so the table
