@@ -734,9 +734,9 @@ void trace_scan_multi_kernel(SceneDev S, InstanceDev in, MaterialsDev M, Overrid
         const Ray ray = beam_ray_lds<SWEEP>(in, pose, j, k, i, scan);
         bool overflow = false;
         Counts c{0u, 0u};
-        // the static walk, specialised for the wavefront's mode (not in the counting and actor variants,
-        // which keep one copy of the loop)
-        Hit h = traverse_multi<LANES, STACK, NR, COUNT, !COUNT && !ACTORS>(
+        // the static walk, specialised for the wavefront's mode (not in the counting variant, which
+        // keeps one copy of the loop)
+        Hit h = traverse_multi<LANES, STACK, NR, COUNT, !COUNT>(
             S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace, stk + q, s, overflow, c,
             min(S.stack_cap, STACK));
         if constexpr (ACTORS) traverse_actors<LANES, STACK, NR>(A, ray, in.t_min, h, stk + q, s, overflow);
