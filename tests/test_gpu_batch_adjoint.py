@@ -408,6 +408,15 @@ def test_error_paths(L):
         ctx.set_pose([np.nan, 0, 0], [1.0, 0.0, 0.0, 0.0])
     with pytest.raises(L.LidarError):
         ctx.set_sensor(S.Sensor(np.array([0.0, np.nan]), 10))
+    # empty, oversized and inconsistent sensors are refused before anything is traced
+    for bad in (S.Sensor(np.zeros(0), 10), S.Sensor(np.zeros(4), 0), S.Sensor(np.zeros(4097), 10),
+                S.Sensor(np.zeros(4096), 1 << 20), S.Sensor(np.array([91.0]), 10),
+                S.Sensor(np.zeros(2), 10, fov_h_deg=0.0), S.Sensor(np.zeros(2), 10, fov_h_deg=361.0),
+                S.Sensor(np.zeros(2), 10, d_max=0.0), S.Sensor(np.zeros(2), 10, t_min=100.0, d_max=100.0),
+                S.Sensor(np.zeros(2), 10, sigma_intensity=-1.0)):
+        with pytest.raises(L.LidarError) as e:
+            ctx.set_sensor(bad)
+        assert e.value.status == A.ERR_INVALID_ARG
     # backward without forward state
     assert lib.lidar_backward(h, None, None, None, None, None, None, None, None, None, None) == A.ERR_NO_FORWARD_STATE
     ctx.simulate(0, 0)
