@@ -88,7 +88,9 @@ typedef struct lidar_batch lidar_batch;
 lidar_status lidar_create(int hip_device, lidar_ctx **out);
 
 /* Frees the context and its context-owned device tables (synchronises the
- * device first).  Caller-owned buffers are untouched.  NULL is accepted. */
+ * device first).  Caller-owned buffers are untouched.  NULL is accepted.
+ * Batches made on the context and not yet destroyed are detached: the only
+ * call that still accepts them is lidar_batch_destroy. */
 lidar_status lidar_destroy(lidar_ctx *ctx);
 
 /* Message describing the last error on `ctx` (or of the last failing
@@ -520,6 +522,16 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep,
  *     as for 1 (default 0).  1 = the scene builder's tree, built by
  *     lidar_actors_set and refit by lidar_actors_update.  Read by
  *     lidar_actors_set.
+ *   LIDAR_OPT_BATCH_STACK: the batched form's walks first run with a short
+ *     stack, so that more wavefronts fit on a CU, and a ray whose walk needs
+ *     more entries is listed and traced again, after the batch's walks and
+ *     in the same launch sequence, by one lane with the whole stack; its
+ *     result is the same as with the whole stack from the start.  0 =
+ *     automatic (default): 32 entries when the tree needs more and a ray
+ *     has one or two lanes; n in 1..96 = at most n entries (to test the
+ *     second pass); -1 = off (one pass with the whole stack).  Up to 2^22
+ *     rays per launch can be listed; beyond that the walks keep what fits
+ *     and lidar_sync_check reports LIDAR_ERR_STACK_OVERFLOW.
  * One option exists to test error handling and does change results:
  *   LIDAR_OPT_STACK_CAP: 0 = a walk of the static scene may use the whole
  *     traversal stack sized for the tree's depth (default); n > 0 = at most n
@@ -532,6 +544,7 @@ lidar_status lidar_simulate_sweep(lidar_ctx *ctx, const lidar_sweep_desc *sweep,
 #define LIDAR_OPT_XCD_REMAP      3u
 #define LIDAR_OPT_STACK_CAP      4u
 #define LIDAR_OPT_ACTOR_TREE     5u
+#define LIDAR_OPT_BATCH_STACK    6u
 lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value);
 
 /* ------------------------------------------------------------------------ */
@@ -581,6 +594,13 @@ lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *batch, const lida
 lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *batch,
                                              const lidar_outputs *out, void *stream);
 
+/* Number of rays that the last lidar_simulate_batch launch on this context
+ * traced again with the whole stack (LIDAR_OPT_BATCH_STACK); waits for the
+ * device.  Measurement and tests only. */
+lidar_status lidar_batch_restarted(lidar_ctx *ctx, uint64_t *n_rays);
+
+/* Frees the batch (synchronises its device first), before or after its
+ * context.  NULL is accepted. */
 lidar_status lidar_batch_destroy(lidar_batch *batch);
 
 /* ------------------------------------------------------------------------ */

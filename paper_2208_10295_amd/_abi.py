@@ -42,6 +42,7 @@ OPT_LANES_PER_RAY = 2
 OPT_XCD_REMAP = 3
 OPT_STACK_CAP = 4
 OPT_ACTOR_TREE = 5
+OPT_BATCH_STACK = 6
 
 STATUS_NAMES = {
     OK: "OK", ERR_INVALID_ARG: "ERR_INVALID_ARG", ERR_NOT_READY: "ERR_NOT_READY",
@@ -162,6 +163,7 @@ SIGNATURES = {
     "lidar_batch_rays": (C.c_int32, [P, C.POINTER(C.c_uint64)]),
     "lidar_simulate_batch": (C.c_int32, [P, P, C.POINTER(Outputs), P]),
     "lidar_simulate_batch_sequential": (C.c_int32, [P, P, C.POINTER(Outputs), P]),
+    "lidar_batch_restarted": (C.c_int32, [P, C.POINTER(C.c_uint64)]),
     "lidar_batch_destroy": (C.c_int32, [P]),
     "lidar_tune": (C.c_int32, [P, C.POINTER(SceneDesc), P, C.c_uint64, P, C.c_uint64, P, C.POINTER(Outputs),
                                C.POINTER(TuneDesc), C.POINTER(TuneResult), P]),

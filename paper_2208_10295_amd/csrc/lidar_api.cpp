@@ -18,6 +18,7 @@ using namespace lidar;
 namespace {
 
 constexpr int kMaxStack = 96;
+constexpr uint64_t kRedoMax = 1ull << 22;   // rays a batch's short-stack pass can list for the second pass
 constexpr uint32_t kMaxAdjMaterials = 256;
 
 thread_local std::string g_create_error;
@@ -71,6 +72,8 @@ struct lidar_ctx {
     BuildResult br{};
     int stack = 32;
     int stack_cap_opt = 0;   // LIDAR_OPT_STACK_CAP (0: the whole stack)
+    std::vector<lidar_batch *> batches;   // live batches made on this context (detached by lidar_destroy)
+    int batch_stack_opt = 0;   // LIDAR_OPT_BATCH_STACK (0: automatic, -1: off, n: first-pass cap n)
     uint32_t leaf_width = 4;
     float build_ms = 0.f;
     // materials
@@ -86,7 +89,8 @@ struct lidar_ctx {
     // pose
     float p[3] = {0, 0, 0};
     float q[4] = {1, 0, 0, 0};
-    // device words: [0] error flags, [1] queue counter, [2..3] refit scratch
+    // device words: [0] error flags, [1] queue counter, [2..3] refit scratch, [4] rays of the last batch
+    // launch traced again by its second pass
     DevBuf words;
     int tile_az_log2 = -1;    // -1: automatic (tile_log2())
     int lanes_per_ray = 4;
@@ -142,7 +146,8 @@ struct lidar_ctx {
 };
 
 struct lidar_batch {
-    lidar_ctx *ctx = nullptr;
+    lidar_ctx *ctx = nullptr;   // null once the context is destroyed (then only lidar_batch_destroy applies)
+    int device = 0;
     uint32_t n_inst = 0;
     std::vector<InstanceDev> h_insts;   // pointers into `tables`
     DevBuf d_insts;
@@ -153,6 +158,9 @@ struct lidar_batch {
     TraceOpts graph_opts{-1, -1, -1, -1};
     uint64_t graph_scene_gen = 0, graph_mat_gen = 0;   // context generations the graph was captured at
     uint64_t inst_mat_gen = 0;                         // material generation of the instances' t_trace
+    DevBuf redo;                                       // rays the first pass lists for the second
+    uint32_t redo_cap = 0;
+    int graph_first_stack = -1, graph_first_cap = -1;  // first-pass stack the graph was captured with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Outputs bound{};
@@ -382,6 +390,7 @@ lidar_status lidar_destroy(lidar_ctx *ctx) {
     for (hipEvent_t ev : ctx->staging_ev)
         if (ev) hipEventDestroy(ev);
     ctx->words.release();
+    for (lidar_batch *b : ctx->batches) b->ctx = nullptr;   // each is freed by its own lidar_batch_destroy
     delete ctx;
     return LIDAR_OK;
 }
@@ -1250,6 +1259,7 @@ lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint
     lidar_batch *b = new (std::nothrow) lidar_batch();
     if (!b) return ctx->fail(LIDAR_ERR_OUT_OF_MEMORY, "batch allocation failed");
     b->ctx = ctx;
+    b->device = ctx->device;
     b->n_inst = n_inst;
     b->packet = packet_rays ? packet_rays : 256;
     b->tile_az_log2 = ctx->batch_tile_log2();
@@ -1276,15 +1286,23 @@ lidar_status lidar_batch_create(lidar_ctx *ctx, const lidar_instance *inst, uint
     b->n_padded = ray_base;
     b->n_rays = out_base;
     b->inst_mat_gen = ctx->mat_gen;
+    // the list of the short-stack pass: padded ray indices as 32-bit words, up to 2^22 rays (16 MB); a batch
+    // of 2^32 padded rays or more runs one pass with the whole stack
+    if (b->n_padded < (1ull << 32)) {
+        const uint32_t cap = (uint32_t)std::min<uint64_t>(b->n_padded, kRedoMax);
+        if (b->redo.ensure(4 * (size_t)cap) == hipSuccess) b->redo_cap = cap;
+    }
     hipError_t e = hipMemcpy(b->d_insts.p, b->h_insts.data(), sizeof(InstanceDev) * n_inst, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         b->tables.release();
         b->d_insts.release();
+        b->redo.release();
         delete b;
         return ctx->hip_fail(e, "batch upload");
     }
+    ctx->batches.push_back(b);
     *out = b;
     return (clamped ? LIDAR_WARN_WAVELENGTH_CLAMPED : LIDAR_OK) | (origin_out ? LIDAR_WARN_ORIGIN_OUTSIDE_SCENE : LIDAR_OK);
 }
@@ -1308,6 +1326,23 @@ lidar_status lidar_batch_rays(const lidar_batch *b, uint64_t *n) {
     return LIDAR_OK;
 }
 
+// The first pass of a batch (stack entries it is compiled for, entries its walks may use), or (0, 0) for
+// one pass with the whole stack.  Automatic: 32 entries when the tree needs more and a ray has one or two
+// lanes (their blocks are held to fewer wavefronts by the stack's LDS; quads are held by registers).
+static void batch_first_pass(const lidar_ctx *ctx, const lidar_batch *b, int &first_stack, int &first_cap) {
+    first_stack = first_cap = 0;
+    const int full = ctx->trace_stack();
+    const int opt = ctx->batch_stack_opt;
+    if (!b->redo_cap || opt < 0) return;
+    if (opt == 0) {
+        if (full > 32 && ctx->lanes_per_ray != 4) first_stack = first_cap = 32;
+        return;
+    }
+    if (opt >= full) return;
+    first_stack = opt <= 32 ? 32 : opt <= 48 ? 48 : opt <= 64 ? 64 : 96;
+    first_cap = opt;
+}
+
 lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_outputs *out, void *stream) {
     lidar_status st = ready(ctx, false);
     if (st != LIDAR_OK) return st;
@@ -1317,15 +1352,20 @@ lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_ou
     if ((st = refresh_batch(ctx, b, (hipStream_t)stream)) != LIDAR_OK) return st;
     Outputs o = to_outputs(out, b->n_rays);
     TraceOpts t = ctx->opts(b->tile_az_log2);
+    int first_stack = 0, first_cap = 0;
+    batch_first_pass(ctx, b, first_stack, first_cap);
     if (!b->has_graph || !same_outputs(o, b->bound) || std::memcmp(&t, &b->graph_opts, sizeof t) != 0 ||
-        b->graph_scene_gen != ctx->scene_gen || b->graph_mat_gen != ctx->mat_gen) {
+        b->graph_scene_gen != ctx->scene_gen || b->graph_mat_gen != ctx->mat_gen ||
+        b->graph_first_stack != first_stack || b->graph_first_cap != first_cap) {
         b->drop_graph();
-        uint32_t grid = (uint32_t)(ctx->n_cu * batch_blocks_per_cu(t));
+        uint32_t grid = (uint32_t)(ctx->n_cu * batch_blocks_per_cu(t, first_stack ? first_stack : t.stack));
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return ctx->hip_fail(e, "graph capture begin");
         uint32_t *words = (uint32_t *)ctx->words.p;
+        const BatchRedo R{first_stack ? (uint32_t *)b->redo.p : nullptr, words + 4, b->redo_cap, first_stack,
+                          first_cap};
         launch_trace_batch(t, ctx->S, (const InstanceDev *)b->d_insts.p, b->n_inst, ctx->M, o, b->n_padded,
-                           b->packet, words + 1, words, grid, b->cap_stream);
+                           b->packet, words + 1, words, R, grid, b->cap_stream);
         e = hipStreamEndCapture(b->cap_stream, &b->graph);
         if (e != hipSuccess) return ctx->hip_fail(e, "graph capture end");
         e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
@@ -1335,6 +1375,8 @@ lidar_status lidar_simulate_batch(lidar_ctx *ctx, lidar_batch *b, const lidar_ou
         }
         b->bound = o;
         b->graph_opts = t;
+        b->graph_first_stack = first_stack;
+        b->graph_first_cap = first_cap;
         b->graph_scene_gen = ctx->scene_gen;
         b->graph_mat_gen = ctx->mat_gen;
         b->has_graph = true;
@@ -1365,14 +1407,31 @@ lidar_status lidar_simulate_batch_sequential(lidar_ctx *ctx, lidar_batch *b, con
     return LIDAR_OK;
 }
 
+lidar_status lidar_batch_restarted(lidar_ctx *ctx, uint64_t *n_rays) {
+    if (!ctx) return LIDAR_ERR_INVALID_ARG;
+    if (!n_rays) return ctx->fail(LIDAR_ERR_INVALID_ARG, "n_rays is null");
+    hipSetDevice(ctx->device);
+    hipError_t e = hipDeviceSynchronize();
+    uint32_t w = 0;
+    if (e == hipSuccess) e = hipMemcpy(&w, (const uint32_t *)ctx->words.p + 4, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ctx->hip_fail(e, "restart count");
+    *n_rays = w;
+    return LIDAR_OK;
+}
+
 lidar_status lidar_batch_destroy(lidar_batch *b) {
     if (!b) return LIDAR_OK;
-    hipSetDevice(b->ctx->device);
+    if (b->ctx) {
+        std::vector<lidar_batch *> &v = b->ctx->batches;
+        v.erase(std::remove(v.begin(), v.end(), b), v.end());
+    }
+    hipSetDevice(b->device);
     hipDeviceSynchronize();
     b->drop_graph();
     if (b->cap_stream) hipStreamDestroy(b->cap_stream);
     b->tables.release();
     b->d_insts.release();
+    b->redo.release();
     delete b;
     return LIDAR_OK;
 }
@@ -1382,6 +1441,7 @@ lidar_status lidar_tune(lidar_ctx *ctx, const lidar_scene_desc *scene, void *per
                         const lidar_tune_desc *desc, lidar_tune_result *res, void *stream) {
     if (!ctx) return LIDAR_ERR_INVALID_ARG;
     if (!scene || !b || !out || !desc || !res) return ctx->fail(LIDAR_ERR_INVALID_ARG, "null argument");
+    if (b->ctx != ctx) return ctx->fail(LIDAR_ERR_INVALID_ARG, "the batch belongs to another context");
     uint32_t cur_lanes = (uint32_t)ctx->lanes_per_ray;
     const uint32_t *lanes = desc->lanes_per_ray ? desc->lanes_per_ray : &cur_lanes;
     uint32_t n_lanes = desc->lanes_per_ray ? desc->n_lanes : 1;
@@ -1610,6 +1670,11 @@ lidar_status lidar_set_option(lidar_ctx *ctx, uint32_t option, int32_t value) {
     case LIDAR_OPT_ACTOR_TREE:
         if (value != 0 && value != 1) return ctx->fail(LIDAR_ERR_INVALID_ARG, "actor tree must be 0 or 1");
         ctx->actor_tree_opt = value;
+        return LIDAR_OK;
+    case LIDAR_OPT_BATCH_STACK:
+        if (value < -1 || value > kMaxStack)
+            return ctx->fail(LIDAR_ERR_INVALID_ARG, "batch stack must be -1 (off), 0 (automatic) or 1..96");
+        ctx->batch_stack_opt = value;
         return LIDAR_OK;
     case LIDAR_OPT_STACK_CAP:
         if (value < 0) return ctx->fail(LIDAR_ERR_INVALID_ARG, "stack cap must be >= 0");

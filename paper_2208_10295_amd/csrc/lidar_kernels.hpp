@@ -87,10 +87,21 @@ void launch_trace_scan(const TraceOpts &t, const SceneDev &S, const InstanceDev 
                        uint32_t *n_tris, const ActorsDev *actors, hipStream_t s);
 void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const MaterialsDev &M, const Overrides &ov,
                        const Outputs &out, int tile_az_log2, uint64_t n_padded, hipStream_t s);
+// A batch's walks may first run with a short stack (more wavefronts fit on a CU): a ray whose walk
+// needs more entries is listed, and a second pass traces the listed rays again with the whole stack.
+struct BatchRedo {
+    uint32_t *list;       // padded ray indices, room for `cap`; null: one pass with the whole stack
+    uint32_t *count;      // rays listed by the last launch (one device word)
+    uint32_t cap;
+    int first_stack;      // stack entries the first pass is compiled for (32, 48, 64 or 96)
+    int first_cap;        // entries its walks may use
+};
+constexpr uint32_t kRedoBlocks = 256;   // second pass: 64-lane blocks striding over the list
 void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
                         const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
-                        uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s);
-int batch_blocks_per_cu(const TraceOpts &t);
+                        uint32_t *queue, uint32_t *err, const BatchRedo &R, uint32_t grid, hipStream_t s);
+// blocks of the batched kernel per CU for a first pass compiled for `stack` entries
+int batch_blocks_per_cu(const TraceOpts &t, int stack);
 
 // --- divergent beams and multi-echo returns (trace.hip) ---
 constexpr int kMaxSub = 16;      // sub-rays per beam

@@ -1093,7 +1093,8 @@ __global__ __launch_bounds__(BLOCK, lds_waves(LANES == 4 ? 8 : LANES == 2 ? 6 : 
                                            4 * (STACK + kStackPad) * (BLOCK / LANES) + (BLOCK / 64) * (3 * 64 * 4 + 96), BLOCK))
 void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts, uint32_t n_inst, MaterialsDev M,
                         Outputs out, int tile_az_log2, uint64_t n_padded_total, uint32_t packet,
-                        uint32_t *queue, uint32_t *err) {
+                        uint32_t *queue, uint32_t *err, uint32_t *__restrict__ redo, uint32_t *redo_count,
+                        uint32_t redo_cap) {
     constexpr int NSLOT = BLOCK / LANES;
     constexpr uint32_t RAYS_PER_WAVE = 64u / LANES;
     __shared__ uint32_t stk[(STACK + kStackPad) * NSLOT];
@@ -1134,14 +1135,26 @@ void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts, uint3
                 Hit h{kNone, kNone, 0.0f, kNone};
                 if (ray_coords(r0 + sub + sub_lane, in, tile_az_log2, j, k)) {
                     const Ray ray = make_ray(in, lds_pose(gpose[wave]), j, k);
+                    bool ovf = false;
                     if constexpr (LANES == 1)
                         h = traverse<STACK, NSLOT, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min,
-                                                          in.t_trace, stk + slot, overflow, cnt,
+                                                          in.t_trace, stk + slot, ovf, cnt,
                                                           min(S.stack_cap, STACK));
                     else
                         h = traverse_multi<LANES, STACK, NSLOT, false, true>(S.nodes, S.tris, S.root, S.max_steps, ray,
-                                                                       in.t_min, in.t_trace, stk + slot, s, overflow,
+                                                                       in.t_min, in.t_trace, stk + slot, s, ovf,
                                                                        cnt, min(S.stack_cap, STACK));
+                    // a walk that ran out of this pass's stack (the same for all lanes of its ray) is
+                    // listed for the second pass, which traces it again with the whole stack
+                    if (ovf) {
+                        if (!redo) {
+                            overflow = true;
+                        } else if (s == 0) {
+                            const uint32_t slot_r = atomicAdd(redo_count, 1u);
+                            if (slot_r < redo_cap) redo[slot_r] = (uint32_t)(base + sub + sub_lane);
+                            else overflow = true;
+                        }
+                    }
                 }
                 if (s == 0) {
                     hand[wave][0][sub + sub_lane] = h.slot;
@@ -1163,7 +1176,40 @@ void trace_batch_kernel(SceneDev S, const InstanceDev *__restrict__ insts, uint3
     if (overflow) atomicOr(err, 1u);
 }
 
-__global__ void reset_queue_kernel(uint32_t *queue) { *queue = 0u; }
+__global__ void reset_queue_kernel(uint32_t *queue, uint32_t *redo_count) {
+    *queue = 0u;
+    if (redo_count) *redo_count = 0u;
+}
+
+// Second pass of a batch whose first pass ran with a short stack: every listed
+// ray (its padded index) is traced again by one lane with the whole stack,
+// shaded and written over the first pass's output.  The hit is the same as
+// any walk's that kept all of its children (the lexicographic (t, index)
+// minimum), so the batch's results do not depend on the first pass's stack.
+template <int STACK>
+__global__ __launch_bounds__(64) void batch_redo_kernel(SceneDev S, const InstanceDev *__restrict__ insts,
+                                                        uint32_t n_inst, MaterialsDev M, Outputs out,
+                                                        int tile_az_log2, const uint32_t *__restrict__ redo,
+                                                        const uint32_t *__restrict__ redo_count, uint32_t redo_cap,
+                                                        uint32_t *err) {
+    __shared__ uint32_t stk[(STACK + kStackPad) * 64];
+    const Overrides ov{nullptr, nullptr, nullptr, nullptr};
+    const uint32_t n = min(*redo_count, redo_cap);
+    bool overflow = false;
+    Counts cnt{0u, 0u};
+    for (uint32_t i = blockIdx.x * 64u + threadIdx.x; i < n; i += gridDim.x * 64u) {
+        const uint64_t r = redo[i];
+        const InstanceDev &in = insts[find_instance(insts, n_inst, r)];
+        uint32_t j, k;
+        if (!ray_coords(r - in.ray_base, in, tile_az_log2, j, k)) continue;
+        const Ray ray = make_ray(in, make_pose(in, nullptr), j, k);
+        const Hit h = traverse<STACK, 64, false>(S.nodes, S.tris, S.root, S.max_steps, ray, in.t_min, in.t_trace,
+                                                 stk + threadIdx.x, overflow, cnt, min(S.stack_cap, STACK));
+        const uint32_t beam = j * in.n_az + k;
+        shade_and_write(in, M, ov, out, in.out_base + beam, beam, in.scan, ray, S.tris, h);
+    }
+    if (overflow) atomicOr(err, 1u);
+}
 
 // ---------------------------------------------------------------------------
 // host launchers
@@ -1274,37 +1320,59 @@ void launch_bruteforce(const SceneDev &S, const InstanceDev &in, const Materials
 template <int STACK, int LANES>
 static void launch_batch_t(const SceneDev &S, const InstanceDev *insts, uint32_t n_inst, const MaterialsDev &M,
                            const Outputs &out, int tile_az_log2, uint64_t n_padded, uint32_t packet,
-                           uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
+                           uint32_t *queue, uint32_t *err, const BatchRedo &R, uint32_t grid, hipStream_t s) {
     constexpr int B = LANES == 4 ? kQuadBlock : LANES == 2 ? kPairBlock : kBlock;
-    reset_queue_kernel<<<1, 1, 0, s>>>(queue);
     trace_batch_kernel<STACK, B, LANES><<<grid, B, 0, s>>>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet,
-                                                           queue, err);
+                                                           queue, err, R.list, R.count, R.cap);
 }
 
 template <int STACK>
-static void launch_batch_s(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
-                           const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
-                           uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
-    if (t.lanes_per_ray == 4)
-        launch_batch_t<STACK, 4>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
-    else if (t.lanes_per_ray == 2)
-        launch_batch_t<STACK, 2>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+static void launch_batch_s(int lanes, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
+                           const MaterialsDev &M, const Outputs &out, int tile_az_log2, uint64_t n_padded,
+                           uint32_t packet, uint32_t *queue, uint32_t *err, const BatchRedo &R, uint32_t grid,
+                           hipStream_t s) {
+    if (lanes == 4)
+        launch_batch_t<STACK, 4>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet, queue, err, R, grid, s);
+    else if (lanes == 2)
+        launch_batch_t<STACK, 2>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet, queue, err, R, grid, s);
     else
-        launch_batch_t<STACK, 1>(S, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, grid, s);
+        launch_batch_t<STACK, 1>(S, insts, n_inst, M, out, tile_az_log2, n_padded, packet, queue, err, R, grid, s);
+}
+
+template <int STACK>
+static void launch_redo_s(const SceneDev &S, const InstanceDev *insts, uint32_t n_inst, const MaterialsDev &M,
+                          const Outputs &out, int tile_az_log2, uint32_t *err, const BatchRedo &R, hipStream_t s) {
+    batch_redo_kernel<STACK><<<kRedoBlocks, 64, 0, s>>>(S, insts, n_inst, M, out, tile_az_log2, R.list, R.count,
+                                                         R.cap, err);
 }
 
 void launch_trace_batch(const TraceOpts &t, const SceneDev &S, const InstanceDev *insts, uint32_t n_inst,
                         const MaterialsDev &M, const Outputs &out, uint64_t n_padded, uint32_t packet,
-                        uint32_t *queue, uint32_t *err, uint32_t grid, hipStream_t s) {
-    if (t.stack <= 32) launch_batch_s<32>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
-    else if (t.stack <= 48) launch_batch_s<48>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
-    else if (t.stack <= 64) launch_batch_s<64>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
-    else launch_batch_s<96>(t, S, insts, n_inst, M, out, n_padded, packet, queue, err, grid, s);
+                        uint32_t *queue, uint32_t *err, const BatchRedo &R, uint32_t grid, hipStream_t s) {
+    reset_queue_kernel<<<1, 1, 0, s>>>(queue, R.count);
+    // the first pass: a short stack (at most R.first_cap entries) when R.list is set, else the whole one
+    SceneDev S1 = S;
+    int st = t.stack;
+    if (R.list) {
+        st = R.first_stack;
+        S1.stack_cap = min(S.stack_cap, R.first_cap);
+    }
+    if (st <= 32) launch_batch_s<32>(t.lanes_per_ray, S1, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, R, grid, s);
+    else if (st <= 48) launch_batch_s<48>(t.lanes_per_ray, S1, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, R, grid, s);
+    else if (st <= 64) launch_batch_s<64>(t.lanes_per_ray, S1, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, R, grid, s);
+    else launch_batch_s<96>(t.lanes_per_ray, S1, insts, n_inst, M, out, t.tile_az_log2, n_padded, packet, queue, err, R, grid, s);
+    if (!R.list) return;
+    if (t.stack <= 32) launch_redo_s<32>(S, insts, n_inst, M, out, t.tile_az_log2, err, R, s);
+    else if (t.stack <= 48) launch_redo_s<48>(S, insts, n_inst, M, out, t.tile_az_log2, err, R, s);
+    else if (t.stack <= 64) launch_redo_s<64>(S, insts, n_inst, M, out, t.tile_az_log2, err, R, s);
+    else launch_redo_s<96>(S, insts, n_inst, M, out, t.tile_az_log2, err, R, s);
 }
 
-int batch_blocks_per_cu(const TraceOpts &t) {
-    // LDS per block = stack entries x stack slots x 4 bytes; 160 KB per CU on gfx950
-    int st = t.stack <= 32 ? 32 : t.stack <= 48 ? 48 : t.stack <= 64 ? 64 : 96;
+int batch_blocks_per_cu(const TraceOpts &t, int stack) {
+    // LDS per block = stack entries x stack slots x 4 bytes; 160 KB per CU on gfx950.  Blocks beyond what
+    // the registers let reside (pairs with a 32-entry stack: 12 of 14) start when the queue is empty and
+    // leave at once.
+    int st = stack <= 32 ? 32 : stack <= 48 ? 48 : stack <= 64 ? 64 : 96;
     int lanes = t.lanes_per_ray;
     int block = lanes == 4 ? kQuadBlock : lanes == 2 ? kPairBlock : kBlock;
     int slots = block / lanes;

@@ -302,6 +302,17 @@ class Context:
         Read by the next set_actors."""
         check(lib.lidar_set_option(self.h, A.OPT_ACTOR_TREE, int(mode)), self.h)
 
+    def set_batch_stack(self, entries: int):
+        """First-pass stack of batched launches: 0 automatic, -1 off, n > 0 at most n entries (rays that need
+        more are traced again with the whole stack; results never change)."""
+        check(lib.lidar_set_option(self.h, A.OPT_BATCH_STACK, int(entries)), self.h)
+
+    def batch_restarted(self) -> int:
+        """Rays the last batched launch traced again with the whole stack (waits for the device)."""
+        n = C.c_uint64()
+        check(lib.lidar_batch_restarted(self.h, C.byref(n)), self.h)
+        return int(n.value)
+
     def set_stack_cap(self, entries: int):
         """Limit the traversal stack of static-scene walks to `entries` (0 = no limit).  Only for testing
         the overflow path: results of walks that overflow are wrong and sync_check() raises."""

@@ -51,6 +51,91 @@ def test_batch_equals_sequential_and_oracle(bat):
     assert tot["n"] == sum(i.sensor.n_beams // 100 for i in insts) and tot["tri_mismatch"] == 0
 
 
+def test_batch_short_stack_first_pass(bat):
+    """The batched walks of one or two lanes per ray first run with a 32-entry stack (the 522k tree needs
+    48), and rays that need more are traced again with the whole stack: with two lanes the automatic
+    first pass, a forced 16-entry one (rays traced twice) and one pass with the whole stack all equal
+    the sequential launches on all 21.4 M rays."""
+    ctx, batch, _, _ = bat
+    assert ctx.stats()["stack_entries"] > 32
+    ref = to_np(batch.simulate(debug=True, sequential=True))
+    ctx.sync_check()
+    try:
+        ctx.set_lanes_per_ray(2)
+        for opt in (0, 16, -1):
+            ctx.set_batch_stack(opt)
+            got = to_np(batch.simulate(debug=True))
+            ctx.sync_check()
+            n = ctx.batch_restarted()
+            print(f"[batch stack] option {opt}: {n} rays traced again", flush=True)
+            if opt == -1:
+                assert n == 0
+            for k in ref:
+                assert np.array_equal(ref[k], got[k]), (opt, k)
+    finally:
+        ctx.set_batch_stack(0)
+        ctx.set_lanes_per_ray(4)
+
+
+def test_batch_short_stack_every_lane_count(L):
+    """A first pass of 1 or 2 stack entries (nearly every walk needs more) with 1, 2 and 4 lanes per ray:
+    the second pass gives the one-pass results; with the stack capped for the whole walk (the error
+    option), the second pass overflows too and sync_check reports it."""
+    from paper_2208_10295_amd import _abi as A
+    scene, sensor, pose = S.small_16ch()
+    insts = [S.Instance(S.Sensor(S.elev_table(16), n_az), pose, seed=11, scan=k) for k, n_az in
+             enumerate((900, 333, 64))]
+    ctx = L.Context(0)
+    ctx.load(scene)
+    b = ctx.batch(insts, 64)
+    ctx.set_batch_stack(-1)
+    ref = to_np(b.simulate(debug=True))
+    ctx.sync_check()
+    for lanes in (1, 2, 4):
+        ctx.set_lanes_per_ray(lanes)
+        for opt in (1, 2):
+            ctx.set_batch_stack(opt)
+            got = to_np(b.simulate(debug=True))
+            ctx.sync_check()
+            assert ctx.batch_restarted() > 0, (lanes, opt)
+            for k in ref:
+                assert np.array_equal(ref[k], got[k]), (lanes, opt, k)
+    ctx.set_stack_cap(1)
+    b.simulate(debug=True)
+    with pytest.raises(L.LidarError) as e:
+        ctx.sync_check()
+    assert e.value.status == A.ERR_STACK_OVERFLOW
+    ctx.set_stack_cap(0)
+    for bad in (-2, 97):
+        with pytest.raises(L.LidarError):
+            ctx.set_batch_stack(bad)
+
+
+def test_batch_may_outlive_its_context(L):
+    """Destroying a context detaches its batches: a batch destroyed afterwards frees only itself and leaves
+    no pending HIP error behind (the next kernel launch of another library still succeeds), and a detached
+    batch is refused by the calls of another context."""
+    scene, sensor, pose = S.small_16ch()
+    insts = [S.Instance(S.Sensor(S.elev_table(16), 64), pose, seed=1)]
+    ctx = L.Context(0)
+    ctx.load(scene)
+    b = ctx.batch(insts, 64)
+    b.simulate()
+    ctx.sync_check()
+    ctx.close()
+    other = L.Context(0)
+    other.load(scene)
+    from paper_2208_10295_amd import _abi as A
+    from paper_2208_10295_amd.lidar import alloc_outputs, outputs_struct, POINT_OUTPUTS
+    o = outputs_struct(alloc_outputs(b.n_rays, POINT_OUTPUTS, other.device))
+    assert A.lib.lidar_simulate_batch(other.h, b.h, C.byref(o), None) == A.ERR_INVALID_ARG
+    b.close()
+    t = torch.arange(1024, device="cuda", dtype=torch.float32)
+    assert float((t * 2).sum().item()) == 1023.0 * 1024.0
+    torch.cuda.synchronize()
+    other.close()
+
+
 def test_batch_graph_replays_are_identical(bat):
     ctx, batch, _, _ = bat
     from paper_2208_10295_amd.lidar import alloc_outputs, POINT_OUTPUTS
