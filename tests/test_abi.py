@@ -141,6 +141,9 @@ def test_null_context_calls_are_rejected(A):
     assert lib.lidar_materials_set(None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_backward(None, None, None, None, None, None, None, None, None, None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_batch_destroy(None) == A.OK
+    assert lib.lidar_batch_restarted(None, None) == A.ERR_INVALID_ARG
+    assert lib.lidar_set_option(None, A.OPT_BATCH_STACK, 0) == A.ERR_INVALID_ARG
+    assert lib.lidar_tune(None, None, None, 0, None, 0, None, None, None, None, None) == A.ERR_INVALID_ARG
     assert lib.lidar_compact_points(None, None, 0, None, None, None, None, 0, None) == A.ERR_INVALID_ARG
     assert lib.lidar_create(0, None) == A.ERR_INVALID_ARG
 
